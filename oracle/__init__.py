@@ -1,0 +1,208 @@
+"""ctypes wrapper of the FP64 reference library (oracle.c).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package.  The HIP product path never does.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+UNIFORM, WEIGHTED, BOUNCEBACK = 0, 1, 2
+PASSIVE, BARYCENTRIC = 0, 1
+XPERIODIC, XRESERVOIR = 0, 1
+
+
+def build(force=True):
+    """Compile oracle.c with gcc (plain C, OpenMP, no FMA contraction)."""
+    if not force and os.path.exists(LIB):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-Wall", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tau_gas", ctypes.c_double), ("tau_species", ctypes.c_double),
+                ("p", ctypes.c_double), ("p_stick", ctypes.c_double),
+                ("c_inlet", ctypes.c_double), ("rho0", ctypes.c_double), ("c0", ctypes.c_double),
+                ("force", ctypes.c_double * 3),
+                ("sputter", ctypes.c_int32), ("coupling", ctypes.c_int32),
+                ("species_x", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.POINTER(Params)]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        for name in ("orc_fields",):
+            getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]
+        L.orc_conversion_map.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_totals.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_step_count.argtypes = [ctypes.c_void_p]
+        L.orc_step_count.restype = ctypes.c_long
+        L.orc_get_state.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_set_state.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_link_counts.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_d3q19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_d3q19.restype = ctypes.c_int
+        for name in ("orc_kn_from_tau", "orc_tau_from_kn", "orc_da_from_p"):
+            getattr(L, name).argtypes = [ctypes.c_double, ctypes.c_double]
+            getattr(L, name).restype = ctypes.c_double
+        L.orc_p_from_da.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+        L.orc_p_from_da.restype = ctypes.c_double
+        L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
+        L.orc_guo_source.argtypes = [ctypes.c_double, dp, dp, dp]
+        L.orc_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def d3q19():
+    c = np.zeros((19, 3), dtype=np.int32)
+    w = np.zeros(19)
+    opp = np.zeros(19, dtype=np.int32)
+    lib().orc_d3q19(c.ctypes.data, w.ctypes.data, opp.ctypes.data)
+    return c, w, opp
+
+
+def kn_from_tau(tau, delta):
+    return lib().orc_kn_from_tau(tau, delta)
+
+
+def tau_from_kn(kn, delta):
+    return lib().orc_tau_from_kn(kn, delta)
+
+
+def p_from_da(da, delta):
+    cl = ctypes.c_int(0)
+    p = lib().orc_p_from_da(da, delta, ctypes.byref(cl))
+    return p, bool(cl.value)
+
+
+def da_from_p(p, delta):
+    return lib().orc_da_from_p(p, delta)
+
+
+def equilibrium(rho, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(19)
+    lib().orc_equilibrium(rho, _dp(u), _dp(out))
+    return out
+
+
+def guo_source(tau, u, F):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros(19)
+    lib().orc_guo_source(tau, _dp(u), _dp(F), _dp(out))
+    return out
+
+
+def threads():
+    return lib().orc_threads()
+
+
+class Oracle:
+    """One FP64 reference simulation of the gas + reactant lattices."""
+
+    def __init__(self, vox, tau=(0.8, 0.7), p=0.1, p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0,
+                 force=(0.0, 0.0, 0.0), sputter=UNIFORM, coupling=PASSIVE, species_x=XRESERVOIR):
+        vox = np.ascontiguousarray(vox, dtype=np.uint8)
+        assert vox.ndim == 3
+        self.nz, self.ny, self.nx = vox.shape
+        self.n = vox.size
+        self.vox = vox
+        prm = Params()
+        prm.tau_gas, prm.tau_species = float(tau[0]), float(tau[1])
+        prm.p, prm.p_stick, prm.c_inlet = float(p), float(p_stick), float(c_inlet)
+        prm.rho0, prm.c0 = float(rho0), float(c0)
+        for a in range(3):
+            prm.force[a] = float(force[a])
+        prm.sputter, prm.coupling, prm.species_x = int(sputter), int(coupling), int(species_x)
+        self.params = prm
+        h = lib().orc_create(self.nx, self.ny, self.nz, vox.ctypes.data, ctypes.byref(prm))
+        if not h:
+            raise MemoryError("orc_create failed")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        lib().orc_step(self._h, int(n))
+
+    @property
+    def step_count(self):
+        return lib().orc_step_count(self._h)
+
+    def fields(self):
+        shape = (self.nz, self.ny, self.nx)
+        rho = np.zeros(self.n)
+        u = np.zeros(3 * self.n)
+        c = np.zeros(self.n)
+        lib().orc_fields(self._h, rho.ctypes.data, u.ctypes.data, c.ctypes.data)
+        return rho.reshape(shape), u.reshape((3,) + shape), c.reshape(shape)
+
+    def conversion_map(self):
+        out = np.zeros(self.n)
+        lib().orc_conversion_map(self._h, out.ctypes.data)
+        return out.reshape((self.nz, self.ny, self.nx))
+
+    def totals(self):
+        t = np.zeros(6)
+        lib().orc_totals(self._h, t.ctypes.data)
+        keys = ("mass_gas", "mass_species", "converted", "lost", "influx", "outflux")
+        return dict(zip(keys, t.tolist()))
+
+    def link_counts(self):
+        b = np.zeros(self.n, dtype=np.uint8)
+        lib().orc_link_counts(self._h, b.ctypes.data)
+        return b.reshape((self.nz, self.ny, self.nx))
+
+    def get_state(self):
+        fC = np.zeros((self.n, 19))
+        fR = np.zeros((self.n, 19))
+        lib().orc_get_state(self._h, fC.ctypes.data, fR.ctypes.data)
+        return fC, fR
+
+    def set_state(self, fC=None, fR=None):
+        a = None if fC is None else np.ascontiguousarray(fC, dtype=np.float64)
+        b = None if fR is None else np.ascontiguousarray(fR, dtype=np.float64)
+        lib().orc_set_state(self._h, None if a is None else a.ctypes.data,
+                            None if b is None else b.ctypes.data)

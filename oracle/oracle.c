@@ -1,0 +1,578 @@
+/*
+ * FP64 reference ("oracle") for the reactive two-lattice lattice-Boltzmann step.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline timing of the benchmark load this library.  The product path (the
+ * HIP library and its Python binding) never links, imports or calls it, and it
+ * shares no code, header or table with that path.
+ *
+ * Plain, slow and obviously correct on purpose: array-of-structures storage
+ * f[node][19], one loop per step of the method, FP64 throughout, a fixed
+ * summation order (directions ascending, nodes in (z, y, x) order, interface
+ * nodes in index order).  The only parallelism is OpenMP over z-planes in the
+ * collision and streaming loops, where every node writes only its own entries,
+ * so results are bit-identical for any thread count.
+ *
+ * What is computed (paper: Appendix "Numerical Method"):
+ *   - BGK lattice Boltzmann equation for each species alpha, Eq. (LBE):
+ *       f_i(x + c_i, t + 1) - f_i(x, t) = omega [f_i^eq(x, t) - f_i(x, t)],
+ *     split as collision followed by streaming;
+ *   - second-order equilibrium w_i rho [1 + c.u/cs^2 + (c.u)^2/(2 cs^4)
+ *     - u^2/(2 cs^2)] with cs^2 = 1/3 (equilibrium equation after Eq. LBE);
+ *   - moments rho = sum_i f_i, rho u = sum_i c_i f_i, and the common
+ *     barycentric velocity sum_a rho_a u_a / sum_a rho_a (moment equations);
+ *   - the lattice is D3Q19 (weights 1/3, 1/18, 1/36), the 3-D counterpart of
+ *     the paper's D2Q9; it meets the paper's weight constraints
+ *     sum w = 1, sum w c = 0, sum w c c = cs^2 I;
+ *   - the "sputtering" stick-and-react boundary condition, first line of the
+ *     eqnarray (f_R_in / f_P_in): a reactant population arriving at a catalytic
+ *     node along an active link is re-emitted into the gas with probability
+ *     (1 - p_S^R) along the directions picked by the sputtering matrix S,
+ *     which conserves what it redistributes (sum_i S_ij = 1); the fraction
+ *     p p_S^R is converted into product (second line), the remaining
+ *     (1 - p) p_S^R is lost, so total (R + P) mass is not conserved unless the
+ *     sticking probability is zero (text after the eqnarray);
+ *   - a body force drives the carrier ("Validation of Numerical Model"),
+ *     implemented with Guo's forcing term and the half-force velocity shift.
+ *
+ * Readings where the paper is silent (the same readings the HIP path uses):
+ *   - gas lattice C and reactant lattice R only; relaxation time per lattice;
+ *   - species advection velocity: PASSIVE (carrier velocity; the text says
+ *     reactant and product are passively transported by the carrier) or
+ *     BARYCENTRIC (the common velocity of the moment equations);
+ *   - halfway bounce-back at every solid link of the gas, and at inert-solid
+ *     links of the species;
+ *   - sputter timing: what arrives at a catalytic node during a step leaves it
+ *     along the reversed active links at the next streaming (link-wise,
+ *     one step, like halfway bounce-back);
+ *   - S as an expectation: UNIFORM (each active direction 1/b), WEIGHTED
+ *     (proportional to w_i) or BOUNCEBACK (reversal);
+ *   - species x-boundaries: RESERVOIR puts an inlet ghost plane at x = -1
+ *     holding w_i c_in and an outlet ghost plane at x = nx that copies plane
+ *     nx - 1 (zero gradient; a solid copy reflects as inert solid);
+ *     PERIODIC wraps x like y and z.  The gas is periodic in x, y and z.
+ */
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define Q 19
+
+/* D3Q19: rest, 6 axis links (w = 1/18), 12 face diagonals (w = 1/36). */
+static const int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+static const double WT[Q] = {1.0 / 3.0,
+                             1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+enum { ORC_FLUID = 0, ORC_INERT = 1, ORC_CATALYTIC = 2 };
+enum { ORC_UNIFORM = 0, ORC_WEIGHTED = 1, ORC_BOUNCEBACK = 2 };
+enum { ORC_PASSIVE = 0, ORC_BARYCENTRIC = 1 };
+enum { ORC_XPERIODIC = 0, ORC_XRESERVOIR = 1 };
+
+typedef struct {
+    double tau_gas, tau_species; /* relaxation times of C and R */
+    double p;                    /* reaction probability */
+    double p_stick;              /* sticking probability p_S^R */
+    double c_inlet;              /* reservoir concentration */
+    double rho0, c0;             /* initial carrier density and concentration */
+    double force[3];             /* body-force density on the carrier */
+    int32_t sputter, coupling, species_x, pad;
+} orc_params;
+
+typedef struct {
+    int nx, ny, nz;
+    long n;
+    unsigned char *vox;
+    orc_params prm;
+    double *fC, *fR;   /* pre-collision populations f[node*Q + i] */
+    double *pC, *pR;   /* post-collision populations */
+    double *em;        /* emission E_i(k) of catalytic nodes, [node*Q + i] */
+    double *acc;       /* accumulated arrivals sum_t In(k, t), per node */
+    double tot[6];     /* mass_gas, mass_species, converted, lost, influx, outflux */
+    long step;
+} orc;
+
+/* ---------------------------------------------------------------- tables -- */
+
+int orc_d3q19(int *c, double *w, int *opp)
+{
+    for (int i = 0; i < Q; ++i) {
+        c[3 * i + 0] = CX[i];
+        c[3 * i + 1] = CY[i];
+        c[3 * i + 2] = CZ[i];
+        w[i] = WT[i];
+        opp[i] = OPP[i];
+    }
+    return Q;
+}
+
+/* ------------------------------------------------------- parameter maps -- */
+
+/* Knudsen number Kn = cs (tau - dt/2) / delta, Eq. (knudsen) with dt = 1. */
+double orc_kn_from_tau(double tau, double delta)
+{
+    return sqrt(1.0 / 3.0) * (tau - 0.5) / delta;
+}
+
+double orc_tau_from_kn(double kn, double delta)
+{
+    return 0.5 + kn * delta / sqrt(1.0 / 3.0);
+}
+
+/* Damkohler number Da = tau_ch / tau_tr, Eq. (Da_def), with the chemical time
+ * tau_ch = dt / p = 1 / p in lattice units and the transport time
+ * tau_tr = delta / v, v taken as the lattice sound speed ("Results &
+ * Discussion", definition of the conversion efficiency study).  Hence
+ * p = cs / (Da delta), clamped to a probability; Da = +inf gives p = 0. */
+double orc_p_from_da(double da, double delta, int *clamped)
+{
+    double p;
+    if (isinf(da))
+        p = 0.0;
+    else
+        p = sqrt(1.0 / 3.0) / (da * delta);
+    if (clamped)
+        *clamped = p > 1.0;
+    return p > 1.0 ? 1.0 : p;
+}
+
+double orc_da_from_p(double p, double delta)
+{
+    return (1.0 / p) / (delta / sqrt(1.0 / 3.0));
+}
+
+/* -------------------------------------------------- kinetic ingredients -- */
+
+/* Second-order equilibrium (equilibrium equation of the Appendix), cs^2 = 1/3. */
+void orc_equilibrium(double rho, const double *u, double *feq)
+{
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; ++i) {
+        double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
+        feq[i] = WT[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+}
+
+/* Guo forcing term (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i . u) c_i] . F. */
+void orc_guo_source(double tau, const double *u, const double *F, double *S)
+{
+    for (int i = 0; i < Q; ++i) {
+        double c[3] = {CX[i], CY[i], CZ[i]};
+        double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a)
+            s += (3.0 * (c[a] - u[a]) + 9.0 * cu * c[a]) * F[a];
+        S[i] = (1.0 - 1.0 / (2.0 * tau)) * WT[i] * s;
+    }
+}
+
+/* Neumaier-compensated running sum, so that the global totals carry no
+ * summation error worth speaking of (a plain serial sum over ~1e6 terms drifts
+ * by ~1e-12 relative, which would hide the conservation properties). */
+typedef struct {
+    double s, c;
+} ksum;
+
+static void kadd(ksum *k, double v)
+{
+    double t = k->s + v;
+    if (fabs(k->s) >= fabs(v))
+        k->c += (k->s - t) + v;
+    else
+        k->c += (v - t) + k->s;
+    k->s = t;
+}
+
+static double kval(const ksum *k)
+{
+    return k->s + k->c;
+}
+
+/* ------------------------------------------------------------- geometry -- */
+
+static long node(const orc *o, int x, int y, int z)
+{
+    return ((long)z * o->ny + y) * o->nx + x;
+}
+
+static int wrap(int a, int n)
+{
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+
+/* Source of the pull along direction i into (x, y, z): (x, y, z) - c_i with y
+ * and z periodic; x periodic when xper, else returned as is (may be -1 or nx). */
+static void source(const orc *o, int x, int y, int z, int i, int xper, int *sx, int *sy, int *sz)
+{
+    *sx = xper ? wrap(x - CX[i], o->nx) : x - CX[i];
+    *sy = wrap(y - CY[i], o->ny);
+    *sz = wrap(z - CZ[i], o->nz);
+}
+
+/* Incoming active links of catalytic node k: j >= 1 whose source k - c_j is an
+ * in-domain gas node.  Returns b(k) and the link set as a bit mask. */
+static int active_links(const orc *o, int x, int y, int z, unsigned *mask)
+{
+    int xper = o->prm.species_x == ORC_XPERIODIC;
+    int b = 0;
+    *mask = 0;
+    for (int j = 1; j < Q; ++j) {
+        int sx, sy, sz;
+        source(o, x, y, z, j, xper, &sx, &sy, &sz);
+        if (sx < 0 || sx >= o->nx)
+            continue;
+        if (o->vox[node(o, sx, sy, sz)] == ORC_FLUID) {
+            *mask |= 1u << j;
+            ++b;
+        }
+    }
+    return b;
+}
+
+void orc_link_counts(const orc *o, unsigned char *b)
+{
+    for (int z = 0; z < o->nz; ++z)
+        for (int y = 0; y < o->ny; ++y)
+            for (int x = 0; x < o->nx; ++x) {
+                long n = node(o, x, y, z);
+                unsigned m;
+                b[n] = o->vox[n] == ORC_CATALYTIC ? (unsigned char)active_links(o, x, y, z, &m) : 0;
+            }
+}
+
+/* ------------------------------------------------------------ lifecycle -- */
+
+static void moments(const double *f, double *rho, double *j)
+{
+    *rho = 0.0;
+    j[0] = j[1] = j[2] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        *rho += f[i];
+        j[0] += CX[i] * f[i];
+        j[1] += CY[i] * f[i];
+        j[2] += CZ[i] * f[i];
+    }
+}
+
+static void totals_mass(orc *o)
+{
+    ksum mc = {0.0, 0.0}, mr = {0.0, 0.0};
+    for (long n = 0; n < o->n; ++n) {
+        if (o->vox[n] != ORC_FLUID)
+            continue;
+        for (int i = 0; i < Q; ++i) {
+            kadd(&mc, o->fC[n * Q + i]);
+            kadd(&mr, o->fR[n * Q + i]);
+        }
+    }
+    o->tot[0] = kval(&mc);
+    o->tot[1] = kval(&mr);
+}
+
+orc *orc_create(int nx, int ny, int nz, const unsigned char *vox, const orc_params *prm)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !vox || !prm)
+        return NULL;
+    orc *o = calloc(1, sizeof(orc));
+    if (!o)
+        return NULL;
+    o->nx = nx;
+    o->ny = ny;
+    o->nz = nz;
+    o->n = (long)nx * ny * nz;
+    o->prm = *prm;
+    o->vox = malloc(o->n);
+    o->fC = calloc(o->n * Q, sizeof(double));
+    o->fR = calloc(o->n * Q, sizeof(double));
+    o->pC = calloc(o->n * Q, sizeof(double));
+    o->pR = calloc(o->n * Q, sizeof(double));
+    o->em = calloc(o->n * Q, sizeof(double));
+    o->acc = calloc(o->n, sizeof(double));
+    if (!o->vox || !o->fC || !o->fR || !o->pC || !o->pR || !o->em || !o->acc) {
+        free(o->vox); free(o->fC); free(o->fR); free(o->pC); free(o->pR); free(o->em); free(o->acc);
+        free(o);
+        return NULL;
+    }
+    memcpy(o->vox, vox, o->n);
+    /* Initial state: carrier at rest with density rho0, species at c0
+     * (the paper starts with no reactant in the domain). */
+    double zero[3] = {0.0, 0.0, 0.0};
+    double eqC[Q], eqR[Q];
+    orc_equilibrium(prm->rho0, zero, eqC);
+    orc_equilibrium(prm->c0, zero, eqR);
+    for (long n = 0; n < o->n; ++n) {
+        if (o->vox[n] != ORC_FLUID)
+            continue;
+        for (int i = 0; i < Q; ++i) {
+            o->fC[n * Q + i] = eqC[i];
+            o->fR[n * Q + i] = eqR[i];
+        }
+    }
+    totals_mass(o);
+    return o;
+}
+
+void orc_destroy(orc *o)
+{
+    if (!o)
+        return;
+    free(o->vox); free(o->fC); free(o->fR); free(o->pC); free(o->pR); free(o->em); free(o->acc);
+    free(o);
+}
+
+/* ----------------------------------------------------------------- step -- */
+
+/* Steps 1-4: moments, common velocity, equilibria, BGK collision (plus the
+ * forcing term on the carrier), node by node. */
+static void collide(orc *o)
+{
+    const orc_params *P = &o->prm;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < o->nz; ++z) {
+        for (int y = 0; y < o->ny; ++y) {
+            for (int x = 0; x < o->nx; ++x) {
+                long n = node(o, x, y, z);
+                if (o->vox[n] != ORC_FLUID)
+                    continue;
+                const double *fc = o->fC + n * Q, *fr = o->fR + n * Q;
+                double rc, jc[3], rr, jr[3], u[3];
+                moments(fc, &rc, jc);
+                moments(fr, &rr, jr);
+                for (int a = 0; a < 3; ++a) {
+                    if (P->coupling == ORC_BARYCENTRIC)
+                        u[a] = (jc[a] + jr[a] + 0.5 * P->force[a]) / (rc + rr);
+                    else
+                        u[a] = (jc[a] + 0.5 * P->force[a]) / rc;
+                }
+                double eqc[Q], eqr[Q], S[Q];
+                orc_equilibrium(rc, u, eqc);
+                orc_equilibrium(rr, u, eqr);
+                orc_guo_source(P->tau_gas, u, P->force, S);
+                for (int i = 0; i < Q; ++i) {
+                    o->pC[n * Q + i] = fc[i] - (fc[i] - eqc[i]) / P->tau_gas + S[i];
+                    o->pR[n * Q + i] = fr[i] - (fr[i] - eqr[i]) / P->tau_species;
+                }
+            }
+        }
+    }
+}
+
+/* Step 5: the sputtering boundary condition at catalytic nodes.  Returns the
+ * total arrival sum_k In(k) of this step. */
+static double interface(orc *o)
+{
+    const orc_params *P = &o->prm;
+    int xper = P->species_x == ORC_XPERIODIC;
+    ksum total = {0.0, 0.0};
+    for (int z = 0; z < o->nz; ++z)
+        for (int y = 0; y < o->ny; ++y)
+            for (int x = 0; x < o->nx; ++x) {
+                long k = node(o, x, y, z);
+                if (o->vox[k] != ORC_CATALYTIC)
+                    continue;
+                unsigned act;
+                int b = active_links(o, x, y, z, &act);
+                if (b == 0)
+                    continue;
+                /* In(k): every reactant population heading into k along an
+                 * active link, f*_j(k - c_j). */
+                double in = 0.0, wsum = 0.0;
+                for (int j = 1; j < Q; ++j) {
+                    if (!(act & (1u << j)))
+                        continue;
+                    int sx, sy, sz;
+                    source(o, x, y, z, j, xper, &sx, &sy, &sz);
+                    in += o->pR[node(o, sx, sy, sz) * Q + j];
+                    wsum += WT[OPP[j]];
+                }
+                o->acc[k] += in;
+                kadd(&total, in);
+                /* Re-emission (1 - p_S^R) sum_j S_ij f_j^out along i = opp(j). */
+                for (int j = 1; j < Q; ++j) {
+                    if (!(act & (1u << j)))
+                        continue;
+                    int i = OPP[j];
+                    double e;
+                    if (P->sputter == ORC_UNIFORM) {
+                        e = (1.0 - P->p_stick) * in / b;
+                    } else if (P->sputter == ORC_WEIGHTED) {
+                        e = (1.0 - P->p_stick) * in * WT[i] / wsum;
+                    } else {
+                        int sx, sy, sz;
+                        source(o, x, y, z, j, xper, &sx, &sy, &sz);
+                        e = (1.0 - P->p_stick) * o->pR[node(o, sx, sy, sz) * Q + j];
+                    }
+                    o->em[k * Q + i] = e;
+                }
+            }
+    return kval(&total);
+}
+
+/* Step 6: pull streaming of both lattices. */
+static void stream(orc *o)
+{
+    const orc_params *P = &o->prm;
+    int res = P->species_x == ORC_XRESERVOIR;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < o->nz; ++z) {
+        for (int y = 0; y < o->ny; ++y) {
+            for (int x = 0; x < o->nx; ++x) {
+                long n = node(o, x, y, z);
+                if (o->vox[n] != ORC_FLUID)
+                    continue;
+                for (int i = 0; i < Q; ++i) {
+                    int sx, sy, sz;
+                    /* carrier: periodic in x; every solid reflects */
+                    source(o, x, y, z, i, 1, &sx, &sy, &sz);
+                    long s = node(o, sx, sy, sz);
+                    o->fC[n * Q + i] = o->vox[s] == ORC_FLUID ? o->pC[s * Q + i] : o->pC[n * Q + OPP[i]];
+                    /* reactant */
+                    source(o, x, y, z, i, !res, &sx, &sy, &sz);
+                    double v;
+                    if (sx < 0) {
+                        v = WT[i] * P->c_inlet;                          /* inlet ghost */
+                    } else if (sx >= o->nx) {
+                        long m = node(o, o->nx - 1, sy, sz);             /* outlet ghost */
+                        v = o->vox[m] == ORC_FLUID ? o->pR[m * Q + i] : o->pR[n * Q + OPP[i]];
+                    } else {
+                        s = node(o, sx, sy, sz);
+                        if (o->vox[s] == ORC_FLUID)
+                            v = o->pR[s * Q + i];
+                        else if (o->vox[s] == ORC_INERT)
+                            v = o->pR[n * Q + OPP[i]];
+                        else
+                            v = o->em[s * Q + i];
+                    }
+                    o->fR[n * Q + i] = v;
+                }
+            }
+        }
+    }
+}
+
+/* Species crossing the x-boundaries during the streaming just done. */
+static void boundary_flux(orc *o, double *in_flux, double *out_flux)
+{
+    ksum fin = {0.0, 0.0}, fout = {0.0, 0.0};
+    *in_flux = 0.0;
+    *out_flux = 0.0;
+    if (o->prm.species_x != ORC_XRESERVOIR)
+        return;
+    for (int z = 0; z < o->nz; ++z)
+        for (int y = 0; y < o->ny; ++y) {
+            long n0 = node(o, 0, y, z);
+            if (o->vox[n0] == ORC_FLUID)
+                for (int i = 1; i < Q; ++i) {
+                    if (CX[i] == 1)
+                        kadd(&fin, WT[i] * o->prm.c_inlet);        /* pulled from the inlet ghost */
+                    if (CX[i] == -1)
+                        kadd(&fout, o->pR[n0 * Q + i]);           /* left through the inlet */
+                }
+            long n1 = node(o, o->nx - 1, y, z);
+            if (o->vox[n1] == ORC_FLUID)
+                for (int i = 1; i < Q; ++i) {
+                    if (CX[i] == 1)
+                        kadd(&fout, o->pR[n1 * Q + i]);           /* sent to the outlet ghost */
+                    if (CX[i] == -1)
+                        kadd(&fout, -o->fR[n1 * Q + i]);          /* came back from it */
+                }
+        }
+    *in_flux = kval(&fin);
+    *out_flux = kval(&fout);
+}
+
+void orc_step(orc *o, long nsteps)
+{
+    const orc_params *P = &o->prm;
+    for (long t = 0; t < nsteps; ++t) {
+        collide(o);
+        double arrived = interface(o);
+        stream(o);
+        double fin, fout;
+        boundary_flux(o, &fin, &fout);
+        totals_mass(o);
+        o->tot[2] += P->p * P->p_stick * arrived;
+        o->tot[3] += (1.0 - P->p) * P->p_stick * arrived;
+        o->tot[4] += fin;
+        o->tot[5] += fout;
+        o->step += 1;
+    }
+}
+
+/* ------------------------------------------------------------- outputs -- */
+
+/* Moments of the pre-collision populations at the current step; solid 0.
+ * u is component-major (u[a * n + node]). */
+void orc_fields(const orc *o, double *rho, double *u, double *conc)
+{
+    const orc_params *P = &o->prm;
+    for (long n = 0; n < o->n; ++n) {
+        double rc = 0.0, jc[3] = {0, 0, 0}, rr = 0.0, jr[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+        if (o->vox[n] == ORC_FLUID) {
+            moments(o->fC + n * Q, &rc, jc);
+            moments(o->fR + n * Q, &rr, jr);
+            for (int a = 0; a < 3; ++a) {
+                if (P->coupling == ORC_BARYCENTRIC)
+                    v[a] = (jc[a] + jr[a] + 0.5 * P->force[a]) / (rc + rr);
+                else
+                    v[a] = (jc[a] + 0.5 * P->force[a]) / rc;
+            }
+        }
+        if (rho) rho[n] = rc;
+        if (conc) conc[n] = rr;
+        if (u)
+            for (int a = 0; a < 3; ++a)
+                u[a * o->n + n] = v[a];
+    }
+}
+
+/* Converted reactant per voxel: p p_S^R sum_t In(k, t) at catalytic nodes. */
+void orc_conversion_map(const orc *o, double *conv)
+{
+    for (long n = 0; n < o->n; ++n)
+        conv[n] = o->vox[n] == ORC_CATALYTIC ? o->prm.p * o->prm.p_stick * o->acc[n] : 0.0;
+}
+
+void orc_totals(const orc *o, double *t)
+{
+    for (int k = 0; k < 6; ++k)
+        t[k] = o->tot[k];
+}
+
+long orc_step_count(const orc *o)
+{
+    return o->step;
+}
+
+/* Direct access to the pre-collision state, for closed-form tests. */
+void orc_get_state(const orc *o, double *fC, double *fR)
+{
+    if (fC) memcpy(fC, o->fC, sizeof(double) * o->n * Q);
+    if (fR) memcpy(fR, o->fR, sizeof(double) * o->n * Q);
+}
+
+void orc_set_state(orc *o, const double *fC, const double *fR)
+{
+    if (fC) memcpy(o->fC, fC, sizeof(double) * o->n * Q);
+    if (fR) memcpy(o->fR, fR, sizeof(double) * o->n * Q);
+    totals_mass(o);
+}
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
