@@ -1,0 +1,205 @@
+"""Benchmark of the reactive two-lattice LBM hot path on one MI355X.
+
+Workload: 256^3 porous membrane (Gaussian random field, porosity 0.60,
+correlation length 8, seed 1001) with 4-voxel gas buffers in x, periodic y/z;
+D3Q19 carrier (tau 0.8, body force) + D3Q19 reactant (tau 0.7, reservoir
+inlet c = 1), sputtering boundary at every gas-catalyst link (UNIFORM,
+p_S^R = 0.95, Da = 1 with delta = 8), FP32 storage and arithmetic.
+
+One step = one interface gather + boundary-flux tally + fused stream-collide
+sweep of both lattices + FP64 reduction.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--storage f32|f16|bf16|f64]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+STORAGES = {"f32": 0, "f16": 1, "bf16": 2, "f64": 3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(info, s):
+    """Bytes the method must move per step (per launch for each kernel).
+
+    Sweep: every population of both lattices written once (38 s per gas node)
+    and read once (38 s), except the reactant populations heading into
+    catalytic solid, which the interface kernel reads instead (L_K s); plus one
+    4-byte emission read per interface node and the 32-byte chunk record per
+    64 voxels.  Interface: the L_K gathered populations, plus per interface
+    node its voxel index, link mask, scale (4 + 4 + 8), the FP64 accumulator
+    read-modify-write (16) and the emission write (4)."""
+    nf, n, nk, lk = info["n_fluid"], info["n_nodes"], info["n_interface"], info["n_catalytic_links"]
+    sweep = (76 * nf - lk) * s + 4 * nk + n // 2
+    iface = lk * s + nk * (4 + 4 + 8 + 16 + 4)
+    return {"sweep": sweep, "interface": iface, "step": sweep + iface}
+
+
+def cpu_baseline(vox256, w, steps):
+    """Time the FP64 oracle on the 64^3 crop of the same geometry."""
+    import oracle
+
+    crop = __import__("paper_1607_02874_amd.inputs", fromlist=["crop"]).crop(vox256, 64, 64, 64)
+    p, _ = oracle.p_from_da(w.da, w.pore_size)
+    o = oracle.Oracle(crop, tau=w.tau, p=p, p_stick=w.p_stick, c_inlet=w.c_inlet, force=w.force())
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    ref = o.fields() + (o.conversion_map(),)
+    o.close()
+    return crop, ref, {"value": crop.size * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+                       "kind": "oracle",
+                       "sample": f"64^3 crop of the 256^3 sample (outlet planes 60-63 gas), {steps} steps, FP64 C "
+                                 f"oracle, OpenMP over z-planes, {dt:.1f} s"}
+
+
+def crop_errors(crop, ref, w, steps, storage):
+    from paper_1607_02874_amd import lbm
+
+    with lbm.Sim(crop, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                 c_inlet=w.c_inlet, storage=storage) as s:
+        s.step(steps)
+        got = s.fields() + (s.conversion_map(),)
+    gas = crop == 0
+    out = {}
+    for name, a, b in zip(("rho", "u", "conc", "conv"), got, ref):
+        if name == "u":
+            d, r = (a - b)[:, gas], b[:, gas]
+        elif name == "conv":
+            d, r = a - b, b
+        else:
+            d, r = (a - b)[gas], b[gas]
+        out[name] = float(np.linalg.norm(d) / np.linalg.norm(r))
+        out[name + "_maxabs_rel"] = float(np.abs(d).max() / np.abs(r).max())
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
+    ap.add_argument("--da", type=float, default=None)
+    ap.add_argument("--cpu-steps", type=int, default=300, help="oracle steps on the 64^3 crop (0 = skip)")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
+    ap.add_argument("--copy-calib", action="store_true", help="also run a 4 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
+              "multi-GPU sharding is a design in DESIGN.md, not an implementation", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1607_02874_amd import inputs, lbm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = inputs.SINGLE_256
+    if args.da is not None:
+        w.da = args.da
+    storage = STORAGES[args.storage]
+    s_bytes = lbm.STORAGE_BYTES[storage]
+
+    t0 = time.perf_counter()
+    vox = w.voxels()
+    log(f"geometry {w.nx}x{w.ny}x{w.nz} porosity {inputs.porosity(vox):.4f} ({time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    sim = lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                  c_inlet=w.c_inlet, storage=storage)
+    info = sim.info()
+    log(f"create {time.perf_counter() - t0:.1f} s, info {info}")
+
+    sim.step(args.warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        sim.set_timing(True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = sim.kernel_times() if not args.no_timing else None
+    tot = sim.totals()
+    sim.close()
+    log(f"elapsed {elapsed:.3f} s, totals {tot}")
+
+    if args.copy_calib:
+        a = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    n = info["n_nodes"]
+    ms_step = elapsed / args.steps * 1e3
+    mlups = n * args.steps / elapsed / 1e6
+    ab = algorithmic_bytes(info, s_bytes)
+    roofline = None
+    if kt and kt["n_sweep"]:
+        t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
+        achieved = ab["sweep"] / t_sweep / 1e9
+        roofline = {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2)}
+    kernels = None
+    if kt:
+        kernels = {k: round(kt["ms_" + k] / max(kt["n_" + k], 1) * 1e3, 2)
+                   for k in ("sweep", "interface", "xflux", "reduce")}
+
+    cpu, errs = None, None
+    if args.cpu_steps > 0:
+        log(f"oracle {args.cpu_steps} steps on the 64^3 crop")
+        crop, ref, cpu = cpu_baseline(vox, w, args.cpu_steps)
+        errs = crop_errors(crop, ref, w, args.cpu_steps, storage)
+        log(f"cpu baseline {cpu}, errors {errs}")
+
+    line = {
+        "metric": "MLUPS (flow+species) and % of HBM roofline at stated error vs FP64 oracle",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f32", 1: "f16-storage/f32", 2: "bf16-storage/f32", 3: "f64"}[storage],
+        "data": "synthetic (seeded Gaussian-random-field porous geometry)",
+        "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} porous membrane, porosity {w.phi}, "
+                               f"correlation length {w.ell}, seed {w.seed}, tau {w.tau}, Da {w.da}, "
+                               f"p_S {w.p_stick}, UNIFORM sputter, PASSIVE coupling, reservoir x-BC",
+                   "n_nodes": n, "n_fluid": info["n_fluid"], "n_interface": info["n_interface"],
+                   "n_catalytic_links": info["n_catalytic_links"], "mflups": round(mlups * info["n_fluid"] / n, 1),
+                   "step_bytes": ab["step"], "step_GBps": round(ab["step"] / (ms_step * 1e-3) / 1e9, 1),
+                   "kernel_us": kernels},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "error_vs_oracle": None if errs is None else {
+            "crop": "64^3", "steps": args.cpu_steps, "metric": "L2-relative over gas nodes", **errs},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

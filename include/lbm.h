@@ -1,0 +1,252 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) reactive lattice-Boltzmann library.
+ *
+ * The library advances two D3Q19 lattices over a voxelised porous solid: the
+ * carrier gas C and the reactant species R.  One step is the fused pull-
+ * streaming + BGK collision of both lattices (Falcucci et al., "Mapping
+ * Reactive Flow Patterns in Monolithic Nanoporous Catalysts", Appendix
+ * "Numerical Method", Eq. LBE with the second-order equilibrium and the
+ * moment equations), halfway bounce-back at solid links, and the paper's
+ * "sputtering" stick-and-react boundary condition at every gas-catalyst link
+ * (Appendix, eqnarray f_R_in / f_P_in and the text that follows it).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns lbm_status (LBM_OK = 0) except lbm_last_error
+ *     and lbm_destroy; nothing throws across the ABI.
+ *   - On error the context keeps its previous state and lbm_last_error(ctx)
+ *     describes the failure; a failed create sets *out = NULL, leaks nothing
+ *     and leaves its message in lbm_last_error(NULL) (thread-local).
+ *   - Host pointers are caller-owned; the library copies what it keeps
+ *     (voxels, parameter structs) during create.  Device memory is owned by
+ *     the context until lbm_destroy.
+ *   - A context is not thread-safe.  Work is queued on the context's HIP
+ *     stream; calls that return host data synchronise that stream.
+ *   - Arrays over voxels are C order (z, y, x) with x (the flow axis) fastest:
+ *     node = (z * ny + y) * nx + x.  Vector fields are component-major:
+ *     u[a * nnodes + node], a = x, y, z.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,        /* invalid argument (range, NULL, inconsistent) */
+    LBM_ENOMEM = 2,        /* host or device allocation failed */
+    LBM_EDEVICE = 3,       /* HIP runtime error (no device, launch failure) */
+    LBM_ESTATE = 4,        /* call not valid in the context's state */
+    LBM_ENONFINITE = 5,    /* a global total became NaN or Inf (state kept) */
+    LBM_EUNSUPPORTED = 6   /* valid request this build does not provide */
+} lbm_status;
+
+/* Voxel values. */
+enum { LBM_FLUID = 0, LBM_INERT = 1, LBM_CATALYTIC = 2 };
+
+/* Sputtering matrix S_ij (probability that reactant arriving along j
+ * re-enters along i, with sum_i S_ij = 1; Appendix, text after the
+ * sputtering equations).  The paper calls S random; the library evolves its
+ * expectation: UNIFORM gives each active direction of the node 1/b(k),
+ * WEIGHTED gives direction i the share w_i / sum_{active} w, BOUNCEBACK
+ * reverses each arrival (S = reversal). */
+typedef enum { LBM_SPUTTER_UNIFORM = 0, LBM_SPUTTER_WEIGHTED = 1, LBM_SPUTTER_BOUNCEBACK = 2 } lbm_sputter;
+
+/* Velocity in the species equilibrium.  PASSIVE: the carrier velocity
+ * (j_C + F/2) / rho_C (reactant passively transported by the carrier,
+ * "Results & Discussion", initial and inlet conditions).  BARYCENTRIC: the
+ * common velocity (j_C + j_R + F/2) / (rho_C + rho_R) of the moment
+ * equations, used by both lattices. */
+typedef enum { LBM_COUPLE_PASSIVE = 0, LBM_COUPLE_BARYCENTRIC = 1 } lbm_coupling;
+
+/* Species boundary along x.  PERIODIC wraps x like y and z.  RESERVOIR puts
+ * an inlet ghost plane at x = -1 holding the rest equilibrium w_i c_inlet
+ * (the paper injects reactant at x = 0) and an outlet ghost plane at x = nx
+ * that copies plane nx - 1 (zero gradient; where that plane is solid the
+ * ghost reflects like inert solid).  The carrier is always periodic. */
+typedef enum { LBM_XBC_PERIODIC = 0, LBM_XBC_RESERVOIR = 1 } lbm_xbc;
+
+/* Population storage.  All formats store the normalised deviation
+ * h_i = f_i / w_i - rho_ref of each population from the rest equilibrium of
+ * the reference density (rho_ref = rho0 for the carrier, c_ref for the
+ * species).  F32, F16 and BF16 compute in FP32; F64 stores and computes in
+ * FP64 (a reference build).  16-bit formats round to nearest even. */
+typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2, LBM_STORE_F64 = 3 } lbm_storage;
+
+typedef struct {
+    int32_t nx, ny, nz;       /* lattice size, each >= 1; nx <= 4096 */
+    int32_t reserved0;
+    const uint8_t *voxels;    /* host, nx*ny*nz values in {0, 1, 2}; copied */
+    double pore_size;         /* delta of Eq. (knudsen) and Eq. (Da_def), > 0 */
+} lbm_geometry;
+
+typedef struct {
+    int32_t sputter;          /* lbm_sputter */
+    int32_t coupling;         /* lbm_coupling */
+    int32_t species_x;        /* lbm_xbc */
+    int32_t storage;          /* lbm_storage */
+    double p_stick;           /* reactant sticking probability p_S^R in [0, 1]
+                                 (Table 1 uses 0.95) */
+    double c_inlet;           /* reservoir concentration (RESERVOIR only), >= 0 */
+    double rho0;              /* initial carrier density, > 0 */
+    double c0;                /* initial species concentration, >= 0 (the paper
+                                 starts with no reactant) */
+    double c_ref;             /* species storage shift; < 0 selects
+                                 max(c_inlet, c0) / 2 */
+    double force[3];          /* body-force density on the carrier (Guo
+                                 forcing, half-force velocity shift) */
+    uint64_t reserved;        /* must be 0 */
+} lbm_bc;
+
+/* Optional device hooks.  stream: a hipStream_t all work is queued on
+ * (NULL = the null stream).  alloc/free: device allocator used for every
+ * device buffer of the context (NULL = hipMalloc/hipFree), e.g. the PyTorch
+ * caching allocator.  The struct is copied; user is passed back verbatim. */
+typedef struct {
+    void *stream;
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} lbm_device;
+
+typedef struct {
+    int64_t step;             /* steps taken since create */
+    double mass_gas;          /* sum of rho_C over gas nodes at this step */
+    double mass_species;      /* sum of rho_R over gas nodes at this step */
+    double converted;         /* cumulative p p_S^R sum_t sum_k In(k, t) */
+    double lost;              /* cumulative (1 - p) p_S^R sum_t sum_k In(k, t) */
+    double influx;            /* cumulative species pulled from the inlet ghost */
+    double outflux;           /* cumulative species leaving through x = -1 and
+                                 x = nx, net of what the outlet ghost returned */
+    int32_t nonfinite;        /* 1 once any total was NaN or Inf */
+    int32_t reserved;
+} lbm_totals_t;
+
+typedef struct {
+    double tau_gas, tau_species;   /* relaxation times in use */
+    double kn;                     /* Kn = cs (tau_gas - 1/2) / delta */
+    double p;                      /* reaction probability in use */
+    double da;                     /* Damkohler number requested */
+    double pore_size;
+    int32_t p_clamped;             /* 1 when cs / (Da delta) exceeded 1 */
+    int32_t storage;
+    int64_t n_nodes;               /* nx * ny * nz */
+    int64_t n_fluid;               /* gas nodes */
+    int64_t n_interface;           /* catalytic nodes with b(k) >= 1 */
+    int64_t n_catalytic_links;     /* sum_k b(k) */
+    int64_t device_bytes;          /* device memory held by the context */
+} lbm_info;
+
+/* Per-kernel device time accumulated while timing is enabled. */
+typedef struct {
+    double ms_sweep, ms_interface, ms_xflux, ms_reduce;
+    int64_t n_sweep, n_interface, n_xflux, n_reduce;
+} lbm_kernel_times_t;
+
+/*
+ * lbm_create / lbm_create_on - build a simulation context.
+ *
+ * g:    geometry; voxels 0 gas, 1 inert solid, 2 catalytic solid.  Per the
+ *       paper every solid node in contact with gas acts catalytically when
+ *       flagged 2 (Appendix, text after the sputtering equations); a
+ *       catalytic node k receives along its active links j, those whose pull
+ *       source k - c_j is a gas node inside the domain; b(k) counts them.
+ * kn:   Knudsen number, Eq. (knudsen): Kn = cs (tau - 1/2) / delta.  Used to
+ *       derive tau_gas = 1/2 + Kn delta / cs when tau[0] == 0.  kn == 0 means
+ *       "not given"; when both are given they must agree to 1e-9 relative.
+ * da:   Damkohler number, Eq. (Da_def), with tau_ch = 1/p and
+ *       tau_tr = delta / cs ("Results & Discussion"): p = cs / (Da delta),
+ *       clamped to 1 (p_clamped set); da = +inf gives p = 0.  da must be > 0.
+ * tau:  {tau_gas, tau_species}; 0 = derive (tau_gas from kn, tau_species =
+ *       tau_gas: the paper takes tau equal for all species); otherwise > 1/2.
+ * bc:   boundary and storage options, see lbm_bc.
+ * dev:  (lbm_create_on) device hooks, may be NULL.
+ * out:  receives the context.
+ *
+ * Errors: LBM_EINVAL for NULL pointers, sizes < 1, nx > 4096, a voxel > 2,
+ * tau <= 1/2, kn < 0, da <= 0 or NaN, inconsistent kn/tau, p_stick outside
+ * [0, 1], c_inlet/c0 < 0, rho0 <= 0, nonzero reserved fields;
+ * LBM_EUNSUPPORTED for an unknown enum value; LBM_EDEVICE without a usable
+ * gfx950 device; LBM_ENOMEM when a buffer cannot be allocated.
+ */
+lbm_status lbm_create(const lbm_geometry *g, double kn, double da, const double tau[2],
+                      const lbm_bc *bc, lbm_ctx **out);
+lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const double tau[2],
+                         const lbm_bc *bc, const lbm_device *dev, lbm_ctx **out);
+
+/*
+ * lbm_step - advance n >= 0 time steps (Eq. LBE for both lattices plus the
+ * sputtering boundary condition).  Asynchronous on the context stream.
+ * Returns LBM_ENONFINITE if a total of an earlier, completed step was found
+ * non-finite (detection lags by at most one call; lbm_totals reports it
+ * exactly); LBM_EINVAL for n < 0.
+ */
+lbm_status lbm_step(lbm_ctx *c, int64_t n);
+
+/*
+ * lbm_fields - moments of the pre-collision populations at the current step
+ * (moment equations of the Appendix): rho = rho_C, u = the velocity of the
+ * coupling mode (PASSIVE: (j_C + F/2) / rho_C), conc = rho_R.  Host arrays of
+ * n_nodes doubles (u: 3 * n_nodes, component-major); any may be NULL.  Solid
+ * voxels read 0.  Synchronises the stream.
+ */
+lbm_status lbm_fields(lbm_ctx *c, double *rho, double *u, double *conc);
+
+/* Same moments written to device arrays of float (n_nodes, 3 * n_nodes,
+ * n_nodes), queued on the context stream without synchronising. */
+lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc);
+
+/*
+ * lbm_conversion_map - per voxel, the reactant converted at that catalytic
+ * node so far: p p_S^R sum_t In(k, t), where In(k, t) is everything arriving
+ * at k along its active links in step t (second line of the sputtering
+ * equations: the source of product).  0 at gas and inert voxels.  Host array
+ * of n_nodes doubles.  Synchronises the stream.
+ */
+lbm_status lbm_conversion_map(lbm_ctx *c, double *conv);
+
+/* Global totals (FP64, fixed-order deterministic reductions). Synchronises. */
+lbm_status lbm_totals(lbm_ctx *c, lbm_totals_t *t);
+
+/* Parameters in use and sizes. */
+lbm_status lbm_query(const lbm_ctx *c, lbm_info *info);
+
+/* b(k) per voxel (0 for non-catalytic voxels), host array of n_nodes bytes. */
+lbm_status lbm_active_links(const lbm_ctx *c, uint8_t *b);
+
+/* Wait for all work queued by the context. */
+lbm_status lbm_synchronize(lbm_ctx *c);
+
+/* Per-kernel HIP-event timing: enable (1) / disable (0) and read; reading
+ * synchronises the stream.  Reset on enable. */
+lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable);
+lbm_status lbm_kernel_times(lbm_ctx *c, lbm_kernel_times_t *t);
+
+/*
+ * Checkpoint of the full state (populations, emission and accumulator
+ * arrays, totals, step) with a header that records the geometry hash and the
+ * parameters; lbm_load requires a context created with the same geometry and
+ * parameters (LBM_EINVAL otherwise) and makes the next steps bit-identical to
+ * an uninterrupted run.  Synchronise the stream.
+ */
+lbm_status lbm_save(lbm_ctx *c, const char *path);
+lbm_status lbm_load(lbm_ctx *c, const char *path);
+
+/* Message of the last failure on c (c == NULL: the calling thread's last
+ * create failure).  Valid until the next call on the same context/thread. */
+const char *lbm_last_error(const lbm_ctx *c);
+
+/* Release the context and its device memory.  NULL is a no-op. */
+void lbm_destroy(lbm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,772 @@
+// C ABI of the reactive lattice-Boltzmann library (declared in include/lbm.h):
+// argument checking, the create-time preprocessing of the voxel map (chunk
+// records and the compacted interface list), device memory, the step loop
+// and the outputs.  All per-step arithmetic runs in the HIP kernels.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbmk;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr double CS = 0.57735026918962576451;  // lattice sound speed 1/sqrt(3)
+constexpr int TIMING_RING = 512;
+constexpr uint64_t CKPT_MAGIC = 0x3147504b434d424cull;  // "LBMCKPG1"
+
+struct StepEvents {
+    hipEvent_t ev[8];  // start/stop of interface, xflux, sweep, reduce
+    bool pending;
+};
+
+uint64_t fnv1a(const uint8_t *p, size_t n) {
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    // sizes and parameters
+    int nx = 0, ny = 0, nz = 0, W = 0;
+    int64_t n = 0, nfluid = 0, nfp = 0, niface = 0, nlinks = 0;
+    double kn = 0, da = 0, delta = 0, p = 0;
+    int p_clamped = 0;
+    Physics ph{};
+    std::vector<uint8_t> vox;
+    std::vector<uint32_t> iface_vox;  // host copy for the conversion map
+    uint64_t geom_hash = 0;
+    std::string err;
+
+    // device
+    lbm_device dev{};
+    hipStream_t stream = nullptr;
+    int64_t device_bytes = 0;
+    std::vector<void *> allocations;
+    ChunkInfo *d_chunks = nullptr;
+    uint32_t *d_iface_vox = nullptr, *d_iface_mask = nullptr;
+    double *d_iface_scale = nullptr, *d_acc = nullptr;
+    void *d_emit = nullptr;
+    void *d_pop[2] = {nullptr, nullptr};
+    double *d_part = nullptr;
+    DevTotals *d_tot = nullptr;
+    int cur = 0;          // d_pop[cur] holds the post-collision state of the current step
+    int64_t step = 0;
+    int64_t blocks_sweep = 0, blocks_iface = 0, blocks_flux = 0;
+
+    // watchdog
+    int32_t *h_flag = nullptr;
+    hipEvent_t flag_event = nullptr;
+    bool flag_pending = false;
+
+    // timing
+    bool timing = false;
+    std::vector<StepEvents> ring;
+    int ring_next = 0;
+    lbm_kernel_times_t times{};
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx *c, lbm_status s, const std::string &msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_create_error = msg;
+    return s;
+}
+
+lbm_status hip_fail(lbm_ctx *c, hipError_t e, const char *what) {
+    return fail(c, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *dev_alloc(lbm_ctx *c, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (c->dev.alloc) {
+        p = c->dev.alloc(bytes, c->dev.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) {
+        c->allocations.push_back(p);
+        c->device_bytes += int64_t(bytes);
+    }
+    return p;
+}
+
+void release(lbm_ctx *c) {
+    for (void *p : c->allocations) {
+        if (c->dev.free)
+            c->dev.free(p, c->dev.user);
+        else
+            (void)hipFree(p);
+    }
+    c->allocations.clear();
+    for (auto &r : c->ring)
+        for (auto &e : r.ev) (void)hipEventDestroy(e);
+    c->ring.clear();
+    if (c->flag_event) (void)hipEventDestroy(c->flag_event);
+    if (c->h_flag) (void)hipHostFree(c->h_flag);
+}
+
+Geometry geometry(const lbm_ctx *c) {
+    Geometry g;
+    g.chunks = c->d_chunks;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    g.W = c->W;
+    g.nfp = c->nfp;
+    g.nfluid = c->nfluid;
+    return g;
+}
+
+Interface interface_list(const lbm_ctx *c) {
+    Interface it;
+    it.vox = c->d_iface_vox;
+    it.mask = c->d_iface_mask;
+    it.scale = c->d_iface_scale;
+    it.acc = c->d_acc;
+    it.n = c->niface;
+    return it;
+}
+
+// Chunk records of every x-row: gas/catalytic bits, storage base, and the
+// periodic left/right neighbours of the chunk.
+void build_chunks(const lbm_ctx *c, std::vector<ChunkInfo> &ch) {
+    const int64_t rows = int64_t(c->ny) * c->nz;
+    ch.assign(size_t(rows * c->W), ChunkInfo{});
+    uint64_t running = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        const uint8_t *v = c->vox.data() + r * c->nx;
+        for (int k = 0; k < c->W; ++k) {
+            ChunkInfo &I = ch[size_t(r * c->W + k)];
+            for (int b = 0; b < 64; ++b) {
+                const int x = 64 * k + b;
+                if (x >= c->nx) break;
+                if (v[x] == LBM_FLUID) I.fluid |= 1ull << b;
+                if (v[x] == LBM_CATALYTIC) I.cat |= 1ull << b;
+            }
+            I.base = uint32_t(running);
+            running += uint64_t(__builtin_popcountll(I.fluid));
+        }
+    }
+    auto rank = [&](int64_t r, int x) -> uint32_t {
+        const ChunkInfo &I = ch[size_t(r * c->W + (x >> 6))];
+        const int b = x & 63;
+        const uint64_t below = b ? (I.fluid & (~0ull >> (64 - b))) : 0ull;
+        return I.base + uint32_t(__builtin_popcountll(below));
+    };
+    for (int64_t r = 0; r < rows; ++r) {
+        const uint8_t *v = c->vox.data() + r * c->nx;
+        for (int k = 0; k < c->W; ++k) {
+            ChunkInfo &I = ch[size_t(r * c->W + k)];
+            const int xp = k > 0 ? 64 * k - 1 : c->nx - 1;
+            const int xn = 64 * k + 64 < c->nx ? 64 * k + 64 : 0;
+            I.edge = (v[xp] == LBM_FLUID ? 1u : 0u) | (v[xp] == LBM_CATALYTIC ? 2u : 0u) |
+                     (v[xn] == LBM_FLUID ? 4u : 0u) | (v[xn] == LBM_CATALYTIC ? 8u : 0u);
+            I.prev_rank = rank(r, xp);
+            I.next_rank = rank(r, xn);
+        }
+    }
+}
+
+// Interface list: catalytic nodes with at least one active link (a link j
+// whose pull source k - c_j is a gas node inside the domain).
+void build_interface(lbm_ctx *c, std::vector<uint32_t> &vox, std::vector<uint32_t> &mask,
+                     std::vector<double> &scale) {
+    const bool xper = c->ph.species_x == XB_PERIODIC;
+    c->nlinks = 0;
+    for (int z = 0; z < c->nz; ++z)
+        for (int y = 0; y < c->ny; ++y)
+            for (int x = 0; x < c->nx; ++x) {
+                const int64_t k = (int64_t(z) * c->ny + y) * c->nx + x;
+                if (c->vox[size_t(k)] != LBM_CATALYTIC) continue;
+                uint32_t m = 0;
+                int b = 0;
+                double wsum = 0.0;
+                for (int j = 1; j < 19; ++j) {
+                    int xs = x - CX[j];
+                    const int ys = (y - CY[j] + c->ny) % c->ny, zs = (z - CZ[j] + c->nz) % c->nz;
+                    if (xs < 0 || xs >= c->nx) {
+                        if (!xper) continue;
+                        xs = (xs + c->nx) % c->nx;
+                    }
+                    if (c->vox[size_t((int64_t(zs) * c->ny + ys) * c->nx + xs)] == LBM_FLUID) {
+                        m |= 1u << j;
+                        ++b;
+                        wsum += wgt<double>(opp(j));
+                    }
+                }
+                if (b == 0) continue;
+                vox.push_back(uint32_t(k));
+                mask.push_back(m);
+                scale.push_back(c->ph.sputter == SP_WEIGHTED ? 1.0 / wsum : 1.0 / b);
+                c->nlinks += b;
+            }
+}
+
+lbm_status check_pending_flag(lbm_ctx *c) {
+    if (c->flag_pending && hipEventQuery(c->flag_event) == hipSuccess) {
+        c->flag_pending = false;
+        if (*c->h_flag) return fail(c, LBM_ENONFINITE, "a global total became non-finite");
+    }
+    return LBM_OK;
+}
+
+void drain_slot(lbm_ctx *c, StepEvents &r) {
+    if (!r.pending) return;
+    (void)hipEventSynchronize(r.ev[7]);
+    float ms[4];
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = 0.0f;
+        if (hipEventElapsedTime(&ms[k], r.ev[2 * k], r.ev[2 * k + 1]) != hipSuccess) ms[k] = 0.0f;
+    }
+    const bool has_iface = c->blocks_iface > 0, has_flux = c->blocks_flux > 0;
+    if (has_iface) {
+        c->times.ms_interface += ms[0];
+        c->times.n_interface += 1;
+    }
+    if (has_flux) {
+        c->times.ms_xflux += ms[1];
+        c->times.n_xflux += 1;
+    }
+    c->times.ms_sweep += ms[2];
+    c->times.n_sweep += 1;
+    c->times.ms_reduce += ms[3];
+    c->times.n_reduce += 1;
+    r.pending = false;
+}
+
+lbm_status one_step(lbm_ctx *c) {
+    const Geometry g = geometry(c);
+    const void *fin = c->d_pop[c->cur];
+    void *fout = c->d_pop[1 - c->cur];
+    double *ps = c->d_part;
+    double *pi = ps + 2 * c->blocks_sweep;
+    double *pf = pi + c->blocks_iface;
+    StepEvents *r = nullptr;
+    if (c->timing) {
+        r = &c->ring[size_t(c->ring_next)];
+        c->ring_next = (c->ring_next + 1) % TIMING_RING;
+        drain_slot(c, *r);
+    }
+    hipError_t e;
+    if (r) (void)hipEventRecord(r->ev[0], c->stream);
+    e = launch_interface(g, c->ph, interface_list(c), fin, c->d_emit, pi, c->blocks_iface, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "interface kernel launch");
+    if (r) (void)hipEventRecord(r->ev[1], c->stream);
+    if (r) (void)hipEventRecord(r->ev[2], c->stream);
+    e = launch_xflux(g, c->ph, fin, pf, c->blocks_flux, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "boundary-flux kernel launch");
+    if (r) (void)hipEventRecord(r->ev[3], c->stream);
+    if (r) (void)hipEventRecord(r->ev[4], c->stream);
+    e = launch_sweep(g, c->ph, fin, fout, c->d_emit, ps, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "sweep kernel launch");
+    if (r) (void)hipEventRecord(r->ev[5], c->stream);
+    if (r) (void)hipEventRecord(r->ev[6], c->stream);
+    e = launch_reduce(ps, c->blocks_sweep, pi, c->blocks_iface, pf, c->blocks_flux, c->ph.p, c->ph.p_stick, c->d_tot,
+                      c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+    if (r) {
+        (void)hipEventRecord(r->ev[7], c->stream);
+        r->pending = true;
+    }
+    c->cur = 1 - c->cur;
+    c->step += 1;
+    return LBM_OK;
+}
+
+lbm_status validate(const lbm_geometry *g, double kn, double da, const double tau[2], const lbm_bc *bc,
+                    lbm_ctx **out) {
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g || !bc || !tau) return fail(nullptr, LBM_EINVAL, "geometry, tau and bc must not be NULL");
+    if (!g->voxels) return fail(nullptr, LBM_EINVAL, "geometry voxels is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(nullptr, LBM_EINVAL, "lattice sizes must be >= 1");
+    if (g->nx > 4096) return fail(nullptr, LBM_EINVAL, "nx must be <= 4096");
+    if (int64_t(g->nx) * g->ny * g->nz >= (int64_t(1) << 32))
+        return fail(nullptr, LBM_EINVAL, "lattice has 2^32 nodes or more");
+    if (g->reserved0 != 0 || bc->reserved != 0) return fail(nullptr, LBM_EINVAL, "reserved fields must be 0");
+    if (!(g->pore_size > 0) || !std::isfinite(g->pore_size))
+        return fail(nullptr, LBM_EINVAL, "pore_size must be finite and > 0");
+    if (bc->sputter < 0 || bc->sputter > 2) return fail(nullptr, LBM_EUNSUPPORTED, "unknown sputter mode");
+    if (bc->coupling < 0 || bc->coupling > 1) return fail(nullptr, LBM_EUNSUPPORTED, "unknown coupling mode");
+    if (bc->species_x < 0 || bc->species_x > 1) return fail(nullptr, LBM_EUNSUPPORTED, "unknown species x-boundary");
+    if (bc->storage < 0 || bc->storage > 3) return fail(nullptr, LBM_EUNSUPPORTED, "unknown storage format");
+    if (!(bc->p_stick >= 0.0 && bc->p_stick <= 1.0)) return fail(nullptr, LBM_EINVAL, "p_stick must be in [0, 1]");
+    if (!(bc->c_inlet >= 0.0) || !std::isfinite(bc->c_inlet)) return fail(nullptr, LBM_EINVAL, "c_inlet must be >= 0");
+    if (!(bc->c0 >= 0.0) || !std::isfinite(bc->c0)) return fail(nullptr, LBM_EINVAL, "c0 must be >= 0");
+    if (!(bc->rho0 > 0.0) || !std::isfinite(bc->rho0)) return fail(nullptr, LBM_EINVAL, "rho0 must be > 0");
+    if (!std::isfinite(bc->c_ref)) return fail(nullptr, LBM_EINVAL, "c_ref must be finite");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(bc->force[a])) return fail(nullptr, LBM_EINVAL, "force must be finite");
+    if (!(kn >= 0.0) || !std::isfinite(kn)) return fail(nullptr, LBM_EINVAL, "kn must be finite and >= 0");
+    if (!(da > 0.0)) return fail(nullptr, LBM_EINVAL, "da must be > 0 (+inf allowed)");
+    for (int k = 0; k < 2; ++k)
+        if (!(tau[k] == 0.0 || tau[k] > 0.5) || !std::isfinite(tau[k]))
+            return fail(nullptr, LBM_EINVAL, "tau must be 0 (derive) or > 1/2");
+    if (tau[0] == 0.0 && kn == 0.0) return fail(nullptr, LBM_EINVAL, "give tau[0] or kn");
+    const size_t n = size_t(g->nx) * g->ny * g->nz;
+    for (size_t i = 0; i < n; ++i)
+        if (g->voxels[i] > 2) return fail(nullptr, LBM_EINVAL, "voxel value > 2 at index " + std::to_string(i));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_create(const lbm_geometry *g, double kn, double da, const double tau[2], const lbm_bc *bc,
+                      lbm_ctx **out) {
+    return lbm_create_on(g, kn, da, tau, bc, nullptr, out);
+}
+
+lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const double tau[2], const lbm_bc *bc,
+                         const lbm_device *dev, lbm_ctx **out) {
+    lbm_status st = validate(g, kn, da, tau, bc, out);
+    if (st != LBM_OK) return st;
+
+    // Parameter maps: Eq. (knudsen) and Eq. (Da_def) with tau_ch = 1/p,
+    // tau_tr = delta / cs.
+    const double delta = g->pore_size;
+    double tau_gas = tau[0];
+    if (tau_gas == 0.0) tau_gas = 0.5 + kn * delta / CS;
+    const double kn_of_tau = CS * (tau_gas - 0.5) / delta;
+    if (tau[0] != 0.0 && kn != 0.0 && std::fabs(kn - kn_of_tau) > 1e-9 * std::max(1.0, kn))
+        return fail(nullptr, LBM_EINVAL, "kn and tau[0] disagree");
+    if (!(tau_gas > 0.5)) return fail(nullptr, LBM_EINVAL, "derived tau_gas must be > 1/2");
+    const double tau_species = tau[1] != 0.0 ? tau[1] : tau_gas;
+    double p = std::isinf(da) ? 0.0 : CS / (da * delta);
+    const int clamped = p > 1.0;
+    if (clamped) p = 1.0;
+
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "no HIP device");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, LBM_EDEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+    if (dev) c->dev = *dev;
+    c->stream = static_cast<hipStream_t>(c->dev.stream);
+    c->nx = g->nx;
+    c->ny = g->ny;
+    c->nz = g->nz;
+    c->W = (g->nx + 63) / 64;
+    c->n = int64_t(g->nx) * g->ny * g->nz;
+    c->kn = kn_of_tau;
+    c->da = da;
+    c->delta = delta;
+    c->p = p;
+    c->p_clamped = clamped;
+    c->ph.tau_gas = tau_gas;
+    c->ph.tau_species = tau_species;
+    for (int a = 0; a < 3; ++a) c->ph.force[a] = bc->force[a];
+    c->ph.rho0 = bc->rho0;
+    c->ph.c0 = bc->c0;
+    c->ph.c_inlet = bc->species_x == LBM_XBC_RESERVOIR ? bc->c_inlet : 0.0;
+    c->ph.rho_ref = bc->rho0;
+    c->ph.c_ref = bc->c_ref >= 0.0 ? bc->c_ref : 0.5 * std::max(bc->c_inlet, bc->c0);
+    c->ph.p_stick = bc->p_stick;
+    c->ph.p = p;
+    c->ph.sputter = bc->sputter;
+    c->ph.coupling = bc->coupling;
+    c->ph.species_x = bc->species_x;
+    c->ph.storage = bc->storage;
+
+    try {
+        c->vox.assign(g->voxels, g->voxels + c->n);
+        c->geom_hash = fnv1a(c->vox.data(), c->vox.size());
+        std::vector<ChunkInfo> chunks;
+        build_chunks(c, chunks);
+        c->nfluid = 0;
+        for (uint8_t v : c->vox) c->nfluid += v == LBM_FLUID;
+        c->nfp = std::max<int64_t>(128, (c->nfluid + 127) / 128 * 128);
+        std::vector<uint32_t> ivox, imask;
+        std::vector<double> iscale;
+        build_interface(c, ivox, imask, iscale);
+        c->niface = int64_t(ivox.size());
+        c->iface_vox = ivox;
+
+        const Geometry gtmp = geometry(c);
+        c->blocks_sweep = sweep_blocks(gtmp);
+        c->blocks_iface = interface_blocks(c->niface);
+        c->blocks_flux = c->ph.species_x == XB_RESERVOIR ? xflux_blocks(gtmp) : 0;
+
+        const int sb = storage_bytes(c->ph.storage);
+        const int tb = c->ph.storage == ST_F64 ? 8 : 4;
+        c->d_chunks = static_cast<ChunkInfo *>(dev_alloc(c, chunks.size() * sizeof(ChunkInfo)));
+        c->d_iface_vox = static_cast<uint32_t *>(dev_alloc(c, ivox.size() * 4));
+        c->d_iface_mask = static_cast<uint32_t *>(dev_alloc(c, imask.size() * 4));
+        c->d_iface_scale = static_cast<double *>(dev_alloc(c, iscale.size() * 8));
+        c->d_acc = static_cast<double *>(dev_alloc(c, size_t(c->niface) * 8));
+        c->d_emit = dev_alloc(c, size_t(c->n) * tb);
+        c->d_pop[0] = dev_alloc(c, size_t(38) * c->nfp * sb);
+        c->d_pop[1] = dev_alloc(c, size_t(38) * c->nfp * sb);
+        const int64_t nparts = 2 * c->blocks_sweep + c->blocks_iface + 2 * c->blocks_flux;
+        c->d_part = static_cast<double *>(dev_alloc(c, size_t(nparts) * 8));
+        c->d_tot = static_cast<DevTotals *>(dev_alloc(c, sizeof(DevTotals)));
+        if (!c->d_chunks || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
+            !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot) {
+            release(c);
+            delete c;
+            return fail(nullptr, LBM_ENOMEM, "device allocation failed");
+        }
+        auto up = [&](void *d, const void *h, size_t bytes) {
+            if (bytes && e == hipSuccess) e = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream);
+        };
+        e = hipSuccess;
+        up(c->d_chunks, chunks.data(), chunks.size() * sizeof(ChunkInfo));
+        up(c->d_iface_vox, ivox.data(), ivox.size() * 4);
+        up(c->d_iface_mask, imask.data(), imask.size() * 4);
+        up(c->d_iface_scale, iscale.data(), iscale.size() * 8);
+        if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, size_t(c->n) * tb, c->stream);
+        DevTotals t0{};
+        t0.mass_gas = double(c->nfluid) * bc->rho0;
+        t0.mass_species = double(c->nfluid) * bc->c0;
+        up(c->d_tot, &t0, sizeof(t0));
+        if (e == hipSuccess) e = launch_init(geometry(c), c->ph, c->d_pop[1], c->d_pop[0], c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host vectors go out of scope
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->h_flag), sizeof(int32_t));
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->flag_event, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            lbm_status s = hip_fail(nullptr, e, "create");
+            release(c);
+            delete c;
+            return s;
+        }
+        *c->h_flag = 0;
+        c->cur = 0;
+    } catch (const std::bad_alloc &) {
+        release(c);
+        delete c;
+        return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t n) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+    lbm_status st = check_pending_flag(c);
+    if (st != LBM_OK) return st;
+    for (int64_t s = 0; s < n; ++s) {
+        st = one_step(c);
+        if (st != LBM_OK) return st;
+    }
+    if (n > 0) {
+        hipError_t e = hipMemcpyAsync(c->h_flag, &c->d_tot->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      c->stream);
+        if (e == hipSuccess) e = hipEventRecord(c->flag_event, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "watchdog copy");
+        c->flag_pending = true;
+    }
+    return LBM_OK;
+}
+
+static lbm_status fields_impl(lbm_ctx *c, void *rho, void *u, void *conc, bool f64) {
+    const int mode = c->step == 0 ? 2 : 1;
+    const void *fin = c->d_pop[1 - c->cur];
+    hipError_t e = launch_fields(geometry(c), c->ph, fin, c->d_emit, mode, rho, u, conc, f64, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "fields kernel launch");
+    return LBM_OK;
+}
+
+lbm_status lbm_fields(lbm_ctx *c, double *rho, double *u, double *conc) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    const size_t n = size_t(c->n);
+    double *d[3] = {nullptr, nullptr, nullptr};
+    double *h[3] = {rho, u, conc};
+    const size_t len[3] = {n, 3 * n, n};
+    for (int k = 0; k < 3; ++k) {
+        if (!h[k]) continue;
+        void *p = nullptr;
+        if (c->dev.alloc)
+            p = c->dev.alloc(len[k] * 8, c->dev.user);
+        else if (hipMalloc(&p, len[k] * 8) != hipSuccess)
+            p = nullptr;
+        if (!p) {
+            for (int j = 0; j < k; ++j)
+                if (d[j]) (c->dev.free ? c->dev.free(d[j], c->dev.user) : (void)hipFree(d[j]));
+            return fail(c, LBM_ENOMEM, "fields scratch allocation failed");
+        }
+        d[k] = static_cast<double *>(p);
+    }
+    lbm_status st = fields_impl(c, d[0], d[1], d[2], true);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && st == LBM_OK; ++k)
+        if (h[k] && e == hipSuccess) e = hipMemcpyAsync(h[k], d[k], len[k] * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 3; ++k)
+        if (d[k]) (c->dev.free ? c->dev.free(d[k], c->dev.user) : (void)hipFree(d[k]));
+    if (st != LBM_OK) return st;
+    if (e != hipSuccess) return hip_fail(c, e, "fields copy");
+    return LBM_OK;
+}
+
+lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    return fields_impl(c, rho, u, conc, false);
+}
+
+lbm_status lbm_conversion_map(lbm_ctx *c, double *conv) {
+    if (!c || !conv) return fail(c, LBM_EINVAL, "NULL argument");
+    std::vector<double> acc(size_t(c->niface));
+    hipError_t e = hipSuccess;
+    if (c->niface) e = hipMemcpyAsync(acc.data(), c->d_acc, acc.size() * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "conversion map copy");
+    std::memset(conv, 0, size_t(c->n) * sizeof(double));
+    const double f = c->ph.p * c->ph.p_stick;
+    for (size_t k = 0; k < acc.size(); ++k) conv[c->iface_vox[k]] = f * acc[k];
+    return LBM_OK;
+}
+
+lbm_status lbm_totals(lbm_ctx *c, lbm_totals_t *t) {
+    if (!c || !t) return fail(c, LBM_EINVAL, "NULL argument");
+    DevTotals d;
+    hipError_t e = hipMemcpyAsync(&d, c->d_tot, sizeof(d), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "totals copy");
+    t->step = c->step;
+    t->mass_gas = d.mass_gas;
+    t->mass_species = d.mass_species;
+    t->converted = d.converted;
+    t->lost = d.lost;
+    t->influx = d.influx;
+    t->outflux = d.outflux;
+    t->nonfinite = d.nonfinite;
+    t->reserved = 0;
+    if (d.nonfinite) return fail(c, LBM_ENONFINITE, "a global total became non-finite");
+    return LBM_OK;
+}
+
+lbm_status lbm_query(const lbm_ctx *c, lbm_info *info) {
+    if (!c || !info) return LBM_EINVAL;
+    info->tau_gas = c->ph.tau_gas;
+    info->tau_species = c->ph.tau_species;
+    info->kn = c->kn;
+    info->p = c->p;
+    info->da = c->da;
+    info->pore_size = c->delta;
+    info->p_clamped = c->p_clamped;
+    info->storage = c->ph.storage;
+    info->n_nodes = c->n;
+    info->n_fluid = c->nfluid;
+    info->n_interface = c->niface;
+    info->n_catalytic_links = c->nlinks;
+    info->device_bytes = c->device_bytes;
+    return LBM_OK;
+}
+
+lbm_status lbm_active_links(const lbm_ctx *c, uint8_t *b) {
+    if (!c || !b) return LBM_EINVAL;
+    std::memset(b, 0, size_t(c->n));
+    const bool xper = c->ph.species_x == XB_PERIODIC;
+    // recount from the voxel map, the same rule the interface list uses
+    for (int z = 0; z < c->nz; ++z)
+        for (int y = 0; y < c->ny; ++y)
+            for (int x = 0; x < c->nx; ++x) {
+                const int64_t k = (int64_t(z) * c->ny + y) * c->nx + x;
+                if (c->vox[size_t(k)] != LBM_CATALYTIC) continue;
+                int cnt = 0;
+                for (int j = 1; j < 19; ++j) {
+                    int xs = x - CX[j];
+                    const int ys = (y - CY[j] + c->ny) % c->ny, zs = (z - CZ[j] + c->nz) % c->nz;
+                    if (xs < 0 || xs >= c->nx) {
+                        if (!xper) continue;
+                        xs = (xs + c->nx) % c->nx;
+                    }
+                    cnt += c->vox[size_t((int64_t(zs) * c->ny + ys) * c->nx + xs)] == LBM_FLUID;
+                }
+                b[k] = uint8_t(cnt);
+            }
+    return LBM_OK;
+}
+
+lbm_status lbm_synchronize(lbm_ctx *c) {
+    if (!c) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronize");
+    return check_pending_flag(c);
+}
+
+lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable) {
+    if (!c) return LBM_EINVAL;
+    if (enable && c->ring.empty()) {
+        c->ring.resize(TIMING_RING);
+        for (auto &r : c->ring) {
+            r.pending = false;
+            for (auto &ev : r.ev) {
+                hipError_t e = hipEventCreate(&ev);
+                if (e != hipSuccess) return hip_fail(c, e, "event create");
+            }
+        }
+    }
+    if (enable) {
+        for (auto &r : c->ring) r.pending = false;
+        c->times = lbm_kernel_times_t{};
+    }
+    c->timing = enable != 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_kernel_times(lbm_ctx *c, lbm_kernel_times_t *t) {
+    if (!c || !t) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronize");
+    for (auto &r : c->ring) drain_slot(c, r);
+    *t = c->times;
+    return LBM_OK;
+}
+
+namespace {
+struct CkptHeader {
+    uint64_t magic;
+    int64_t nx, ny, nz, storage, step, nfluid, niface, nfp, cur;
+    uint64_t geom_hash;
+    double params[16];
+    DevTotals tot;
+};
+
+void pack_params(const lbm_ctx *c, double *p) {
+    std::memset(p, 0, 16 * sizeof(double));
+    p[0] = c->ph.tau_gas;
+    p[1] = c->ph.tau_species;
+    p[2] = c->ph.force[0];
+    p[3] = c->ph.force[1];
+    p[4] = c->ph.force[2];
+    p[5] = c->ph.rho_ref;
+    p[6] = c->ph.c_ref;
+    p[7] = c->ph.rho0;
+    p[8] = c->ph.c0;
+    p[9] = c->ph.c_inlet;
+    p[10] = c->ph.p_stick;
+    p[11] = c->ph.p;
+    p[12] = c->ph.sputter;
+    p[13] = c->ph.coupling;
+    p[14] = c->ph.species_x;
+}
+}  // namespace
+
+lbm_status lbm_save(lbm_ctx *c, const char *path) {
+    if (!c || !path) return fail(c, LBM_EINVAL, "NULL argument");
+    CkptHeader h{};
+    h.magic = CKPT_MAGIC;
+    h.nx = c->nx;
+    h.ny = c->ny;
+    h.nz = c->nz;
+    h.storage = c->ph.storage;
+    h.step = c->step;
+    h.nfluid = c->nfluid;
+    h.niface = c->niface;
+    h.nfp = c->nfp;
+    h.cur = c->cur;
+    h.geom_hash = c->geom_hash;
+    pack_params(c, h.params);
+    hipError_t e = hipMemcpyAsync(&h.tot, c->d_tot, sizeof(DevTotals), hipMemcpyDeviceToHost, c->stream);
+    const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
+    const size_t emit = size_t(c->n) * (c->ph.storage == ST_F64 ? 8 : 4);
+    std::vector<char> buf;
+    try {
+        buf.resize(2 * pop + emit + size_t(c->niface) * 8);
+    } catch (const std::bad_alloc &) {
+        return fail(c, LBM_ENOMEM, "checkpoint buffer");
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(buf.data(), c->d_pop[0], pop, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(buf.data() + pop, c->d_pop[1], pop, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(buf.data() + 2 * pop, c->d_emit, emit, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && c->niface)
+        e = hipMemcpyAsync(buf.data() + 2 * pop + emit, c->d_acc, size_t(c->niface) * 8, hipMemcpyDeviceToHost,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(c, LBM_EINVAL, std::string("cannot open ") + path);
+    const bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+    if (std::fclose(f) != 0 || !ok) return fail(c, LBM_EINVAL, std::string("write failed: ") + path);
+    return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx *c, const char *path) {
+    if (!c || !path) return fail(c, LBM_EINVAL, "NULL argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(c, LBM_EINVAL, std::string("cannot open ") + path);
+    CkptHeader h{};
+    if (std::fread(&h, sizeof(h), 1, f) != 1 || h.magic != CKPT_MAGIC) {
+        std::fclose(f);
+        return fail(c, LBM_EINVAL, "not a checkpoint of this library");
+    }
+    double params[16];
+    pack_params(c, params);
+    if (h.nx != c->nx || h.ny != c->ny || h.nz != c->nz || h.storage != c->ph.storage || h.nfluid != c->nfluid ||
+        h.niface != c->niface || h.nfp != c->nfp || h.geom_hash != c->geom_hash ||
+        std::memcmp(params, h.params, sizeof(params)) != 0) {
+        std::fclose(f);
+        return fail(c, LBM_EINVAL, "checkpoint does not match this context's geometry or parameters");
+    }
+    const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
+    const size_t emit = size_t(c->n) * (c->ph.storage == ST_F64 ? 8 : 4);
+    std::vector<char> buf;
+    try {
+        buf.resize(2 * pop + emit + size_t(c->niface) * 8);
+    } catch (const std::bad_alloc &) {
+        std::fclose(f);
+        return fail(c, LBM_ENOMEM, "checkpoint buffer");
+    }
+    const bool ok = std::fread(buf.data(), 1, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return fail(c, LBM_EINVAL, "truncated checkpoint");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_pop[0], buf.data(), pop, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_pop[1], buf.data() + pop, pop, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_emit, buf.data() + 2 * pop, emit, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->niface)
+        e = hipMemcpyAsync(c->d_acc, buf.data() + 2 * pop + emit, size_t(c->niface) * 8, hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_tot, &h.tot, sizeof(DevTotals), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "checkpoint upload");
+    c->step = h.step;
+    c->cur = int(h.cur);
+    c->flag_pending = false;
+    *c->h_flag = h.tot.nonfinite;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+}
+
+}  // extern "C"

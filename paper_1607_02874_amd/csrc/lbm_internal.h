@@ -1,0 +1,108 @@
+// Internal interface between the C-ABI host code (lbm_api.cpp) and the HIP
+// kernels (lbm_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbmk {
+
+// D3Q19 velocities in the library's numbering: 0 rest; 1..9 one of each
+// velocity pair; 10..18 their negatives, so opp(i) = i + 9 (i <= 9) or i - 9.
+// Weights: 1/3 (rest), 1/18 (axis), 1/36 (face diagonal).
+constexpr int CX[19] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+constexpr int CY[19] = {0, 0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+constexpr int CZ[19] = {0, 0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i <= 9 ? i + 9 : i - 9); }
+
+template <typename T>
+__host__ __device__ constexpr T wgt(int i) {
+    return i == 0 ? T(1) / T(3) : ((CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]) == 1 ? T(1) / T(18) : T(1) / T(36));
+}
+
+template <typename T>
+__host__ __device__ constexpr T inv_wgt(int i) {
+    return i == 0 ? T(3) : ((CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i]) == 1 ? T(18) : T(36));
+}
+
+// One 64-voxel segment of an x-row.  The populations of gas nodes are stored
+// compactly (gas nodes only, in (z, y, x) order), so a gas node's storage
+// index is base + (number of gas bits below it in this chunk).
+struct ChunkInfo {
+    uint64_t fluid;      // bit b: voxel x = 64 c + b (< nx) is gas
+    uint64_t cat;        // bit b: voxel is catalytic solid
+    uint32_t base;       // storage index of the first gas voxel of the chunk
+    uint32_t edge;       // 1: left neighbour gas, 2: left catalytic, 4: right gas, 8: right catalytic
+    uint32_t prev_rank;  // storage index of the periodic left neighbour x = 64 c - 1 (if gas)
+    uint32_t next_rank;  // storage index of the periodic right neighbour (if gas)
+};
+static_assert(sizeof(ChunkInfo) == 32, "ChunkInfo must stay 32 bytes (one scalar load)");
+
+enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_F64 = 3 };
+enum { SP_UNIFORM = 0, SP_WEIGHTED = 1, SP_BOUNCEBACK = 2 };
+enum { CP_PASSIVE = 0, CP_BARYCENTRIC = 1 };
+enum { XB_PERIODIC = 0, XB_RESERVOIR = 1 };
+
+// Slots of the per-step partial sums (FP64) written by the kernels.
+enum { PART_MASS_C = 0, PART_MASS_R = 1, PART_IN = 2, PART_INFLUX = 3, PART_OUTFLUX = 4, NPART = 5 };
+
+// Device totals: step-cumulative FP64 values and the non-finite flag.
+struct DevTotals {
+    double mass_gas, mass_species, converted, lost, influx, outflux;
+    int64_t step;
+    int32_t nonfinite;
+    int32_t pad;
+};
+
+struct Geometry {
+    const ChunkInfo *chunks;  // rows * W records, row = z * ny + y
+    int32_t nx, ny, nz, W;    // W = ceil(nx / 64)
+    int64_t nfp;              // elements per direction in a population buffer
+    int64_t nfluid;
+};
+
+// Physical parameters in FP64; kernels convert to their compute type.
+struct Physics {
+    double tau_gas, tau_species;
+    double force[3];
+    double rho_ref, c_ref;       // storage shifts of the two lattices
+    double rho0, c0, c_inlet;
+    double p_stick, p;
+    int32_t sputter, coupling, species_x, storage;
+};
+
+// Interface list (catalytic nodes with b(k) >= 1), sorted by voxel index.
+struct Interface {
+    const uint32_t *vox;    // linear voxel index of node k
+    const uint32_t *mask;   // bit j (kernel direction numbering): j is an active link
+    const double *scale;    // 1/b(k) (UNIFORM) or 1/sum_{active} w_opp(j) (WEIGHTED)
+    double *acc;            // sum_t In(k, t)
+    int64_t n;
+};
+
+int storage_bytes(int storage);
+
+// All launchers queue on `stream` and return the launch status.
+hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *post, hipStream_t s);
+hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, const void *fin,
+                            void *emit, double *part, int64_t blocks, hipStream_t s);
+hipError_t launch_xflux(const Geometry &g, const Physics &ph, const void *fin, double *part, int64_t blocks,
+                        hipStream_t s);
+hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
+                        double *part, hipStream_t s);
+// mode 1: moments after streaming fin (fields at step >= 1); mode 2: local
+// moments of fin (the initial state, step 0).  Outputs are float arrays, or
+// double arrays when out_f64 is set; any output may be null.
+hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
+                         void *rho, void *u, void *conc, bool out_f64, hipStream_t s);
+hipError_t launch_reduce(const double *part_sweep, int64_t n_sweep, const double *part_iface, int64_t n_iface,
+                         const double *part_flux, int64_t n_flux, double p, double p_stick, DevTotals *tot,
+                         hipStream_t s);
+
+int64_t sweep_blocks(const Geometry &g);
+int64_t interface_blocks(int64_t n);
+int64_t xflux_blocks(const Geometry &g);
+
+}  // namespace lbmk

@@ -1,0 +1,78 @@
+"""The C-ABI library: it loads, exports every function include/lbm.h
+declares, and rejects invalid arguments before touching a device (so these
+run on a machine without a GPU)."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1607_02874_amd import lbm
+
+
+def test_every_declared_function_is_exported():
+    names = lbm.header_functions()
+    assert {"lbm_create", "lbm_create_on", "lbm_step", "lbm_fields", "lbm_conversion_map", "lbm_totals",
+            "lbm_query", "lbm_destroy", "lbm_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(lbm.library(), n), n
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(lbm.lbm_geometry) == 32
+    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8
+    assert ctypes.sizeof(lbm.lbm_totals_t) == 8 + 6 * 8 + 8
+    assert ctypes.sizeof(lbm.lbm_device) == 32
+
+
+def _create(vox, **kw):
+    args = dict(da=1.0, tau=(0.8, 0.7), pore_size=4.0)
+    args.update(kw)
+    return lbm.lbm_create(vox, **args)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tau=(0.5, 0.7)), "tau"),
+    (dict(tau=(0.8, 0.3)), "tau"),
+    (dict(da=0.0), "da"),
+    (dict(da=-1.0), "da"),
+    (dict(da=float("nan")), "da"),
+    (dict(p_stick=1.5), "p_stick"),
+    (dict(p_stick=-0.1), "p_stick"),
+    (dict(pore_size=0.0), "pore_size"),
+    (dict(rho0=0.0), "rho0"),
+    (dict(c_inlet=-1.0), "c_inlet"),
+    (dict(tau=(0.0, 0.0), kn=0.0), "kn"),
+    (dict(kn=-0.5), "kn"),
+    (dict(tau=(0.8, 0.7), kn=0.3), "disagree"),
+    (dict(force=(float("inf"), 0, 0)), "force"),
+])
+def test_invalid_parameters_are_rejected(kw, msg):
+    vox = np.zeros((4, 4, 8), np.uint8)
+    with pytest.raises(lbm.LbmError) as e:
+        _create(vox, **kw)
+    assert e.value.status == lbm.LBM_EINVAL
+    assert msg in str(e.value)
+
+
+def test_invalid_voxel_and_mode_values():
+    vox = np.zeros((4, 4, 8), np.uint8)
+    vox[1, 2, 3] = 3
+    with pytest.raises(lbm.LbmError) as e:
+        _create(vox)
+    assert e.value.status == lbm.LBM_EINVAL and "voxel" in str(e.value)
+    vox[1, 2, 3] = 0
+    for kw in (dict(sputter=7), dict(coupling=2), dict(species_x=5), dict(storage=9)):
+        with pytest.raises(lbm.LbmError) as e:
+            _create(vox, **kw)
+        assert e.value.status == lbm.LBM_EUNSUPPORTED
+
+
+def test_null_arguments():
+    L = lbm.library()
+    out = ctypes.c_void_p(1)
+    st = L.lbm_create(None, 0.0, 1.0, None, None, ctypes.byref(out))
+    assert st == lbm.LBM_EINVAL and out.value is None
+    assert b"NULL" in L.lbm_last_error(None)
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    L.lbm_destroy(None)  # no-op

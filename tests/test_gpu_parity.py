@@ -1,0 +1,293 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle.
+
+Bars: the FP64 build of the kernels agrees with the oracle to 1e-12 (same
+arithmetic, different summation order); the FP32 path to 1e-5 L2-relative
+on density, velocity and concentration over the gas nodes (the stated target
+for FP32); geometry bookkeeping (link counts, node counts) bit-exact.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_02874_amd import inputs
+
+from parity import case, errors, make_sim, run_gpu, run_oracle, totals_rel
+
+pytestmark = pytest.mark.gpu
+
+F32, F16, BF16, F64 = 0, 1, 2, 3
+
+PLAIN = inputs.PLAIN_32
+
+
+def plain_case(steps=PLAIN.steps, **kw):
+    args = dict(da=PLAIN.da, tau=PLAIN.tau, pore_size=PLAIN.pore_size, force=PLAIN.force(),
+                p_stick=PLAIN.p_stick, c_inlet=PLAIN.c_inlet)
+    args.update(kw)
+    return case(PLAIN.voxels(), steps, **args)
+
+
+@pytest.fixture(scope="module")
+def plain_ref():
+    c = plain_case()
+    return c, run_oracle(c)
+
+
+def _report(name, e, t=None):
+    print(name, {k: (f"{v:.3e}" if isinstance(v, float) else v) for k, v in e.items()},
+          "" if t is None else {k: f"{v:.2e}" for k, v in t.items()}, flush=True)
+
+
+def test_plain_fp64_build_matches_oracle(plain_ref):
+    c, ref = plain_ref
+    gpu = run_gpu(c, F64)
+    e, t = errors(gpu, ref, c["vox"]), totals_rel(gpu, ref)
+    _report("fp64", e, t)
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < 1e-12, (k, e[k])
+    assert e["rho_solid_zero"] and e["conc_solid_zero"]
+    for k, v in t.items():
+        assert v < 1e-11, (k, v)
+    assert gpu["totals"]["step"] == c["steps"]
+
+
+def test_plain_fp32_matches_oracle(plain_ref):
+    c, ref = plain_ref
+    gpu = run_gpu(c, F32)
+    e, t = errors(gpu, ref, c["vox"]), totals_rel(gpu, ref)
+    _report("fp32", e, t)
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < 1e-5, (k, e[k])
+    for k, v in t.items():
+        assert v < 1e-5, (k, v)
+
+
+@pytest.mark.parametrize("storage,bound", [(F16, 1e-3), (BF16, 1e-2)])
+def test_plain_16bit_storage_error(plain_ref, storage, bound):
+    """16-bit deviation storage with FP32 arithmetic.  Target 1e-3; BF16's
+    unit roundoff (2^-8) exceeds it per stored value, so its bound is looser
+    and the measured figures are reported."""
+    c, ref = plain_ref
+    gpu = run_gpu(c, storage)
+    e = errors(gpu, ref, c["vox"])
+    _report({F16: "f16", BF16: "bf16"}[storage], e)
+    for k in ("rho", "u", "conc"):
+        assert e[k] < bound, (k, e[k])
+
+
+def test_geometry_bookkeeping_is_exact(plain_ref):
+    c, ref = plain_ref
+    s = make_sim(c, F32)
+    info = s.info()
+    links = s.active_links()
+    s.close()
+    vox = c["vox"]
+    assert np.array_equal(links, ref["links"])
+    assert info["n_fluid"] == int((vox == 0).sum())
+    assert info["n_interface"] == int((ref["links"] > 0).sum())
+    assert info["n_catalytic_links"] == int(ref["links"].sum(dtype=np.int64))
+    assert info["p"] == pytest.approx(ref["p"], rel=1e-15, abs=0)
+    assert info["kn"] == pytest.approx(oracle.kn_from_tau(c["tau"][0], c["pore_size"]), rel=1e-14)
+
+
+@pytest.mark.parametrize("sputter,coupling,species_x", [
+    ("WEIGHTED", "PASSIVE", "RESERVOIR"),
+    ("BOUNCEBACK", "PASSIVE", "RESERVOIR"),
+    ("UNIFORM", "BARYCENTRIC", "RESERVOIR"),
+    ("UNIFORM", "PASSIVE", "PERIODIC"),
+    ("WEIGHTED", "BARYCENTRIC", "PERIODIC"),
+])
+def test_modes_fp64_match_oracle(sputter, coupling, species_x):
+    c = plain_case(steps=60, sputter=sputter, coupling=coupling, species_x=species_x, c0=0.2, p_stick=0.6)
+    ref = run_oracle(c)
+    gpu = run_gpu(c, F64)
+    e, t = errors(gpu, ref, c["vox"]), totals_rel(gpu, ref)
+    _report(f"{sputter}-{coupling}-{species_x}", e, t)
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < 1e-12, (k, e[k])
+    for k, v in t.items():
+        assert v < 1e-11, (k, v)
+
+
+RAGGED = [
+    ("nx1", (3, 4, 1)),
+    ("nx63", (5, 6, 63)),
+    ("nx64", (3, 5, 64)),
+    ("nx65", (4, 3, 65)),
+    ("nx130", (3, 4, 130)),
+    ("tall", (9, 2, 7)),
+]
+
+
+@pytest.mark.parametrize("name,shape", RAGGED)
+def test_ragged_shapes_fp64_and_fp32(name, shape):
+    """Chunk edges, partial chunks and x-wrap: sizes that do not fill a
+    64-wide chunk, span several chunks with a ragged tail, or are 1 wide."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(sum(shape))
+    vox = np.where(rng.random(shape) < 0.3, 2, 0).astype(np.uint8)
+    vox[rng.random(shape) < 0.1] = 1
+    if nx > 2:
+        vox[:, :, 0] = 0
+    for species_x in ("RESERVOIR", "PERIODIC"):
+        c = case(vox, 25, da=0.3, tau=(0.9, 0.75), pore_size=2.0, force=(1e-4, 2e-5, -1e-5), c0=0.1,
+                 p_stick=0.7, species_x=species_x)
+        ref = run_oracle(c)
+        g64 = run_gpu(c, F64)
+        e = errors(g64, ref, vox)
+        _report(f"{name}-{species_x}-f64", e)
+        for k in ("rho", "u", "conc", "conv"):
+            assert e[k] < 1e-12, (k, e[k])
+        assert np.array_equal(g64["links"], ref["links"])
+        g32 = run_gpu(c, F32)
+        e = errors(g32, ref, vox)
+        for k in ("rho", "u", "conc", "conv"):
+            assert e[k] < 1e-5, (k, e[k])
+
+
+def test_degenerate_geometries():
+    """All solid (nothing to update), all gas (no interface), and a single
+    gas voxel surrounded by catalyst."""
+    solid = np.full((4, 4, 8), 2, np.uint8)
+    c = case(solid, 5)
+    g = run_gpu(c, F32)
+    assert g["info"]["n_fluid"] == 0 and g["info"]["n_interface"] == 0
+    assert g["totals"]["mass_gas"] == 0.0 and not g["rho"].any()
+    gas = np.zeros((4, 5, 70), np.uint8)
+    c = case(gas, 20, force=(1e-4, 0, 0), c0=0.3)
+    ref, g = run_oracle(c), run_gpu(c, F64)
+    e = errors(g, ref, gas)
+    for k in ("rho", "u", "conc"):
+        assert e[k] < 1e-12
+    one = np.full((3, 3, 3), 2, np.uint8)
+    one[1, 1, 1] = 0
+    c = case(one, 10, c0=0.5, species_x="PERIODIC")
+    ref, g = run_oracle(c), run_gpu(c, F64)
+    e = errors(g, ref, one)
+    for k in ("rho", "conc", "conv"):
+        assert e[k] < 1e-12, (k, e[k])
+
+
+def test_step_zero_fields_and_totals():
+    c = plain_case(steps=0, c0=0.25)
+    ref, g = run_oracle(c), run_gpu(c, F64)
+    e = errors(g, ref, c["vox"])
+    for k in ("rho", "u", "conc"):
+        assert e[k] < 1e-14, (k, e[k])
+    assert g["totals"]["mass_gas"] == pytest.approx(ref["totals"]["mass_gas"], rel=1e-14)
+
+
+@pytest.mark.parametrize("storage", [F64, F32])
+def test_poiseuille_closed_form_on_gpu(storage):
+    """Discrete Poiseuille profile rho u(y) = F/(2 nu) (h^2 - z^2) + F (6 nu -
+    1/(8 nu)) reached by the kernels themselves."""
+    n, tau, F = 32, 0.8, 1e-5
+    vox = inputs.channel(n, nx=3, nz=2)
+    c = case(vox, 30000, da=float("inf"), tau=(tau, tau), force=(F, 0, 0), p_stick=0.0, species_x="PERIODIC")
+    g = run_gpu(c, storage)
+    nu = (tau - 0.5) / 3
+    z = np.arange(n) - (n - 1) / 2
+    exact = F / (2 * nu) * ((n / 2) ** 2 - z * z) + F * (6 * nu - 1 / (8 * nu))
+    ru = (g["rho"] * g["u"][0])[:, :n, :]
+    err = np.abs(ru - exact[None, :, None]).max() / np.abs(exact).max()
+    print("poiseuille", storage, err)
+    assert err < (1e-10 if storage == F64 else 2e-5)
+
+
+@pytest.mark.parametrize("storage", [F64, F32])
+@pytest.mark.parametrize("sputter", ["UNIFORM", "WEIGHTED"])
+def test_reactive_slab_closed_form_on_gpu(storage, sputter):
+    n, tau, ps, cin = 12, 0.7, 0.6, 1.0
+    c = case(inputs.reactive_slab(n, ny=2, nz=3), 40000, da=0.5, tau=(0.8, tau), p_stick=ps, c_inlet=cin,
+             sputter=sputter)
+    g = run_gpu(c, storage)
+    x = np.arange(n)
+    exact = cin * (1 - ps * (x + tau) / (n * ps + 2 * tau - 1))
+    err = np.abs(g["conc"][:, :, :n] - exact).max()
+    print("slab", storage, sputter, err)
+    assert err < (1e-10 if storage == F64 else 2e-6)
+
+
+def test_runs_are_bit_identical():
+    c = plain_case(steps=50)
+    a, b = run_gpu(c, F32), run_gpu(c, F32)
+    for k in ("rho", "u", "conc", "conv"):
+        assert np.array_equal(a[k], b[k])
+    assert a["totals"] == b["totals"]
+
+
+def test_checkpoint_resume_is_bit_identical(tmp_path):
+    c = plain_case(steps=40)
+    whole = make_sim(c, F32)
+    whole.step(40)
+    want = whole.fields(), whole.conversion_map(), whole.totals()
+    whole.close()
+    first = make_sim(c, F32)
+    first.step(15)
+    first.save(tmp_path / "ck.bin")
+    first.close()
+    second = make_sim(c, F32)
+    second.load(tmp_path / "ck.bin")
+    second.step(25)
+    got = second.fields(), second.conversion_map(), second.totals()
+    second.close()
+    for a, b in zip(want[0], got[0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(want[1], got[1])
+    assert want[2] == got[2]
+
+
+def test_checkpoint_rejects_other_geometry(tmp_path):
+    from paper_1607_02874_amd import lbm
+
+    c = plain_case(steps=3)
+    s = make_sim(c, F32)
+    s.step(3)
+    s.save(tmp_path / "a.bin")
+    s.close()
+    other = plain_case(steps=3)
+    other["vox"] = other["vox"].copy()
+    other["vox"][5, 5, 10] = 0 if other["vox"][5, 5, 10] else 2
+    t = make_sim(other, F32)
+    with pytest.raises(lbm.LbmError) as e:
+        t.load(tmp_path / "a.bin")
+    assert e.value.status == lbm.LBM_EINVAL
+    t.close()
+
+
+def test_nonfinite_watchdog():
+    """A violently unstable run (tau near 1/2, large force) overflows; the
+    FP64 totals see it and the API reports LBM_ENONFINITE."""
+    from paper_1607_02874_amd import lbm
+
+    vox = inputs.porous_slab(16, 8, 8, 0.7, 2.0, 3)
+    c = case(vox, 1, tau=(0.5001, 0.5001), force=(0.9, 0.5, 0.0), pore_size=2.0)
+    s = make_sim(c, F32)
+    with pytest.raises(lbm.LbmError) as e:
+        for _ in range(400):
+            s.step(10)
+            s.synchronize()
+    assert e.value.status == lbm.LBM_ENONFINITE
+    t = lbm.lbm_totals_t()
+    assert lbm.library().lbm_totals(s.handle, t) == lbm.LBM_ENONFINITE and t.nonfinite == 1
+    s.close()
+
+
+def test_fields_device_matches_host_fields():
+    import torch
+
+    c = plain_case(steps=20)
+    s = make_sim(c, F32)
+    s.step(20)
+    rho, u, conc = s.fields()
+    n = rho.size
+    d_rho = torch.empty(n, device="cuda", dtype=torch.float32)
+    d_u = torch.empty(3 * n, device="cuda", dtype=torch.float32)
+    d_c = torch.empty(n, device="cuda", dtype=torch.float32)
+    s.fields_device(d_rho, d_u, d_c)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_rho.cpu().numpy(), rho.ravel().astype(np.float32))
+    assert np.array_equal(d_u.cpu().numpy(), u.ravel().astype(np.float32))
+    assert np.array_equal(d_c.cpu().numpy(), conc.ravel().astype(np.float32))
+    s.close()
