@@ -97,8 +97,9 @@ typedef struct {
     double rho0;              /* initial carrier density, > 0 */
     double c0;                /* initial species concentration, >= 0 (the paper
                                  starts with no reactant) */
-    double c_ref;             /* species storage shift; < 0 selects
-                                 max(c_inlet, c0) / 2 */
+    double c_ref;             /* species storage shift; < 0 selects 0
+                                 (unshifted: best relative precision where
+                                 the concentration is depleted) */
     double force[3];          /* body-force density on the carrier (Guo
                                  forcing, half-force velocity shift) */
     uint64_t reserved;        /* must be 0 */

@@ -390,7 +390,10 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.c0 = bc->c0;
     c->ph.c_inlet = bc->species_x == LBM_XBC_RESERVOIR ? bc->c_inlet : 0.0;
     c->ph.rho_ref = bc->rho0;
-    c->ph.c_ref = bc->c_ref >= 0.0 ? bc->c_ref : 0.5 * std::max(bc->c_inlet, bc->c0);
+    // Species populations are stored unshifted by default (c_ref = 0): the
+    // concentration is depleted next to the catalyst, and a shift would cost
+    // relative precision exactly where the conversion is decided.
+    c->ph.c_ref = bc->c_ref >= 0.0 ? bc->c_ref : 0.0;
     c->ph.p_stick = bc->p_stick;
     c->ph.p = p;
     c->ph.sputter = bc->sputter;

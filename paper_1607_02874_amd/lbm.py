@@ -78,6 +78,14 @@ class lbm_kernel_times_t(ctypes.Structure):
 
 
 def _load():
+    # One HIP runtime per process: PyTorch bundles its own libamdhip64 with the
+    # same soname as the system one.  Loading torch first makes liblbm.so bind
+    # to the runtime torch already holds, so the library can share torch's
+    # device memory and streams; without torch the system runtime is used.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library {LIB_PATH} is not built; run "
                           "`python -m paper_1607_02874_amd.build` (no CPU fallback exists)")
