@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300, help="oracle steps on the 64^3 crop (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 4 GiB device copy (counter calibration)")
+    ap.add_argument("--ytile", type=int, default=None, help="sweep y-tile height (default: the library's)")
+    ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -125,6 +127,18 @@ def main():
     info = sim.info()
     log(f"create {time.perf_counter() - t0:.1f} s, info {info}")
 
+    if args.scan_ytile:
+        for yt in [int(v) for v in args.scan_ytile.split(",")]:
+            sim.set_tunable(lbm.TUNE_YTILE, yt)
+            sim.step(20)
+            sim.synchronize()
+            sim.set_timing(True)
+            sim.step(100)
+            kt = sim.kernel_times()
+            sim.set_timing(False)
+            log(f"ytile {yt}: sweep {kt['ms_sweep'] / kt['n_sweep'] * 1e3:.1f} us")
+    if args.ytile:
+        sim.set_tunable(lbm.TUNE_YTILE, args.ytile)
     sim.step(args.warmup)
     sim.synchronize()
     torch.cuda.synchronize()
@@ -138,6 +152,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt = sim.kernel_times() if not args.no_timing else None
+    ytile = sim.get_tunable(lbm.TUNE_YTILE)
     tot = sim.totals()
     sim.close()
     log(f"elapsed {elapsed:.3f} s, totals {tot}")
@@ -163,8 +178,7 @@ def main():
                     "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2)}
     kernels = None
     if kt:
-        kernels = {k: round(kt["ms_" + k] / max(kt["n_" + k], 1) * 1e3, 2)
-                   for k in ("sweep", "interface", "xflux", "reduce")}
+        kernels = {k: round(kt["ms_" + k] / max(kt["n_" + k], 1) * 1e3, 2) for k in ("sweep", "interface", "reduce")}
 
     cpu, errs = None, None
     if args.cpu_steps > 0:
@@ -192,7 +206,7 @@ def main():
                    "n_nodes": n, "n_fluid": info["n_fluid"], "n_interface": info["n_interface"],
                    "n_catalytic_links": info["n_catalytic_links"], "mflups": round(mlups * info["n_fluid"] / n, 1),
                    "step_bytes": ab["step"], "step_GBps": round(ab["step"] / (ms_step * 1e-3) / 1e9, 1),
-                   "kernel_us": kernels},
+                   "kernel_us": kernels, "ytile": ytile},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": None if errs is None else {

@@ -224,6 +224,14 @@ lbm_status lbm_active_links(const lbm_ctx *c, uint8_t *b);
 /* Wait for all work queued by the context. */
 lbm_status lbm_synchronize(lbm_ctx *c);
 
+/* Launch-shape tunables (results never depend on them).
+ * LBM_TUNE_YTILE: rows per y-tile of the sweep traversal, 1..ny (default
+ * 16).  The sweep walks tiles of that many x-rows in y, z-planes inside a
+ * tile, so a row's z-neighbours are read while still cached. */
+typedef enum { LBM_TUNE_YTILE = 0 } lbm_tunable;
+lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value);   /* LBM_EINVAL: unknown or out of range */
+lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value);
+
 /* Per-kernel HIP-event timing: enable (1) / disable (0) and read; reading
  * synchronises the stream.  Reset on enable. */
 lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable);

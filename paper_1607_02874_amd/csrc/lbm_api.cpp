@@ -61,6 +61,7 @@ struct lbm_ctx {
     int64_t device_bytes = 0;
     std::vector<void *> allocations;
     ChunkInfo *d_chunks = nullptr;
+    uint32_t *d_order = nullptr;
     uint32_t *d_iface_vox = nullptr, *d_iface_mask = nullptr;
     double *d_iface_scale = nullptr, *d_acc = nullptr;
     void *d_emit = nullptr;
@@ -69,7 +70,8 @@ struct lbm_ctx {
     DevTotals *d_tot = nullptr;
     int cur = 0;          // d_pop[cur] holds the post-collision state of the current step
     int64_t step = 0;
-    int64_t blocks_sweep = 0, blocks_iface = 0, blocks_flux = 0;
+    int64_t blocks_sweep = 0, blocks_iface = 0;
+    int ytile = 16;       // rows per y-tile of the sweep traversal
 
     // watchdog
     int32_t *h_flag = nullptr;
@@ -131,10 +133,13 @@ void release(lbm_ctx *c) {
 Geometry geometry(const lbm_ctx *c) {
     Geometry g;
     g.chunks = c->d_chunks;
+    g.order = c->d_order;
     g.nx = c->nx;
     g.ny = c->ny;
     g.nz = c->nz;
     g.W = c->W;
+    g.units = uint32_t(int64_t(c->ny) * c->nz * c->W);
+    g.pad = 0;
     g.nfp = c->nfp;
     g.nfluid = c->nfluid;
     return g;
@@ -241,14 +246,9 @@ void drain_slot(lbm_ctx *c, StepEvents &r) {
         ms[k] = 0.0f;
         if (hipEventElapsedTime(&ms[k], r.ev[2 * k], r.ev[2 * k + 1]) != hipSuccess) ms[k] = 0.0f;
     }
-    const bool has_iface = c->blocks_iface > 0, has_flux = c->blocks_flux > 0;
-    if (has_iface) {
+    if (c->blocks_iface > 0) {
         c->times.ms_interface += ms[0];
         c->times.n_interface += 1;
-    }
-    if (has_flux) {
-        c->times.ms_xflux += ms[1];
-        c->times.n_xflux += 1;
     }
     c->times.ms_sweep += ms[2];
     c->times.n_sweep += 1;
@@ -262,8 +262,8 @@ lbm_status one_step(lbm_ctx *c) {
     const void *fin = c->d_pop[c->cur];
     void *fout = c->d_pop[1 - c->cur];
     double *ps = c->d_part;
-    double *pi = ps + 2 * c->blocks_sweep;
-    double *pf = pi + c->blocks_iface;
+    double *pi = ps + 4 * c->blocks_sweep;
+    double *fold = pi + c->blocks_iface;
     StepEvents *r = nullptr;
     if (c->timing) {
         r = &c->ring[size_t(c->ring_next)];
@@ -275,17 +275,14 @@ lbm_status one_step(lbm_ctx *c) {
     e = launch_interface(g, c->ph, interface_list(c), fin, c->d_emit, pi, c->blocks_iface, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "interface kernel launch");
     if (r) (void)hipEventRecord(r->ev[1], c->stream);
-    if (r) (void)hipEventRecord(r->ev[2], c->stream);
-    e = launch_xflux(g, c->ph, fin, pf, c->blocks_flux, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "boundary-flux kernel launch");
-    if (r) (void)hipEventRecord(r->ev[3], c->stream);
+    if (r) (void)hipEventRecord(r->ev[2], c->stream);  // no separate boundary-flux kernel:
+    if (r) (void)hipEventRecord(r->ev[3], c->stream);  // the sweep tallies the x-planes
     if (r) (void)hipEventRecord(r->ev[4], c->stream);
     e = launch_sweep(g, c->ph, fin, fout, c->d_emit, ps, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "sweep kernel launch");
     if (r) (void)hipEventRecord(r->ev[5], c->stream);
     if (r) (void)hipEventRecord(r->ev[6], c->stream);
-    e = launch_reduce(ps, c->blocks_sweep, pi, c->blocks_iface, pf, c->blocks_flux, c->ph.p, c->ph.p_stick, c->d_tot,
-                      c->stream);
+    e = launch_reduce(ps, c->blocks_sweep, pi, c->blocks_iface, fold, c->ph.p, c->ph.p_stick, c->d_tot, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
     if (r) {
         (void)hipEventRecord(r->ev[7], c->stream);
@@ -303,7 +300,8 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
     if (!g || !bc || !tau) return fail(nullptr, LBM_EINVAL, "geometry, tau and bc must not be NULL");
     if (!g->voxels) return fail(nullptr, LBM_EINVAL, "geometry voxels is NULL");
     if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(nullptr, LBM_EINVAL, "lattice sizes must be >= 1");
-    if (g->nx > 4096) return fail(nullptr, LBM_EINVAL, "nx must be <= 4096");
+    if (g->nx > 4096 || g->ny > 4096 || g->nz > 4096)
+        return fail(nullptr, LBM_EINVAL, "nx, ny and nz must be <= 4096");
     if (int64_t(g->nx) * g->ny * g->nz >= (int64_t(1) << 32))
         return fail(nullptr, LBM_EINVAL, "lattice has 2^32 nodes or more");
     if (g->reserved0 != 0 || bc->reserved != 0) return fail(nullptr, LBM_EINVAL, "reserved fields must be 0");
@@ -408,7 +406,9 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         build_chunks(c, chunks);
         c->nfluid = 0;
         for (uint8_t v : c->vox) c->nfluid += v == LBM_FLUID;
-        c->nfp = std::max<int64_t>(128, (c->nfluid + 127) / 128 * 128);
+        // one spare element per direction array at least: the last one holds
+        // the inlet ghost population of the reactant
+        c->nfp = (c->nfluid + 1 + 127) / 128 * 128;
         std::vector<uint32_t> ivox, imask;
         std::vector<double> iscale;
         build_interface(c, ivox, imask, iscale);
@@ -418,22 +418,31 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         const Geometry gtmp = geometry(c);
         c->blocks_sweep = sweep_blocks(gtmp);
         c->blocks_iface = interface_blocks(c->niface);
-        c->blocks_flux = c->ph.species_x == XB_RESERVOIR ? xflux_blocks(gtmp) : 0;
 
         const int sb = storage_bytes(c->ph.storage);
-        const int tb = c->ph.storage == ST_F64 ? 8 : 4;
         c->d_chunks = static_cast<ChunkInfo *>(dev_alloc(c, chunks.size() * sizeof(ChunkInfo)));
+        c->d_order = static_cast<uint32_t *>(dev_alloc(c, chunks.size() * sizeof(uint32_t)));
+        std::vector<uint32_t> order(chunks.size());
+        c->ytile = std::min(c->ytile, c->ny);
+        build_order(c->nx, c->ny, c->nz, c->ytile, order.data());
         c->d_iface_vox = static_cast<uint32_t *>(dev_alloc(c, ivox.size() * 4));
         c->d_iface_mask = static_cast<uint32_t *>(dev_alloc(c, imask.size() * 4));
         c->d_iface_scale = static_cast<double *>(dev_alloc(c, iscale.size() * 8));
         c->d_acc = static_cast<double *>(dev_alloc(c, size_t(c->niface) * 8));
-        c->d_emit = dev_alloc(c, size_t(c->n) * tb);
-        c->d_pop[0] = dev_alloc(c, size_t(38) * c->nfp * sb);
-        c->d_pop[1] = dev_alloc(c, size_t(38) * c->nfp * sb);
-        const int64_t nparts = 2 * c->blocks_sweep + c->blocks_iface + 2 * c->blocks_flux;
+        // One pool: population buffers A and B, then the emission array.  The
+        // sweep addresses all three from one base with integer offsets, so the
+        // emission array must start a whole number of direction strides (nfp
+        // elements) after each buffer, and voxel indices must fit in 32 bits.
+        char *pool = static_cast<char *>(dev_alloc(c, (size_t(76) * c->nfp + size_t(c->n)) * sb));
+        if (pool) {
+            c->d_pop[0] = pool;
+            c->d_pop[1] = pool + size_t(38) * c->nfp * sb;
+            c->d_emit = pool + size_t(76) * c->nfp * sb;
+        }
+        const int64_t nparts = 4 * c->blocks_sweep + c->blocks_iface + FOLD_BLOCKS * NPART;
         c->d_part = static_cast<double *>(dev_alloc(c, size_t(nparts) * 8));
         c->d_tot = static_cast<DevTotals *>(dev_alloc(c, sizeof(DevTotals)));
-        if (!c->d_chunks || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
+        if (!c->d_chunks || !c->d_order || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
             !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot) {
             release(c);
             delete c;
@@ -444,11 +453,12 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         };
         e = hipSuccess;
         up(c->d_chunks, chunks.data(), chunks.size() * sizeof(ChunkInfo));
+        up(c->d_order, order.data(), order.size() * sizeof(uint32_t));
         up(c->d_iface_vox, ivox.data(), ivox.size() * 4);
         up(c->d_iface_mask, imask.data(), imask.size() * 4);
         up(c->d_iface_scale, iscale.data(), iscale.size() * 8);
         if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, size_t(c->n) * tb, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, size_t(c->n) * sb, c->stream);
         DevTotals t0{};
         t0.mass_gas = double(c->nfluid) * bc->rho0;
         t0.mass_species = double(c->nfluid) * bc->c0;
@@ -620,6 +630,33 @@ lbm_status lbm_synchronize(lbm_ctx *c) {
     return check_pending_flag(c);
 }
 
+lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value) {
+    if (!c) return LBM_EINVAL;
+    if (which == LBM_TUNE_YTILE) {
+        if (value < 1 || value > c->ny) return fail(c, LBM_EINVAL, "ytile must be in [1, ny]");
+        if (int(value) == c->ytile) return LBM_OK;
+        std::vector<uint32_t> order(size_t(int64_t(c->ny) * c->nz * c->W));
+        build_order(c->nx, c->ny, c->nz, int(value), order.data());
+        // the stream may still be reading the old table
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_order, order.data(), order.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(c, e, "traversal table upload");
+        c->ytile = int(value);
+        return LBM_OK;
+    }
+    return fail(c, LBM_EINVAL, "unknown tunable");
+}
+
+lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value) {
+    if (!c || !value) return LBM_EINVAL;
+    if (which == LBM_TUNE_YTILE) {
+        *value = c->ytile;
+        return LBM_OK;
+    }
+    return LBM_EINVAL;
+}
+
 lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable) {
     if (!c) return LBM_EINVAL;
     if (enable && c->ring.empty()) {
@@ -695,7 +732,7 @@ lbm_status lbm_save(lbm_ctx *c, const char *path) {
     pack_params(c, h.params);
     hipError_t e = hipMemcpyAsync(&h.tot, c->d_tot, sizeof(DevTotals), hipMemcpyDeviceToHost, c->stream);
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t emit = size_t(c->n) * (c->ph.storage == ST_F64 ? 8 : 4);
+    const size_t emit = size_t(c->n) * storage_bytes(c->ph.storage);
     std::vector<char> buf;
     try {
         buf.resize(2 * pop + emit + size_t(c->niface) * 8);
@@ -735,7 +772,7 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
         return fail(c, LBM_EINVAL, "checkpoint does not match this context's geometry or parameters");
     }
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t emit = size_t(c->n) * (c->ph.storage == ST_F64 ? 8 : 4);
+    const size_t emit = size_t(c->n) * storage_bytes(c->ph.storage);
     std::vector<char> buf;
     try {
         buf.resize(2 * pop + emit + size_t(c->niface) * 8);

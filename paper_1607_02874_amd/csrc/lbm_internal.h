@@ -45,7 +45,9 @@ enum { SP_UNIFORM = 0, SP_WEIGHTED = 1, SP_BOUNCEBACK = 2 };
 enum { CP_PASSIVE = 0, CP_BARYCENTRIC = 1 };
 enum { XB_PERIODIC = 0, XB_RESERVOIR = 1 };
 
-// Slots of the per-step partial sums (FP64) written by the kernels.
+// Slots of the per-step partial sums (FP64).  The sweep writes four per
+// block (carrier mass, reactant mass, influx, outflux), the interface kernel
+// one (arrivals In).
 enum { PART_MASS_C = 0, PART_MASS_R = 1, PART_IN = 2, PART_INFLUX = 3, PART_OUTFLUX = 4, NPART = 5 };
 
 // Device totals: step-cumulative FP64 values and the non-finite flag.
@@ -58,7 +60,10 @@ struct DevTotals {
 
 struct Geometry {
     const ChunkInfo *chunks;  // rows * W records, row = z * ny + y
+    const uint32_t *order;    // sweep traversal: per wave y | z << 12 | chunk << 24
     int32_t nx, ny, nz, W;    // W = ceil(nx / 64)
+    uint32_t units;           // ny * nz * W waves
+    int32_t pad;
     int64_t nfp;              // elements per direction in a population buffer
     int64_t nfluid;
 };
@@ -84,12 +89,17 @@ struct Interface {
 
 int storage_bytes(int storage);
 
+// Traversal table for the sweep: tiles of `ytile` x-rows in y, z-planes in
+// order inside a tile, rows in y, then the chunks of a row.  A row's
+// z-neighbours are then ytile rows apart in launch order, inside the set of
+// blocks an XCD has in flight, so the populations they share are still in its
+// L2.
+void build_order(int nx, int ny, int nz, int ytile, uint32_t *order);
+
 // All launchers queue on `stream` and return the launch status.
 hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *post, hipStream_t s);
 hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, const void *fin,
                             void *emit, double *part, int64_t blocks, hipStream_t s);
-hipError_t launch_xflux(const Geometry &g, const Physics &ph, const void *fin, double *part, int64_t blocks,
-                        hipStream_t s);
 hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
                         double *part, hipStream_t s);
 // mode 1: moments after streaming fin (fields at step >= 1); mode 2: local
@@ -97,12 +107,14 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
 // double arrays when out_f64 is set; any output may be null.
 hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
                          void *rho, void *u, void *conc, bool out_f64, hipStream_t s);
+// Two-stage fixed-order reduction of the per-block partials: FOLD_BLOCKS
+// blocks fold contiguous slices into `fold` (FOLD_BLOCKS * NPART doubles),
+// then one block sums those and updates the totals.
+constexpr int FOLD_BLOCKS = 256;
 hipError_t launch_reduce(const double *part_sweep, int64_t n_sweep, const double *part_iface, int64_t n_iface,
-                         const double *part_flux, int64_t n_flux, double p, double p_stick, DevTotals *tot,
-                         hipStream_t s);
+                         double *fold, double p, double p_stick, DevTotals *tot, hipStream_t s);
 
 int64_t sweep_blocks(const Geometry &g);
 int64_t interface_blocks(int64_t n);
-int64_t xflux_blocks(const Geometry &g);
 
 }  // namespace lbmk

@@ -32,8 +32,11 @@
 namespace lbmk {
 namespace {
 
-// Row offset slot of (cy, cz): 9 source rows.
-__host__ __device__ constexpr int row_slot(int cy, int cz) { return (cy + 1) * 3 + (cz + 1); }
+// Storage order of the direction arrays inside a lattice: the rest
+// population first, then each velocity next to its opposite (i, opp(i)), so a
+// pull and its bounce-back alternative share one base.
+__host__ __device__ constexpr int dslot(int i) { return i == 0 ? 0 : (i <= 9 ? 2 * i - 1 : 2 * (i - 9)); }
+__host__ __device__ constexpr int pair_slot(int i) { return i == 0 ? 0 : 2 * (i <= 9 ? i : i - 9) - 1; }
 
 // ------------------------------------------------------------ storage --
 template <int ST>
@@ -42,6 +45,8 @@ template <>
 struct Store<ST_F32> {
     using S = float;
     using T = float;
+    __device__ static T cv(S v) { return v; }
+    __device__ static S enc(T v) { return v; }
     __device__ static T ld(const S *p) { return *p; }
     __device__ static void st(S *p, T v) { *p = v; }
 };
@@ -49,28 +54,30 @@ template <>
 struct Store<ST_F16> {
     using S = _Float16;
     using T = float;
+    __device__ static T cv(S v) { return static_cast<float>(v); }
     __device__ static T ld(const S *p) { return static_cast<float>(*p); }
-    __device__ static void st(S *p, T v) { *p = static_cast<_Float16>(v); }  // round to nearest even
+    __device__ static S enc(T v) { return static_cast<_Float16>(v); }  // round to nearest even
+    __device__ static void st(S *p, T v) { *p = enc(v); }
 };
 template <>
 struct Store<ST_BF16> {
     using S = uint16_t;
     using T = float;
+    __device__ static T cv(S v) { return __uint_as_float(uint32_t(v) << 16); }
     __device__ static T ld(const S *p) { return __uint_as_float(uint32_t(*p) << 16); }
-    __device__ static void st(S *p, T v) {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) {
-            *p = uint16_t((u >> 16) | 0x40u);  // quiet NaN stays NaN
-            return;
-        }
-        u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-        *p = uint16_t(u >> 16);
+    __device__ static S enc(T v) {
+        const uint32_t u = __float_as_uint(v);
+        const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // round to nearest even
+        return (u & 0x7fffffffu) > 0x7f800000u ? uint16_t((u >> 16) | 0x40u) : uint16_t(rounded);  // NaN stays NaN
     }
+    __device__ static void st(S *p, T v) { *p = enc(v); }
 };
 template <>
 struct Store<ST_F64> {
     using S = double;
     using T = double;
+    __device__ static T cv(S v) { return v; }
+    __device__ static S enc(T v) { return v; }
     __device__ static T ld(const S *p) { return *p; }
     __device__ static void st(S *p, T v) { *p = v; }
 };
@@ -85,6 +92,7 @@ struct PhysK {
     T h_inlet;        // c_inlet - c_ref: normalised inlet ghost population
     T keep;           // 1 - p_stick
     T h0c, h0r;       // initial state, normalised: rho0 - rho_ref, c0 - c_ref
+    double c_in;      // reservoir concentration (influx tally)
     int32_t sputter, coupling, species_x;
 };
 
@@ -103,6 +111,7 @@ PhysK<T> to_kernel(const Physics &p) {
     k.keep = T(1.0 - p.p_stick);
     k.h0c = T(p.rho0 - p.rho_ref);
     k.h0r = T(p.c0 - p.c_ref);
+    k.c_in = p.c_inlet;
     k.sputter = p.sputter;
     k.coupling = p.coupling;
     k.species_x = p.species_x;
@@ -110,6 +119,16 @@ PhysK<T> to_kernel(const Physics &p) {
 }
 
 // ------------------------------------------------------------ helpers --
+// Keep a selected value opaque to the optimizer (no instruction is emitted):
+// stops it from folding a select into the address arithmetic and turning the
+// select back into divergent branches.
+__device__ __forceinline__ void opaque(uint32_t &v) { asm("" : "+v"(v)); }
+// Same for a wave-uniform 64-bit value kept in a scalar register pair.
+__device__ __forceinline__ uint64_t opaque_s(uint64_t v) {
+    asm("" : "+s"(v));
+    return v;
+}
+
 __device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
     // number of set bits of m below this lane (lane = position within the chunk)
     return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
@@ -138,45 +157,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
         for (int k = 0; k < NV; ++k) out[k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
 }
 
-// Source of a pull along a direction with x-component cx, seen from this
-// lane, in the source row described by I.  `below` counts the gas bits of
-// I.fluid below this lane.
-struct Src {
-    bool fluid, cat;
-    uint32_t rank;
-};
-
-__device__ __forceinline__ Src source_in_row(const ChunkInfo &I, uint32_t below, int lane, int cx, bool last_x) {
-    Src s;
-    if (cx == 0) {
-        s.fluid = (I.fluid >> lane) & 1u;
-        s.cat = (I.cat >> lane) & 1u;
-        s.rank = I.base + below;
-    } else if (cx == 1) {  // source x - 1
-        if (lane > 0) {
-            const uint32_t b = uint32_t(I.fluid >> (lane - 1)) & 1u;
-            s.fluid = b;
-            s.cat = (I.cat >> (lane - 1)) & 1u;
-            s.rank = I.base + below - b;
-        } else {
-            s.fluid = I.edge & 1u;
-            s.cat = I.edge & 2u;
-            s.rank = I.prev_rank;
-        }
-    } else {  // cx == -1, source x + 1
-        if (lane < 63 && !last_x) {
-            s.fluid = (I.fluid >> (lane + 1)) & 1u;
-            s.cat = (I.cat >> (lane + 1)) & 1u;
-            s.rank = I.base + below + (uint32_t(I.fluid >> lane) & 1u);
-        } else {
-            s.fluid = I.edge & 4u;
-            s.cat = I.edge & 8u;
-            s.rank = I.next_rank;
-        }
-    }
-    return s;
-}
-
 // Where a wavefront sits: which row and chunk, and this lane's node.
 struct WaveUnit {
     int row, chunk, lane, x, y, z;
@@ -194,94 +174,175 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 __device__ __forceinline__ WaveUnit locate(const Geometry &g) {
+    // The traversal order (which x-row chunk each wave takes) is a host-built
+    // table of codes y | z << 12 | chunk << 24, one per wave, read with one
+    // scalar load.
     WaveUnit u;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const int64_t unit = int64_t(xcd_block(int(blockIdx.x), int(gridDim.x))) * 4 + wave;
-    const int64_t units = int64_t(g.ny) * g.nz * g.W;
-    u.valid = unit < units;
-    const int64_t un = u.valid ? unit : 0;
-    u.row = __builtin_amdgcn_readfirstlane(int(un / g.W));
-    u.chunk = __builtin_amdgcn_readfirstlane(int(un - int64_t(u.row) * g.W));
-    u.y = u.row % g.ny;
-    u.z = u.row / g.ny;
+    const uint32_t unit = uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))) * 4u + uint32_t(wave);
+    u.valid = unit < g.units;
+    const uint32_t code = g.order[u.valid ? unit : 0u];
+    u.y = int(code & 0xfffu);
+    u.z = int((code >> 12) & 0xfffu);
+    u.chunk = int(code >> 24);
+    u.row = u.z * g.ny + u.y;
     u.lane = int(threadIdx.x & 63);
     u.x = u.chunk * 64 + u.lane;
-    const ChunkInfo &I = g.chunks[int64_t(u.row) * g.W + u.chunk];
+    const ChunkInfo &I = g.chunks[uint32_t(u.row) * uint32_t(g.W) + uint32_t(u.chunk)];
     const uint64_t fl = I.fluid;
     u.active = u.valid && u.x < g.nx && ((fl >> u.lane) & 1u);
     u.idx = I.base + bits_below_lane(fl);
     return u;
 }
 
+// Loads and stores at a wave-uniform base plus a 32-bit per-lane byte
+// offset: the global memory instructions take the base in scalar registers,
+// so no per-lane 64-bit address arithmetic is needed.
+template <typename S>
+__device__ __forceinline__ S ld_at(const S *base, uint32_t byte_off) {
+    return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename S>
+__device__ __forceinline__ void st_at(S *base, uint32_t byte_off, S v) {
+    *reinterpret_cast<S *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
+// Base address of each direction array of a population buffer (carrier
+// slots 0..18, reactant 19..37, in storage order), formed on the host so the
+// kernels do no 64-bit base arithmetic.
+struct Slots {
+    const void *p[38];
+};
+struct OutSlots {
+    void *p[38];
+};
+
+// Directions grouped by source row (cy, cz), so each row's chunk record is
+// needed for one stretch of the pull only.
+constexpr int ORDER[18] = {1, 10, 2, 4, 14, 11, 13, 5, 3, 6, 16, 12, 15, 7, 8, 9, 17, 18};
+
+// Per-lane predicates of one pull direction, held as 64-bit lane masks
+// (bit L = lane L of the wave) so that they are formed once per wave on the
+// scalar unit and feed the vector selects directly.
+__device__ __forceinline__ bool lane_in(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
+
+__device__ __forceinline__ uint32_t rank_of_mask(uint64_t m, uint32_t add) {
+    // add + number of set bits of m below this lane
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), add));
+}
+
 // Pull both lattices into registers: hC[i], hR[i] are the normalised
 // populations of this node after streaming (the pre-collision state).
-template <int ST>
-__device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Store<ST>::T> &ph,
-                                     const typename Store<ST>::S *__restrict__ fin,
-                                     const typename Store<ST>::T *__restrict__ emit, const WaveUnit &u,
+template <int ST, int SP>
+__device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
+                                     const typename Store<ST>::S *__restrict__ emit, const WaveUnit &u,
                                      typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19]) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
+    constexpr uint32_t SB = sizeof(S);
     const int64_t nfp = g.nfp;
-    const S *finR = fin + 19 * nfp;
+    const uint32_t nfp_b = uint32_t(nfp) * SB;   // one direction array, in bytes
+    const uint32_t slot_b = uint32_t(nfp - 1) * SB;  // reserved last element of each array
     const bool reservoir = ph.species_x == XB_RESERVOIR;
-    const bool first_x = u.x == 0, last_x = u.x == g.nx - 1;
+    const int sputter = SP >= 0 ? SP : ph.sputter;
+    const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
+    auto base = [&](int slot) { return static_cast<const S *>(in.p[slot]); };
+    const uint32_t own_b = u.idx * SB;
+    const uint32_t x_b = uint32_t(u.x) * SB;
+    // wave-uniform shape of the chunk
+    const int nvalid = min(64, g.nx - 64 * u.chunk);
+    const int last_lane = nvalid - 1;
+    const bool first_chunk = u.chunk == 0, last_chunk = u.chunk == g.W - 1;
+    const uint64_t lane0 = 1ull, lane_last = 1ull << last_lane;
 
-    // the nine source rows (uniform per wave)
-    ChunkInfo rows[9];
-    uint32_t below[9];
+    // Phase 1: every address, then every load (56 loads in flight per lane).
+    S rc[19], rr[19], re[19];
+    uint32_t cat_bits = 0;
+    rc[0] = ld_at(base(dslot(0)), own_b);
+    rr[0] = ld_at(base(19 + dslot(0)), own_b);
+    // the nine source rows (wave-uniform): chunk record and first voxel
+    const ChunkInfo *recs[9];
+    uint32_t row_vox[9];
 #pragma unroll
-    for (int cy = -1; cy <= 1; ++cy)
+    for (int cy = -1; cy <= 1; ++cy) {
+        int ys = u.y - cy;
+        ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
 #pragma unroll
         for (int cz = -1; cz <= 1; ++cz) {
-            int ys = u.y - cy, zs = u.z - cz;
-            ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+            int zs = u.z - cz;
             zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
-            const int r = __builtin_amdgcn_readfirstlane(zs * g.ny + ys);
-            rows[row_slot(cy, cz)] = g.chunks[int64_t(r) * g.W + u.chunk];
-            below[row_slot(cy, cz)] = bits_below_lane(rows[row_slot(cy, cz)].fluid);
+            const uint32_t r = uint32_t(__builtin_amdgcn_readfirstlane(zs * g.ny + ys));
+            recs[(cy + 1) * 3 + cz + 1] = g.chunks + (r * uint32_t(g.W) + uint32_t(u.chunk));
+            row_vox[(cy + 1) * 3 + cz + 1] = r * uint32_t(g.nx);
         }
-
-    hC[0] = Store<ST>::ld(fin + u.idx);
-    hR[0] = Store<ST>::ld(finR + u.idx);
+    }
+#pragma unroll
+    for (int k = 0; k < 18; ++k) {
+        const int i = ORDER[k];
+        const int cx = CX[i];
+        // source row of this direction and its chunk record
+        const ChunkInfo &I = *recs[(CY[i] + 1) * 3 + CZ[i] + 1];
+        const uint32_t rv = row_vox[(CY[i] + 1) * 3 + CZ[i] + 1];
+        // F / C: the source x - cx of each lane is gas / catalytic; rank: its
+        // storage index when gas.
+        uint64_t F, C;
+        uint32_t rank;
+        if (cx == 0) {
+            F = I.fluid;
+            C = I.cat;
+            rank = rank_of_mask(I.fluid, I.base);
+        } else if (cx == 1) {  // source x - 1; lane 0 takes the left neighbour of the chunk
+            const uint32_t pf = I.edge & 1u;
+            F = (I.fluid << 1) | pf;
+            C = (I.cat << 1) | ((I.edge >> 1) & 1u);
+            rank = rank_of_mask(F, I.base - pf);
+            if (first_chunk) rank = lane_in(lane0) ? I.prev_rank : rank;  // periodic wrap to x = nx - 1
+        } else {  // source x + 1; the last valid lane takes the right neighbour
+            F = (I.fluid >> 1) | (uint64_t((I.edge >> 2) & 1u) << last_lane);
+            C = (I.cat >> 1) | (uint64_t((I.edge >> 3) & 1u) << last_lane);
+            rank = rank_of_mask(I.fluid >> 1, I.base + uint32_t(I.fluid & 1u));
+            if (last_chunk) rank = lane_in(lane_last) ? I.next_rank : rank;  // periodic wrap to x = 0
+        }
+        // Direction i and opp(i) are adjacent arrays: one base, and the pull
+        // or the bounce-back is an offset of 0 or nfp elements plus a node.
+        const uint32_t half = dslot(i) < dslot(opp(i)) ? 0u : nfp_b;  // i's array inside the pair
+        const uint32_t bb_b = own_b + (nfp_b - half);                   // own opp(i) entry
+        const uint32_t pull_b = rank * SB + half;
+        rc[i] = ld_at(base(pair_slot(i)), lane_in(F) ? pull_b : bb_b);
+        // Reactant: reservoir ghosts at the x-ends, the reactive pull at
+        // catalytic sources.
+        const uint64_t inlet = (reservoir && cx == 1 && first_chunk) ? lane0 : 0ull;
+        const uint64_t outlet = (reservoir && cx == -1 && last_chunk) ? lane_last : 0ull;  // copies plane nx - 1
+        // inlet lanes take the reserved slot even though their periodic
+        // carrier source is gas; outlet lanes read the copy of plane nx - 1
+        const uint64_t SF = (F & ~outlet & ~inlet) | (I.fluid & outlet);
+        const uint64_t CAT = ~F & C & ~inlet & ~outlet;
+        const uint64_t EMIT = bounce ? 0ull : CAT;
+        uint32_t srank_b = pull_b;
+        if (outlet) srank_b = lane_in(outlet) ? rank_of_mask(I.fluid, I.base) * SB + half : srank_b;
+        // the inlet ghost value sits in the reserved last element of the array
+        uint32_t r_b = lane_in(EMIT) ? 0u : bb_b;
+        r_b = lane_in(inlet) ? slot_b + half : r_b;
+        r_b = lane_in(SF) ? srank_b : r_b;
+        rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
+        // emission of a catalytic source voxel (element 0 when not used)
+        uint32_t vox_b = (rv - cx) * SB + x_b;
+        if (cx == 1 && first_chunk) vox_b = lane_in(lane0) ? (rv + g.nx - 1) * SB : vox_b;
+        if (cx == -1 && last_chunk) vox_b = lane_in(lane_last) ? rv * SB : vox_b;
+        re[i] = ld_at(emit, lane_in(EMIT) ? vox_b : 0u);
+        cat_bits |= lane_in(CAT) ? (1u << i) : 0u;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // Phase 2: decode and apply the sputtering rule.
+    hC[0] = Store<ST>::cv(rc[0]);
+    hR[0] = Store<ST>::cv(rr[0]);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
-        const int slot = row_slot(CY[i], CZ[i]);
-        const ChunkInfo &I = rows[slot];
-        const Src s = source_in_row(I, below[slot], u.lane, CX[i], last_x);
-        // carrier: periodic in x, every solid reflects
-        const S *ac = s.fluid ? fin + i * nfp + s.rank : fin + opp(i) * nfp + u.idx;
-        hC[i] = Store<ST>::ld(ac);
-        // reactant
-        bool sf = s.fluid, sc = s.cat;
-        uint32_t rank = s.rank;
-        bool inlet = false;
-        if (reservoir && CX[i] == 1 && first_x) {
-            inlet = true;
-        } else if (reservoir && CX[i] == -1 && last_x) {
-            // outlet ghost: copy of plane nx - 1 at the source row
-            sf = (I.fluid >> u.lane) & 1u;
-            sc = false;
-            rank = I.base + below[slot];
-        }
-        const bool cat = !inlet && !sf && sc;
-        const bool bb_cat = cat && ph.sputter == SP_BOUNCEBACK;
-        T v = ph.h_inlet;
-        if (!inlet && (!cat || bb_cat)) {
-            const S *ar = sf ? finR + i * nfp + rank : finR + opp(i) * nfp + u.idx;
-            v = Store<ST>::ld(ar);
-            if (bb_cat) v = ph.keep * (v + ph.cref) - ph.cref;
-        }
-        if (cat && !bb_cat) {
-            int xs = u.x - CX[i];
-            xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
-            int ys = u.y - CY[i], zs = u.z - CZ[i];
-            ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
-            zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
-            const T e = emit[(int64_t(zs) * g.ny + ys) * g.nx + xs];
-            v = (ph.sputter == SP_UNIFORM ? e * inv_wgt<T>(i) : e) - ph.cref;
-        }
-        hR[i] = v;
+        hC[i] = Store<ST>::cv(rc[i]);
+        const T v = Store<ST>::cv(rr[i]);
+        const T e = Store<ST>::cv(re[i]);
+        const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
+        hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
 }
 
@@ -293,28 +354,55 @@ struct Mom {
 };
 
 template <typename T>
+__device__ __forceinline__ void weighted_moments(const T (&h)[19], T &d, T &jx, T &jy, T &jz) {
+    // sum_i w_i h_i and sum_i w_i c_i h_i, grouped by weight class
+    T axis = 0, diag = 0, ax = 0, ay = 0, az = 0, gx = 0, gy = 0, gz = 0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const bool is_axis = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i] == 1;
+        T &sum = is_axis ? axis : diag;
+        sum += h[i];
+        T &mx = is_axis ? ax : gx;
+        T &my = is_axis ? ay : gy;
+        T &mz = is_axis ? az : gz;
+        if (CX[i] == 1) mx += h[i];
+        if (CX[i] == -1) mx -= h[i];
+        if (CY[i] == 1) my += h[i];
+        if (CY[i] == -1) my -= h[i];
+        if (CZ[i] == 1) mz += h[i];
+        if (CZ[i] == -1) mz -= h[i];
+    }
+    d = wgt<T>(0) * h[0] + wgt<T>(1) * axis + wgt<T>(4) * diag;
+    jx = wgt<T>(1) * ax + wgt<T>(4) * gx;
+    jy = wgt<T>(1) * ay + wgt<T>(4) * gy;
+    jz = wgt<T>(1) * az + wgt<T>(4) * gz;
+}
+
+template <typename T>
 __device__ __forceinline__ Mom<T> moments(const PhysK<T> &ph, const T (&hC)[19], const T (&hR)[19]) {
     Mom<T> m;
-    T dc = 0, jx = 0, jy = 0, jz = 0, dr = 0, rx = 0, ry = 0, rz = 0;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const T a = wgt<T>(i) * hC[i], b = wgt<T>(i) * hR[i];
-        dc += a;
-        dr += b;
-        if (CX[i]) { jx += CX[i] * a; rx += CX[i] * b; }
-        if (CY[i]) { jy += CY[i] * a; ry += CY[i] * b; }
-        if (CZ[i]) { jz += CZ[i] * a; rz += CZ[i] * b; }
-    }
-    m.dc = dc;
-    m.dr = dr;
-    m.rc = ph.rref + dc;
-    m.rr = ph.cref + dr;
+    T jx, jy, jz;
+    weighted_moments(hC, m.dc, jx, jy, jz);
+    m.rc = ph.rref + m.dc;
     if (ph.coupling == CP_BARYCENTRIC) {
+        T rx, ry, rz;
+        weighted_moments(hR, m.dr, rx, ry, rz);
+        m.rr = ph.cref + m.dr;
         const T inv = T(1) / (m.rc + m.rr);
         m.ux = (jx + rx + T(0.5) * ph.fx) * inv;
         m.uy = (jy + ry + T(0.5) * ph.fy) * inv;
         m.uz = (jz + rz + T(0.5) * ph.fz) * inv;
     } else {
+        T axis = 0, diag = 0;
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+            if (CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i] == 1)
+                axis += hR[i];
+            else
+                diag += hR[i];
+        }
+        m.dr = wgt<T>(0) * hR[0] + wgt<T>(1) * axis + wgt<T>(4) * diag;
+        m.rr = ph.cref + m.dr;
         const T inv = T(1) / m.rc;
         m.ux = (jx + T(0.5) * ph.fx) * inv;
         m.uy = (jy + T(0.5) * ph.fy) * inv;
@@ -325,56 +413,111 @@ __device__ __forceinline__ Mom<T> moments(const PhysK<T> &ph, const T (&hC)[19],
 
 // BGK collision in normalised form: h* = h - omega (h - heq) (+ Guo / w_i on
 // the carrier), heq_i = (rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u).
+// Directions are taken in opposite pairs (c.u and c.F change sign), which
+// shares most of the arithmetic between the two.
 template <typename T>
 __device__ __forceinline__ void collide(const PhysK<T> &ph, const Mom<T> &m, T (&hC)[19], T (&hR)[19]) {
     const T uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
     const T uf = m.ux * ph.fx + m.uy * ph.fy + m.uz * ph.fz;
     const T base_c = m.dc - T(1.5) * m.rc * uu, base_r = m.dr - T(1.5) * m.rr * uu;
+    const T guo3 = T(3) * ph.guo, guo9 = T(9) * ph.guo;
+    // h - omega (h - heq) keeps the small non-equilibrium part exact
+    hC[0] = hC[0] - ph.om_c * (hC[0] - base_c) - guo3 * uf;
+    hR[0] = hR[0] - ph.om_r * (hR[0] - base_r);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 1; i <= 9; ++i) {
+        const int j = opp(i);
         const T cu = T(CX[i]) * m.ux + T(CY[i]) * m.uy + T(CZ[i]) * m.uz;
-        const T cf = T(CX[i]) * ph.fx + T(CY[i]) * ph.fy + T(CZ[i]) * ph.fz;
-        const T poly = T(3) * cu + T(4.5) * cu * cu;
-        const T eqc = base_c + m.rc * poly;
-        const T eqr = base_r + m.rr * poly;
-        const T src = ph.guo * (T(3) * (cf - uf) + T(9) * cu * cf);
-        hC[i] = hC[i] - ph.om_c * (hC[i] - eqc) + src;
-        hR[i] = hR[i] - ph.om_r * (hR[i] - eqr);
+        const T cf = T(CX[i]) * ph.fx + T(CY[i]) * ph.fy + T(CZ[i]) * ph.fz;  // wave-uniform
+        const T q = T(4.5) * cu * cu, l = T(3) * cu;
+        const T tc = base_c + m.rc * q, sc = m.rc * l;
+        const T tr = base_r + m.rr * q, sr = m.rr * l;
+        const T a = guo9 * cu * cf - guo3 * uf, b = guo3 * cf;  // Guo term: a + b (i), a - b (opp)
+        hC[i] = hC[i] - ph.om_c * (hC[i] - (tc + sc)) + (a + b);
+        hC[j] = hC[j] - ph.om_c * (hC[j] - (tc - sc)) + (a - b);
+        hR[i] = hR[i] - ph.om_r * (hR[i] - (tr + sr));
+        hR[j] = hR[j] - ph.om_r * (hR[j] - (tr - sr));
     }
 }
 
 // ------------------------------------------------------------ kernels --
 
+// Reactant leaving through x = -1 (own post-collision populations of x = 0
+// along c_x = -1) or x = nx (of x = nx - 1 along c_x = +1), and the influx
+// pulled at x = 0.  Out of line: it runs on two lanes per x-row and would
+// otherwise raise the register budget of the whole sweep.
+struct InOut {
+    double in, out;
+};
+
 template <int ST>
-__global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<ST>::T> ph,
-                                                const typename Store<ST>::S *__restrict__ fin,
-                                                typename Store<ST>::S *__restrict__ fout,
-                                                const typename Store<ST>::T *__restrict__ emit,
+__device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double c_in,
+                                             const typename Store<ST>::S *own, int64_t nfp, bool first_x,
+                                             bool last_x) {
+    using T = typename Store<ST>::T;
+    double fin = 0.0, fout = 0.0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        if (CX[i] == 1) {
+            if (first_x) fin += double(wgt<T>(i)) * c_in;
+            if (last_x) fout += double(wgt<T>(i) * (Store<ST>::ld(own + dslot(i) * nfp) + c_ref));
+        }
+        if (CX[i] == -1 && first_x) fout += double(wgt<T>(i) * (Store<ST>::ld(own + dslot(i) * nfp) + c_ref));
+    }
+    return InOut{fin, fout};
+}
+
+template <int ST, int SP>
+__global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
+                                                const typename Store<ST>::S *__restrict__ emit,
                                                 double *__restrict__ part) {
+    using S = typename Store<ST>::S;
     using T = typename Store<ST>::T;
     const WaveUnit u = locate(g);
-    double acc[2] = {0.0, 0.0};
+    // per-block partials: carrier mass, reactant mass, influx, outflux
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (u.active) {
         T hC[19], hR[19];
-        pull<ST>(g, ph, fin, emit, u, hC, hR);
+        pull<ST, SP>(g, ph, in, emit, u, hC, hR);
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
+        // Reactant crossing the reservoir planes in this streaming: what the
+        // outlet ghost returned to x = nx - 1 (pulled along c_x = -1) counts
+        // against what left there (below).
+        const bool reservoir = ph.species_x == XB_RESERVOIR;
+        const bool first_x = u.x == 0, last_x = u.x == g.nx - 1;
+        if (reservoir && last_x) {
+#pragma unroll
+            for (int i = 1; i < 19; ++i)
+                if (CX[i] == -1) acc[3] -= double(wgt<T>(i) * (hR[i] + ph.cref));
+        }
         collide(ph, m, hC, hR);
         const int64_t nfp = g.nfp;
+        uint32_t own_b = u.idx * uint32_t(sizeof(typename Store<ST>::S));
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            Store<ST>::st(fout + i * nfp + u.idx, hC[i]);
-            Store<ST>::st(fout + (19 + i) * nfp + u.idx, hR[i]);
+            // opaque per store: keeps each store in the scalar-base form instead
+            // of a shared 64-bit vector address plus per-store 64-bit adds
+            opaque(own_b);
+            st_at(static_cast<S *>(out.p[dslot(i)]), own_b, Store<ST>::enc(hC[i]));
+            opaque(own_b);
+            st_at(static_cast<S *>(out.p[19 + dslot(i)]), own_b, Store<ST>::enc(hR[i]));
+        }
+        if (reservoir && (first_x || last_x)) {
+            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p[19]) + u.idx, nfp, first_x,
+                                               last_x);
+            acc[2] += f.in;
+            acc[3] += f.out;
         }
     }
-    block_sum<2>(acc, part + int64_t(blockIdx.x) * 2);
+    block_sum<4>(acc, part + int64_t(blockIdx.x) * 4);
 }
 
 template <int ST, bool LOCAL, typename OUT>
 __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store<ST>::T> ph,
-                                                 const typename Store<ST>::S *__restrict__ fin,
-                                                 const typename Store<ST>::T *__restrict__ emit, OUT *rho, OUT *vel,
+                                                 Slots in, const typename Store<ST>::S *__restrict__ emit,
+                                                 OUT *rho, OUT *vel,
                                                  OUT *conc) {
     using T = typename Store<ST>::T;
     const WaveUnit u = locate(g);
@@ -385,11 +528,11 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
         if (LOCAL) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                hC[i] = Store<ST>::ld(fin + i * g.nfp + u.idx);
-                hR[i] = Store<ST>::ld(fin + (19 + i) * g.nfp + u.idx);
+                hC[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[dslot(i)]) + u.idx);
+                hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[19 + dslot(i)]) + u.idx);
             }
         } else {
-            pull<ST>(g, ph, fin, emit, u, hC, hR);
+            pull<ST, -1>(g, ph, in, emit, u, hC, hR);
         }
         const Mom<T> m = moments(ph, hC, hR);
         r = m.rc;
@@ -417,21 +560,33 @@ __global__ __launch_bounds__(256) void k_init(Geometry g, PhysK<typename Store<S
                                                typename Store<ST>::S *__restrict__ post) {
     using T = typename Store<ST>::T;
     const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (n >= g.nfluid) return;
+    if (n >= g.nfp) return;
     T hC[19], hR[19];
+    if (n >= g.nfluid) {
+        // padding; the last element of each reactant array holds the inlet
+        // ghost population (normalised), which the sweep pulls at x = 0
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            Store<ST>::st(pre + dslot(i) * g.nfp + n, T(0));
+            Store<ST>::st(post + dslot(i) * g.nfp + n, T(0));
+            Store<ST>::st(pre + (19 + dslot(i)) * g.nfp + n, ph.h_inlet);
+            Store<ST>::st(post + (19 + dslot(i)) * g.nfp + n, ph.h_inlet);
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         hC[i] = ph.h0c;
         hR[i] = ph.h0r;
-        Store<ST>::st(pre + i * g.nfp + n, hC[i]);
-        Store<ST>::st(pre + (19 + i) * g.nfp + n, hR[i]);
+        Store<ST>::st(pre + dslot(i) * g.nfp + n, hC[i]);
+        Store<ST>::st(pre + (19 + dslot(i)) * g.nfp + n, hR[i]);
     }
     const Mom<T> m = moments(ph, hC, hR);
     collide(ph, m, hC, hR);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        Store<ST>::st(post + i * g.nfp + n, hC[i]);
-        Store<ST>::st(post + (19 + i) * g.nfp + n, hR[i]);
+        Store<ST>::st(post + dslot(i) * g.nfp + n, hC[i]);
+        Store<ST>::st(post + (19 + dslot(i)) * g.nfp + n, hR[i]);
     }
 }
 
@@ -447,7 +602,7 @@ __device__ __forceinline__ uint32_t rank_of(const Geometry &g, int row, int x, b
 template <int ST>
 __global__ __launch_bounds__(256) void k_interface(Geometry g, PhysK<typename Store<ST>::T> ph, Interface it,
                                                     const typename Store<ST>::S *__restrict__ fin,
-                                                    typename Store<ST>::T *__restrict__ emit,
+                                                    typename Store<ST>::S *__restrict__ emit,
                                                     double *__restrict__ part) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
@@ -470,66 +625,23 @@ __global__ __launch_bounds__(256) void k_interface(Geometry g, PhysK<typename St
                 zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
                 bool fl;
                 const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
-                const T h = Store<ST>::ld(finR + j * g.nfp + r);
+                const T h = Store<ST>::ld(finR + dslot(j) * g.nfp + r);
                 in += double(wgt<T>(j) * (h + ph.cref));
             }
         }
         it.acc[k] += in;
-        if (ph.sputter != SP_BOUNCEBACK) emit[v] = T(double(ph.keep) * in * it.scale[k]);
+        if (ph.sputter != SP_BOUNCEBACK) Store<ST>::st(emit + v, T(double(ph.keep) * in * it.scale[k]));
         arrived[0] = in;
     }
     block_sum<1>(arrived, part + blockIdx.x);
 }
 
-// Species crossing the reservoir planes during the coming streaming: influx
-// pulled from the inlet ghost, and what leaves through x = -1 and x = nx net
-// of what the outlet ghost returns.  One lane per x-row.
-template <int ST>
-__global__ __launch_bounds__(256) void k_xflux(Geometry g, PhysK<typename Store<ST>::T> ph, double c_inlet,
-                                                const typename Store<ST>::S *__restrict__ fin,
-                                                double *__restrict__ part) {
-    using T = typename Store<ST>::T;
-    using S = typename Store<ST>::S;
-    const int64_t rows = int64_t(g.ny) * g.nz;
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    double acc[2] = {0.0, 0.0};
-    if (r < rows) {
-        const S *finR = fin + 19 * g.nfp;
-        const int y = int(r % g.ny), z = int(r / g.ny);
-        bool fl;
-        const uint32_t r0 = rank_of(g, int(r), 0, &fl);
-        if (fl) {
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                if (CX[i] == 1) acc[0] += double(wgt<T>(i)) * c_inlet;
-                if (CX[i] == -1) acc[1] += double(wgt<T>(i) * (Store<ST>::ld(finR + i * g.nfp + r0) + ph.cref));
-            }
-        }
-        const uint32_t r1 = rank_of(g, int(r), g.nx - 1, &fl);
-        if (fl) {
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                if (CX[i] == 1) acc[1] += double(wgt<T>(i) * (Store<ST>::ld(finR + i * g.nfp + r1) + ph.cref));
-                if (CX[i] == -1) {
-                    int ys = y - CY[i], zs = z - CZ[i];
-                    ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
-                    zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
-                    bool mf;
-                    const uint32_t rm = rank_of(g, zs * g.ny + ys, g.nx - 1, &mf);
-                    const T h = mf ? Store<ST>::ld(finR + i * g.nfp + rm) : Store<ST>::ld(finR + opp(i) * g.nfp + r1);
-                    acc[1] -= double(wgt<T>(i) * (h + ph.cref));
-                }
-            }
-        }
-    }
-    block_sum<2>(acc, part + int64_t(blockIdx.x) * 2);
-}
-
-// Fixed-order sum of column `col` of a row-major [n][ncol] partial array.
-__device__ double column_sum(const double *p, int64_t n, int ncol, int col) {
+// Fixed-order sum over rows [r0, r1) of column `col` of a row-major
+// [n][ncol] partial array, by the whole block (thread-strided, then a tree).
+__device__ double column_sum(const double *p, int64_t r0, int64_t r1, int ncol, int col) {
     __shared__ double sh[256];
     double s = 0.0;
-    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) s += p[r * ncol + col];
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) s += p[r * ncol + col];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
@@ -541,23 +653,43 @@ __device__ double column_sum(const double *p, int64_t n, int ncol, int col) {
     return out;
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const double *ps, int64_t ns, const double *pi, int64_t ni,
-                                                 const double *pf, int64_t nf, double p, double p_stick,
+// First stage of the totals: block b folds its contiguous slice of rows of
+// each partial array into one row of `out` (fixed order, so deterministic).
+__global__ __launch_bounds__(256) void k_fold(const double *ps, int64_t ns, const double *pi, int64_t ni,
+                                              double *out) {
+    const int64_t b = blockIdx.x, nb = gridDim.x;
+    auto slice = [&](int64_t n, int64_t *r0, int64_t *r1) {
+        const int64_t per = (n + nb - 1) / nb;
+        *r0 = b * per < n ? b * per : n;
+        *r1 = (b + 1) * per < n ? (b + 1) * per : n;
+    };
+    int64_t r0, r1;
+    double v[NPART];
+    slice(ns, &r0, &r1);
+    v[PART_MASS_C] = column_sum(ps, r0, r1, 4, 0);
+    v[PART_MASS_R] = column_sum(ps, r0, r1, 4, 1);
+    v[PART_INFLUX] = column_sum(ps, r0, r1, 4, 2);
+    v[PART_OUTFLUX] = column_sum(ps, r0, r1, 4, 3);
+    slice(ni, &r0, &r1);
+    v[PART_IN] = column_sum(pi, r0, r1, 1, 0);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NPART; ++k) out[b * NPART + k] = v[k];
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double *folded, int64_t nb, double p, double p_stick,
                                                  DevTotals *tot) {
-    const double mc = column_sum(ps, ns, 2, 0);
-    const double mr = column_sum(ps, ns, 2, 1);
-    const double in = ni ? column_sum(pi, ni, 1, 0) : 0.0;
-    const double fin = nf ? column_sum(pf, nf, 2, 0) : 0.0;
-    const double fout = nf ? column_sum(pf, nf, 2, 1) : 0.0;
+    double v[NPART];
+    for (int k = 0; k < NPART; ++k) v[k] = column_sum(folded, 0, nb, NPART, k);
     if (threadIdx.x == 0) {
-        tot->mass_gas = mc;
-        tot->mass_species = mr;
-        tot->converted += p * p_stick * in;
-        tot->lost += (1.0 - p) * p_stick * in;
-        tot->influx += fin;
-        tot->outflux += fout;
+        tot->mass_gas = v[PART_MASS_C];
+        tot->mass_species = v[PART_MASS_R];
+        tot->converted += p * p_stick * v[PART_IN];
+        tot->lost += (1.0 - p) * p_stick * v[PART_IN];
+        tot->influx += v[PART_INFLUX];
+        tot->outflux += v[PART_OUTFLUX];
         tot->step += 1;
-        const double all = mc + mr + in + fin + fout;
+        double all = 0.0;
+        for (int k = 0; k < NPART; ++k) all += v[k];
         if (!(all - all == 0.0)) tot->nonfinite = 1;
     }
 }
@@ -585,17 +717,24 @@ int storage_bytes(int storage) {
     }
 }
 
-int64_t sweep_blocks(const Geometry &g) { return (int64_t(g.ny) * g.nz * g.W + 3) / 4; }
+int64_t sweep_blocks(const Geometry &g) { return (int64_t(g.units) + 3) / 4; }
+
+void build_order(int nx, int ny, int nz, int ytile, uint32_t *order) {
+    const int W = (nx + 63) / 64;
+    size_t k = 0;
+    for (int y0 = 0; y0 < ny; y0 += ytile)
+        for (int z = 0; z < nz; ++z)
+            for (int y = y0; y < y0 + ytile && y < ny; ++y)
+                for (int c = 0; c < W; ++c) order[k++] = uint32_t(y) | (uint32_t(z) << 12) | (uint32_t(c) << 24);
+}
 int64_t interface_blocks(int64_t n) { return n > 0 ? (n + 255) / 256 : 0; }
-int64_t xflux_blocks(const Geometry &g) { return (int64_t(g.ny) * g.nz + 255) / 256; }
 
 hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *post, hipStream_t s) {
     return dispatch(ph.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         using SS = typename Store<ST>::S;
         using T = typename Store<ST>::T;
-        const int64_t blocks = (g.nfluid + 255) / 256;
-        if (blocks == 0) return hipSuccess;
+        const int64_t blocks = (g.nfp + 255) / 256;
         hipLaunchKernelGGL(k_init<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph),
                            static_cast<SS *>(pre), static_cast<SS *>(post));
         return hipGetLastError();
@@ -610,22 +749,17 @@ hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interfac
         using SS = typename Store<ST>::S;
         using T = typename Store<ST>::T;
         hipLaunchKernelGGL(k_interface<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph), it,
-                           static_cast<const SS *>(fin), static_cast<T *>(emit), part);
+                           static_cast<const SS *>(fin), static_cast<SS *>(emit), part);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_xflux(const Geometry &g, const Physics &ph, const void *fin, double *part, int64_t blocks,
-                        hipStream_t s) {
-    if (blocks == 0) return hipSuccess;
-    return dispatch(ph.storage, [&](auto st) {
-        constexpr int ST = decltype(st)::value;
-        using SS = typename Store<ST>::S;
-        using T = typename Store<ST>::T;
-        hipLaunchKernelGGL(k_xflux<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph), ph.c_inlet,
-                           static_cast<const SS *>(fin), part);
-        return hipGetLastError();
-    });
+template <int ST>
+Slots slots_of(const Geometry &g, const void *buf) {
+    Slots sl;
+    using S = typename Store<ST>::S;
+    for (int k = 0; k < 38; ++k) sl.p[k] = static_cast<const S *>(buf) + int64_t(k) * g.nfp;
+    return sl;
 }
 
 hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
@@ -634,8 +768,18 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
         constexpr int ST = decltype(st)::value;
         using SS = typename Store<ST>::S;
         using T = typename Store<ST>::T;
-        hipLaunchKernelGGL(k_sweep<ST>, dim3(unsigned(sweep_blocks(g))), dim3(256), 0, s, g, to_kernel<T>(ph),
-                           static_cast<const SS *>(fin), static_cast<SS *>(fout), static_cast<const T *>(emit), part);
+        const Slots in = slots_of<ST>(g, fin);
+        OutSlots out;
+        for (int k = 0; k < 38; ++k) out.p[k] = static_cast<SS *>(fout) + int64_t(k) * g.nfp;
+        const dim3 grid(unsigned(sweep_blocks(g))), block(256);
+        const SS *e = static_cast<const SS *>(emit);
+        const PhysK<T> k = to_kernel<T>(ph);
+        if (ph.sputter == SP_UNIFORM)
+            hipLaunchKernelGGL((k_sweep<ST, SP_UNIFORM>), grid, block, 0, s, g, k, in, out, e, part);
+        else if (ph.sputter == SP_WEIGHTED)
+            hipLaunchKernelGGL((k_sweep<ST, SP_WEIGHTED>), grid, block, 0, s, g, k, in, out, e, part);
+        else
+            hipLaunchKernelGGL((k_sweep<ST, SP_BOUNCEBACK>), grid, block, 0, s, g, k, in, out, e, part);
         return hipGetLastError();
     });
 }
@@ -647,8 +791,8 @@ hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, 
         using SS = typename Store<ST>::S;
         using T = typename Store<ST>::T;
         const dim3 grid(unsigned(sweep_blocks(g))), block(256);
-        const SS *f = static_cast<const SS *>(fin);
-        const T *e = static_cast<const T *>(emit);
+        const Slots f = slots_of<ST>(g, fin);
+        const SS *e = static_cast<const SS *>(emit);
         const PhysK<T> k = to_kernel<T>(ph);
         if (out_f64) {
             double *a = static_cast<double *>(rho), *b = static_cast<double *>(u), *c = static_cast<double *>(conc);
@@ -668,10 +812,11 @@ hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, 
 }
 
 hipError_t launch_reduce(const double *part_sweep, int64_t n_sweep, const double *part_iface, int64_t n_iface,
-                         const double *part_flux, int64_t n_flux, double p, double p_stick, DevTotals *tot,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, part_sweep, n_sweep, part_iface, n_iface, part_flux,
-                       n_flux, p, p_stick, tot);
+                         double *fold, double p, double p_stick, DevTotals *tot, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold, dim3(FOLD_BLOCKS), dim3(256), 0, s, part_sweep, n_sweep, part_iface, n_iface, fold);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, fold, int64_t(FOLD_BLOCKS), p, p_stick, tot);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ SPUTTER_UNIFORM, SPUTTER_WEIGHTED, SPUTTER_BOUNCEBACK = 0, 1, 2
 COUPLE_PASSIVE, COUPLE_BARYCENTRIC = 0, 1
 XBC_PERIODIC, XBC_RESERVOIR = 0, 1
 STORE_F32, STORE_F16, STORE_BF16, STORE_F64 = 0, 1, 2, 3
+TUNE_YTILE = 0
 STORAGE_BYTES = {STORE_F32: 4, STORE_F16: 2, STORE_BF16: 2, STORE_F64: 8}
 STORAGE_NAMES = {STORE_F32: "f32", STORE_F16: "f16", STORE_BF16: "bf16", STORE_F64: "f64"}
 
@@ -107,6 +108,8 @@ def _load():
         "lbm_active_links": (st, [ctx, ctypes.c_void_p]),
         "lbm_synchronize": (st, [ctx]),
         "lbm_set_timing": (st, [ctx, ctypes.c_int32]),
+        "lbm_set_tunable": (st, [ctx, ctypes.c_int32, ctypes.c_int64]),
+        "lbm_get_tunable": (st, [ctx, ctypes.c_int32, P(ctypes.c_int64)]),
         "lbm_kernel_times": (st, [ctx, P(lbm_kernel_times_t)]),
         "lbm_save": (st, [ctx, ctypes.c_char_p]),
         "lbm_load": (st, [ctx, ctypes.c_char_p]),
@@ -266,6 +269,14 @@ class Sim:
         b = np.zeros(self.n, dtype=np.uint8)
         _check(_LIB.lbm_active_links(self._h, b.ctypes.data), self._h)
         return b.reshape(self.shape)
+
+    def set_tunable(self, which, value):
+        _check(_LIB.lbm_set_tunable(self._h, int(which), int(value)), self._h)
+
+    def get_tunable(self, which):
+        v = ctypes.c_int64()
+        _check(_LIB.lbm_get_tunable(self._h, int(which), ctypes.byref(v)), self._h)
+        return v.value
 
     def set_timing(self, on=True):
         _check(_LIB.lbm_set_timing(self._h, 1 if on else 0), self._h)
