@@ -64,6 +64,8 @@ struct lbm_ctx {
     uint32_t *d_order = nullptr;
     uint32_t *d_iface_vox = nullptr, *d_iface_mask = nullptr;
     double *d_iface_scale = nullptr, *d_acc = nullptr;
+    uint32_t *d_iface_start = nullptr, *d_link_map = nullptr, *d_link_base = nullptr;
+    void *d_link = nullptr;
     void *d_emit = nullptr;
     void *d_pop[2] = {nullptr, nullptr};
     double *d_part = nullptr;
@@ -134,6 +136,8 @@ Geometry geometry(const lbm_ctx *c) {
     Geometry g;
     g.chunks = c->d_chunks;
     g.order = c->d_order;
+    g.link_base = c->d_link_base;
+    g.link = c->d_link;
     g.nx = c->nx;
     g.ny = c->ny;
     g.nz = c->nz;
@@ -151,6 +155,9 @@ Interface interface_list(const lbm_ctx *c) {
     it.mask = c->d_iface_mask;
     it.scale = c->d_iface_scale;
     it.acc = c->d_acc;
+    it.start = c->d_iface_start;
+    it.map = c->d_link_map;
+    it.link = c->d_link;
     it.n = c->niface;
     return it;
 }
@@ -230,6 +237,43 @@ void build_interface(lbm_ctx *c, std::vector<uint32_t> &vox, std::vector<uint32_
             }
 }
 
+// Link-buffer layout.  The sweep exports every reactant population that
+// heads into a catalytic node: gas nodes in storage order ((z, y, x)), each
+// node's links in ascending direction.  link_base[chunk] is the first slot of
+// each 64-voxel chunk; map lists, per interface node and active link j
+// (ascending), the slot its arriving population is written to.
+void build_links(const lbm_ctx *c, const std::vector<uint32_t> &ivox, const std::vector<uint32_t> &imask,
+                 std::vector<uint32_t> &start, std::vector<uint32_t> &map, std::vector<uint32_t> &link_base) {
+    const bool xper = c->ph.species_x == XB_PERIODIC;
+    std::vector<int32_t> iface_of(size_t(c->n), -1);
+    for (size_t k = 0; k < ivox.size(); ++k) iface_of[ivox[k]] = int32_t(k);
+    start.assign(ivox.size() + 1, 0);
+    for (size_t k = 0; k < ivox.size(); ++k) start[k + 1] = start[k] + uint32_t(__builtin_popcount(imask[k]));
+    map.assign(start.back(), 0);
+    link_base.assign(size_t(int64_t(c->ny) * c->nz * c->W), 0);
+    uint32_t slot = 0;
+    for (int z = 0; z < c->nz; ++z)
+        for (int y = 0; y < c->ny; ++y)
+            for (int x = 0; x < c->nx; ++x) {
+                if ((x & 63) == 0) link_base[size_t((int64_t(z) * c->ny + y) * c->W + (x >> 6))] = slot;
+                if (c->vox[size_t((int64_t(z) * c->ny + y) * c->nx + x)] != LBM_FLUID) continue;
+                for (int i = 1; i < 19; ++i) {
+                    int xs = x - CX[i];
+                    if (xs < 0 || xs >= c->nx) {
+                        if (!xper) continue;  // reservoir ghost, not a catalytic source
+                        xs = (xs + c->nx) % c->nx;
+                    }
+                    const int ys = (y - CY[i] + c->ny) % c->ny, zs = (z - CZ[i] + c->nz) % c->nz;
+                    const int64_t src = (int64_t(zs) * c->ny + ys) * c->nx + xs;
+                    if (c->vox[size_t(src)] != LBM_CATALYTIC) continue;
+                    const int32_t k = iface_of[size_t(src)];
+                    const int j = opp(i);
+                    const uint32_t m = imask[size_t(k)];
+                    map[start[size_t(k)] + uint32_t(__builtin_popcount(m & ((1u << j) - 1u)))] = slot++;
+                }
+            }
+}
+
 lbm_status check_pending_flag(lbm_ctx *c) {
     if (c->flag_pending && hipEventQuery(c->flag_event) == hipSuccess) {
         c->flag_pending = false;
@@ -272,7 +316,7 @@ lbm_status one_step(lbm_ctx *c) {
     }
     hipError_t e;
     if (r) (void)hipEventRecord(r->ev[0], c->stream);
-    e = launch_interface(g, c->ph, interface_list(c), fin, c->d_emit, pi, c->blocks_iface, c->stream);
+    e = launch_interface(g, c->ph, interface_list(c), c->d_emit, pi, c->blocks_iface, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "interface kernel launch");
     if (r) (void)hipEventRecord(r->ev[1], c->stream);
     if (r) (void)hipEventRecord(r->ev[2], c->stream);  // no separate boundary-flux kernel:
@@ -414,6 +458,8 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         build_interface(c, ivox, imask, iscale);
         c->niface = int64_t(ivox.size());
         c->iface_vox = ivox;
+        std::vector<uint32_t> istart, lmap, lbase;
+        build_links(c, ivox, imask, istart, lmap, lbase);
 
         const Geometry gtmp = geometry(c);
         c->blocks_sweep = sweep_blocks(gtmp);
@@ -429,6 +475,10 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         c->d_iface_mask = static_cast<uint32_t *>(dev_alloc(c, imask.size() * 4));
         c->d_iface_scale = static_cast<double *>(dev_alloc(c, iscale.size() * 8));
         c->d_acc = static_cast<double *>(dev_alloc(c, size_t(c->niface) * 8));
+        c->d_iface_start = static_cast<uint32_t *>(dev_alloc(c, istart.size() * 4));
+        c->d_link_map = static_cast<uint32_t *>(dev_alloc(c, lmap.size() * 4));
+        c->d_link_base = static_cast<uint32_t *>(dev_alloc(c, lbase.size() * 4));
+        c->d_link = dev_alloc(c, lmap.size() * size_t(storage_bytes(c->ph.storage)));
         // One pool: population buffers A and B, then the emission array.  The
         // sweep addresses all three from one base with integer offsets, so the
         // emission array must start a whole number of direction strides (nfp
@@ -442,7 +492,8 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         const int64_t nparts = 4 * c->blocks_sweep + c->blocks_iface + FOLD_BLOCKS * NPART;
         c->d_part = static_cast<double *>(dev_alloc(c, size_t(nparts) * 8));
         c->d_tot = static_cast<DevTotals *>(dev_alloc(c, sizeof(DevTotals)));
-        if (!c->d_chunks || !c->d_order || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
+        if (!c->d_chunks || !c->d_order || !c->d_iface_start || !c->d_link_map || !c->d_link_base ||
+            !c->d_link || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
             !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot) {
             release(c);
             delete c;
@@ -457,6 +508,9 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         up(c->d_iface_vox, ivox.data(), ivox.size() * 4);
         up(c->d_iface_mask, imask.data(), imask.size() * 4);
         up(c->d_iface_scale, iscale.data(), iscale.size() * 8);
+        up(c->d_iface_start, istart.data(), istart.size() * 4);
+        up(c->d_link_map, lmap.data(), lmap.size() * 4);
+        up(c->d_link_base, lbase.data(), lbase.size() * 4);
         if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, size_t(c->n) * sb, c->stream);
         DevTotals t0{};
@@ -464,6 +518,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         t0.mass_species = double(c->nfluid) * bc->c0;
         up(c->d_tot, &t0, sizeof(t0));
         if (e == hipSuccess) e = launch_init(geometry(c), c->ph, c->d_pop[1], c->d_pop[0], c->stream);
+        if (e == hipSuccess) e = launch_export(geometry(c), c->ph, interface_list(c), c->d_pop[0], c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host vectors go out of scope
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->h_flag), sizeof(int32_t));
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->flag_event, hipEventDisableTiming);
@@ -791,10 +846,12 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
         e = hipMemcpyAsync(c->d_acc, buf.data() + 2 * pop + emit, size_t(c->niface) * 8, hipMemcpyHostToDevice,
                            c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_tot, &h.tot, sizeof(DevTotals), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "checkpoint upload");
     c->step = h.step;
     c->cur = int(h.cur);
+    // the link buffer is derived state: rebuild it from the current populations
+    if (e == hipSuccess) e = launch_export(geometry(c), c->ph, interface_list(c), c->d_pop[c->cur], c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "checkpoint upload");
     c->flag_pending = false;
     *c->h_flag = h.tot.nonfinite;
     return LBM_OK;

@@ -61,6 +61,8 @@ struct DevTotals {
 struct Geometry {
     const ChunkInfo *chunks;  // rows * W records, row = z * ny + y
     const uint32_t *order;    // sweep traversal: per wave y | z << 12 | chunk << 24
+    const uint32_t *link_base;  // per chunk (row * W + chunk): first link-buffer slot it exports
+    void *link;               // link buffer (storage type), see Interface
     int32_t nx, ny, nz, W;    // W = ceil(nx / 64)
     uint32_t units;           // ny * nz * W waves
     int32_t pad;
@@ -84,6 +86,9 @@ struct Interface {
     const uint32_t *mask;   // bit j (kernel direction numbering): j is an active link
     const double *scale;    // 1/b(k) (UNIFORM) or 1/sum_{active} w_opp(j) (WEIGHTED)
     double *acc;            // sum_t In(k, t)
+    const uint32_t *start;  // node k's links are map[start[k] .. start[k + 1]) (n + 1 entries)
+    const uint32_t *map;    // link-buffer slot of each (node, active link), links in ascending j
+    void *link;             // link buffer: arriving populations f*_j(k - c_j), stored form
     int64_t n;
 };
 
@@ -98,8 +103,9 @@ void build_order(int nx, int ny, int nz, int ytile, uint32_t *order);
 
 // All launchers queue on `stream` and return the launch status.
 hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *post, hipStream_t s);
-hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, const void *fin,
-                            void *emit, double *part, int64_t blocks, hipStream_t s);
+hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, void *emit, double *part,
+                            int64_t blocks, hipStream_t s);
+hipError_t launch_export(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s);
 hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
                         double *part, hipStream_t s);
 // mode 1: moments after streaming fin (fields at step >= 1); mode 2: local

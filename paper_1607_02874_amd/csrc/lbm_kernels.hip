@@ -236,7 +236,8 @@ __device__ __forceinline__ uint32_t rank_of_mask(uint64_t m, uint32_t add) {
 template <int ST, int SP>
 __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
                                      const typename Store<ST>::S *__restrict__ emit, const WaveUnit &u,
-                                     typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19]) {
+                                     typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
+                                     uint32_t &cat_out) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     constexpr uint32_t SB = sizeof(S);
@@ -344,6 +345,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
+    cat_out = cat_bits;
 }
 
 // Moments of both lattices and the equilibrium velocity.
@@ -450,6 +452,30 @@ struct InOut {
     double in, out;
 };
 
+// Sum over the lanes below this one of a small per-lane count (< 32): the
+// count's bits are ballotted and counted below the lane.
+__device__ __forceinline__ uint32_t lanes_below_sum(uint32_t count) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) s += rank_of_mask(__builtin_amdgcn_ballot_w64((count >> b) & 1u), 0u) << b;
+    return s;
+}
+
+// Write this lane's catalytic-link populations (ascending direction) to
+// consecutive link slots starting at `slot`.
+template <int ST>
+__device__ __forceinline__ void export_links(typename Store<ST>::S *link, uint32_t slot, uint32_t cat_bits,
+                                             const typename Store<ST>::T (&hR)[19]) {
+    using S = typename Store<ST>::S;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        if ((cat_bits >> i) & 1u) {
+            st_at(link, slot * uint32_t(sizeof(S)), Store<ST>::enc(hR[opp(i)]));
+            ++slot;
+        }
+    }
+}
+
 template <int ST>
 __device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double c_in,
                                              const typename Store<ST>::S *own, int64_t nfp, bool first_x,
@@ -478,7 +504,8 @@ __global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (u.active) {
         T hC[19], hR[19];
-        pull<ST, SP>(g, ph, in, emit, u, hC, hR);
+        uint32_t cat_bits;
+        pull<ST, SP>(g, ph, in, emit, u, hC, hR, cat_bits);
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
@@ -503,6 +530,16 @@ __global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<
             st_at(static_cast<S *>(out.p[dslot(i)]), own_b, Store<ST>::enc(hC[i]));
             opaque(own_b);
             st_at(static_cast<S *>(out.p[19 + dslot(i)]), own_b, Store<ST>::enc(hR[i]));
+        }
+        // Export the reactant populations that head into catalytic nodes
+        // (the reversed catalytic-source directions) to the link buffer for
+        // the next step's interface sum, as the same stored bits.  Layout:
+        // gas nodes in storage order, each node's links in ascending
+        // direction; this chunk's first slot comes from the host.
+        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
+            S *link = static_cast<S *>(g.link);
+            const uint32_t lb = g.link_base[uint32_t(u.row) * uint32_t(g.W) + uint32_t(u.chunk)];
+            export_links<ST>(link, lb + lanes_below_sum(uint32_t(__popc(cat_bits))), cat_bits, hR);
         }
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p[19]) + u.idx, nfp, first_x,
@@ -532,7 +569,8 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
                 hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[19 + dslot(i)]) + u.idx);
             }
         } else {
-            pull<ST, -1>(g, ph, in, emit, u, hC, hR);
+            uint32_t cat_bits;
+            pull<ST, -1>(g, ph, in, emit, u, hC, hR, cat_bits);
         }
         const Mom<T> m = moments(ph, hC, hR);
         r = m.rc;
@@ -598,10 +636,13 @@ __device__ __forceinline__ uint32_t rank_of(const Geometry &g, int row, int x, b
     return I.base + uint32_t(__popcll(below));
 }
 
-// Sputtering gather: In(k) over the active links of each interface node.
+// Sputtering sum: In(k) = sum_j f*_j(k - c_j) over the active links of each
+// interface node (first line of the sputtering equations).  The arriving
+// populations were written to the link buffer by the sweep that produced
+// them (or by k_export); node k's links sit at map[start[k] .. start[k+1])
+// in ascending direction order, so the sum order is fixed.
 template <int ST>
-__global__ __launch_bounds__(256) void k_interface(Geometry g, PhysK<typename Store<ST>::T> ph, Interface it,
-                                                    const typename Store<ST>::S *__restrict__ fin,
+__global__ __launch_bounds__(256) void k_interface(PhysK<typename Store<ST>::T> ph, Interface it,
                                                     typename Store<ST>::S *__restrict__ emit,
                                                     double *__restrict__ part) {
     using T = typename Store<ST>::T;
@@ -609,31 +650,56 @@ __global__ __launch_bounds__(256) void k_interface(Geometry g, PhysK<typename St
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double arrived[1] = {0.0};
     if (k < it.n) {
-        const uint32_t v = it.vox[k];
+        const S *link = static_cast<const S *>(it.link);
         const uint32_t mask = it.mask[k];
-        const int x = int(v % uint32_t(g.nx));
-        const int row = int(v / uint32_t(g.nx));
-        const int y = row % g.ny, z = row / g.ny;
-        const S *finR = fin + 19 * g.nfp;
+        const uint32_t s0 = it.start[k];
+        // all slot indices, then all values (latency paid twice, not per link)
+        uint32_t slot[19];
+        uint32_t t = s0;
+#pragma unroll
+        for (int j = 1; j < 19; ++j)
+            if (mask & (1u << j)) slot[j] = it.map[t++];
+        S raw[19];
+#pragma unroll
+        for (int j = 1; j < 19; ++j)
+            if (mask & (1u << j)) raw[j] = link[slot[j]];
         double in = 0.0;
 #pragma unroll
-        for (int j = 1; j < 19; ++j) {
-            if (mask & (1u << j)) {
-                int xs = x - CX[j], ys = y - CY[j], zs = z - CZ[j];
-                xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
-                ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
-                zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
-                bool fl;
-                const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
-                const T h = Store<ST>::ld(finR + dslot(j) * g.nfp + r);
-                in += double(wgt<T>(j) * (h + ph.cref));
-            }
-        }
+        for (int j = 1; j < 19; ++j)
+            if (mask & (1u << j)) in += double(wgt<T>(j) * (Store<ST>::cv(raw[j]) + ph.cref));
         it.acc[k] += in;
-        if (ph.sputter != SP_BOUNCEBACK) Store<ST>::st(emit + v, T(double(ph.keep) * in * it.scale[k]));
+        if (ph.sputter != SP_BOUNCEBACK) Store<ST>::st(emit + it.vox[k], T(double(ph.keep) * in * it.scale[k]));
         arrived[0] = in;
     }
     block_sum<1>(arrived, part + blockIdx.x);
+}
+
+// Fill the link buffer from a population buffer (after create and after a
+// checkpoint load; during stepping the sweep writes it).
+template <int ST>
+__global__ __launch_bounds__(256) void k_export(Geometry g, PhysK<typename Store<ST>::T> ph, Interface it,
+                                                 const typename Store<ST>::S *__restrict__ fin) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= it.n) return;
+    const uint32_t v = it.vox[k];
+    const uint32_t mask = it.mask[k];
+    const int x = int(v % uint32_t(g.nx));
+    const int row = int(v / uint32_t(g.nx));
+    const int y = row % g.ny, z = row / g.ny;
+    typename Store<ST>::S *link = static_cast<typename Store<ST>::S *>(it.link);
+    uint32_t t = it.start[k];
+#pragma unroll
+    for (int j = 1; j < 19; ++j) {
+        if (mask & (1u << j)) {
+            int xs = x - CX[j], ys = y - CY[j], zs = z - CZ[j];
+            xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+            ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+            zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
+            bool fl;
+            const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
+            link[it.map[t++]] = fin[(19 + dslot(j)) * g.nfp + r];
+        }
+    }
 }
 
 // Fixed-order sum over rows [r0, r1) of column `col` of a row-major
@@ -741,15 +807,28 @@ hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *po
     });
 }
 
-hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, void *emit,
-                            double *part, int64_t blocks, hipStream_t s) {
+hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, void *emit, double *part,
+                            int64_t blocks, hipStream_t s) {
     if (blocks == 0) return hipSuccess;
     return dispatch(ph.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         using SS = typename Store<ST>::S;
         using T = typename Store<ST>::T;
-        hipLaunchKernelGGL(k_interface<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph), it,
-                           static_cast<const SS *>(fin), static_cast<SS *>(emit), part);
+        hipLaunchKernelGGL(k_interface<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, to_kernel<T>(ph), it,
+                           static_cast<SS *>(emit), part);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_export(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s) {
+    const int64_t blocks = interface_blocks(it.n);
+    if (blocks == 0) return hipSuccess;
+    return dispatch(ph.storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        using SS = typename Store<ST>::S;
+        using T = typename Store<ST>::T;
+        hipLaunchKernelGGL(k_export<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph), it,
+                           static_cast<const SS *>(fin));
         return hipGetLastError();
     });
 }
