@@ -47,6 +47,27 @@ def algorithmic_bytes(info, s):
     return {"sweep": sweep, "interface": iface, "step": sweep + iface}
 
 
+def measured_traffic(kernel, workload, storage_name):
+    """Calibrated HBM bytes per launch from the PMC record in profiles/traffic.json,
+    or None when there is no record for this kernel, workload and storage, or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+        if not rec or rec["workload"] != workload or rec["storage"] != storage_name:
+            return None
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return int(rec["fetch_kib_per_dispatch"] * 1024 * rec["fetch_scale"]
+                   + rec["write_kib_per_dispatch"] * 1024 * rec["write_scale"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(vox256, w, steps):
     """Time the FP64 oracle on the 64^3 crop of the same geometry."""
     import oracle
@@ -174,7 +195,8 @@ def main():
         t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
         achieved = ab["sweep"] / t_sweep / 1e9
         roofline = {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("k_sweep", w.name, args.storage),
                     "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2)}
     kernels = None
     if kt:
