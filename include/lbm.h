@@ -254,6 +254,45 @@ const char *lbm_last_error(const lbm_ctx *c);
 /* Release the context and its device memory.  NULL is a no-op. */
 void lbm_destroy(lbm_ctx *c);
 
+/*
+ * Batches: many independent samples (each a full context: its own geometry,
+ * Kn, Da, tau and boundary options) advanced together, one launch per kernel
+ * per step for the whole batch instead of one per sample.  Every sample
+ * evolves exactly as it would alone (same kernels and summation order), so
+ * its fields, conversion map and totals are bit-identical to a single
+ * context created with the same arguments and stepped as often.
+ *
+ * lbm_batch_create - n >= 1 samples; sample i takes g[i], kn[i] (kn may be
+ *       NULL: all "not given"), da[i], tau[i] and bc[i] with the meaning of
+ *       lbm_create.  bc[i].storage, .sputter, .coupling and .species_x must
+ *       be equal for all samples (LBM_EINVAL otherwise).  dev as in
+ *       lbm_create_on; every sample and the batch use its stream.  A failed
+ *       create releases everything, sets *out = NULL and leaves a message
+ *       naming the sample in lbm_batch_last_error(NULL).
+ * lbm_batch_step - advance every sample n >= 0 steps (asynchronous).  With
+ *       graphs enabled (lbm_batch_set_graph) pairs of steps replay one
+ *       captured HIP graph.  LBM_ENONFINITE as for lbm_step, with the sample
+ *       named in the message.
+ * lbm_batch_fields / _conversion_map / _totals / _query - lbm_fields,
+ *       lbm_conversion_map, lbm_totals and lbm_query of sample i
+ *       (0 <= i < n, LBM_EINVAL otherwise).
+ * lbm_batch_set_graph - 1: capture the step in a HIP graph on first use and
+ *       replay it; 0 (default): launch directly.  Results are identical.
+ */
+typedef struct lbm_batch lbm_batch;
+lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, const double *da,
+                            const double (*tau)[2], const lbm_bc *bc, const lbm_device *dev,
+                            lbm_batch **out);
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
+lbm_status lbm_batch_fields(lbm_batch *b, int32_t i, double *rho, double *u, double *conc);
+lbm_status lbm_batch_conversion_map(lbm_batch *b, int32_t i, double *conv);
+lbm_status lbm_batch_totals(lbm_batch *b, int32_t i, lbm_totals_t *t);
+lbm_status lbm_batch_query(const lbm_batch *b, int32_t i, lbm_info *info);
+lbm_status lbm_batch_synchronize(lbm_batch *b);
+lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t enable);
+const char *lbm_batch_last_error(const lbm_batch *b);
+void lbm_batch_destroy(lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -461,6 +461,19 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         std::vector<uint32_t> istart, lmap, lbase;
         build_links(c, ivox, imask, istart, lmap, lbase);
 
+        // The kernels address every buffer with 32-bit byte offsets from a
+        // scalar base: a population pair (2 nfp elements), the emission array
+        // (n elements) and the link buffer must each stay below 4 GiB.
+        {
+            const uint64_t sbytes = uint64_t(storage_bytes(c->ph.storage)), lim = uint64_t(1) << 32;
+            if (2 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(c->n) * sbytes >= lim ||
+                uint64_t(lmap.size()) * sbytes >= lim) {
+                release(c);
+                delete c;
+                return fail(nullptr, LBM_EUNSUPPORTED,
+                            "lattice too large for this storage type (a buffer would exceed 4 GiB of 32-bit offsets)");
+            }
+        }
         const Geometry gtmp = geometry(c);
         c->blocks_sweep = sweep_blocks(gtmp);
         c->blocks_iface = interface_blocks(c->niface);
@@ -864,6 +877,320 @@ void lbm_destroy(lbm_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     release(c);
     delete c;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+
+struct lbm_batch {
+    std::vector<lbm_ctx *> ctx;
+    lbm_device dev{};
+    hipStream_t stream = nullptr;
+    int storage = 0, sputter = 0;
+    std::vector<void *> allocations;
+    void *d_records = nullptr;
+    ReduceK *d_reduce = nullptr;
+    uint32_t *d_sweep_sample = nullptr, *d_iface_sample = nullptr;
+    int64_t sweep_blocks_total = 0, iface_blocks_total = 0;
+    int parity = 0;
+    bool use_graph = false;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // two steps starting at buffer parity 0 / 1
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_create_error;
+
+lbm_status bfail(lbm_batch *b, lbm_status s, const std::string &msg) {
+    if (b)
+        b->err = msg;
+    else
+        g_batch_create_error = msg;
+    return s;
+}
+
+void batch_release(lbm_batch *b) {
+    if (b->stream || !b->ctx.empty()) (void)hipStreamSynchronize(b->stream);
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+    }
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (void *p : b->allocations) {
+        if (b->dev.free)
+            b->dev.free(p, b->dev.user);
+        else
+            (void)hipFree(p);
+    }
+    b->allocations.clear();
+    for (lbm_ctx *c : b->ctx) lbm_destroy(c);
+    b->ctx.clear();
+}
+
+void *batch_alloc(lbm_batch *b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (b->dev.alloc)
+        p = b->dev.alloc(bytes, b->dev.user);
+    else if (hipMalloc(&p, bytes) != hipSuccess)
+        p = nullptr;
+    if (p) b->allocations.push_back(p);
+    return p;
+}
+
+lbm_status batch_launch(lbm_batch *b, int parity, hipStream_t s) {
+    hipError_t e = launch_batch_step(b->storage, b->sputter, b->d_records, b->d_sweep_sample, b->sweep_blocks_total,
+                                     b->d_iface_sample, b->iface_blocks_total, b->d_reduce, int(b->ctx.size()),
+                                     parity, s);
+    if (e != hipSuccess) return bfail(b, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
+                                      std::string("batch step launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// Capture two consecutive steps starting at buffer parity `parity` on a
+// private stream; the executable graph is later launched on the batch stream.
+lbm_status batch_capture(lbm_batch *b, int parity) {
+    hipError_t e = hipSuccess;
+    if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    lbm_status st = batch_launch(b, parity, b->capture);
+    if (st == LBM_OK) st = batch_launch(b, 1 - parity, b->capture);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->capture, &g);
+    if (st != LBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[parity], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        b->exec[parity] = nullptr;
+        return bfail(b, LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    b->graph[parity] = g;
+    return LBM_OK;
+}
+
+lbm_status batch_sample(lbm_batch *b, int32_t i, lbm_ctx **c) {
+    if (!b) return LBM_EINVAL;
+    if (i < 0 || size_t(i) >= b->ctx.size()) return bfail(b, LBM_EINVAL, "sample index out of range");
+    *c = b->ctx[size_t(i)];
+    return LBM_OK;
+}
+
+lbm_status batch_forward(lbm_batch *b, int32_t i, lbm_status st) {
+    if (st != LBM_OK) b->err = "sample " + std::to_string(i) + ": " + b->ctx[size_t(i)]->err;
+    return st;
+}
+
+}  // namespace
+
+lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, const double *da,
+                            const double (*tau)[2], const lbm_bc *bc, const lbm_device *dev, lbm_batch **out) {
+    if (!out) return bfail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1) return bfail(nullptr, LBM_EINVAL, "a batch needs n >= 1 samples");
+    if (!g || !da || !tau || !bc) return bfail(nullptr, LBM_EINVAL, "g, da, tau and bc must not be NULL");
+    for (int32_t i = 1; i < n; ++i)
+        if (bc[i].storage != bc[0].storage || bc[i].sputter != bc[0].sputter || bc[i].coupling != bc[0].coupling ||
+            bc[i].species_x != bc[0].species_x)
+            return bfail(nullptr, LBM_EINVAL,
+                         "sample " + std::to_string(i) + ": storage, sputter, coupling and species_x must match sample 0");
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return bfail(nullptr, LBM_ENOMEM, "host allocation failed");
+    if (dev) b->dev = *dev;
+    b->stream = static_cast<hipStream_t>(b->dev.stream);
+    b->storage = bc[0].storage;
+    b->sputter = bc[0].sputter;
+    try {
+        b->ctx.reserve(size_t(n));
+        for (int32_t i = 0; i < n; ++i) {
+            lbm_ctx *c = nullptr;
+            lbm_status st = lbm_create_on(&g[i], kn ? kn[i] : 0.0, da[i], tau[i], &bc[i], dev, &c);
+            if (st != LBM_OK) {
+                std::string msg = "sample " + std::to_string(i) + ": " + g_create_error;
+                batch_release(b);
+                delete b;
+                return bfail(nullptr, st, msg);
+            }
+            b->ctx.push_back(c);
+        }
+        // Logical block ranges: samples in order, each with its single-sample
+        // block count.
+        std::vector<BatchSample> smp(static_cast<size_t>(n));
+        std::vector<ReduceK> red(static_cast<size_t>(n));
+        int64_t nb = 0, ni = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            lbm_ctx *c = b->ctx[size_t(i)];
+            BatchSample &s = smp[size_t(i)];
+            s.g = geometry(c);
+            s.it = interface_list(c);
+            s.ph = c->ph;
+            s.pop[0] = c->d_pop[0];
+            s.pop[1] = c->d_pop[1];
+            s.emit = c->d_emit;
+            s.part_sweep = c->d_part;
+            s.part_iface = c->d_part + 4 * c->blocks_sweep;
+            s.block0 = uint32_t(nb);
+            s.iblock0 = uint32_t(ni);
+            nb += c->blocks_sweep;
+            ni += c->blocks_iface;
+            ReduceK &r = red[size_t(i)];
+            r.ps = s.part_sweep;
+            r.ns = c->blocks_sweep;
+            r.pi = s.part_iface;
+            r.ni = c->blocks_iface;
+            r.fold = s.part_iface + c->blocks_iface;
+            r.p = c->ph.p;
+            r.p_stick = c->ph.p_stick;
+            r.tot = c->d_tot;
+        }
+        if (nb >= (int64_t(1) << 31) || ni >= (int64_t(1) << 31)) {
+            batch_release(b);
+            delete b;
+            return bfail(nullptr, LBM_EINVAL, "batch too large for one launch");
+        }
+        b->sweep_blocks_total = nb;
+        b->iface_blocks_total = ni;
+        std::vector<uint32_t> sweep_sample(size_t(std::max<int64_t>(nb, 1))), iface_sample(size_t(std::max<int64_t>(ni, 1)));
+        for (int32_t i = 0; i < n; ++i) {
+            const lbm_ctx *c = b->ctx[size_t(i)];
+            std::fill_n(sweep_sample.begin() + smp[size_t(i)].block0, c->blocks_sweep, uint32_t(i));
+            std::fill_n(iface_sample.begin() + smp[size_t(i)].iblock0, c->blocks_iface, uint32_t(i));
+        }
+        b->d_records = batch_alloc(b, batch_record_bytes(b->storage) * size_t(n));
+        b->d_reduce = static_cast<ReduceK *>(batch_alloc(b, sizeof(ReduceK) * size_t(n)));
+        b->d_sweep_sample = static_cast<uint32_t *>(batch_alloc(b, sweep_sample.size() * 4));
+        b->d_iface_sample = static_cast<uint32_t *>(batch_alloc(b, iface_sample.size() * 4));
+        if (!b->d_records || !b->d_reduce || !b->d_sweep_sample || !b->d_iface_sample) {
+            batch_release(b);
+            delete b;
+            return bfail(nullptr, LBM_ENOMEM, "device allocation failed");
+        }
+        hipError_t e = batch_upload(b->storage, smp.data(), n, b->d_records, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_reduce, red.data(), red.size() * sizeof(ReduceK), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_sweep_sample, sweep_sample.data(), sweep_sample.size() * 4, hipMemcpyHostToDevice,
+                               b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_iface_sample, iface_sample.data(), iface_sample.size() * 4, hipMemcpyHostToDevice,
+                               b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) {
+            std::string msg = std::string("batch upload: ") + hipGetErrorString(e);
+            batch_release(b);
+            delete b;
+            return bfail(nullptr, LBM_EDEVICE, msg);
+        }
+    } catch (const std::bad_alloc &) {
+        batch_release(b);
+        delete b;
+        return bfail(nullptr, LBM_ENOMEM, "host allocation failed");
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
+    if (!b) return LBM_EINVAL;
+    if (n < 0) return bfail(b, LBM_EINVAL, "n must be >= 0");
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        const lbm_status st = check_pending_flag(b->ctx[i]);
+        if (st != LBM_OK) return batch_forward(b, int32_t(i), st);
+    }
+    int64_t done = 0;
+    lbm_status failed = LBM_OK;
+    if (b->use_graph) {
+        while (done + 2 <= n) {
+            if (!b->exec[b->parity]) {
+                failed = batch_capture(b, b->parity);
+                if (failed != LBM_OK) break;
+            }
+            const hipError_t e = hipGraphLaunch(b->exec[b->parity], b->stream);
+            if (e != hipSuccess) {
+                failed = bfail(b, LBM_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+                break;
+            }
+            done += 2;
+        }
+    }
+    for (; failed == LBM_OK && done < n; ++done) {
+        failed = batch_launch(b, b->parity, b->stream);
+        if (failed != LBM_OK) break;
+        b->parity = 1 - b->parity;
+    }
+    n = done;  // the steps actually queued
+    // two-step graph replays leave the parity unchanged; the per-sample
+    // contexts track the same parity and step count
+    for (lbm_ctx *c : b->ctx) {
+        c->cur = b->parity;
+        c->step += n;
+    }
+    if (n > 0) {
+        for (size_t i = 0; i < b->ctx.size(); ++i) {
+            lbm_ctx *c = b->ctx[i];
+            hipError_t e = hipMemcpyAsync(c->h_flag, &c->d_tot->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                          b->stream);
+            if (e == hipSuccess) e = hipEventRecord(c->flag_event, b->stream);
+            if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("watchdog copy: ") + hipGetErrorString(e));
+            c->flag_pending = true;
+        }
+    }
+    return failed;
+}
+
+lbm_status lbm_batch_fields(lbm_batch *b, int32_t i, double *rho, double *u, double *conc) {
+    lbm_ctx *c = nullptr;
+    lbm_status st = batch_sample(b, i, &c);
+    return st != LBM_OK ? st : batch_forward(b, i, lbm_fields(c, rho, u, conc));
+}
+
+lbm_status lbm_batch_conversion_map(lbm_batch *b, int32_t i, double *conv) {
+    lbm_ctx *c = nullptr;
+    lbm_status st = batch_sample(b, i, &c);
+    return st != LBM_OK ? st : batch_forward(b, i, lbm_conversion_map(c, conv));
+}
+
+lbm_status lbm_batch_totals(lbm_batch *b, int32_t i, lbm_totals_t *t) {
+    lbm_ctx *c = nullptr;
+    lbm_status st = batch_sample(b, i, &c);
+    return st != LBM_OK ? st : batch_forward(b, i, lbm_totals(c, t));
+}
+
+lbm_status lbm_batch_query(const lbm_batch *b, int32_t i, lbm_info *info) {
+    if (!b || i < 0 || size_t(i) >= b->ctx.size()) return LBM_EINVAL;
+    return lbm_query(b->ctx[size_t(i)], info);
+}
+
+lbm_status lbm_batch_synchronize(lbm_batch *b) {
+    if (!b) return LBM_EINVAL;
+    const hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("synchronize: ") + hipGetErrorString(e));
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        const lbm_status st = check_pending_flag(b->ctx[i]);
+        if (st != LBM_OK) return batch_forward(b, int32_t(i), st);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t enable) {
+    if (!b) return LBM_EINVAL;
+    if (enable != 0 && enable != 1) return bfail(b, LBM_EINVAL, "enable must be 0 or 1");
+    b->use_graph = enable == 1;
+    return LBM_OK;
+}
+
+const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : g_batch_create_error.c_str(); }
+
+void lbm_batch_destroy(lbm_batch *b) {
+    if (!b) return;
+    batch_release(b);
+    delete b;
 }
 
 }  // extern "C"

@@ -123,4 +123,38 @@ hipError_t launch_reduce(const double *part_sweep, int64_t n_sweep, const double
 int64_t sweep_blocks(const Geometry &g);
 int64_t interface_blocks(int64_t n);
 
+// One sample of a batch as the host describes it.  block0 / iblock0 are the
+// first global logical sweep / interface blocks of the sample; its blocks use
+// part_sweep / part_iface exactly as a single-sample step does.
+struct BatchSample {
+    Geometry g;
+    Interface it;
+    Physics ph;
+    void *pop[2];
+    void *emit;
+    double *part_sweep, *part_iface;
+    uint32_t block0, iblock0;
+};
+
+// Per-sample inputs of the batched reduction (same two stages as launch_reduce).
+struct ReduceK {
+    const double *ps;
+    int64_t ns;
+    const double *pi;
+    int64_t ni;
+    double *fold;
+    double p, p_stick;
+    DevTotals *tot;
+};
+
+// Size of one device record of a batch sample, and the upload of n records
+// built from `smp` (synchronous on `s`).
+size_t batch_record_bytes(int storage);
+hipError_t batch_upload(int storage, const BatchSample *smp, int n, void *d_records, hipStream_t s);
+// One step of every sample: batched interface, sweep (reading population
+// buffer `parity` of every sample, writing the other) and reduction.
+hipError_t launch_batch_step(int storage, int sputter, const void *d_records, const uint32_t *sweep_sample,
+                             int64_t sweep_blocks_total, const uint32_t *iface_sample, int64_t iface_blocks_total,
+                             const ReduceK *d_reduce, int n, int parity, hipStream_t s);
+
 }  // namespace lbmk

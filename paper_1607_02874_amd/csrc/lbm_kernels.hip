@@ -25,7 +25,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <type_traits>
+#include <vector>
 
 #include "lbm_internal.h"
 
@@ -119,6 +121,13 @@ PhysK<T> to_kernel(const Physics &p) {
 }
 
 // ------------------------------------------------------------ helpers --
+// Every buffer lives in device global memory; saying so lets the compiler use
+// global (not flat) instructions also for pointers read from a batch record.
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ LBM_GLOBAL T *glb(T *p) {
+    return (LBM_GLOBAL T *)(p);
+}
 // Keep a selected value opaque to the optimizer (no instruction is emitted):
 // stops it from folding a select into the address arithmetic and turning the
 // select back into divergent branches.
@@ -154,7 +163,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int k = 0; k < NV; ++k) out[k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
+        for (int k = 0; k < NV; ++k) glb(out)[k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
 }
 
 // Where a wavefront sits: which row and chunk, and this lane's node.
@@ -173,22 +182,22 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
-__device__ __forceinline__ WaveUnit locate(const Geometry &g) {
+__device__ __forceinline__ WaveUnit locate(const Geometry &g, uint32_t block) {
     // The traversal order (which x-row chunk each wave takes) is a host-built
     // table of codes y | z << 12 | chunk << 24, one per wave, read with one
-    // scalar load.
+    // scalar load.  `block` is the logical block (after the XCD remap).
     WaveUnit u;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const uint32_t unit = uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))) * 4u + uint32_t(wave);
+    const uint32_t unit = block * 4u + uint32_t(wave);
     u.valid = unit < g.units;
-    const uint32_t code = g.order[u.valid ? unit : 0u];
+    const uint32_t code = glb(g.order)[u.valid ? unit : 0u];
     u.y = int(code & 0xfffu);
     u.z = int((code >> 12) & 0xfffu);
     u.chunk = int(code >> 24);
     u.row = u.z * g.ny + u.y;
     u.lane = int(threadIdx.x & 63);
     u.x = u.chunk * 64 + u.lane;
-    const ChunkInfo &I = g.chunks[uint32_t(u.row) * uint32_t(g.W) + uint32_t(u.chunk)];
+    const LBM_GLOBAL ChunkInfo &I = glb(g.chunks)[uint32_t(u.row) * uint32_t(g.W) + uint32_t(u.chunk)];
     const uint64_t fl = I.fluid;
     u.active = u.valid && u.x < g.nx && ((fl >> u.lane) & 1u);
     u.idx = I.base + bits_below_lane(fl);
@@ -200,11 +209,11 @@ __device__ __forceinline__ WaveUnit locate(const Geometry &g) {
 // so no per-lane 64-bit address arithmetic is needed.
 template <typename S>
 __device__ __forceinline__ S ld_at(const S *base, uint32_t byte_off) {
-    return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + byte_off);
+    return *(const LBM_GLOBAL S *)((const LBM_GLOBAL char *)(base) + byte_off);
 }
 template <typename S>
 __device__ __forceinline__ void st_at(S *base, uint32_t byte_off, S v) {
-    *reinterpret_cast<S *>(reinterpret_cast<char *>(base) + byte_off) = v;
+    *(LBM_GLOBAL S *)((LBM_GLOBAL char *)(base) + byte_off) = v;
 }
 
 // Base address of each direction array of a population buffer (carrier
@@ -262,7 +271,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     rc[0] = ld_at(base(dslot(0)), own_b);
     rr[0] = ld_at(base(19 + dslot(0)), own_b);
     // the nine source rows (wave-uniform): chunk record and first voxel
-    const ChunkInfo *recs[9];
+    const LBM_GLOBAL ChunkInfo *recs[9];
     uint32_t row_vox[9];
 #pragma unroll
     for (int cy = -1; cy <= 1; ++cy) {
@@ -273,7 +282,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
             int zs = u.z - cz;
             zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
             const uint32_t r = uint32_t(__builtin_amdgcn_readfirstlane(zs * g.ny + ys));
-            recs[(cy + 1) * 3 + cz + 1] = g.chunks + (r * uint32_t(g.W) + uint32_t(u.chunk));
+            recs[(cy + 1) * 3 + cz + 1] = glb(g.chunks) + (r * uint32_t(g.W) + uint32_t(u.chunk));
             row_vox[(cy + 1) * 3 + cz + 1] = r * uint32_t(g.nx);
         }
     }
@@ -282,7 +291,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const int i = ORDER[k];
         const int cx = CX[i];
         // source row of this direction and its chunk record
-        const ChunkInfo &I = *recs[(CY[i] + 1) * 3 + CZ[i] + 1];
+        const LBM_GLOBAL ChunkInfo &I = *recs[(CY[i] + 1) * 3 + CZ[i] + 1];
         const uint32_t rv = row_vox[(CY[i] + 1) * 3 + CZ[i] + 1];
         // F / C: the source x - cx of each lane is gas / catalytic; rank: its
         // storage index when gas.
@@ -493,13 +502,16 @@ __device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double
     return InOut{fin, fout};
 }
 
+// One block of the fused sweep: logical block `block` of the sample described
+// by g / ph, reading `in` and writing `out`; its four partial sums go to row
+// `block` of `part`.
 template <int ST, int SP>
-__global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
-                                                const typename Store<ST>::S *__restrict__ emit,
-                                                double *__restrict__ part) {
+__device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
+                                            const OutSlots &out, const typename Store<ST>::S *__restrict__ emit,
+                                            double *__restrict__ part, uint32_t block) {
     using S = typename Store<ST>::S;
     using T = typename Store<ST>::T;
-    const WaveUnit u = locate(g);
+    const WaveUnit u = locate(g, block);
     // per-block partials: carrier mass, reactant mass, influx, outflux
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (u.active) {
@@ -538,7 +550,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<
         // direction; this chunk's first slot comes from the host.
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
             S *link = static_cast<S *>(g.link);
-            const uint32_t lb = g.link_base[uint32_t(u.row) * uint32_t(g.W) + uint32_t(u.chunk)];
+            const uint32_t lb = glb(g.link_base)[uint32_t(u.row) * uint32_t(g.W) + uint32_t(u.chunk)];
             export_links<ST>(link, lb + lanes_below_sum(uint32_t(__popc(cat_bits))), cat_bits, hR);
         }
         if (reservoir && (first_x || last_x)) {
@@ -548,7 +560,14 @@ __global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<
             acc[3] += f.out;
         }
     }
-    block_sum<4>(acc, part + int64_t(blockIdx.x) * 4);
+    block_sum<4>(acc, part + int64_t(block) * 4);
+}
+
+template <int ST, int SP>
+__global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
+                                                const typename Store<ST>::S *__restrict__ emit,
+                                                double *__restrict__ part) {
+    sweep_block<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
 }
 
 template <int ST, bool LOCAL, typename OUT>
@@ -557,7 +576,7 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
                                                  OUT *rho, OUT *vel,
                                                  OUT *conc) {
     using T = typename Store<ST>::T;
-    const WaveUnit u = locate(g);
+    const WaveUnit u = locate(g, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
     if (!u.valid || u.x >= g.nx) return;
     T r = 0, ux = 0, uy = 0, uz = 0, c = 0;
     if (u.active) {
@@ -642,23 +661,23 @@ __device__ __forceinline__ uint32_t rank_of(const Geometry &g, int row, int x, b
 // them (or by k_export); node k's links sit at map[start[k] .. start[k+1])
 // in ascending direction order, so the sum order is fixed.
 template <int ST>
-__global__ __launch_bounds__(256) void k_interface(PhysK<typename Store<ST>::T> ph, Interface it,
-                                                    typename Store<ST>::S *__restrict__ emit,
-                                                    double *__restrict__ part) {
+__device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::T> &ph, const Interface &it,
+                                                typename Store<ST>::S *__restrict__ emit, double *__restrict__ part,
+                                                uint32_t block) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
-    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t k = int64_t(block) * blockDim.x + threadIdx.x;
     double arrived[1] = {0.0};
     if (k < it.n) {
-        const S *link = static_cast<const S *>(it.link);
-        const uint32_t mask = it.mask[k];
-        const uint32_t s0 = it.start[k];
+        const LBM_GLOBAL S *link = glb(static_cast<const S *>(it.link));
+        const uint32_t mask = glb(it.mask)[k];
+        const uint32_t s0 = glb(it.start)[k];
         // all slot indices, then all values (latency paid twice, not per link)
         uint32_t slot[19];
         uint32_t t = s0;
 #pragma unroll
         for (int j = 1; j < 19; ++j)
-            if (mask & (1u << j)) slot[j] = it.map[t++];
+            if (mask & (1u << j)) slot[j] = glb(it.map)[t++];
         S raw[19];
 #pragma unroll
         for (int j = 1; j < 19; ++j)
@@ -667,11 +686,20 @@ __global__ __launch_bounds__(256) void k_interface(PhysK<typename Store<ST>::T> 
 #pragma unroll
         for (int j = 1; j < 19; ++j)
             if (mask & (1u << j)) in += double(wgt<T>(j) * (Store<ST>::cv(raw[j]) + ph.cref));
-        it.acc[k] += in;
-        if (ph.sputter != SP_BOUNCEBACK) Store<ST>::st(emit + it.vox[k], T(double(ph.keep) * in * it.scale[k]));
+        glb(it.acc)[k] += in;
+        if (ph.sputter != SP_BOUNCEBACK)
+            st_at(emit, glb(it.vox)[k] * uint32_t(sizeof(S)),
+                  Store<ST>::enc(T(double(ph.keep) * in * glb(it.scale)[k])));
         arrived[0] = in;
     }
-    block_sum<1>(arrived, part + blockIdx.x);
+    block_sum<1>(arrived, part + block);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_interface(PhysK<typename Store<ST>::T> ph, Interface it,
+                                                    typename Store<ST>::S *__restrict__ emit,
+                                                    double *__restrict__ part) {
+    interface_block<ST>(ph, it, emit, part, blockIdx.x);
 }
 
 // Fill the link buffer from a population buffer (after create and after a
@@ -721,9 +749,8 @@ __device__ double column_sum(const double *p, int64_t r0, int64_t r1, int ncol, 
 
 // First stage of the totals: block b folds its contiguous slice of rows of
 // each partial array into one row of `out` (fixed order, so deterministic).
-__global__ __launch_bounds__(256) void k_fold(const double *ps, int64_t ns, const double *pi, int64_t ni,
-                                              double *out) {
-    const int64_t b = blockIdx.x, nb = gridDim.x;
+__device__ void fold_block(const double *ps, int64_t ns, const double *pi, int64_t ni, double *out, int64_t b,
+                           int64_t nb) {
     auto slice = [&](int64_t n, int64_t *r0, int64_t *r1) {
         const int64_t per = (n + nb - 1) / nb;
         *r0 = b * per < n ? b * per : n;
@@ -742,8 +769,12 @@ __global__ __launch_bounds__(256) void k_fold(const double *ps, int64_t ns, cons
         for (int k = 0; k < NPART; ++k) out[b * NPART + k] = v[k];
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const double *folded, int64_t nb, double p, double p_stick,
-                                                 DevTotals *tot) {
+__global__ __launch_bounds__(256) void k_fold(const double *ps, int64_t ns, const double *pi, int64_t ni,
+                                              double *out) {
+    fold_block(ps, ns, pi, ni, out, blockIdx.x, gridDim.x);
+}
+
+__device__ void reduce_block(const double *folded, int64_t nb, double p, double p_stick, DevTotals *tot) {
     double v[NPART];
     for (int k = 0; k < NPART; ++k) v[k] = column_sum(folded, 0, nb, NPART, k);
     if (threadIdx.x == 0) {
@@ -758,6 +789,58 @@ __global__ __launch_bounds__(256) void k_reduce(const double *folded, int64_t nb
         for (int k = 0; k < NPART; ++k) all += v[k];
         if (!(all - all == 0.0)) tot->nonfinite = 1;
     }
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double *folded, int64_t nb, double p, double p_stick,
+                                                 DevTotals *tot) {
+    reduce_block(folded, nb, p, p_stick, tot);
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernels: one launch covers every sample of a batch.  Each sample
+// owns a contiguous range of logical blocks (first block in its record); a
+// per-block table names the sample, and the block reads that sample's
+// geometry, physics and buffers from its record with scalar loads.  A
+// sample's blocks run exactly the code and partial layout of its
+// single-sample launch, so its results are bit-identical to those.
+
+template <int ST>
+struct SampleK {
+    Geometry g;
+    Interface it;
+    PhysK<typename Store<ST>::T> ph;
+    Slots pop[2];  // population buffers A and B
+    typename Store<ST>::S *emit;
+    double *part_sweep, *part_iface;
+    uint32_t block0, iblock0;  // first logical sweep / interface block of the sample
+};
+
+template <int ST, int SP>
+__global__ __launch_bounds__(256) void k_sweep_batch(const SampleK<ST> *__restrict__ smp,
+                                                      const uint32_t *__restrict__ block_sample, int parity) {
+    const uint32_t b = uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x)));
+    const SampleK<ST> &d = smp[__builtin_amdgcn_readfirstlane(block_sample[b])];
+    const Slots &in = d.pop[parity];
+    const OutSlots &out = reinterpret_cast<const OutSlots &>(d.pop[1 - parity]);
+    sweep_block<ST, SP>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_interface_batch(const SampleK<ST> *__restrict__ smp,
+                                                          const uint32_t *__restrict__ block_sample) {
+    const uint32_t b = blockIdx.x;
+    const SampleK<ST> &d = smp[__builtin_amdgcn_readfirstlane(block_sample[b])];
+    interface_block<ST>(d.ph, d.it, d.emit, d.part_iface, b - d.iblock0);
+}
+
+__global__ __launch_bounds__(256) void k_fold_batch(const ReduceK *__restrict__ r) {
+    const ReduceK &d = r[blockIdx.y];
+    fold_block(d.ps, d.ns, d.pi, d.ni, d.fold, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_batch(const ReduceK *__restrict__ r) {
+    const ReduceK &d = r[blockIdx.x];
+    reduce_block(d.fold, FOLD_BLOCKS, d.p, d.p_stick, d.tot);
 }
 
 template <typename F>
@@ -897,6 +980,71 @@ hipError_t launch_reduce(const double *part_sweep, int64_t n_sweep, const double
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, fold, int64_t(FOLD_BLOCKS), p, p_stick, tot);
     return hipGetLastError();
+}
+
+size_t batch_record_bytes(int storage) {
+    switch (storage) {
+        case ST_F32: return sizeof(SampleK<ST_F32>);
+        case ST_F16: return sizeof(SampleK<ST_F16>);
+        case ST_BF16: return sizeof(SampleK<ST_BF16>);
+        case ST_F64: return sizeof(SampleK<ST_F64>);
+        default: return 0;
+    }
+}
+
+hipError_t batch_upload(int storage, const BatchSample *smp, int n, void *d_records, hipStream_t s) {
+    return dispatch(storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        using SS = typename Store<ST>::S;
+        using T = typename Store<ST>::T;
+        std::vector<SampleK<ST>> rec(static_cast<size_t>(n));
+        for (int i = 0; i < n; ++i) {
+            SampleK<ST> &r = rec[size_t(i)];
+            std::memset(static_cast<void *>(&r), 0, sizeof(r));
+            r.g = smp[i].g;
+            r.it = smp[i].it;
+            r.ph = to_kernel<T>(smp[i].ph);
+            r.pop[0] = slots_of<ST>(smp[i].g, smp[i].pop[0]);
+            r.pop[1] = slots_of<ST>(smp[i].g, smp[i].pop[1]);
+            r.emit = static_cast<SS *>(smp[i].emit);
+            r.part_sweep = smp[i].part_sweep;
+            r.part_iface = smp[i].part_iface;
+            r.block0 = smp[i].block0;
+            r.iblock0 = smp[i].iblock0;
+        }
+        hipError_t e = hipMemcpyAsync(d_records, rec.data(), rec.size() * sizeof(SampleK<ST>), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e;
+    });
+}
+
+hipError_t launch_batch_step(int storage, int sputter, const void *d_records, const uint32_t *sweep_sample,
+                             int64_t sweep_blocks_total, const uint32_t *iface_sample, int64_t iface_blocks_total,
+                             const ReduceK *d_reduce, int n, int parity, hipStream_t s) {
+    return dispatch(storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        const SampleK<ST> *rec = static_cast<const SampleK<ST> *>(d_records);
+        if (iface_blocks_total > 0) {
+            hipLaunchKernelGGL(k_interface_batch<ST>, dim3(unsigned(iface_blocks_total)), dim3(256), 0, s, rec,
+                               iface_sample);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        const dim3 grid(static_cast<unsigned>(sweep_blocks_total)), block(256);
+        if (sputter == SP_UNIFORM)
+            hipLaunchKernelGGL((k_sweep_batch<ST, SP_UNIFORM>), grid, block, 0, s, rec, sweep_sample, parity);
+        else if (sputter == SP_WEIGHTED)
+            hipLaunchKernelGGL((k_sweep_batch<ST, SP_WEIGHTED>), grid, block, 0, s, rec, sweep_sample, parity);
+        else
+            hipLaunchKernelGGL((k_sweep_batch<ST, SP_BOUNCEBACK>), grid, block, 0, s, rec, sweep_sample, parity);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fold_batch, dim3(FOLD_BLOCKS, unsigned(n)), dim3(256), 0, s, d_reduce);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_reduce_batch, dim3(unsigned(n)), dim3(256), 0, s, d_reduce);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace lbmk

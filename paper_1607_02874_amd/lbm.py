@@ -115,6 +115,17 @@ def _load():
         "lbm_load": (st, [ctx, ctypes.c_char_p]),
         "lbm_last_error": (ctypes.c_char_p, [ctx]),
         "lbm_destroy": (None, [ctx]),
+        "lbm_batch_create": (st, [ctypes.c_int32, P(lbm_geometry), P(ctypes.c_double), P(ctypes.c_double),
+                                  P(ctypes.c_double), P(lbm_bc), P(lbm_device), P(ctx)]),
+        "lbm_batch_step": (st, [ctx, ctypes.c_int64]),
+        "lbm_batch_fields": (st, [ctx, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+        "lbm_batch_conversion_map": (st, [ctx, ctypes.c_int32, ctypes.c_void_p]),
+        "lbm_batch_totals": (st, [ctx, ctypes.c_int32, P(lbm_totals_t)]),
+        "lbm_batch_query": (st, [ctx, ctypes.c_int32, P(lbm_info)]),
+        "lbm_batch_synchronize": (st, [ctx]),
+        "lbm_batch_set_graph": (st, [ctx, ctypes.c_int32]),
+        "lbm_batch_last_error": (ctypes.c_char_p, [ctx]),
+        "lbm_batch_destroy": (None, [ctx]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -140,6 +151,12 @@ def header_functions(path=HEADER):
 def _check(status, ctx=None):
     if status != LBM_OK:
         msg = _LIB.lbm_last_error(ctx)
+        raise LbmError(status, msg.decode() if msg else "")
+
+
+def _bcheck(status, batch=None):
+    if status != LBM_OK:
+        msg = _LIB.lbm_batch_last_error(batch)
         raise LbmError(status, msg.decode() if msg else "")
 
 
@@ -175,19 +192,28 @@ class _TorchDevice:
         self.torch.cuda.caching_allocator_delete(ptr)
 
 
-def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, sputter=SPUTTER_UNIFORM,
-               coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32, p_stick=0.95,
-               c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0), device=None):
-    """Call lbm_create_on.  vox is a (nz, ny, nx) uint8 array; device is an
-    lbm_device struct holder (see use_torch) or None for hipMalloc and the
-    null stream.  Returns the raw context handle."""
+def _geometry(vox, pore_size):
     vox = np.ascontiguousarray(vox, dtype=np.uint8)
     if vox.ndim != 3:
         raise ValueError("vox must be (nz, ny, nx)")
     nz, ny, nx = vox.shape
-    g = lbm_geometry(nx, ny, nz, 0, vox.ctypes.data, float(pore_size))
-    bc = lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
-                float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]), 0)
+    return vox, lbm_geometry(nx, ny, nz, 0, vox.ctypes.data, float(pore_size))
+
+
+def _bc(sputter=SPUTTER_UNIFORM, coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32,
+        p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0)):
+    return lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
+                  float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]), 0)
+
+
+def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc_kw):
+    """Call lbm_create_on.  vox is a (nz, ny, nx) uint8 array; device is an
+    lbm_device struct holder (see use_torch) or None for hipMalloc and the
+    null stream; bc_kw are the lbm_bc fields (sputter, coupling, species_x,
+    storage, p_stick, c_inlet, rho0, c0, c_ref, force).  Returns the raw
+    context handle."""
+    vox, g = _geometry(vox, pore_size)
+    bc = _bc(**bc_kw)
     t = (ctypes.c_double * 2)(float(tau[0]), float(tau[1]))
     out = ctypes.c_void_p()
     dev = ctypes.byref(device.struct) if device is not None else None
@@ -291,3 +317,94 @@ class Sim:
 
     def load(self, path):
         _check(_LIB.lbm_load(self._h, str(path).encode()), self._h)
+
+
+class Batch:
+    """Many independent samples advanced together (lbm_batch_*).  samples is
+    a list of dicts with the arguments of Sim: vox, da, and optionally tau,
+    kn, pore_size and the lbm_bc fields; storage, sputter, coupling and
+    species_x must be the same in all."""
+
+    def __init__(self, samples, use_torch=True, stream=None, graph=False):
+        self._h = None
+        self._device = None
+        if use_torch:
+            import torch
+
+            if torch.cuda.is_available():
+                self._device = _TorchDevice(stream)
+        n = len(samples)
+        self.shapes = []
+        keep = []
+        geoms = (lbm_geometry * n)()
+        bcs = (lbm_bc * n)()
+        kn = (ctypes.c_double * n)()
+        da = (ctypes.c_double * n)()
+        tau = (ctypes.c_double * (2 * n))()
+        for i, smp in enumerate(samples):
+            smp = dict(smp)
+            vox, g = _geometry(smp.pop("vox"), smp.pop("pore_size", 1.0))
+            keep.append(vox)
+            self.shapes.append(vox.shape)
+            geoms[i] = g
+            da[i] = float(smp.pop("da"))
+            kn[i] = float(smp.pop("kn", 0.0))
+            t = smp.pop("tau", (0.0, 0.0))
+            tau[2 * i], tau[2 * i + 1] = float(t[0]), float(t[1])
+            bcs[i] = _bc(**smp)
+        out = ctypes.c_void_p()
+        dev = ctypes.byref(self._device.struct) if self._device is not None else None
+        _bcheck(_LIB.lbm_batch_create(n, geoms, kn, da, tau, bcs, dev, ctypes.byref(out)))
+        self._h = out
+        self.n = n
+        if graph:
+            self.set_graph(True)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _LIB.lbm_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, n=1):
+        _bcheck(_LIB.lbm_batch_step(self._h, int(n)), self._h)
+
+    def synchronize(self):
+        _bcheck(_LIB.lbm_batch_synchronize(self._h), self._h)
+
+    def set_graph(self, on=True):
+        _bcheck(_LIB.lbm_batch_set_graph(self._h, 1 if on else 0), self._h)
+
+    def fields(self, i):
+        shape = self.shapes[i]
+        nn = int(np.prod(shape))
+        rho, u, c = np.zeros(nn), np.zeros(3 * nn), np.zeros(nn)
+        _bcheck(_LIB.lbm_batch_fields(self._h, int(i), rho.ctypes.data, u.ctypes.data, c.ctypes.data), self._h)
+        return rho.reshape(shape), u.reshape((3,) + shape), c.reshape(shape)
+
+    def conversion_map(self, i):
+        shape = self.shapes[i]
+        out = np.zeros(int(np.prod(shape)))
+        _bcheck(_LIB.lbm_batch_conversion_map(self._h, int(i), out.ctypes.data), self._h)
+        return out.reshape(shape)
+
+    def totals(self, i):
+        t = lbm_totals_t()
+        _bcheck(_LIB.lbm_batch_totals(self._h, int(i), ctypes.byref(t)), self._h)
+        return {k: getattr(t, k) for k, _ in lbm_totals_t._fields_ if k != "reserved"}
+
+    def info(self, i):
+        inf = lbm_info()
+        _bcheck(_LIB.lbm_batch_query(self._h, int(i), ctypes.byref(inf)), self._h)
+        return {k: getattr(inf, k) for k, _ in lbm_info._fields_}

@@ -76,3 +76,37 @@ def test_null_arguments():
     assert b"NULL" in L.lbm_last_error(None)
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
     L.lbm_destroy(None)  # no-op
+
+
+def _batch_args(n, storages=None, taus=None):
+    geoms = (lbm.lbm_geometry * max(n, 1))()
+    bcs = (lbm.lbm_bc * max(n, 1))()
+    vox = np.zeros((4, 4, 8), np.uint8)
+    for i in range(n):
+        geoms[i] = lbm.lbm_geometry(8, 4, 4, 0, vox.ctypes.data, 4.0)
+        bcs[i] = lbm._bc(storage=(storages[i] if storages else 0))
+    da = (ctypes.c_double * max(n, 1))(*([1.0] * n))
+    tau = (ctypes.c_double * (2 * max(n, 1)))()
+    for i in range(n):
+        tau[2 * i], tau[2 * i + 1] = (taus[i] if taus else (0.8, 0.7))
+    return vox, geoms, da, tau, bcs
+
+
+def test_batch_rejects_invalid_arguments_before_device_work():
+    L = lbm.library()
+    out = ctypes.c_void_p(1)
+    vox, geoms, da, tau, bcs = _batch_args(3)
+    assert L.lbm_batch_create(0, geoms, None, da, tau, bcs, None, ctypes.byref(out)) == lbm.LBM_EINVAL
+    assert out.value is None and b"n >= 1" in L.lbm_batch_last_error(None)
+    assert L.lbm_batch_create(3, geoms, None, None, tau, bcs, None, ctypes.byref(out)) == lbm.LBM_EINVAL
+    # every sample must share storage, sputter, coupling and species_x
+    vox, geoms, da, tau, bcs = _batch_args(3, storages=[0, 1, 0])
+    assert L.lbm_batch_create(3, geoms, None, da, tau, bcs, None, ctypes.byref(out)) == lbm.LBM_EINVAL
+    assert b"sample 1" in L.lbm_batch_last_error(None)
+    # a sample's own parameters are checked by lbm_create; the message names it
+    vox, geoms, da, tau, bcs = _batch_args(2, taus=[(0.4, 0.7), (0.8, 0.7)])
+    assert L.lbm_batch_create(2, geoms, None, da, tau, bcs, None, ctypes.byref(out)) == lbm.LBM_EINVAL
+    assert b"sample 0" in L.lbm_batch_last_error(None) and b"tau" in L.lbm_batch_last_error(None)
+    assert L.lbm_batch_step(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_batch_set_graph(None, 1) == lbm.LBM_EINVAL
+    L.lbm_batch_destroy(None)  # no-op

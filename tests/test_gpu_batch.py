@@ -1,0 +1,128 @@
+"""Batched stepping (lbm_batch_*): every sample of a batch must evolve exactly
+as the same sample alone.  The batched kernels run the single-sample code and
+partial-sum layout per sample, so fields, conversion map and totals are
+compared bit for bit; one sample is also checked against the FP64 oracle.
+Graph replays are compared with eager stepping after every replay."""
+
+import numpy as np
+import pytest
+
+from paper_1607_02874_amd import inputs, lbm
+
+from parity import case, errors, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+F32, F16, BF16, F64 = 0, 1, 2, 3
+
+
+def mixed_samples(storage=F32, sputter=lbm.SPUTTER_UNIFORM, coupling=lbm.COUPLE_PASSIVE,
+                  species_x=lbm.XBC_RESERVOIR):
+    """Five samples of different shapes (ragged nx across 64-voxel chunks),
+    porosities, relaxation times, Da, forces and sticking probabilities; one
+    has no catalytic voxel at all."""
+    specs = [
+        (40, 20, 12, 0.65, 3.0, 11, (0.8, 0.7), 1.0, 0.95),
+        (70, 18, 10, 0.60, 4.0, 12, (0.9, 0.9), 0.3, 0.5),
+        (130, 12, 9, 0.70, 3.0, 13, (0.6, 0.75), 20.0, 0.95),
+        (33, 33, 7, 0.55, 2.5, 14, (1.1, 0.65), 0.05, 0.8),
+        (64, 10, 10, 1.00, 3.0, 15, (0.7, 0.7), 1.0, 0.95),
+    ]
+    out = []
+    for nx, ny, nz, phi, ell, seed, tau, da, ps in specs:
+        vox = inputs.porous_slab(nx, ny, nz, phi, ell, seed) if phi < 1.0 else np.zeros((nz, ny, nx), np.uint8)
+        out.append(dict(vox=vox, da=da, tau=tau, pore_size=ell, force=inputs.body_force(ell, tau[0]), p_stick=ps,
+                        c_inlet=1.0, storage=storage, sputter=sputter, coupling=coupling, species_x=species_x))
+    return out
+
+
+def single(smp, steps):
+    kw = {k: v for k, v in smp.items() if k not in ("vox", "da", "tau", "pore_size")}
+    with lbm.Sim(smp["vox"], da=smp["da"], tau=smp["tau"], pore_size=smp["pore_size"], **kw) as s:
+        s.step(steps)
+        return s.fields(), s.conversion_map(), s.totals()
+
+
+def assert_same(batch, i, ref):
+    (rho, u, c), conv, tot = ref
+    brho, bu, bc = batch.fields(i)
+    assert np.array_equal(brho, rho) and np.array_equal(bu, u) and np.array_equal(bc, c), i
+    assert np.array_equal(batch.conversion_map(i), conv), i
+    assert batch.totals(i) == tot, (i, batch.totals(i), tot)
+
+
+@pytest.mark.parametrize("storage,sputter", [(F32, lbm.SPUTTER_UNIFORM), (F32, lbm.SPUTTER_WEIGHTED),
+                                             (F32, lbm.SPUTTER_BOUNCEBACK), (F16, lbm.SPUTTER_UNIFORM),
+                                             (F64, lbm.SPUTTER_UNIFORM)])
+def test_batch_bit_identical_to_single_samples(storage, sputter):
+    samples = mixed_samples(storage=storage, sputter=sputter)
+    steps = 23
+    print(f"batch storage={storage} sputter={sputter}", flush=True)
+    with lbm.Batch(samples) as b:
+        b.step(10)
+        b.step(steps - 10)
+        for i, smp in enumerate(samples):
+            assert_same(b, i, single(smp, steps))
+            assert b.totals(i)["step"] == steps
+
+
+def test_batch_barycentric_periodic_matches_single():
+    samples = mixed_samples(coupling=lbm.COUPLE_BARYCENTRIC, species_x=lbm.XBC_PERIODIC)
+    for s in samples:
+        s["c0"] = 0.3
+    with lbm.Batch(samples) as b:
+        b.step(17)
+        for i, smp in enumerate(samples):
+            assert_same(b, i, single(smp, 17))
+
+
+def test_batch_graph_replays_match_eager():
+    samples = mixed_samples()
+    with lbm.Batch(samples) as eager, lbm.Batch(samples, graph=True) as graphed:
+        for rep in range(4):
+            n = 2 if rep < 3 else 3  # three two-step replays, then a replay plus one eager step
+            print(f"graph replay {rep} ({n} steps)", flush=True)
+            graphed.step(n)
+            eager.step(n)
+            graphed.synchronize()
+            eager.synchronize()
+            for i in range(len(samples)):
+                assert graphed.totals(i) == eager.totals(i), (rep, i)
+                ge, ee = graphed.fields(i), eager.fields(i)
+                assert all(np.array_equal(a, b) for a, b in zip(ge, ee)), (rep, i)
+                assert np.array_equal(graphed.conversion_map(i), eager.conversion_map(i)), (rep, i)
+
+
+def test_batch_sample_matches_oracle():
+    samples = mixed_samples()
+    smp = samples[0]
+    steps = 40
+    c = case(smp["vox"], steps, da=smp["da"], tau=smp["tau"], pore_size=smp["pore_size"], p_stick=smp["p_stick"],
+             force=smp["force"])
+    ref = run_oracle(c)
+    with lbm.Batch(samples) as b:
+        b.step(steps)
+        rho, u, conc = b.fields(0)
+        gpu = dict(rho=rho, u=u, conc=conc, conv=b.conversion_map(0))
+    e = errors(gpu, ref, c["vox"])
+    print("batch sample 0 vs oracle", {k: f"{v:.2e}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < 1e-5, (k, e[k])
+
+
+def test_batch_info_and_index_errors():
+    samples = mixed_samples()
+    with lbm.Batch(samples) as b:
+        for i, smp in enumerate(samples):
+            inf = b.info(i)
+            assert inf["n_nodes"] == smp["vox"].size
+            assert inf["n_fluid"] == int((smp["vox"] == 0).sum())
+            assert inf["tau_gas"] == smp["tau"][0]
+        assert b.info(4)["n_interface"] == 0
+        L = lbm.library()
+        for bad in (-1, len(samples)):
+            assert L.lbm_batch_fields(b._h, bad, None, None, None) == lbm.LBM_EINVAL
+            assert L.lbm_batch_conversion_map(b._h, bad, None) == lbm.LBM_EINVAL
+        assert b"out of range" in L.lbm_batch_last_error(b._h)
+        with pytest.raises(lbm.LbmError):
+            b.step(-1)
