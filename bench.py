@@ -11,6 +11,7 @@ sweep of both lattices + FP64 reduction.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--storage f32|f16|bf16|f64]
     python bench.py --workload batch [--steps K]   (64-sample batch vs sequential)
+    python bench.py --workload precision [--steps K]   (512^3, FP32/FP16/BF16 vs the FP64 build)
 """
 
 import argparse
@@ -190,6 +191,81 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def run_precision(args):
+    """512^3 porous sample (porosity 0.70, correlation length 12, seed 1002):
+    the same run with FP32, FP16 and BF16 storage (FP32 arithmetic) and the
+    FP64 build; per storage the throughput, the speedup over FP32 and the
+    L2-relative field errors against the FP64 build after the same steps."""
+    import torch
+
+    from paper_1607_02874_amd import inputs, lbm
+
+    w = inputs.PRECISION_512
+    t0 = time.perf_counter()
+    vox = w.voxels()
+    gas = vox == 0
+    log(f"geometry {w.nx}x{w.ny}x{w.nz} porosity {inputs.porosity(vox):.4f} ({time.perf_counter() - t0:.1f} s)")
+    results, fields = {}, {}
+    for name in ("f64", "f32", "f16", "bf16"):
+        storage = STORAGES[name]
+        sim = lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                      c_inlet=w.c_inlet, storage=storage)
+        info = sim.info()
+        sim.step(args.warmup)
+        sim.synchronize()
+        sim.set_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.step(args.steps)
+        sim.synchronize()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        kt = sim.kernel_times()
+        rho, u, c = sim.fields()
+        conv = sim.conversion_map()
+        sim.close()
+        ab = algorithmic_bytes(info, lbm.STORAGE_BYTES[storage])
+        t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
+        results[name] = {"mlups": round(vox.size * args.steps / el / 1e6, 1),
+                         "ms_per_step": round(el / args.steps * 1e3, 4),
+                         "sweep_us": round(t_sweep * 1e6, 2),
+                         "sweep_GBps": round(ab["sweep"] / t_sweep / 1e9, 1)}
+        if name == "f64":
+            fields["f64"] = (rho[gas], u[:, gas], c[gas], conv)
+        else:
+            ref = fields["f64"]
+            got = (rho[gas], u[:, gas], c[gas], conv)
+            results[name]["error_vs_f64"] = {k: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+                                             for k, a, b in zip(("rho", "u", "conc", "conv"), got, ref)}
+        del rho, u, c, conv
+        log(f"{name}: {results[name]}")
+    for name in ("f16", "bf16"):
+        results[name]["speedup_vs_f32"] = round(results["f32"]["ms_per_step"] / results[name]["ms_per_step"], 3)
+    best = "f16"
+    line = {
+        "metric": "MLUPS (flow+species) and % of HBM roofline at stated error vs FP64 oracle",
+        "value": results[best]["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": results[best]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16-storage/f32",
+        "data": "synthetic (seeded Gaussian-random-field porous geometry)",
+        "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} porous sample, porosity {w.phi}, correlation length "
+                               f"{w.ell}, seed {w.seed}, tau {w.tau}, Da {w.da}",
+                   "n_nodes": int(vox.size), "n_fluid": int(gas.sum()), "per_storage": results},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep (f16 storage)",
+                     "achieved": results[best]["sweep_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(results[best]["sweep_GBps"] / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,8 +278,9 @@ def main():
     ap.add_argument("--copy-calib", action="store_true", help="also run a 4 GiB device copy (counter calibration)")
     ap.add_argument("--ytile", type=int, default=None, help="sweep y-tile height (default: the library's)")
     ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
-    ap.add_argument("--workload", default="single", choices=("single", "batch"),
-                    help="single: the 256^3 sample; batch: the 64-sample mixed batch")
+    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision"),
+                    help="single: the 256^3 sample; batch: the 64-sample mixed batch; precision: 512^3 "
+                         "with FP32/FP16/BF16 storage against the FP64 build")
     ap.add_argument("--no-graph", action="store_true", help="batch: launch directly instead of graph replays")
     args = ap.parse_args()
 
@@ -221,6 +298,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "precision":
+        run_precision(args)
         return
     w = inputs.SINGLE_256
     if args.da is not None:

@@ -212,6 +212,19 @@ lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc);
  */
 lbm_status lbm_conversion_map(lbm_ctx *c, double *conv);
 
+/*
+ * lbm_populations - the pre-collision populations f_i of both lattices at the
+ * current step (the state Eq. LBE advances) in a box of voxels: origin
+ * {x0, y0, z0}, extent {wx, wy, wz} >= 1, inside the lattice (LBM_EINVAL
+ * otherwise).  fC and fR are host arrays of 19 * wx * wy * wz doubles,
+ * direction-major: f[i][z][y][x] relative to the origin; solid voxels are 0.
+ * Direction numbering: i = 0 rest; i = 1..9 are (1,0,0), (0,1,0), (0,0,1),
+ * (1,1,0), (1,-1,0), (1,0,1), (1,0,-1), (0,1,1), (0,1,-1); i = 10..18 are the
+ * negatives of i - 9.  Synchronises the stream.
+ */
+lbm_status lbm_populations(lbm_ctx *c, const int32_t origin[3], const int32_t extent[3], double *fC,
+                           double *fR);
+
 /* Global totals (FP64, fixed-order deterministic reductions). Synchronises. */
 lbm_status lbm_totals(lbm_ctx *c, lbm_totals_t *t);
 

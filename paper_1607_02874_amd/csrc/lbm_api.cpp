@@ -616,6 +616,41 @@ lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc) {
     return fields_impl(c, rho, u, conc, false);
 }
 
+lbm_status lbm_populations(lbm_ctx *c, const int32_t origin[3], const int32_t extent[3], double *fC, double *fR) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (!origin || !extent || !fC || !fR) return fail(c, LBM_EINVAL, "NULL argument");
+    const int dims[3] = {c->nx, c->ny, c->nz};
+    for (int a = 0; a < 3; ++a)
+        if (origin[a] < 0 || extent[a] < 1 || int64_t(origin[a]) + extent[a] > dims[a])
+            return fail(c, LBM_EINVAL, "box must lie inside the lattice with extent >= 1");
+    const Window win{origin[0], origin[1], origin[2], extent[0], extent[1], extent[2]};
+    const size_t len = size_t(19) * size_t(extent[0]) * size_t(extent[1]) * size_t(extent[2]);
+    double *d[2] = {nullptr, nullptr};
+    for (int k = 0; k < 2; ++k) {
+        void *p = nullptr;
+        if (c->dev.alloc)
+            p = c->dev.alloc(len * 8, c->dev.user);
+        else if (hipMalloc(&p, len * 8) != hipSuccess)
+            p = nullptr;
+        if (!p) {
+            if (d[0]) (c->dev.free ? c->dev.free(d[0], c->dev.user) : (void)hipFree(d[0]));
+            return fail(c, LBM_ENOMEM, "populations scratch allocation failed");
+        }
+        d[k] = static_cast<double *>(p);
+    }
+    hipError_t e = hipMemsetAsync(d[0], 0, len * 8, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d[1], 0, len * 8, c->stream);
+    if (e == hipSuccess)
+        e = launch_populations(geometry(c), c->ph, c->d_pop[1 - c->cur], c->d_emit, c->step == 0 ? 2 : 1, win, d[0],
+                               d[1], c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(fC, d[0], len * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(fR, d[1], len * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 2; ++k) (c->dev.free ? c->dev.free(d[k], c->dev.user) : (void)hipFree(d[k]));
+    if (e != hipSuccess) return hip_fail(c, e, "populations");
+    return LBM_OK;
+}
+
 lbm_status lbm_conversion_map(lbm_ctx *c, double *conv) {
     if (!c || !conv) return fail(c, LBM_EINVAL, "NULL argument");
     std::vector<double> acc(size_t(c->niface));

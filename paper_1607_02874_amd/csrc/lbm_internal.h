@@ -113,6 +113,14 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
 // double arrays when out_f64 is set; any output may be null.
 hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
                          void *rho, void *u, void *conc, bool out_f64, hipStream_t s);
+// A box of voxels: origin and extent, inside the lattice.
+struct Window {
+    int32_t x0, y0, z0, wx, wy, wz;
+};
+// Pre-collision populations (mode as for launch_fields) of the voxels in
+// `win`, FP64, direction-major [19][wz][wy][wx] in the library's numbering.
+hipError_t launch_populations(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
+                              const Window &win, double *fC, double *fR, hipStream_t s);
 // Two-stage fixed-order reduction of the per-block partials: FOLD_BLOCKS
 // blocks fold contiguous slices into `fold` (FOLD_BLOCKS * NPART doubles),
 // then one block sums those and updates the totals.

@@ -702,6 +702,45 @@ __global__ __launch_bounds__(256) void k_interface(PhysK<typename Store<ST>::T> 
     interface_block<ST>(ph, it, emit, part, blockIdx.x);
 }
 
+// Pre-collision populations of both lattices in a box of voxels (the same
+// pull as the sweep and the field kernels), as FP64 f_i = w_i (h_i + ref),
+// direction-major [19][wz][wy][wx]; solid voxels 0.
+template <int ST, bool LOCAL>
+__global__ __launch_bounds__(256) void k_populations(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in,
+                                                      const typename Store<ST>::S *__restrict__ emit, Window win,
+                                                      double *__restrict__ fC, double *__restrict__ fR) {
+    using T = typename Store<ST>::T;
+    const WaveUnit u = locate(g, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
+    if (!u.valid) return;
+    const int wxi = u.x - win.x0, wyi = u.y - win.y0, wzi = u.z - win.z0;
+    const bool inside = u.x < g.nx && wxi >= 0 && wxi < win.wx && wyi >= 0 && wyi < win.wy && wzi >= 0 &&
+                        wzi < win.wz;
+    if (!__builtin_amdgcn_ballot_w64(inside)) return;  // whole wavefront outside the box
+    T hC[19], hR[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) hC[i] = hR[i] = T(0);
+    if (u.active) {
+        if (LOCAL) {
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                hC[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[dslot(i)]) + u.idx);
+                hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[19 + dslot(i)]) + u.idx);
+            }
+        } else {
+            uint32_t cat_bits;
+            pull<ST, -1>(g, ph, in, emit, u, hC, hR, cat_bits);
+        }
+    }
+    if (!inside) return;
+    const int64_t wn = int64_t(win.wx) * win.wy * win.wz;
+    const int64_t w = (int64_t(wzi) * win.wy + wyi) * win.wx + wxi;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        fC[i * wn + w] = u.active ? wgt<double>(i) * (double(hC[i]) + double(ph.rref)) : 0.0;
+        fR[i * wn + w] = u.active ? wgt<double>(i) * (double(hR[i]) + double(ph.cref)) : 0.0;
+    }
+}
+
 // Fill the link buffer from a population buffer (after create and after a
 // checkpoint load; during stepping the sweep writes it).
 template <int ST>
@@ -969,6 +1008,24 @@ hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, 
             else
                 hipLaunchKernelGGL((k_fields<ST, false, float>), grid, block, 0, s, g, k, f, e, a, b, c);
         }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_populations(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
+                              const Window &win, double *fC, double *fR, hipStream_t s) {
+    return dispatch(ph.storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        using SS = typename Store<ST>::S;
+        using T = typename Store<ST>::T;
+        const dim3 grid(unsigned(sweep_blocks(g))), block(256);
+        const Slots f = slots_of<ST>(g, fin);
+        const SS *e = static_cast<const SS *>(emit);
+        const PhysK<T> k = to_kernel<T>(ph);
+        if (mode == 2)
+            hipLaunchKernelGGL((k_populations<ST, true>), grid, block, 0, s, g, k, f, e, win, fC, fR);
+        else
+            hipLaunchKernelGGL((k_populations<ST, false>), grid, block, 0, s, g, k, f, e, win, fC, fR);
         return hipGetLastError();
     });
 }

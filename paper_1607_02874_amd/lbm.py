@@ -30,6 +30,10 @@ STORE_F32, STORE_F16, STORE_BF16, STORE_F64 = 0, 1, 2, 3
 TUNE_YTILE = 0
 STORAGE_BYTES = {STORE_F32: 4, STORE_F16: 2, STORE_BF16: 2, STORE_F64: 8}
 STORAGE_NAMES = {STORE_F32: "f32", STORE_F16: "f16", STORE_BF16: "bf16", STORE_F64: "f64"}
+# Direction numbering of lbm_populations (as documented in include/lbm.h).
+D3Q19 = np.array([(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1),
+                  (0, 1, 1), (0, 1, -1)] + [(-1, 0, 0), (0, -1, 0), (0, 0, -1), (-1, -1, 0), (-1, 1, 0),
+                                            (-1, 0, -1), (-1, 0, 1), (0, -1, -1), (0, -1, 1)], dtype=np.int64)
 
 
 class LbmError(RuntimeError):
@@ -103,6 +107,7 @@ def _load():
         "lbm_fields": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_fields_device": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_conversion_map": (st, [ctx, ctypes.c_void_p]),
+        "lbm_populations": (st, [ctx, P(ctypes.c_int32), P(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_totals": (st, [ctx, P(lbm_totals_t)]),
         "lbm_query": (st, [ctx, P(lbm_info)]),
         "lbm_active_links": (st, [ctx, ctypes.c_void_p]),
@@ -275,6 +280,21 @@ class Sim:
     def fields_device(self, rho=None, u=None, conc=None):
         """Write float32 fields into device tensors (any may be None)."""
         _check(_LIB.lbm_fields_device(self._h, _ptr(rho), _ptr(u), _ptr(conc)), self._h)
+
+    def populations(self, origin=(0, 0, 0), extent=None):
+        """Pre-collision populations (fC, fR) of the box origin (x, y, z) and
+        extent (wx, wy, wz), each float64 of shape (19, wz, wy, wx) in the
+        library's direction numbering (D3Q19 below)."""
+        nz, ny, nx = self.shape
+        if extent is None:
+            extent = (nx - origin[0], ny - origin[1], nz - origin[2])
+        o = (ctypes.c_int32 * 3)(*[int(v) for v in origin])
+        e = (ctypes.c_int32 * 3)(*[int(v) for v in extent])
+        shape = (19, int(extent[2]), int(extent[1]), int(extent[0]))
+        fC = np.zeros(shape)
+        fR = np.zeros(shape)
+        _check(_LIB.lbm_populations(self._h, o, e, fC.ctypes.data, fR.ctypes.data), self._h)
+        return fC, fR
 
     def conversion_map(self):
         out = np.zeros(self.n)

@@ -1,0 +1,165 @@
+"""Parity at the full benchmark sizes, in the configuration the benchmark
+times (one context, FP32 storage, the library's default launch shape).
+
+At 256^3 the FP64 oracle cannot rerun the whole history, so the checks are
+(a) sampled outputs the oracle computes exactly: the GPU's pre-collision
+populations in a few boxes are handed to the oracle, which advances one step
+on the box; its populations and conversion increments must match the GPU's
+next step on the box interior (two nodes in from every face, where the box
+faces cannot reach in one step), and (b) properties that hold at any size:
+the per-step reactant bookkeeping and the conservation of carrier mass.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_02874_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+F32, F16, BF16, F64 = 0, 1, 2, 3
+
+
+def oracle_order():
+    """perm[j] = library direction of the oracle's direction j (matched by velocity)."""
+    c, _, _ = oracle.d3q19()
+    return np.array([int(np.flatnonzero((lbm.D3Q19 == c[j]).all(axis=1))[0]) for j in range(19)])
+
+
+def to_oracle_state(f, perm):
+    """(19, wz, wy, wx) in library numbering -> oracle state [node][19]."""
+    return np.ascontiguousarray(f.reshape(19, -1)[perm].T)
+
+
+def workload_sim(w, vox, storage, c0=0.0):
+    return lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                   c_inlet=w.c_inlet, c0=c0, storage=storage)
+
+
+def test_populations_match_oracle_state():
+    """lbm_populations returns exactly the oracle's state (FP64 build, 32^3)."""
+    w = inputs.PLAIN_32
+    vox = w.voxels()
+    p, _ = oracle.p_from_da(w.da, w.pore_size)
+    perm = oracle_order()
+    o = oracle.Oracle(vox, tau=w.tau, p=p, p_stick=w.p_stick, c_inlet=w.c_inlet, force=w.force())
+    with workload_sim(w, vox, F64) as s:
+        for steps in (0, 37):
+            if steps:
+                s.step(steps)
+                o.step(steps)
+            fC, fR = s.populations()
+            rC, rR = o.get_state()
+            for got, ref in ((to_oracle_state(fC, perm), rC), (to_oracle_state(fR, perm), rR)):
+                err = np.linalg.norm(got - ref) / np.linalg.norm(ref) if np.linalg.norm(ref) else np.abs(got).max()
+                assert err < 1e-12, (steps, err)
+            # a box is the same data as the whole lattice, cut
+            bC, bR = s.populations((3, 5, 7), (20, 11, 9))
+            assert np.array_equal(bC, fC[:, 7:16, 5:16, 3:23]) and np.array_equal(bR, fR[:, 7:16, 5:16, 3:23])
+        with pytest.raises(lbm.LbmError) as e:
+            s.populations((30, 0, 0), (4, 1, 1))
+        assert e.value.status == lbm.LBM_EINVAL
+    o.close()
+
+
+def one_step_boxes(sim, w, vox, boxes, tol_pop, tol_conv, label, c0):
+    """Hand each box's GPU state to the oracle, advance both one step and
+    compare on the box interior."""
+    p, _ = oracle.p_from_da(w.da, w.pore_size)
+    perm = oracle_order()
+    before = [sim.populations(o, e) for o, e in boxes]
+    conv0 = sim.conversion_map()
+    sim.step(1)
+    after = [sim.populations(o, e) for o, e in boxes]
+    dconv = sim.conversion_map() - conv0
+    for (org, ext), (fC, fR), (gC, gR) in zip(boxes, before, after):
+        x0, y0, z0 = org
+        wx, wy, wz = ext
+        crop = np.ascontiguousarray(vox[z0:z0 + wz, y0:y0 + wy, x0:x0 + wx])
+        # the crop wraps periodically in every direction; only the interior is compared
+        o = oracle.Oracle(crop, tau=w.tau, p=p, p_stick=w.p_stick, c_inlet=w.c_inlet, c0=c0, force=w.force(),
+                          species_x=oracle.XPERIODIC)
+        o.set_state(to_oracle_state(fC, perm), to_oracle_state(fR, perm))
+        o.step(1)
+        rC, rR = o.get_state()
+        rconv = o.conversion_map()
+        o.close()
+        inner = np.zeros(crop.shape, bool)
+        inner[2:-2, 2:-2, 2:-2] = True
+        gas = inner & (crop == inputs.FLUID)
+        cat1 = np.zeros(crop.shape, bool)
+        cat1[1:-1, 1:-1, 1:-1] = True
+        cat1 &= crop == inputs.CATALYTIC
+        gas_flat = gas.reshape(-1)
+        errs = {}
+        for name, got, ref in (("C", gC, rC), ("R", gR, rR)):
+            g = to_oracle_state(got, perm)[gas_flat]
+            r = ref[gas_flat]
+            errs[name] = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+        dc = dconv[z0:z0 + wz, y0:y0 + wy, x0:x0 + wx][cat1]
+        rc = rconv[cat1]
+        errs["conv"] = float(np.linalg.norm(dc - rc) / np.linalg.norm(rc)) if rc.size and np.linalg.norm(rc) else 0.0
+        print(label, org, ext, "gas", int(gas.sum()), "catalytic", int(cat1.sum()),
+              {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        assert gas.sum() > 1000 and cat1.sum() > 100
+        assert errs["C"] < tol_pop and errs["R"] < tol_pop, errs
+        assert errs["conv"] < tol_conv, errs
+
+
+def boxes_for(shape, n, ext, lo_x, hi_x, seed):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    out = []
+    for _ in range(n):
+        out.append(((int(rng.integers(lo_x, hi_x - ext[0])), int(rng.integers(0, ny - ext[1])),
+                     int(rng.integers(0, nz - ext[2]))), ext))
+    return out
+
+
+@pytest.fixture(scope="module")
+def vox256():
+    return inputs.SINGLE_256.voxels()
+
+
+@pytest.mark.parametrize("storage,tol_pop,tol_conv", [(F32, 1e-5, 1e-5), (F16, 1e-3, 1e-3)])
+def test_256_sampled_boxes_one_step(vox256, storage, tol_pop, tol_conv):
+    w = inputs.SINGLE_256
+    print(f"256^3 storage {storage}: 200 steps, then one step in 4 boxes", flush=True)
+    # an initial reactant concentration everywhere, so every box holds reactant
+    with workload_sim(w, vox256, storage, c0=0.5) as s:
+        s.step(200)
+        boxes = boxes_for(vox256.shape, 4, (24, 24, 24), 8, 248, 7 + storage)
+        one_step_boxes(s, w, vox256, boxes, tol_pop, tol_conv, f"256^3/s{storage}", 0.5)
+
+
+def test_256_bookkeeping_and_carrier_mass_every_step(vox256):
+    w = inputs.SINGLE_256
+    p, _ = oracle.p_from_da(w.da, w.pore_size)
+    with workload_sim(w, vox256, F32) as s:
+        t0 = s.totals()
+        for k in range(1, 31):
+            s.step(1)
+            t = s.totals()
+            absorbed = t["converted"] + t["lost"]
+            lhs = t["mass_species"] - t0["mass_species"]
+            rhs = t["influx"] - t["outflux"] - absorbed
+            scale = abs(t["influx"]) + abs(t["outflux"]) + abs(t["mass_species"])
+            assert abs(lhs - rhs) < 1e-6 * scale, (k, lhs, rhs)
+            assert abs(t["mass_gas"] - t0["mass_gas"]) < 1e-6 * t0["mass_gas"], k
+            if absorbed > 0:
+                assert abs(t["converted"] / absorbed - p) < 1e-9, k
+        assert t["step"] == 30 and t["nonfinite"] == 0
+
+
+def test_membrane_1024x512x512_sampled_boxes_one_step():
+    """The largest single-GPU case (268 M nodes, FP32): boxes across the
+    porous layer x in [384, 640)."""
+    w = inputs.MEMBRANE_1024
+    print("membrane: geometry", flush=True)
+    vox = w.voxels()
+    print("membrane: create and 20 steps", flush=True)
+    with workload_sim(w, vox, F32, c0=0.5) as s:
+        s.step(20)
+        boxes = boxes_for(vox.shape, 3, (24, 24, 24), 384, 640, 11)
+        one_step_boxes(s, w, vox, boxes, 1e-5, 1e-5, "membrane", 0.5)
