@@ -138,12 +138,29 @@ def run_batch(args):
         return time.perf_counter() - t
 
     batch = lbm.Batch(samples, graph=not args.no_graph)
+    if args.sweep is not None:
+        batch.set_tunable(lbm.TUNE_SWEEP, args.sweep)
+    if args.ytile:
+        batch.set_tunable(lbm.TUNE_YTILE, args.ytile)
+    if not args.no_autotune and args.ytile is None and args.sweep is None:
+        ms = batch.autotune(3)
+        log(f"autotune: sweep {batch.get_tunable(lbm.TUNE_SWEEP)} ytile {batch.get_tunable(lbm.TUNE_YTILE)} "
+            f"({ms * 1e3:.1f} us)")
+    sweep_variant = batch.get_tunable(lbm.TUNE_SWEEP)
+    ytile_batch = batch.get_tunable(lbm.TUNE_YTILE)
     infos = [batch.info(i) for i in range(len(samples))]
     log(f"batched: timing {args.steps} steps")
     t_batch = timed(batch.step, batch.synchronize, args.steps)
     batch.close()
     sims = [lbm.Sim(s["vox"], da=s["da"], tau=s["tau"], pore_size=s["pore_size"], force=s["force"],
                     p_stick=s["p_stick"], c_inlet=s["c_inlet"], storage=storage) for s in samples]
+    for sim in sims:  # the sequential runs autotune each sample on its own
+        if args.no_autotune or args.ytile is not None or args.sweep is not None:
+            sim.set_tunable(lbm.TUNE_SWEEP, sweep_variant)
+            if args.ytile:
+                sim.set_tunable(lbm.TUNE_YTILE, min(args.ytile, sim.shape[1]))
+        else:
+            sim.autotune(3)
 
     def seq_step(k):
         for sim in sims:
@@ -179,6 +196,7 @@ def run_batch(args):
         "config": {"workload": "batch64: 64 porous cubes, side U{48..128}, porosity U[0.5,0.75], correlation "
                                "length 6, tau U[0.55,1.2], Da logU[0.01,100], seeds 2000+s",
                    "n_nodes": n_nodes, "n_fluid": n_fluid, "graph": not args.no_graph,
+                   "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks", "ytile": ytile_batch,
                    "sequential_mlups": round(n_nodes * args.steps / t_seq / 1e6, 1),
                    "sequential_ms_per_step": round(t_seq / args.steps * 1e3, 4),
                    "speedup_vs_sequential": round(t_seq / t_batch, 3),
@@ -211,6 +229,8 @@ def run_precision(args):
         sim = lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
                       c_inlet=w.c_inlet, storage=storage)
         info = sim.info()
+        if not args.no_autotune:
+            sim.autotune(3)
         sim.step(args.warmup)
         sim.synchronize()
         sim.set_timing(True)
@@ -221,12 +241,14 @@ def run_precision(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         kt = sim.kernel_times()
+        sim_tunables = {"variant": sim.get_tunable(lbm.TUNE_SWEEP), "ytile": sim.get_tunable(lbm.TUNE_YTILE)}
         rho, u, c = sim.fields()
         conv = sim.conversion_map()
         sim.close()
         ab = algorithmic_bytes(info, lbm.STORAGE_BYTES[storage])
         t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
         results[name] = {"mlups": round(vox.size * args.steps / el / 1e6, 1),
+                         "sweep": sim_tunables,
                          "ms_per_step": round(el / args.steps * 1e3, 4),
                          "sweep_us": round(t_sweep * 1e6, 2),
                          "sweep_GBps": round(ab["sweep"] / t_sweep / 1e9, 1)}
@@ -278,10 +300,14 @@ def main():
     ap.add_argument("--copy-calib", action="store_true", help="also run a 4 GiB device copy (counter calibration)")
     ap.add_argument("--ytile", type=int, default=None, help="sweep y-tile height (default: the library's)")
     ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
+    ap.add_argument("--sweep", type=int, default=None, choices=(0, 1),
+                    help="sweep variant: 1 node-compact (library default), 0 one wave per 64-voxel chunk")
     ap.add_argument("--workload", default="single", choices=("single", "batch", "precision"),
                     help="single: the 256^3 sample; batch: the 64-sample mixed batch; precision: 512^3 "
                          "with FP32/FP16/BF16 storage against the FP64 build")
     ap.add_argument("--no-graph", action="store_true", help="batch: launch directly instead of graph replays")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shape instead of autotuning it before timing")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -317,6 +343,8 @@ def main():
     info = sim.info()
     log(f"create {time.perf_counter() - t0:.1f} s, info {info}")
 
+    if args.sweep is not None:
+        sim.set_tunable(lbm.TUNE_SWEEP, args.sweep)
     if args.scan_ytile:
         for yt in [int(v) for v in args.scan_ytile.split(",")]:
             sim.set_tunable(lbm.TUNE_YTILE, yt)
@@ -329,6 +357,12 @@ def main():
             log(f"ytile {yt}: sweep {kt['ms_sweep'] / kt['n_sweep'] * 1e3:.1f} us")
     if args.ytile:
         sim.set_tunable(lbm.TUNE_YTILE, args.ytile)
+    tuned = None
+    if not args.no_autotune and args.ytile is None and args.sweep is None:
+        tuned = sim.autotune(5)
+        log(f"autotune: sweep {sim.get_tunable(lbm.TUNE_SWEEP)} ytile {sim.get_tunable(lbm.TUNE_YTILE)} "
+            f"({tuned * 1e3:.1f} us)")
+    sweep_variant = sim.get_tunable(lbm.TUNE_SWEEP)
     sim.step(args.warmup)
     sim.synchronize()
     torch.cuda.synchronize()
@@ -363,9 +397,10 @@ def main():
     if kt and kt["n_sweep"]:
         t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
         achieved = ab["sweep"] / t_sweep / 1e9
-        roofline = {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        kname = "k_sweep_c" if sweep_variant == 1 else "k_sweep"
+        roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("k_sweep", w.name, args.storage),
+                    "traffic": measured_traffic(kname, w.name, args.storage),
                     "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2)}
     kernels = None
     if kt:
@@ -397,7 +432,8 @@ def main():
                    "n_nodes": n, "n_fluid": info["n_fluid"], "n_interface": info["n_interface"],
                    "n_catalytic_links": info["n_catalytic_links"], "mflups": round(mlups * info["n_fluid"] / n, 1),
                    "step_bytes": ab["step"], "step_GBps": round(ab["step"] / (ms_step * 1e-3) / 1e9, 1),
-                   "kernel_us": kernels, "ytile": ytile},
+                   "kernel_us": kernels, "ytile": ytile, "autotuned": tuned is not None,
+                   "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": None if errs is None else {

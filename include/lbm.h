@@ -237,13 +237,31 @@ lbm_status lbm_active_links(const lbm_ctx *c, uint8_t *b);
 /* Wait for all work queued by the context. */
 lbm_status lbm_synchronize(lbm_ctx *c);
 
-/* Launch-shape tunables (results never depend on them).
+/* Launch-shape tunables.
  * LBM_TUNE_YTILE: rows per y-tile of the sweep traversal, 1..ny (default
  * 16).  The sweep walks tiles of that many x-rows in y, z-planes inside a
- * tile, so a row's z-neighbours are read while still cached. */
-typedef enum { LBM_TUNE_YTILE = 0 } lbm_tunable;
+ * tile, so a row's z-neighbours are read while still cached.  Results do not
+ * depend on it.
+ * LBM_TUNE_SWEEP: 1 (default where available) = node-compact sweep, one lane
+ * per gas node; 0 = one wavefront per 64-voxel chunk of an x-row (solid
+ * voxels leave lanes idle).  The two compute the same values; the totals
+ * may differ in the last bits (per-block partial sums group nodes
+ * differently).  The compact sweep needs ny, nz <= 1024 (LBM_EUNSUPPORTED
+ * otherwise). */
+typedef enum { LBM_TUNE_YTILE = 0, LBM_TUNE_SWEEP = 1 } lbm_tunable;
 lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value);   /* LBM_EINVAL: unknown or out of range */
 lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value);
+
+/*
+ * lbm_autotune - pick the launch shape: time `reps` (1..1000) sweeps for each
+ * candidate (sweep variant x y-tile in {4, 8, 16, 32, 64, 128}, clamped to
+ * ny) and keep the fastest.  The trial sweeps run in place; the population
+ * buffer and link buffer they overwrite are saved to temporary device memory
+ * first and restored afterwards, so the state (and every later result) is
+ * exactly as before the call.  best_ms (may be NULL) receives the mean sweep
+ * time of the winner.  Synchronises the stream.
+ */
+lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms);
 
 /* Per-kernel HIP-event timing: enable (1) / disable (0) and read; reading
  * synchronises the stream.  Reset on enable. */
@@ -303,6 +321,13 @@ lbm_status lbm_batch_totals(lbm_batch *b, int32_t i, lbm_totals_t *t);
 lbm_status lbm_batch_query(const lbm_batch *b, int32_t i, lbm_info *info);
 lbm_status lbm_batch_synchronize(lbm_batch *b);
 lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t enable);
+/* Tunables of every sample (see lbm_set_tunable).  LBM_TUNE_SWEEP applies to
+ * the whole batch (1 needs every sample to support the compact sweep);
+ * LBM_TUNE_YTILE is clamped to each sample's ny; get reports sample 0's. */
+lbm_status lbm_batch_set_tunable(lbm_batch *b, int32_t which, int64_t value);
+lbm_status lbm_batch_get_tunable(const lbm_batch *b, int32_t which, int64_t *value);
+/* lbm_autotune for the batched sweep: one variant and y-tile for the batch. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, double *best_ms);
 const char *lbm_batch_last_error(const lbm_batch *b);
 void lbm_batch_destroy(lbm_batch *b);
 

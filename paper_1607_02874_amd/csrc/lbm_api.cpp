@@ -74,6 +74,12 @@ struct lbm_ctx {
     int64_t step = 0;
     int64_t blocks_sweep = 0, blocks_iface = 0;
     int ytile = 16;       // rows per y-tile of the sweep traversal
+    // node-compact sweep: per-node coordinates, wave launch order, per-wave
+    // link base; compact = 1 selects it (needs ny, nz <= 1024)
+    uint32_t *d_pos = nullptr, *d_worder = nullptr, *d_wlink = nullptr;
+    int64_t nwaves = 0;
+    bool compact_ok = false;
+    int compact = 0;
 
     // watchdog
     int32_t *h_flag = nullptr;
@@ -146,7 +152,41 @@ Geometry geometry(const lbm_ctx *c) {
     g.pad = 0;
     g.nfp = c->nfp;
     g.nfluid = c->nfluid;
+    g.pos = c->d_pos;
+    g.worder = c->d_worder;
+    g.wlink = c->d_wlink;
+    g.nwaves = uint32_t(c->nwaves);
+    g.pad2 = 0;
     return g;
+}
+
+// Sweep blocks of the variant in use (the partial sums have one row each).
+int64_t active_sweep_blocks(const lbm_ctx *c) {
+    return c->compact ? sweep_blocks_c(geometry(c)) : c->blocks_sweep;
+}
+
+// Launch order of the node-compact waves: wave w (storage indices 64 w ..)
+// goes with the row of its first node, rows in the y-tiled order of
+// build_order, waves of one row in storage order.
+void build_wave_order(const lbm_ctx *c, const std::vector<uint32_t> &pos, int ytile, std::vector<uint32_t> &worder) {
+    std::vector<uint32_t> order(size_t(int64_t(c->ny) * c->nz * c->W));
+    build_order(c->nx, c->ny, c->nz, ytile, order.data());
+    std::vector<uint32_t> row_seq(size_t(int64_t(c->ny) * c->nz), 0);
+    uint32_t seq = 0;
+    for (uint32_t code : order) {
+        if ((code >> 24) != 0) continue;  // first chunk of each row
+        const uint32_t y = code & 0xfffu, z = (code >> 12) & 0xfffu;
+        row_seq[size_t(z) * c->ny + y] = seq++;
+    }
+    std::vector<uint64_t> key(size_t(c->nwaves));
+    for (int64_t w = 0; w < c->nwaves; ++w) {
+        const uint32_t p = pos[size_t(w * 64)];
+        const uint32_t y = (p >> 12) & 0x3ffu, z = p >> 22;
+        key[size_t(w)] = (uint64_t(row_seq[size_t(z) * c->ny + y]) << 32) | uint64_t(w);
+    }
+    std::sort(key.begin(), key.end());
+    worder.resize(size_t(c->nwaves));
+    for (size_t k = 0; k < key.size(); ++k) worder[k] = uint32_t(key[k] & 0xffffffffu);
 }
 
 Interface interface_list(const lbm_ctx *c) {
@@ -243,7 +283,8 @@ void build_interface(lbm_ctx *c, std::vector<uint32_t> &vox, std::vector<uint32_
 // each 64-voxel chunk; map lists, per interface node and active link j
 // (ascending), the slot its arriving population is written to.
 void build_links(const lbm_ctx *c, const std::vector<uint32_t> &ivox, const std::vector<uint32_t> &imask,
-                 std::vector<uint32_t> &start, std::vector<uint32_t> &map, std::vector<uint32_t> &link_base) {
+                 std::vector<uint32_t> &start, std::vector<uint32_t> &map, std::vector<uint32_t> &link_base,
+                 std::vector<uint32_t> &wlink) {
     const bool xper = c->ph.species_x == XB_PERIODIC;
     std::vector<int32_t> iface_of(size_t(c->n), -1);
     for (size_t k = 0; k < ivox.size(); ++k) iface_of[ivox[k]] = int32_t(k);
@@ -251,12 +292,16 @@ void build_links(const lbm_ctx *c, const std::vector<uint32_t> &ivox, const std:
     for (size_t k = 0; k < ivox.size(); ++k) start[k + 1] = start[k] + uint32_t(__builtin_popcount(imask[k]));
     map.assign(start.back(), 0);
     link_base.assign(size_t(int64_t(c->ny) * c->nz * c->W), 0);
+    wlink.assign(size_t((c->nfluid + 63) / 64), 0);
     uint32_t slot = 0;
+    int64_t rank = 0;
     for (int z = 0; z < c->nz; ++z)
         for (int y = 0; y < c->ny; ++y)
             for (int x = 0; x < c->nx; ++x) {
                 if ((x & 63) == 0) link_base[size_t((int64_t(z) * c->ny + y) * c->W + (x >> 6))] = slot;
                 if (c->vox[size_t((int64_t(z) * c->ny + y) * c->nx + x)] != LBM_FLUID) continue;
+                if ((rank & 63) == 0) wlink[size_t(rank >> 6)] = slot;
+                ++rank;
                 for (int i = 1; i < 19; ++i) {
                     int xs = x - CX[i];
                     if (xs < 0 || xs >= c->nx) {
@@ -322,11 +367,13 @@ lbm_status one_step(lbm_ctx *c) {
     if (r) (void)hipEventRecord(r->ev[2], c->stream);  // no separate boundary-flux kernel:
     if (r) (void)hipEventRecord(r->ev[3], c->stream);  // the sweep tallies the x-planes
     if (r) (void)hipEventRecord(r->ev[4], c->stream);
-    e = launch_sweep(g, c->ph, fin, fout, c->d_emit, ps, c->stream);
+    e = c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, ps, c->stream)
+                   : launch_sweep(g, c->ph, fin, fout, c->d_emit, ps, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "sweep kernel launch");
     if (r) (void)hipEventRecord(r->ev[5], c->stream);
     if (r) (void)hipEventRecord(r->ev[6], c->stream);
-    e = launch_reduce(ps, c->blocks_sweep, pi, c->blocks_iface, fold, c->ph.p, c->ph.p_stick, c->d_tot, c->stream);
+    e = launch_reduce(ps, active_sweep_blocks(c), pi, c->blocks_iface, fold, c->ph.p, c->ph.p_stick, c->d_tot,
+                      c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
     if (r) {
         (void)hipEventRecord(r->ev[7], c->stream);
@@ -458,8 +505,23 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         build_interface(c, ivox, imask, iscale);
         c->niface = int64_t(ivox.size());
         c->iface_vox = ivox;
-        std::vector<uint32_t> istart, lmap, lbase;
-        build_links(c, ivox, imask, istart, lmap, lbase);
+        std::vector<uint32_t> istart, lmap, lbase, wlink;
+        c->nwaves = (c->nfluid + 63) / 64;
+        build_links(c, ivox, imask, istart, lmap, lbase, wlink);
+        // node-compact sweep tables (coordinates packed as x | y << 12 | z << 22)
+        c->compact_ok = c->ny <= 1024 && c->nz <= 1024 && c->nfluid > 0;
+        std::vector<uint32_t> pos, worder;
+        if (c->compact_ok) {
+            pos.assign(size_t(c->nfp), 0);
+            size_t r = 0;
+            for (int z = 0; z < c->nz; ++z)
+                for (int y = 0; y < c->ny; ++y)
+                    for (int x = 0; x < c->nx; ++x)
+                        if (c->vox[size_t((int64_t(z) * c->ny + y) * c->nx + x)] == LBM_FLUID)
+                            pos[r++] = uint32_t(x) | (uint32_t(y) << 12) | (uint32_t(z) << 22);
+            build_wave_order(c, pos, std::min(c->ytile, c->ny), worder);
+            c->compact = 1;
+        }
 
         // The kernels address every buffer with 32-bit byte offsets from a
         // scalar base: a population pair (2 nfp elements), the emission array
@@ -492,6 +554,11 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         c->d_link_map = static_cast<uint32_t *>(dev_alloc(c, lmap.size() * 4));
         c->d_link_base = static_cast<uint32_t *>(dev_alloc(c, lbase.size() * 4));
         c->d_link = dev_alloc(c, lmap.size() * size_t(storage_bytes(c->ph.storage)));
+        if (c->compact_ok) {
+            c->d_pos = static_cast<uint32_t *>(dev_alloc(c, pos.size() * 4));
+            c->d_worder = static_cast<uint32_t *>(dev_alloc(c, worder.size() * 4));
+            c->d_wlink = static_cast<uint32_t *>(dev_alloc(c, wlink.size() * 4));
+        }
         // One pool: population buffers A and B, then the emission array.  The
         // sweep addresses all three from one base with integer offsets, so the
         // emission array must start a whole number of direction strides (nfp
@@ -507,7 +574,8 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         c->d_tot = static_cast<DevTotals *>(dev_alloc(c, sizeof(DevTotals)));
         if (!c->d_chunks || !c->d_order || !c->d_iface_start || !c->d_link_map || !c->d_link_base ||
             !c->d_link || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
-            !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot) {
+            !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot ||
+            (c->compact_ok && (!c->d_pos || !c->d_worder || !c->d_wlink))) {
             release(c);
             delete c;
             return fail(nullptr, LBM_ENOMEM, "device allocation failed");
@@ -524,6 +592,11 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         up(c->d_iface_start, istart.data(), istart.size() * 4);
         up(c->d_link_map, lmap.data(), lmap.size() * 4);
         up(c->d_link_base, lbase.data(), lbase.size() * 4);
+        if (c->compact_ok) {
+            up(c->d_pos, pos.data(), pos.size() * 4);
+            up(c->d_worder, worder.data(), worder.size() * 4);
+            up(c->d_wlink, wlink.data(), wlink.size() * 4);
+        }
         if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, size_t(c->n) * sb, c->stream);
         DevTotals t0{};
@@ -745,7 +818,23 @@ lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value) {
         if (e == hipSuccess)
             e = hipMemcpy(c->d_order, order.data(), order.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(c, e, "traversal table upload");
+        if (c->compact_ok) {
+            std::vector<uint32_t> pos(size_t(c->nwaves) * 64), worder;
+            e = hipMemcpy(pos.data(), c->d_pos, std::min(pos.size(), size_t(c->nfp)) * 4, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) {
+                build_wave_order(c, pos, int(value), worder);
+                e = hipMemcpy(c->d_worder, worder.data(), worder.size() * 4, hipMemcpyHostToDevice);
+            }
+            if (e != hipSuccess) return hip_fail(c, e, "wave order upload");
+        }
         c->ytile = int(value);
+        return LBM_OK;
+    }
+    if (which == LBM_TUNE_SWEEP) {
+        if (value != 0 && value != 1) return fail(c, LBM_EINVAL, "sweep variant must be 0 or 1");
+        if (value == 1 && !c->compact_ok)
+            return fail(c, LBM_EUNSUPPORTED, "the node-compact sweep needs ny, nz <= 1024 and a gas node");
+        c->compact = int(value);
         return LBM_OK;
     }
     return fail(c, LBM_EINVAL, "unknown tunable");
@@ -755,6 +844,10 @@ lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value) {
     if (!c || !value) return LBM_EINVAL;
     if (which == LBM_TUNE_YTILE) {
         *value = c->ytile;
+        return LBM_OK;
+    }
+    if (which == LBM_TUNE_SWEEP) {
+        *value = c->compact;
         return LBM_OK;
     }
     return LBM_EINVAL;
@@ -905,6 +998,148 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
     return LBM_OK;
 }
 
+// Autotuner: time the sweep for every candidate (sweep variant x y-tile)
+// in place, then restore what the trial sweeps overwrote.  A sweep reads the
+// current post-collision buffer and the emission array and writes only the
+// other population buffer, the link buffer and its partial sums, so saving
+// and restoring the first two leaves the state exactly as it was.
+}  // extern "C"
+
+namespace {
+
+struct Candidate {
+    int compact, ytile;
+};
+
+std::vector<Candidate> tuning_candidates(bool compact_ok, int ny) {
+    std::vector<Candidate> out;
+    const int ytiles[] = {4, 8, 16, 32, 64, 128};
+    for (int v = 0; v <= (compact_ok ? 1 : 0); ++v) {
+        int last = -1;
+        for (int yt : ytiles) {
+            const int t = std::min(yt, ny);
+            if (t == last) continue;
+            out.push_back({v, t});
+            last = t;
+        }
+    }
+    return out;
+}
+
+struct Saved {
+    void *pop = nullptr, *link = nullptr;
+};
+
+lbm_status save_written(lbm_ctx *c, Saved &sv, void *(*alloc)(lbm_ctx *, size_t)) {
+    const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
+    const size_t link = size_t(c->nlinks) * storage_bytes(c->ph.storage);
+    sv.pop = alloc(c, pop);
+    sv.link = alloc(c, std::max<size_t>(link, 256));
+    if (!sv.pop || !sv.link) return fail(c, LBM_ENOMEM, "autotune scratch allocation failed");
+    hipError_t e = hipMemcpyAsync(sv.pop, c->d_pop[1 - c->cur], pop, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && link) e = hipMemcpyAsync(sv.link, c->d_link, link, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune save");
+    return LBM_OK;
+}
+
+lbm_status restore_written(lbm_ctx *c, Saved &sv) {
+    const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
+    const size_t link = size_t(c->nlinks) * storage_bytes(c->ph.storage);
+    hipError_t e = hipMemcpyAsync(c->d_pop[1 - c->cur], sv.pop, pop, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && link) e = hipMemcpyAsync(c->d_link, sv.link, link, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune restore");
+    return LBM_OK;
+}
+
+void *scratch_alloc(lbm_ctx *c, size_t bytes) {
+    void *p = nullptr;
+    if (c->dev.alloc)
+        p = c->dev.alloc(bytes, c->dev.user);
+    else if (hipMalloc(&p, bytes) != hipSuccess)
+        p = nullptr;
+    return p;
+}
+
+void scratch_free(lbm_ctx *c, void *p) {
+    if (!p) return;
+    if (c->dev.free)
+        c->dev.free(p, c->dev.user);
+    else
+        (void)hipFree(p);
+}
+
+// Mean time of `reps` launches of `launch` (after one untimed launch).
+template <typename F>
+lbm_status time_launches(hipStream_t s, int reps, F &&launch, float *ms, std::string *err) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) {
+        *err = std::string("autotune timing: ") + hipGetErrorString(e);
+        return LBM_EDEVICE;
+    }
+    *ms /= float(reps);
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (reps < 1 || reps > 1000) return fail(c, LBM_EINVAL, "reps must be in [1, 1000]");
+    lbm_status st = check_pending_flag(c);
+    if (st != LBM_OK) return st;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune");
+    Saved sv;
+    st = save_written(c, sv, scratch_alloc);
+    const Candidate keep{c->compact, c->ytile};
+    Candidate best = keep;
+    float best_t = 0.0f;
+    if (st == LBM_OK) {
+        for (const Candidate &cd : tuning_candidates(c->compact_ok, c->ny)) {
+            st = lbm_set_tunable(c, LBM_TUNE_YTILE, cd.ytile);
+            if (st == LBM_OK) st = lbm_set_tunable(c, LBM_TUNE_SWEEP, cd.compact);
+            if (st != LBM_OK) break;
+            const Geometry g = geometry(c);
+            const void *fin = c->d_pop[c->cur];
+            void *fout = c->d_pop[1 - c->cur];
+            float ms = 0.0f;
+            st = time_launches(c->stream, reps, [&]() {
+                return c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, c->d_part, c->stream)
+                                  : launch_sweep(g, c->ph, fin, fout, c->d_emit, c->d_part, c->stream);
+            }, &ms, &c->err);
+            if (st != LBM_OK) break;
+            if (best_t == 0.0f || ms < best_t) {
+                best_t = ms;
+                best = cd;
+            }
+        }
+    }
+    lbm_status rs = sv.pop ? restore_written(c, sv) : LBM_OK;
+    scratch_free(c, sv.pop);
+    scratch_free(c, sv.link);
+    const Candidate use = st == LBM_OK ? best : keep;
+    lbm_status ts = lbm_set_tunable(c, LBM_TUNE_YTILE, use.ytile);
+    if (ts == LBM_OK) ts = lbm_set_tunable(c, LBM_TUNE_SWEEP, use.compact);
+    if (st != LBM_OK) return st;
+    if (rs != LBM_OK) return rs;
+    if (ts != LBM_OK) return ts;
+    if (best_ms) *best_ms = double(best_t);
+    return LBM_OK;
+}
+
 const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 void lbm_destroy(lbm_ctx *c) {
@@ -922,6 +1157,7 @@ struct lbm_batch {
     lbm_device dev{};
     hipStream_t stream = nullptr;
     int storage = 0, sputter = 0;
+    bool compact = false;  // node-compact sweep for every sample (all support it)
     std::vector<void *> allocations;
     void *d_records = nullptr;
     ReduceK *d_reduce = nullptr;
@@ -977,9 +1213,9 @@ void *batch_alloc(lbm_batch *b, size_t bytes) {
 }
 
 lbm_status batch_launch(lbm_batch *b, int parity, hipStream_t s) {
-    hipError_t e = launch_batch_step(b->storage, b->sputter, b->d_records, b->d_sweep_sample, b->sweep_blocks_total,
-                                     b->d_iface_sample, b->iface_blocks_total, b->d_reduce, int(b->ctx.size()),
-                                     parity, s);
+    hipError_t e = launch_batch_step(b->storage, b->sputter, b->compact, b->d_records, b->d_sweep_sample,
+                                     b->sweep_blocks_total, b->d_iface_sample, b->iface_blocks_total, b->d_reduce,
+                                     int(b->ctx.size()), parity, s);
     if (e != hipSuccess) return bfail(b, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
                                       std::string("batch step launch: ") + hipGetErrorString(e));
     return LBM_OK;
@@ -1022,6 +1258,71 @@ lbm_status batch_forward(lbm_batch *b, int32_t i, lbm_status st) {
     return st;
 }
 
+// Per-sample block ranges (samples in order, each with its single-sample
+// block count for the batch's sweep variant), the block-to-sample tables and
+// the device records; every context is switched to the batch's variant so a
+// sample's single-context calls match its batched steps.
+lbm_status batch_tables(lbm_batch *b) {
+    const int n = int(b->ctx.size());
+    for (lbm_ctx *c : b->ctx) c->compact = b->compact ? 1 : 0;
+    std::vector<BatchSample> smp(static_cast<size_t>(n));
+    std::vector<ReduceK> red(static_cast<size_t>(n));
+    int64_t nb = 0, ni = 0;
+    for (int i = 0; i < n; ++i) {
+        lbm_ctx *c = b->ctx[size_t(i)];
+        BatchSample &s = smp[size_t(i)];
+        s.g = geometry(c);
+        s.it = interface_list(c);
+        s.ph = c->ph;
+        s.pop[0] = c->d_pop[0];
+        s.pop[1] = c->d_pop[1];
+        s.emit = c->d_emit;
+        s.part_sweep = c->d_part;
+        s.part_iface = c->d_part + 4 * c->blocks_sweep;
+        s.block0 = uint32_t(nb);
+        s.iblock0 = uint32_t(ni);
+        nb += active_sweep_blocks(c);
+        ni += c->blocks_iface;
+        ReduceK &r = red[size_t(i)];
+        r.ps = s.part_sweep;
+        r.ns = active_sweep_blocks(c);
+        r.pi = s.part_iface;
+        r.ni = c->blocks_iface;
+        r.fold = s.part_iface + c->blocks_iface;
+        r.p = c->ph.p;
+        r.p_stick = c->ph.p_stick;
+        r.tot = c->d_tot;
+    }
+    b->sweep_blocks_total = nb;
+    b->iface_blocks_total = ni;
+    std::vector<uint32_t> sweep_sample(size_t(std::max<int64_t>(nb, 1))), iface_sample(size_t(std::max<int64_t>(ni, 1)));
+    for (int i = 0; i < n; ++i) {
+        const lbm_ctx *c = b->ctx[size_t(i)];
+        std::fill_n(sweep_sample.begin() + smp[size_t(i)].block0, active_sweep_blocks(c), uint32_t(i));
+        std::fill_n(iface_sample.begin() + smp[size_t(i)].iblock0, c->blocks_iface, uint32_t(i));
+    }
+    hipError_t e = hipStreamSynchronize(b->stream);  // earlier steps may still read the tables
+    if (e == hipSuccess) e = batch_upload(b->storage, smp.data(), n, b->d_records, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_reduce, red.data(), red.size() * sizeof(ReduceK), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_sweep_sample, sweep_sample.data(), sweep_sample.size() * 4, hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_iface_sample, iface_sample.data(), iface_sample.size() * 4, hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch upload: ") + hipGetErrorString(e));
+    // captured graphs hold the old launch shapes
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
+    return LBM_OK;
+}
+
 }  // namespace
 
 lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, const double *da,
@@ -1054,73 +1355,35 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
             }
             b->ctx.push_back(c);
         }
-        // Logical block ranges: samples in order, each with its single-sample
-        // block count.
-        std::vector<BatchSample> smp(static_cast<size_t>(n));
-        std::vector<ReduceK> red(static_cast<size_t>(n));
-        int64_t nb = 0, ni = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            lbm_ctx *c = b->ctx[size_t(i)];
-            BatchSample &s = smp[size_t(i)];
-            s.g = geometry(c);
-            s.it = interface_list(c);
-            s.ph = c->ph;
-            s.pop[0] = c->d_pop[0];
-            s.pop[1] = c->d_pop[1];
-            s.emit = c->d_emit;
-            s.part_sweep = c->d_part;
-            s.part_iface = c->d_part + 4 * c->blocks_sweep;
-            s.block0 = uint32_t(nb);
-            s.iblock0 = uint32_t(ni);
-            nb += c->blocks_sweep;
+        // One sweep variant for all samples: node-compact if every sample
+        // supports it.
+        b->compact = true;
+        for (lbm_ctx *c : b->ctx) b->compact = b->compact && c->compact_ok;
+        int64_t nb_max = 0, ni = 0;
+        for (lbm_ctx *c : b->ctx) {
+            nb_max += c->blocks_sweep;  // the chunk sweep has the most blocks
             ni += c->blocks_iface;
-            ReduceK &r = red[size_t(i)];
-            r.ps = s.part_sweep;
-            r.ns = c->blocks_sweep;
-            r.pi = s.part_iface;
-            r.ni = c->blocks_iface;
-            r.fold = s.part_iface + c->blocks_iface;
-            r.p = c->ph.p;
-            r.p_stick = c->ph.p_stick;
-            r.tot = c->d_tot;
         }
-        if (nb >= (int64_t(1) << 31) || ni >= (int64_t(1) << 31)) {
+        if (nb_max >= (int64_t(1) << 31) || ni >= (int64_t(1) << 31)) {
             batch_release(b);
             delete b;
             return bfail(nullptr, LBM_EINVAL, "batch too large for one launch");
         }
-        b->sweep_blocks_total = nb;
-        b->iface_blocks_total = ni;
-        std::vector<uint32_t> sweep_sample(size_t(std::max<int64_t>(nb, 1))), iface_sample(size_t(std::max<int64_t>(ni, 1)));
-        for (int32_t i = 0; i < n; ++i) {
-            const lbm_ctx *c = b->ctx[size_t(i)];
-            std::fill_n(sweep_sample.begin() + smp[size_t(i)].block0, c->blocks_sweep, uint32_t(i));
-            std::fill_n(iface_sample.begin() + smp[size_t(i)].iblock0, c->blocks_iface, uint32_t(i));
-        }
         b->d_records = batch_alloc(b, batch_record_bytes(b->storage) * size_t(n));
         b->d_reduce = static_cast<ReduceK *>(batch_alloc(b, sizeof(ReduceK) * size_t(n)));
-        b->d_sweep_sample = static_cast<uint32_t *>(batch_alloc(b, sweep_sample.size() * 4));
-        b->d_iface_sample = static_cast<uint32_t *>(batch_alloc(b, iface_sample.size() * 4));
+        b->d_sweep_sample = static_cast<uint32_t *>(batch_alloc(b, size_t(std::max<int64_t>(nb_max, 1)) * 4));
+        b->d_iface_sample = static_cast<uint32_t *>(batch_alloc(b, size_t(std::max<int64_t>(ni, 1)) * 4));
         if (!b->d_records || !b->d_reduce || !b->d_sweep_sample || !b->d_iface_sample) {
             batch_release(b);
             delete b;
             return bfail(nullptr, LBM_ENOMEM, "device allocation failed");
         }
-        hipError_t e = batch_upload(b->storage, smp.data(), n, b->d_records, b->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->d_reduce, red.data(), red.size() * sizeof(ReduceK), hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->d_sweep_sample, sweep_sample.data(), sweep_sample.size() * 4, hipMemcpyHostToDevice,
-                               b->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->d_iface_sample, iface_sample.data(), iface_sample.size() * 4, hipMemcpyHostToDevice,
-                               b->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-        if (e != hipSuccess) {
-            std::string msg = std::string("batch upload: ") + hipGetErrorString(e);
+        const lbm_status st = batch_tables(b);
+        if (st != LBM_OK) {
+            std::string msg = b->err;
             batch_release(b);
             delete b;
-            return bfail(nullptr, LBM_EDEVICE, msg);
+            return bfail(nullptr, st, msg);
         }
     } catch (const std::bad_alloc &) {
         batch_release(b);
@@ -1217,6 +1480,95 @@ lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t enable) {
     if (!b) return LBM_EINVAL;
     if (enable != 0 && enable != 1) return bfail(b, LBM_EINVAL, "enable must be 0 or 1");
     b->use_graph = enable == 1;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_tunable(lbm_batch *b, int32_t which, int64_t value) {
+    if (!b) return LBM_EINVAL;
+    if (which == LBM_TUNE_SWEEP) {
+        if (value != 0 && value != 1) return bfail(b, LBM_EINVAL, "sweep variant must be 0 or 1");
+        if (value == 1)
+            for (const lbm_ctx *c : b->ctx)
+                if (!c->compact_ok) return bfail(b, LBM_EUNSUPPORTED, "a sample does not support the compact sweep");
+        b->compact = value == 1;
+        return batch_tables(b);
+    }
+    if (which == LBM_TUNE_YTILE) {
+        if (value < 1) return bfail(b, LBM_EINVAL, "ytile must be >= 1");
+        for (size_t i = 0; i < b->ctx.size(); ++i) {
+            lbm_ctx *c = b->ctx[i];
+            const lbm_status st = lbm_set_tunable(c, LBM_TUNE_YTILE, std::min<int64_t>(value, c->ny));
+            if (st != LBM_OK) return batch_forward(b, int32_t(i), st);
+        }
+        return LBM_OK;
+    }
+    return bfail(b, LBM_EINVAL, "unknown tunable");
+}
+
+lbm_status lbm_batch_get_tunable(const lbm_batch *b, int32_t which, int64_t *value) {
+    if (!b || !value || b->ctx.empty()) return LBM_EINVAL;
+    if (which == LBM_TUNE_SWEEP) {
+        *value = b->compact ? 1 : 0;
+        return LBM_OK;
+    }
+    return lbm_get_tunable(b->ctx[0], which, value);
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, double *best_ms) {
+    if (!b) return LBM_EINVAL;
+    if (reps < 1 || reps > 1000) return bfail(b, LBM_EINVAL, "reps must be in [1, 1000]");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        const lbm_status st = check_pending_flag(b->ctx[i]);
+        if (st != LBM_OK) return batch_forward(b, int32_t(i), st);
+    }
+    bool compact_ok = true;
+    int ny_max = 1;
+    for (const lbm_ctx *c : b->ctx) {
+        compact_ok = compact_ok && c->compact_ok;
+        ny_max = std::max(ny_max, c->ny);
+    }
+    std::vector<Saved> sv(b->ctx.size());
+    lbm_status st = LBM_OK;
+    for (size_t i = 0; i < b->ctx.size() && st == LBM_OK; ++i) {
+        st = save_written(b->ctx[i], sv[i], scratch_alloc);
+        if (st != LBM_OK) st = batch_forward(b, int32_t(i), st);
+    }
+    const Candidate keep{b->compact ? 1 : 0, b->ctx[0]->ytile};
+    Candidate best = keep;
+    float best_t = 0.0f;
+    if (st == LBM_OK) {
+        for (const Candidate &cd : tuning_candidates(compact_ok, ny_max)) {
+            st = lbm_batch_set_tunable(b, LBM_TUNE_YTILE, cd.ytile);
+            if (st == LBM_OK) st = lbm_batch_set_tunable(b, LBM_TUNE_SWEEP, cd.compact);
+            if (st != LBM_OK) break;
+            const int parity = b->parity;
+            float ms = 0.0f;
+            st = time_launches(b->stream, reps, [&]() {
+                return launch_batch_sweep(b->storage, b->sputter, b->compact, b->d_records, b->d_sweep_sample,
+                                          b->sweep_blocks_total, parity, b->stream);
+            }, &ms, &b->err);
+            if (st != LBM_OK) break;
+            if (best_t == 0.0f || ms < best_t) {
+                best_t = ms;
+                best = cd;
+            }
+        }
+    }
+    lbm_status rs = LBM_OK;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        if (sv[i].pop && rs == LBM_OK) rs = restore_written(b->ctx[i], sv[i]);
+        scratch_free(b->ctx[i], sv[i].pop);
+        scratch_free(b->ctx[i], sv[i].link);
+    }
+    const Candidate use = st == LBM_OK ? best : keep;
+    lbm_status ts = lbm_batch_set_tunable(b, LBM_TUNE_YTILE, use.ytile);
+    if (ts == LBM_OK) ts = lbm_batch_set_tunable(b, LBM_TUNE_SWEEP, use.compact);
+    if (st != LBM_OK) return st;
+    if (rs != LBM_OK) return bfail(b, rs, "autotune restore failed");
+    if (ts != LBM_OK) return ts;
+    if (best_ms) *best_ms = double(best_t);
     return LBM_OK;
 }
 

@@ -68,6 +68,13 @@ struct Geometry {
     int32_t pad;
     int64_t nfp;              // elements per direction in a population buffer
     int64_t nfluid;
+    // Node-compact sweep (one lane per gas node, 64 consecutive storage
+    // indices per wave); null when the lattice is too large for `pos`.
+    const uint32_t *pos;      // per gas node: x | y << 12 | z << 22
+    const uint32_t *worder;   // launch order of the 64-node waves
+    const uint32_t *wlink;    // per 64-node wave: first link-buffer slot it exports
+    uint32_t nwaves;          // ceil(nfluid / 64)
+    int32_t pad2;
 };
 
 // Physical parameters in FP64; kernels convert to their compute type.
@@ -108,6 +115,10 @@ hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interfac
 hipError_t launch_export(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s);
 hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
                         double *part, hipStream_t s);
+// The node-compact sweep (same results; needs g.pos, g.worder, g.wlink).
+hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
+                          double *part, hipStream_t s);
+int64_t sweep_blocks_c(const Geometry &g);
 // mode 1: moments after streaming fin (fields at step >= 1); mode 2: local
 // moments of fin (the initial state, step 0).  Outputs are float arrays, or
 // double arrays when out_f64 is set; any output may be null.
@@ -159,10 +170,13 @@ struct ReduceK {
 // built from `smp` (synchronous on `s`).
 size_t batch_record_bytes(int storage);
 hipError_t batch_upload(int storage, const BatchSample *smp, int n, void *d_records, hipStream_t s);
+// The batched sweep alone (reads buffer `parity` of every sample).
+hipError_t launch_batch_sweep(int storage, int sputter, bool compact, const void *d_records,
+                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, int parity, hipStream_t s);
 // One step of every sample: batched interface, sweep (reading population
 // buffer `parity` of every sample, writing the other) and reduction.
-hipError_t launch_batch_step(int storage, int sputter, const void *d_records, const uint32_t *sweep_sample,
-                             int64_t sweep_blocks_total, const uint32_t *iface_sample, int64_t iface_blocks_total,
-                             const ReduceK *d_reduce, int n, int parity, hipStream_t s);
+hipError_t launch_batch_step(int storage, int sputter, bool compact, const void *d_records,
+                             const uint32_t *sweep_sample, int64_t sweep_blocks_total, const uint32_t *iface_sample,
+                             int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s);
 
 }  // namespace lbmk

@@ -176,7 +176,8 @@ struct WaveUnit {
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {
     // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of rows so neighbouring rows share its L2.
+    // contiguous range of rows so neighbouring rows share its L2.  The sweep
+    // grids are padded to a multiple of 8 blocks; other grids keep their order.
     const int per = nb >> 3;
     if ((nb & 7) != 0 || per == 0) return b;
     return (b & 7) * per + (b >> 3);
@@ -352,6 +353,113 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const T v = Store<ST>::cv(rr[i]);
         const T e = Store<ST>::cv(re[i]);
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
+        hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
+    }
+    cat_out = cat_bits;
+}
+
+// The same pull for the node-compact sweep: each lane is one gas node at
+// (x, y, z) with storage index idx, lanes of a wave need not share a row.  For
+// each of the nine source rows a lane reads the record of its own chunk in
+// that row and takes a three-bit window (x - 1, x, x + 1) of its gas and
+// catalytic masks; the chunk's edge bits and periodic neighbour ranks stand
+// in where x -+ 1 leaves the chunk.  Same sources, same arithmetic and same
+// decode as pull() above.
+template <int ST, int SP>
+__device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
+                                       const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
+                                       int z, typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
+                                       uint32_t &cat_out) {
+    using T = typename Store<ST>::T;
+    using S = typename Store<ST>::S;
+    constexpr uint32_t SB = sizeof(S);
+    const int64_t nfp = g.nfp;
+    const uint32_t nfp_b = uint32_t(nfp) * SB;
+    const uint32_t slot_b = uint32_t(nfp - 1) * SB;
+    const bool reservoir = ph.species_x == XB_RESERVOIR;
+    const int sputter = SP >= 0 ? SP : ph.sputter;
+    const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
+    auto base = [&](int slot) { return static_cast<const S *>(in.p[slot]); };
+    const uint32_t own_b = idx * SB;
+    const uint32_t xl = uint32_t(x) & 63u, chunk = uint32_t(x) >> 6;
+    const bool ledge = xl == 0u;                       // x - 1 lies in the previous chunk (or wraps)
+    const bool redge = xl == 63u || x == g.nx - 1;     // x + 1 lies in the next chunk (or wraps)
+    const bool first_x = x == 0, last_x = x == g.nx - 1;
+    const uint32_t shr = ledge ? 0u : xl - 1u;
+    const uint64_t below = (uint64_t(1) << xl) - 1u;
+
+    S rc[19], rr[19], re[19];
+    uint32_t cat_bits = 0;
+    rc[0] = ld_at(base(dslot(0)), own_b);
+    rr[0] = ld_at(base(19 + dslot(0)), own_b);
+#pragma unroll
+    for (int cls = 0; cls < 9; ++cls) {
+        // source row class (cy, cz) of directions ORDER[..] in this group
+        constexpr int CYS[9] = {0, 1, -1, 0, 0, 1, 1, -1, -1};
+        constexpr int CZS[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+        const int cy = CYS[cls], cz = CZS[cls];
+        int ys = y - cy, zs = z - cz;
+        ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+        zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
+        const uint32_t rown = uint32_t(zs) * uint32_t(g.ny) + uint32_t(ys);
+        const LBM_GLOBAL ChunkInfo &R = glb(g.chunks)[rown * uint32_t(g.W) + chunk];
+        const uint64_t fm = R.fluid, cm = R.cat;
+        const uint32_t e = R.edge;
+        // bit 0: x - 1, bit 1: x, bit 2: x + 1
+        uint32_t wf = uint32_t(ledge ? fm << 1 : fm >> shr) & 7u;
+        uint32_t wc = uint32_t(ledge ? cm << 1 : cm >> shr) & 7u;
+        wf |= ledge ? (e & 1u) : 0u;
+        wc |= ledge ? ((e >> 1) & 1u) : 0u;
+        wf = redge ? (wf & 3u) | (((e >> 2) & 1u) << 2) : wf;
+        wc = redge ? (wc & 3u) | (((e >> 3) & 1u) << 2) : wc;
+        const uint32_t r0 = R.base + uint32_t(__popcll(fm & below));
+        const uint32_t rm = ledge ? R.prev_rank : r0 - 1u;
+        const uint32_t rp = redge ? R.next_rank : r0 + ((wf >> 1) & 1u);
+        const uint32_t rv = rown * uint32_t(g.nx);
+#pragma unroll
+        for (int k = 0; k < 18; ++k) {
+            const int i = ORDER[k];
+            if (CY[i] != cy || CZ[i] != cz) continue;
+            const int cx = CX[i];
+            const uint32_t bit = uint32_t(1 - cx);
+            const bool F = (wf >> bit) & 1u, C = (wc >> bit) & 1u;
+            const uint32_t rank = cx == 0 ? r0 : (cx == 1 ? rm : rp);
+            const uint32_t half = dslot(i) < dslot(opp(i)) ? 0u : nfp_b;
+            const uint32_t bb_b = own_b + (nfp_b - half);
+            const uint32_t pull_b = rank * SB + half;
+            uint32_t c_b = F ? pull_b : bb_b;
+            opaque(c_b);
+            rc[i] = ld_at(base(pair_slot(i)), c_b);
+            const bool inlet = reservoir && cx == 1 && first_x;
+            const bool outlet = reservoir && cx == -1 && last_x;  // copies plane nx - 1
+            const bool F0 = (wf >> 1) & 1u;
+            const bool SF = outlet ? F0 : (F && !inlet);
+            const bool CAT = !F && C && !inlet && !outlet;
+            const bool EMIT = !bounce && CAT;
+            const uint32_t s_b = outlet ? r0 * SB + half : pull_b;
+            uint32_t r_b = EMIT ? 0u : bb_b;
+            r_b = inlet ? slot_b + half : r_b;
+            r_b = SF ? s_b : r_b;
+            opaque(r_b);
+            rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
+            uint32_t xs = uint32_t(x - cx);
+            if (cx == 1) xs = first_x ? uint32_t(g.nx - 1) : xs;
+            if (cx == -1) xs = last_x ? 0u : xs;
+            uint32_t v_b = EMIT ? (rv + xs) * SB : 0u;
+            opaque(v_b);
+            re[i] = ld_at(emit, v_b);
+            cat_bits |= CAT ? (1u << i) : 0u;
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    hC[0] = Store<ST>::cv(rc[0]);
+    hR[0] = Store<ST>::cv(rr[0]);
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        hC[i] = Store<ST>::cv(rc[i]);
+        const T v = Store<ST>::cv(rr[i]);
+        const T ev = Store<ST>::cv(re[i]);
+        const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? ev * inv_wgt<T>(i) : ev) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
     cat_out = cat_bits;
@@ -561,6 +669,68 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
         }
     }
     block_sum<4>(acc, part + int64_t(block) * 4);
+}
+
+// One block of the node-compact sweep: wave slot `block * 4 + wave` takes
+// the 64 gas nodes of wave worder[slot] (storage indices 64 w .. 64 w + 63).
+template <int ST, int SP>
+__device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph,
+                                              const Slots &in, const OutSlots &out,
+                                              const typename Store<ST>::S *__restrict__ emit,
+                                              double *__restrict__ part, uint32_t block) {
+    using S = typename Store<ST>::S;
+    using T = typename Store<ST>::T;
+    const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+    const uint32_t slot = block * 4u + wave;
+    const bool wvalid = slot < g.nwaves;
+    const uint32_t w = glb(g.worder)[wvalid ? slot : 0u];
+    const uint32_t idx = w * 64u + (threadIdx.x & 63u);
+    const bool active = wvalid && int64_t(idx) < g.nfluid;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const uint32_t p = glb(g.pos)[idx];
+        const int x = int(p & 0xfffu), y = int((p >> 12) & 0x3ffu), z = int(p >> 22);
+        T hC[19], hR[19];
+        uint32_t cat_bits;
+        pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits);
+        const Mom<T> m = moments(ph, hC, hR);
+        acc[0] = double(m.rc);
+        acc[1] = double(m.rr);
+        const bool reservoir = ph.species_x == XB_RESERVOIR;
+        const bool first_x = x == 0, last_x = x == g.nx - 1;
+        if (reservoir && last_x) {
+#pragma unroll
+            for (int i = 1; i < 19; ++i)
+                if (CX[i] == -1) acc[3] -= double(wgt<T>(i) * (hR[i] + ph.cref));
+        }
+        collide(ph, m, hC, hR);
+        uint32_t own_b = idx * uint32_t(sizeof(S));
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            opaque(own_b);
+            st_at(static_cast<S *>(out.p[dslot(i)]), own_b, Store<ST>::enc(hC[i]));
+            opaque(own_b);
+            st_at(static_cast<S *>(out.p[19 + dslot(i)]), own_b, Store<ST>::enc(hR[i]));
+        }
+        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
+            S *link = static_cast<S *>(g.link);
+            export_links<ST>(link, glb(g.wlink)[w] + lanes_below_sum(uint32_t(__popc(cat_bits))), cat_bits, hR);
+        }
+        if (reservoir && (first_x || last_x)) {
+            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p[19]) + idx, g.nfp,
+                                               first_x, last_x);
+            acc[2] += f.in;
+            acc[3] += f.out;
+        }
+    }
+    block_sum<4>(acc, part + int64_t(block) * 4);
+}
+
+template <int ST, int SP>
+__global__ __launch_bounds__(256) void k_sweep_c(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in,
+                                                  OutSlots out, const typename Store<ST>::S *__restrict__ emit,
+                                                  double *__restrict__ part) {
+    sweep_block_c<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
 }
 
 template <int ST, int SP>
@@ -864,6 +1034,16 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const SampleK<ST> *__restri
     sweep_block<ST, SP>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0);
 }
 
+template <int ST, int SP>
+__global__ __launch_bounds__(256) void k_sweep_batch_c(const SampleK<ST> *__restrict__ smp,
+                                                        const uint32_t *__restrict__ block_sample, int parity) {
+    const uint32_t b = uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x)));
+    const SampleK<ST> &d = smp[__builtin_amdgcn_readfirstlane(block_sample[b])];
+    const Slots &in = d.pop[parity];
+    const OutSlots &out = reinterpret_cast<const OutSlots &>(d.pop[1 - parity]);
+    sweep_block_c<ST, SP>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0);
+}
+
 template <int ST>
 __global__ __launch_bounds__(256) void k_interface_batch(const SampleK<ST> *__restrict__ smp,
                                                           const uint32_t *__restrict__ block_sample) {
@@ -905,7 +1085,10 @@ int storage_bytes(int storage) {
     }
 }
 
-int64_t sweep_blocks(const Geometry &g) { return (int64_t(g.units) + 3) / 4; }
+// Sweep grids are padded to a multiple of 8 blocks (the padding blocks find
+// no work and add zero partials) so that xcd_block can give every XCD one
+// contiguous range of the traversal.
+int64_t sweep_blocks(const Geometry &g) { return ((int64_t(g.units) + 3) / 4 + 7) / 8 * 8; }
 
 void build_order(int nx, int ny, int nz, int ytile, uint32_t *order) {
     const int W = (nx + 63) / 64;
@@ -981,6 +1164,30 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
             hipLaunchKernelGGL((k_sweep<ST, SP_WEIGHTED>), grid, block, 0, s, g, k, in, out, e, part);
         else
             hipLaunchKernelGGL((k_sweep<ST, SP_BOUNCEBACK>), grid, block, 0, s, g, k, in, out, e, part);
+        return hipGetLastError();
+    });
+}
+
+int64_t sweep_blocks_c(const Geometry &g) { return ((int64_t(g.nwaves) + 3) / 4 + 7) / 8 * 8; }
+
+hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
+                          double *part, hipStream_t s) {
+    return dispatch(ph.storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        using SS = typename Store<ST>::S;
+        using T = typename Store<ST>::T;
+        const Slots in = slots_of<ST>(g, fin);
+        OutSlots out;
+        for (int k = 0; k < 38; ++k) out.p[k] = static_cast<SS *>(fout) + int64_t(k) * g.nfp;
+        const dim3 grid(static_cast<unsigned>(sweep_blocks_c(g))), block(256);
+        const SS *e = static_cast<const SS *>(emit);
+        const PhysK<T> k = to_kernel<T>(ph);
+        if (ph.sputter == SP_UNIFORM)
+            hipLaunchKernelGGL((k_sweep_c<ST, SP_UNIFORM>), grid, block, 0, s, g, k, in, out, e, part);
+        else if (ph.sputter == SP_WEIGHTED)
+            hipLaunchKernelGGL((k_sweep_c<ST, SP_WEIGHTED>), grid, block, 0, s, g, k, in, out, e, part);
+        else
+            hipLaunchKernelGGL((k_sweep_c<ST, SP_BOUNCEBACK>), grid, block, 0, s, g, k, in, out, e, part);
         return hipGetLastError();
     });
 }
@@ -1075,9 +1282,34 @@ hipError_t batch_upload(int storage, const BatchSample *smp, int n, void *d_reco
     });
 }
 
-hipError_t launch_batch_step(int storage, int sputter, const void *d_records, const uint32_t *sweep_sample,
-                             int64_t sweep_blocks_total, const uint32_t *iface_sample, int64_t iface_blocks_total,
-                             const ReduceK *d_reduce, int n, int parity, hipStream_t s) {
+hipError_t launch_batch_sweep(int storage, int sputter, bool compact, const void *d_records,
+                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, int parity, hipStream_t s) {
+    return dispatch(storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        const SampleK<ST> *rec = static_cast<const SampleK<ST> *>(d_records);
+        const dim3 grid(static_cast<unsigned>(sweep_blocks_total)), block(256);
+        if (compact) {
+            if (sputter == SP_UNIFORM)
+                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP_UNIFORM>), grid, block, 0, s, rec, sweep_sample, parity);
+            else if (sputter == SP_WEIGHTED)
+                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP_WEIGHTED>), grid, block, 0, s, rec, sweep_sample, parity);
+            else
+                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP_BOUNCEBACK>), grid, block, 0, s, rec, sweep_sample,
+                                   parity);
+        } else if (sputter == SP_UNIFORM) {
+            hipLaunchKernelGGL((k_sweep_batch<ST, SP_UNIFORM>), grid, block, 0, s, rec, sweep_sample, parity);
+        } else if (sputter == SP_WEIGHTED) {
+            hipLaunchKernelGGL((k_sweep_batch<ST, SP_WEIGHTED>), grid, block, 0, s, rec, sweep_sample, parity);
+        } else {
+            hipLaunchKernelGGL((k_sweep_batch<ST, SP_BOUNCEBACK>), grid, block, 0, s, rec, sweep_sample, parity);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_step(int storage, int sputter, bool compact, const void *d_records,
+                             const uint32_t *sweep_sample, int64_t sweep_blocks_total, const uint32_t *iface_sample,
+                             int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s) {
     return dispatch(storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         const SampleK<ST> *rec = static_cast<const SampleK<ST> *>(d_records);
@@ -1087,14 +1319,8 @@ hipError_t launch_batch_step(int storage, int sputter, const void *d_records, co
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        const dim3 grid(static_cast<unsigned>(sweep_blocks_total)), block(256);
-        if (sputter == SP_UNIFORM)
-            hipLaunchKernelGGL((k_sweep_batch<ST, SP_UNIFORM>), grid, block, 0, s, rec, sweep_sample, parity);
-        else if (sputter == SP_WEIGHTED)
-            hipLaunchKernelGGL((k_sweep_batch<ST, SP_WEIGHTED>), grid, block, 0, s, rec, sweep_sample, parity);
-        else
-            hipLaunchKernelGGL((k_sweep_batch<ST, SP_BOUNCEBACK>), grid, block, 0, s, rec, sweep_sample, parity);
-        hipError_t e = hipGetLastError();
+        hipError_t e = launch_batch_sweep(storage, sputter, compact, d_records, sweep_sample, sweep_blocks_total,
+                                          parity, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_fold_batch, dim3(FOLD_BLOCKS, unsigned(n)), dim3(256), 0, s, d_reduce);
         e = hipGetLastError();

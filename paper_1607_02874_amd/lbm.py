@@ -27,7 +27,7 @@ SPUTTER_UNIFORM, SPUTTER_WEIGHTED, SPUTTER_BOUNCEBACK = 0, 1, 2
 COUPLE_PASSIVE, COUPLE_BARYCENTRIC = 0, 1
 XBC_PERIODIC, XBC_RESERVOIR = 0, 1
 STORE_F32, STORE_F16, STORE_BF16, STORE_F64 = 0, 1, 2, 3
-TUNE_YTILE = 0
+TUNE_YTILE, TUNE_SWEEP = 0, 1
 STORAGE_BYTES = {STORE_F32: 4, STORE_F16: 2, STORE_BF16: 2, STORE_F64: 8}
 STORAGE_NAMES = {STORE_F32: "f32", STORE_F16: "f16", STORE_BF16: "bf16", STORE_F64: "f64"}
 # Direction numbering of lbm_populations (as documented in include/lbm.h).
@@ -116,6 +116,8 @@ def _load():
         "lbm_set_tunable": (st, [ctx, ctypes.c_int32, ctypes.c_int64]),
         "lbm_get_tunable": (st, [ctx, ctypes.c_int32, P(ctypes.c_int64)]),
         "lbm_kernel_times": (st, [ctx, P(lbm_kernel_times_t)]),
+        "lbm_autotune": (st, [ctx, ctypes.c_int32, P(ctypes.c_double)]),
+        "lbm_batch_autotune": (st, [ctx, ctypes.c_int32, P(ctypes.c_double)]),
         "lbm_save": (st, [ctx, ctypes.c_char_p]),
         "lbm_load": (st, [ctx, ctypes.c_char_p]),
         "lbm_last_error": (ctypes.c_char_p, [ctx]),
@@ -129,6 +131,8 @@ def _load():
         "lbm_batch_query": (st, [ctx, ctypes.c_int32, P(lbm_info)]),
         "lbm_batch_synchronize": (st, [ctx]),
         "lbm_batch_set_graph": (st, [ctx, ctypes.c_int32]),
+        "lbm_batch_set_tunable": (st, [ctx, ctypes.c_int32, ctypes.c_int64]),
+        "lbm_batch_get_tunable": (st, [ctx, ctypes.c_int32, P(ctypes.c_int64)]),
         "lbm_batch_last_error": (ctypes.c_char_p, [ctx]),
         "lbm_batch_destroy": (None, [ctx]),
     }
@@ -327,6 +331,13 @@ class Sim:
     def set_timing(self, on=True):
         _check(_LIB.lbm_set_timing(self._h, 1 if on else 0), self._h)
 
+    def autotune(self, reps=5):
+        """Time the sweep for every launch-shape candidate and keep the
+        fastest (state unchanged).  Returns the winner's mean sweep time (ms)."""
+        ms = ctypes.c_double()
+        _check(_LIB.lbm_autotune(self._h, int(reps), ctypes.byref(ms)), self._h)
+        return ms.value
+
     def kernel_times(self):
         t = lbm_kernel_times_t()
         _check(_LIB.lbm_kernel_times(self._h, ctypes.byref(t)), self._h)
@@ -405,6 +416,19 @@ class Batch:
 
     def set_graph(self, on=True):
         _bcheck(_LIB.lbm_batch_set_graph(self._h, 1 if on else 0), self._h)
+
+    def set_tunable(self, which, value):
+        _bcheck(_LIB.lbm_batch_set_tunable(self._h, int(which), int(value)), self._h)
+
+    def autotune(self, reps=5):
+        ms = ctypes.c_double()
+        _bcheck(_LIB.lbm_batch_autotune(self._h, int(reps), ctypes.byref(ms)), self._h)
+        return ms.value
+
+    def get_tunable(self, which):
+        v = ctypes.c_int64()
+        _bcheck(_LIB.lbm_batch_get_tunable(self._h, int(which), ctypes.byref(v)), self._h)
+        return v.value
 
     def fields(self, i):
         shape = self.shapes[i]

@@ -126,3 +126,34 @@ def test_batch_info_and_index_errors():
         assert b"out of range" in L.lbm_batch_last_error(b._h)
         with pytest.raises(lbm.LbmError):
             b.step(-1)
+
+
+def test_batch_chunk_sweep_variant_matches_single():
+    samples = mixed_samples()
+    with lbm.Batch(samples) as b:
+        assert b.get_tunable(lbm.TUNE_SWEEP) == 1
+        b.set_tunable(lbm.TUNE_SWEEP, 0)
+        b.set_tunable(lbm.TUNE_YTILE, 4)
+        b.step(11)
+        for i, smp in enumerate(samples):
+            kw = {k: v for k, v in smp.items() if k not in ("vox", "da", "tau", "pore_size")}
+            with lbm.Sim(smp["vox"], da=smp["da"], tau=smp["tau"], pore_size=smp["pore_size"], **kw) as s:
+                s.set_tunable(lbm.TUNE_SWEEP, 0)
+                s.set_tunable(lbm.TUNE_YTILE, min(4, smp["vox"].shape[1]))
+                s.step(11)
+                assert_same(b, i, (s.fields(), s.conversion_map(), s.totals()))
+
+
+def test_batch_autotune_leaves_state_unchanged():
+    samples = mixed_samples()
+    with lbm.Batch(samples) as a, lbm.Batch(samples) as b:
+        a.step(9)
+        assert a.autotune(reps=2) > 0
+        b.set_tunable(lbm.TUNE_SWEEP, a.get_tunable(lbm.TUNE_SWEEP))
+        b.set_tunable(lbm.TUNE_YTILE, a.get_tunable(lbm.TUNE_YTILE))
+        a.step(8)
+        b.step(17)
+        for i in range(len(samples)):
+            fa, fb = a.fields(i), b.fields(i)
+            assert all(np.array_equal(x, y) for x, y in zip(fa, fb)), i
+            assert np.array_equal(a.conversion_map(i), b.conversion_map(i)), i

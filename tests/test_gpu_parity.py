@@ -292,3 +292,69 @@ def test_fields_device_matches_host_fields():
     assert np.array_equal(d_u.cpu().numpy(), u.ravel().astype(np.float32))
     assert np.array_equal(d_c.cpu().numpy(), conc.ravel().astype(np.float32))
     s.close()
+
+
+SHAPES_SWEEP = {
+    "plain32": lambda: PLAIN.voxels(),
+    "nx1": lambda: np.zeros((7, 9, 1), np.uint8),
+    "nx65_tall": lambda: inputs.porous_slab(65, 40, 6, 0.6, 3.0, 21),
+    "nx130": lambda: inputs.porous_slab(130, 11, 9, 0.65, 3.0, 22),
+    "nx63": lambda: inputs.porous_slab(63, 14, 12, 0.55, 2.5, 23),
+}
+
+
+@pytest.mark.parametrize("shape", sorted(SHAPES_SWEEP))
+@pytest.mark.parametrize("sputter,coupling,species_x", [("UNIFORM", "PASSIVE", "RESERVOIR"),
+                                                        ("WEIGHTED", "BARYCENTRIC", "PERIODIC"),
+                                                        ("BOUNCEBACK", "PASSIVE", "PERIODIC"),
+                                                        ("UNIFORM", "BARYCENTRIC", "RESERVOIR")])
+def test_compact_and_chunk_sweeps_agree(shape, sputter, coupling, species_x):
+    """The node-compact sweep (default) and the 64-voxel-chunk sweep compute
+    the same populations: fields and conversion map bit-identical, totals to
+    the rounding of their differently grouped partial sums."""
+    from paper_1607_02874_amd import lbm
+
+    vox = SHAPES_SWEEP[shape]()
+    c = case(vox, 23, da=0.5, tau=(0.8, 0.7), pore_size=3.0, force=(2e-5, 1e-6, 0.0), p_stick=0.8, c0=0.2,
+             sputter=sputter, coupling=coupling, species_x=species_x)
+    out = []
+    for variant in (1, 0):
+        s = make_sim(c, F32)
+        assert s.get_tunable(lbm.TUNE_SWEEP) == 1
+        s.set_tunable(lbm.TUNE_SWEEP, variant)
+        s.step(c["steps"])
+        out.append((s.fields(), s.conversion_map(), s.totals()))
+        s.close()
+    (fa, ca, ta), (fb, cb, tb) = out
+    assert all(np.array_equal(a, b) for a, b in zip(fa, fb)), shape
+    assert np.array_equal(ca, cb)
+    for k in ("mass_gas", "mass_species", "converted", "lost", "influx", "outflux"):
+        assert abs(ta[k] - tb[k]) <= 1e-12 * max(abs(tb[k]), abs(tb["mass_gas"])), (k, ta[k], tb[k])
+
+
+def test_autotune_leaves_state_unchanged():
+    """Autotuning mid-run picks a launch shape without touching the state:
+    the run continues exactly as a run that used the chosen shape throughout
+    (fields and conversion map bit-identical, totals to partial-sum rounding)."""
+    from paper_1607_02874_amd import lbm
+
+    c = plain_case(steps=10, sputter="UNIFORM")
+    a = make_sim(c, F32)
+    a.step(10)
+    ms = a.autotune(reps=2)
+    assert ms > 0
+    variant, ytile = a.get_tunable(lbm.TUNE_SWEEP), a.get_tunable(lbm.TUNE_YTILE)
+    a.step(10)
+    b = make_sim(c, F32)
+    b.set_tunable(lbm.TUNE_SWEEP, variant)
+    b.set_tunable(lbm.TUNE_YTILE, ytile)
+    b.step(20)
+    fa, fb = a.fields(), b.fields()
+    assert all(np.array_equal(x, y) for x, y in zip(fa, fb))
+    assert np.array_equal(a.conversion_map(), b.conversion_map())
+    ta, tb = a.totals(), b.totals()
+    assert ta["step"] == tb["step"] == 20
+    for k in ("mass_gas", "mass_species", "converted", "lost", "influx", "outflux"):
+        assert abs(ta[k] - tb[k]) <= 1e-12 * max(abs(tb[k]), abs(tb["mass_gas"])), k
+    a.close()
+    b.close()
