@@ -49,25 +49,28 @@ def algorithmic_bytes(info, s):
     return {"sweep": sweep, "interface": iface, "step": sweep + iface}
 
 
-def measured_traffic(kernel, workload, storage_name):
-    """Calibrated HBM bytes per launch from the PMC record in profiles/traffic.json,
-    or None when there is no record for this kernel, workload and storage, or the
-    kernel source has changed since the counters were taken."""
+def measured_traffic(kernel, workload, storage_name, sweep, ytile):
+    """Calibrated HBM bytes per launch from the PMC records in
+    profiles/traffic.json, or None when no record matches this kernel,
+    workload, storage and launch shape, or the kernel source has changed
+    since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
-            rec = json.load(f).get(kernel)
-        if not rec or rec["workload"] != workload or rec["storage"] != storage_name:
-            return None
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-                return None
-        return int(rec["fetch_kib_per_dispatch"] * 1024 * rec["fetch_scale"]
-                   + rec["write_kib_per_dispatch"] * 1024 * rec["write_scale"])
+            recs = json.load(f).get(kernel, [])
+        for rec in recs:
+            if (rec["workload"], rec["storage"], rec["sweep"], rec["ytile"]) != (workload, storage_name, sweep, ytile):
+                continue
+            with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                    return None
+            return int(rec["fetch_kib_per_dispatch"] * 1024 * rec["fetch_scale"]
+                       + rec["write_kib_per_dispatch"] * 1024 * rec["write_scale"])
     except (OSError, KeyError, ValueError):
         return None
+    return None
 
 
 def cpu_baseline(vox256, w, steps):
@@ -359,7 +362,7 @@ def main():
         sim.set_tunable(lbm.TUNE_YTILE, args.ytile)
     tuned = None
     if not args.no_autotune and args.ytile is None and args.sweep is None:
-        tuned = sim.autotune(5)
+        tuned = sim.autotune(10)
         log(f"autotune: sweep {sim.get_tunable(lbm.TUNE_SWEEP)} ytile {sim.get_tunable(lbm.TUNE_YTILE)} "
             f"({tuned * 1e3:.1f} us)")
     sweep_variant = sim.get_tunable(lbm.TUNE_SWEEP)
@@ -400,7 +403,8 @@ def main():
         kname = "k_sweep_c" if sweep_variant == 1 else "k_sweep"
         roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(kname, w.name, args.storage),
+                    "traffic": measured_traffic(kname, w.name, args.storage,
+                                                "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile),
                     "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2)}
     kernels = None
     if kt:

@@ -255,7 +255,8 @@ lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value);
 /*
  * lbm_autotune - pick the launch shape: time `reps` (1..1000) sweeps for each
  * candidate (sweep variant x y-tile in {4, 8, 16, 32, 64, 128}, clamped to
- * ny) and keep the fastest.  The trial sweeps run in place; the population
+ * ny) in two interleaved rounds and keep the candidate with the fastest
+ * round.  The trial sweeps run in place; the population
  * buffer and link buffer they overwrite are saved to temporary device memory
  * first and restored afterwards, so the state (and every later result) is
  * exactly as before the call.  best_ms (may be NULL) receives the mean sweep

@@ -1107,8 +1107,12 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
     const Candidate keep{c->compact, c->ytile};
     Candidate best = keep;
     float best_t = 0.0f;
-    if (st == LBM_OK) {
-        for (const Candidate &cd : tuning_candidates(c->compact_ok, c->ny)) {
+    const std::vector<Candidate> cands = tuning_candidates(c->compact_ok, c->ny);
+    std::vector<float> t_min(cands.size(), 0.0f);
+    // two interleaved rounds; each candidate keeps its faster round
+    for (int round = 0; round < 2 && st == LBM_OK; ++round) {
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            const Candidate &cd = cands[ci];
             st = lbm_set_tunable(c, LBM_TUNE_YTILE, cd.ytile);
             if (st == LBM_OK) st = lbm_set_tunable(c, LBM_TUNE_SWEEP, cd.compact);
             if (st != LBM_OK) break;
@@ -1121,12 +1125,14 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
                                   : launch_sweep(g, c->ph, fin, fout, c->d_emit, c->d_part, c->stream);
             }, &ms, &c->err);
             if (st != LBM_OK) break;
-            if (best_t == 0.0f || ms < best_t) {
-                best_t = ms;
-                best = cd;
-            }
+            if (round == 0 || ms < t_min[ci]) t_min[ci] = ms;
         }
     }
+    for (size_t ci = 0; ci < cands.size() && st == LBM_OK; ++ci)
+        if (best_t == 0.0f || t_min[ci] < best_t) {
+            best_t = t_min[ci];
+            best = cands[ci];
+        }
     lbm_status rs = sv.pop ? restore_written(c, sv) : LBM_OK;
     scratch_free(c, sv.pop);
     scratch_free(c, sv.link);
@@ -1538,8 +1544,11 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, double *best_ms) {
     const Candidate keep{b->compact ? 1 : 0, b->ctx[0]->ytile};
     Candidate best = keep;
     float best_t = 0.0f;
-    if (st == LBM_OK) {
-        for (const Candidate &cd : tuning_candidates(compact_ok, ny_max)) {
+    const std::vector<Candidate> cands = tuning_candidates(compact_ok, ny_max);
+    std::vector<float> t_min(cands.size(), 0.0f);
+    for (int round = 0; round < 2 && st == LBM_OK; ++round) {
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            const Candidate &cd = cands[ci];
             st = lbm_batch_set_tunable(b, LBM_TUNE_YTILE, cd.ytile);
             if (st == LBM_OK) st = lbm_batch_set_tunable(b, LBM_TUNE_SWEEP, cd.compact);
             if (st != LBM_OK) break;
@@ -1550,12 +1559,14 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, double *best_ms) {
                                           b->sweep_blocks_total, parity, b->stream);
             }, &ms, &b->err);
             if (st != LBM_OK) break;
-            if (best_t == 0.0f || ms < best_t) {
-                best_t = ms;
-                best = cd;
-            }
+            if (round == 0 || ms < t_min[ci]) t_min[ci] = ms;
         }
     }
+    for (size_t ci = 0; ci < cands.size() && st == LBM_OK; ++ci)
+        if (best_t == 0.0f || t_min[ci] < best_t) {
+            best_t = t_min[ci];
+            best = cands[ci];
+        }
     lbm_status rs = LBM_OK;
     for (size_t i = 0; i < b->ctx.size(); ++i) {
         if (sv[i].pop && rs == LBM_OK) rs = restore_written(b->ctx[i], sv[i]);

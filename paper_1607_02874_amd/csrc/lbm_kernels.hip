@@ -217,14 +217,21 @@ __device__ __forceinline__ void st_at(S *base, uint32_t byte_off, S v) {
     *(LBM_GLOBAL S *)((LBM_GLOBAL char *)(base) + byte_off) = v;
 }
 
-// Base address of each direction array of a population buffer (carrier
-// slots 0..18, reactant 19..37, in storage order), formed on the host so the
-// kernels do no 64-bit base arithmetic.
+// A population buffer: 38 direction arrays (carrier slots 0..18, reactant
+// 19..37) of `stride` bytes each from `base`.  A direction's base address is
+// formed in scalar registers where it is used (one 64-bit multiply-add), so
+// the kernels do not hold 76 pointers in scalar registers.
+// (The create path guarantees that two direction arrays span less than
+// 4 GiB, so the stride fits in 32 bits.)
 struct Slots {
-    const void *p[38];
+    const char *base;
+    uint32_t stride, pad;
+    __device__ __forceinline__ const void *p(int slot) const { return base + uint64_t(uint32_t(slot)) * stride; }
 };
 struct OutSlots {
-    void *p[38];
+    char *base;
+    uint32_t stride, pad;
+    __device__ __forceinline__ void *p(int slot) const { return base + uint64_t(uint32_t(slot)) * stride; }
 };
 
 // Directions grouped by source row (cy, cz), so each row's chunk record is
@@ -257,7 +264,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     const bool reservoir = ph.species_x == XB_RESERVOIR;
     const int sputter = SP >= 0 ? SP : ph.sputter;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
-    auto base = [&](int slot) { return static_cast<const S *>(in.p[slot]); };
+    auto base = [&](int slot) { return static_cast<const S *>(in.p(slot)); };
     const uint32_t own_b = u.idx * SB;
     const uint32_t x_b = uint32_t(u.x) * SB;
     // wave-uniform shape of the chunk
@@ -379,7 +386,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     const bool reservoir = ph.species_x == XB_RESERVOIR;
     const int sputter = SP >= 0 ? SP : ph.sputter;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
-    auto base = [&](int slot) { return static_cast<const S *>(in.p[slot]); };
+    auto base = [&](int slot) { return static_cast<const S *>(in.p(slot)); };
     const uint32_t own_b = idx * SB;
     const uint32_t xl = uint32_t(x) & 63u, chunk = uint32_t(x) >> 6;
     const bool ledge = xl == 0u;                       // x - 1 lies in the previous chunk (or wraps)
@@ -647,9 +654,9 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
             // opaque per store: keeps each store in the scalar-base form instead
             // of a shared 64-bit vector address plus per-store 64-bit adds
             opaque(own_b);
-            st_at(static_cast<S *>(out.p[dslot(i)]), own_b, Store<ST>::enc(hC[i]));
+            st_at(static_cast<S *>(out.p(dslot(i))), own_b, Store<ST>::enc(hC[i]));
             opaque(own_b);
-            st_at(static_cast<S *>(out.p[19 + dslot(i)]), own_b, Store<ST>::enc(hR[i]));
+            st_at(static_cast<S *>(out.p(19 + dslot(i))), own_b, Store<ST>::enc(hR[i]));
         }
         // Export the reactant populations that head into catalytic nodes
         // (the reversed catalytic-source directions) to the link buffer for
@@ -662,7 +669,7 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
             export_links<ST>(link, lb + lanes_below_sum(uint32_t(__popc(cat_bits))), cat_bits, hR);
         }
         if (reservoir && (first_x || last_x)) {
-            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p[19]) + u.idx, nfp, first_x,
+            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p(19)) + u.idx, nfp, first_x,
                                                last_x);
             acc[2] += f.in;
             acc[3] += f.out;
@@ -708,16 +715,16 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             opaque(own_b);
-            st_at(static_cast<S *>(out.p[dslot(i)]), own_b, Store<ST>::enc(hC[i]));
+            st_at(static_cast<S *>(out.p(dslot(i))), own_b, Store<ST>::enc(hC[i]));
             opaque(own_b);
-            st_at(static_cast<S *>(out.p[19 + dslot(i)]), own_b, Store<ST>::enc(hR[i]));
+            st_at(static_cast<S *>(out.p(19 + dslot(i))), own_b, Store<ST>::enc(hR[i]));
         }
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
             S *link = static_cast<S *>(g.link);
             export_links<ST>(link, glb(g.wlink)[w] + lanes_below_sum(uint32_t(__popc(cat_bits))), cat_bits, hR);
         }
         if (reservoir && (first_x || last_x)) {
-            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p[19]) + idx, g.nfp,
+            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p(19)) + idx, g.nfp,
                                                first_x, last_x);
             acc[2] += f.in;
             acc[3] += f.out;
@@ -754,8 +761,8 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
         if (LOCAL) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                hC[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[dslot(i)]) + u.idx);
-                hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[19 + dslot(i)]) + u.idx);
+                hC[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p(dslot(i))) + u.idx);
+                hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p(19 + dslot(i))) + u.idx);
             }
         } else {
             uint32_t cat_bits;
@@ -893,8 +900,8 @@ __global__ __launch_bounds__(256) void k_populations(Geometry g, PhysK<typename 
         if (LOCAL) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                hC[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[dslot(i)]) + u.idx);
-                hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p[19 + dslot(i)]) + u.idx);
+                hC[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p(dslot(i))) + u.idx);
+                hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p(19 + dslot(i))) + u.idx);
             }
         } else {
             uint32_t cat_bits;
@@ -1142,7 +1149,9 @@ template <int ST>
 Slots slots_of(const Geometry &g, const void *buf) {
     Slots sl;
     using S = typename Store<ST>::S;
-    for (int k = 0; k < 38; ++k) sl.p[k] = static_cast<const S *>(buf) + int64_t(k) * g.nfp;
+    sl.base = static_cast<const char *>(buf);
+    sl.stride = uint32_t(uint64_t(g.nfp) * sizeof(S));
+    sl.pad = 0;
     return sl;
 }
 
@@ -1154,7 +1163,9 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
         using T = typename Store<ST>::T;
         const Slots in = slots_of<ST>(g, fin);
         OutSlots out;
-        for (int k = 0; k < 38; ++k) out.p[k] = static_cast<SS *>(fout) + int64_t(k) * g.nfp;
+        out.base = static_cast<char *>(fout);
+        out.stride = uint32_t(uint64_t(g.nfp) * sizeof(SS));
+        out.pad = 0;
         const dim3 grid(unsigned(sweep_blocks(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
         const PhysK<T> k = to_kernel<T>(ph);
@@ -1178,7 +1189,9 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
         using T = typename Store<ST>::T;
         const Slots in = slots_of<ST>(g, fin);
         OutSlots out;
-        for (int k = 0; k < 38; ++k) out.p[k] = static_cast<SS *>(fout) + int64_t(k) * g.nfp;
+        out.base = static_cast<char *>(fout);
+        out.stride = uint32_t(uint64_t(g.nfp) * sizeof(SS));
+        out.pad = 0;
         const dim3 grid(static_cast<unsigned>(sweep_blocks_c(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
         const PhysK<T> k = to_kernel<T>(ph);
