@@ -25,7 +25,7 @@ thread_local std::string g_create_error;
 
 constexpr double CS = 0.57735026918962576451;  // lattice sound speed 1/sqrt(3)
 constexpr int TIMING_RING = 512;
-constexpr uint64_t CKPT_MAGIC = 0x3147504b434d424cull;  // "LBMCKPG1"
+constexpr uint64_t CKPT_MAGIC = 0x3247504b434d424cull;  // "LBMCKPG2"
 
 struct StepEvents {
     hipEvent_t ev[8];  // start/stop of interface, xflux, sweep, reduce
@@ -204,40 +204,46 @@ Interface interface_list(const lbm_ctx *c) {
 
 // Chunk records of every x-row: gas/catalytic bits, storage base, and the
 // periodic left/right neighbours of the chunk.
-void build_chunks(const lbm_ctx *c, std::vector<ChunkInfo> &ch) {
+void build_chunks(const lbm_ctx *c, const std::vector<uint32_t> &ivox, std::vector<ChunkInfo> &ch) {
     const int64_t rows = int64_t(c->ny) * c->nz;
     ch.assign(size_t(rows * c->W), ChunkInfo{});
-    uint64_t running = 0;
+    std::vector<uint8_t> is_iface(size_t(c->n), 0);
+    for (uint32_t v : ivox) is_iface[v] = 1;
+    uint64_t running = 0, irunning = 0;
     for (int64_t r = 0; r < rows; ++r) {
         const uint8_t *v = c->vox.data() + r * c->nx;
+        const uint8_t *f = is_iface.data() + r * c->nx;
         for (int k = 0; k < c->W; ++k) {
             ChunkInfo &I = ch[size_t(r * c->W + k)];
             for (int b = 0; b < 64; ++b) {
                 const int x = 64 * k + b;
                 if (x >= c->nx) break;
                 if (v[x] == LBM_FLUID) I.fluid |= 1ull << b;
-                if (v[x] == LBM_CATALYTIC) I.cat |= 1ull << b;
+                if (f[x]) I.cat |= 1ull << b;
             }
             I.base = uint32_t(running);
+            I.ibase = uint32_t(irunning);
             running += uint64_t(__builtin_popcountll(I.fluid));
+            irunning += uint64_t(__builtin_popcountll(I.cat));
         }
     }
-    auto rank = [&](int64_t r, int x) -> uint32_t {
+    // periodic x-neighbours of each chunk: storage index when gas, interface
+    // index when an interface node
+    auto neighbour = [&](int64_t r, int x) -> uint32_t {
         const ChunkInfo &I = ch[size_t(r * c->W + (x >> 6))];
         const int b = x & 63;
-        const uint64_t below = b ? (I.fluid & (~0ull >> (64 - b))) : 0ull;
-        return I.base + uint32_t(__builtin_popcountll(below));
+        const uint64_t below = b ? (~0ull >> (64 - b)) : 0ull;
+        if ((I.fluid >> b) & 1u) return NB_GAS | (I.base + uint32_t(__builtin_popcountll(I.fluid & below)));
+        if ((I.cat >> b) & 1u) return NB_CAT | (I.ibase + uint32_t(__builtin_popcountll(I.cat & below)));
+        return 0u;
     };
     for (int64_t r = 0; r < rows; ++r) {
-        const uint8_t *v = c->vox.data() + r * c->nx;
         for (int k = 0; k < c->W; ++k) {
             ChunkInfo &I = ch[size_t(r * c->W + k)];
             const int xp = k > 0 ? 64 * k - 1 : c->nx - 1;
             const int xn = 64 * k + 64 < c->nx ? 64 * k + 64 : 0;
-            I.edge = (v[xp] == LBM_FLUID ? 1u : 0u) | (v[xp] == LBM_CATALYTIC ? 2u : 0u) |
-                     (v[xn] == LBM_FLUID ? 4u : 0u) | (v[xn] == LBM_CATALYTIC ? 8u : 0u);
-            I.prev_rank = rank(r, xp);
-            I.next_rank = rank(r, xn);
+            I.prev = neighbour(r, xp);
+            I.next = neighbour(r, xn);
         }
     }
 }
@@ -493,8 +499,6 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     try {
         c->vox.assign(g->voxels, g->voxels + c->n);
         c->geom_hash = fnv1a(c->vox.data(), c->vox.size());
-        std::vector<ChunkInfo> chunks;
-        build_chunks(c, chunks);
         c->nfluid = 0;
         for (uint8_t v : c->vox) c->nfluid += v == LBM_FLUID;
         // one spare element per direction array at least: the last one holds
@@ -505,6 +509,13 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         build_interface(c, ivox, imask, iscale);
         c->niface = int64_t(ivox.size());
         c->iface_vox = ivox;
+        if (c->nfluid >= int64_t(NB_IDX) || c->niface >= int64_t(NB_IDX)) {
+            release(c);
+            delete c;
+            return fail(nullptr, LBM_EUNSUPPORTED, "more than 2^30 gas or interface nodes");
+        }
+        std::vector<ChunkInfo> chunks;
+        build_chunks(c, ivox, chunks);
         std::vector<uint32_t> istart, lmap, lbase, wlink;
         c->nwaves = (c->nfluid + 63) / 64;
         build_links(c, ivox, imask, istart, lmap, lbase, wlink);
@@ -525,10 +536,11 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
 
         // The kernels address every buffer with 32-bit byte offsets from a
         // scalar base: a population pair (2 nfp elements), the emission array
-        // (n elements) and the link buffer must each stay below 4 GiB.
+        // (one element per interface node) and the link buffer must each stay
+        // below 4 GiB.
         {
             const uint64_t sbytes = uint64_t(storage_bytes(c->ph.storage)), lim = uint64_t(1) << 32;
-            if (2 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(c->n) * sbytes >= lim ||
+            if (2 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(c->niface) * sbytes >= lim ||
                 uint64_t(lmap.size()) * sbytes >= lim) {
                 release(c);
                 delete c;
@@ -559,11 +571,9 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
             c->d_worder = static_cast<uint32_t *>(dev_alloc(c, worder.size() * 4));
             c->d_wlink = static_cast<uint32_t *>(dev_alloc(c, wlink.size() * 4));
         }
-        // One pool: population buffers A and B, then the emission array.  The
-        // sweep addresses all three from one base with integer offsets, so the
-        // emission array must start a whole number of direction strides (nfp
-        // elements) after each buffer, and voxel indices must fit in 32 bits.
-        char *pool = static_cast<char *>(dev_alloc(c, (size_t(76) * c->nfp + size_t(c->n)) * sb));
+        // One pool: population buffers A and B, then the emission array (one
+        // element per interface node, indexed by interface index).
+        char *pool = static_cast<char *>(dev_alloc(c, (size_t(76) * c->nfp + size_t(c->niface)) * sb));
         if (pool) {
             c->d_pop[0] = pool;
             c->d_pop[1] = pool + size_t(38) * c->nfp * sb;
@@ -598,7 +608,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
             up(c->d_wlink, wlink.data(), wlink.size() * 4);
         }
         if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, size_t(c->n) * sb, c->stream);
+        if (e == hipSuccess && c->niface) e = hipMemsetAsync(c->d_emit, 0, size_t(c->niface) * sb, c->stream);
         DevTotals t0{};
         t0.mass_gas = double(c->nfluid) * bc->rho0;
         t0.mass_species = double(c->nfluid) * bc->c0;
@@ -928,7 +938,7 @@ lbm_status lbm_save(lbm_ctx *c, const char *path) {
     pack_params(c, h.params);
     hipError_t e = hipMemcpyAsync(&h.tot, c->d_tot, sizeof(DevTotals), hipMemcpyDeviceToHost, c->stream);
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t emit = size_t(c->n) * storage_bytes(c->ph.storage);
+    const size_t emit = size_t(c->niface) * storage_bytes(c->ph.storage);
     std::vector<char> buf;
     try {
         buf.resize(2 * pop + emit + size_t(c->niface) * 8);
@@ -968,7 +978,7 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
         return fail(c, LBM_EINVAL, "checkpoint does not match this context's geometry or parameters");
     }
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t emit = size_t(c->n) * storage_bytes(c->ph.storage);
+    const size_t emit = size_t(c->niface) * storage_bytes(c->ph.storage);
     std::vector<char> buf;
     try {
         buf.resize(2 * pop + emit + size_t(c->niface) * 8);

@@ -31,13 +31,15 @@ __host__ __device__ constexpr T inv_wgt(int i) {
 // compactly (gas nodes only, in (z, y, x) order), so a gas node's storage
 // index is base + (number of gas bits below it in this chunk).
 struct ChunkInfo {
-    uint64_t fluid;      // bit b: voxel x = 64 c + b (< nx) is gas
-    uint64_t cat;        // bit b: voxel is catalytic solid
-    uint32_t base;       // storage index of the first gas voxel of the chunk
-    uint32_t edge;       // 1: left neighbour gas, 2: left catalytic, 4: right gas, 8: right catalytic
-    uint32_t prev_rank;  // storage index of the periodic left neighbour x = 64 c - 1 (if gas)
-    uint32_t next_rank;  // storage index of the periodic right neighbour (if gas)
+    uint64_t fluid;   // bit b: voxel x = 64 c + b (< nx) is gas
+    uint64_t cat;     // bit b: voxel is an interface node (catalytic, >= 1 active link)
+    uint32_t base;    // storage index of the first gas voxel of the chunk
+    uint32_t ibase;   // interface index of the first interface voxel of the chunk
+    uint32_t prev;    // periodic left neighbour x = 64 c - 1: NB_GAS | storage index, NB_CAT | interface index, or 0
+    uint32_t next;    // periodic right neighbour (x = 64 c + 64, or 0 after the last chunk), same encoding
 };
+// Neighbour-field flags; indices stay below 2^30 (checked at create).
+constexpr uint32_t NB_GAS = 1u << 31, NB_CAT = 1u << 30, NB_IDX = NB_CAT - 1u;
 static_assert(sizeof(ChunkInfo) == 32, "ChunkInfo must stay 32 bytes (one scalar load)");
 
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_F64 = 3 };

@@ -266,7 +266,6 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
     auto base = [&](int slot) { return static_cast<const S *>(in.p(slot)); };
     const uint32_t own_b = u.idx * SB;
-    const uint32_t x_b = uint32_t(u.x) * SB;
     // wave-uniform shape of the chunk
     const int nvalid = min(64, g.nx - 64 * u.chunk);
     const int last_lane = nvalid - 1;
@@ -280,7 +279,6 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     rr[0] = ld_at(base(19 + dslot(0)), own_b);
     // the nine source rows (wave-uniform): chunk record and first voxel
     const LBM_GLOBAL ChunkInfo *recs[9];
-    uint32_t row_vox[9];
 #pragma unroll
     for (int cy = -1; cy <= 1; ++cy) {
         int ys = u.y - cy;
@@ -291,7 +289,6 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
             zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
             const uint32_t r = uint32_t(__builtin_amdgcn_readfirstlane(zs * g.ny + ys));
             recs[(cy + 1) * 3 + cz + 1] = glb(g.chunks) + (r * uint32_t(g.W) + uint32_t(u.chunk));
-            row_vox[(cy + 1) * 3 + cz + 1] = r * uint32_t(g.nx);
         }
     }
 #pragma unroll
@@ -300,26 +297,37 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const int cx = CX[i];
         // source row of this direction and its chunk record
         const LBM_GLOBAL ChunkInfo &I = *recs[(CY[i] + 1) * 3 + CZ[i] + 1];
-        const uint32_t rv = row_vox[(CY[i] + 1) * 3 + CZ[i] + 1];
         // F / C: the source x - cx of each lane is gas / catalytic; rank: its
         // storage index when gas.
+        // irank: the source's interface index when it is an interface node
         uint64_t F, C;
-        uint32_t rank;
+        uint32_t rank, irank;
         if (cx == 0) {
             F = I.fluid;
             C = I.cat;
             rank = rank_of_mask(I.fluid, I.base);
+            irank = rank_of_mask(I.cat, I.ibase);
         } else if (cx == 1) {  // source x - 1; lane 0 takes the left neighbour of the chunk
-            const uint32_t pf = I.edge & 1u;
+            const uint32_t pv = I.prev;
+            const uint32_t pf = pv >> 31, pc = (pv >> 30) & 1u;
             F = (I.fluid << 1) | pf;
-            C = (I.cat << 1) | ((I.edge >> 1) & 1u);
+            C = (I.cat << 1) | pc;
             rank = rank_of_mask(F, I.base - pf);
-            if (first_chunk) rank = lane_in(lane0) ? I.prev_rank : rank;  // periodic wrap to x = nx - 1
+            irank = rank_of_mask(C, I.ibase - pc);
+            if (first_chunk) {  // periodic wrap to x = nx - 1
+                rank = lane_in(lane0) ? (pv & NB_IDX) : rank;
+                irank = lane_in(lane0) ? (pv & NB_IDX) : irank;
+            }
         } else {  // source x + 1; the last valid lane takes the right neighbour
-            F = (I.fluid >> 1) | (uint64_t((I.edge >> 2) & 1u) << last_lane);
-            C = (I.cat >> 1) | (uint64_t((I.edge >> 3) & 1u) << last_lane);
+            const uint32_t nv = I.next;
+            F = (I.fluid >> 1) | (uint64_t(nv >> 31) << last_lane);
+            C = (I.cat >> 1) | (uint64_t((nv >> 30) & 1u) << last_lane);
             rank = rank_of_mask(I.fluid >> 1, I.base + uint32_t(I.fluid & 1u));
-            if (last_chunk) rank = lane_in(lane_last) ? I.next_rank : rank;  // periodic wrap to x = 0
+            irank = rank_of_mask(I.cat >> 1, I.ibase + uint32_t(I.cat & 1u));
+            if (last_chunk) {  // periodic wrap to x = 0
+                rank = lane_in(lane_last) ? (nv & NB_IDX) : rank;
+                irank = lane_in(lane_last) ? (nv & NB_IDX) : irank;
+            }
         }
         // Direction i and opp(i) are adjacent arrays: one base, and the pull
         // or the bounce-back is an offset of 0 or nfp elements plus a node.
@@ -343,11 +351,8 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         r_b = lane_in(inlet) ? slot_b + half : r_b;
         r_b = lane_in(SF) ? srank_b : r_b;
         rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
-        // emission of a catalytic source voxel (element 0 when not used)
-        uint32_t vox_b = (rv - cx) * SB + x_b;
-        if (cx == 1 && first_chunk) vox_b = lane_in(lane0) ? (rv + g.nx - 1) * SB : vox_b;
-        if (cx == -1 && last_chunk) vox_b = lane_in(lane_last) ? rv * SB : vox_b;
-        re[i] = ld_at(emit, lane_in(EMIT) ? vox_b : 0u);
+        // emission of a catalytic source, by interface index (element 0 when not used)
+        re[i] = ld_at(emit, lane_in(EMIT) ? irank * SB : 0u);
         cat_bits |= lane_in(CAT) ? (1u << i) : 0u;
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -411,18 +416,21 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         const uint32_t rown = uint32_t(zs) * uint32_t(g.ny) + uint32_t(ys);
         const LBM_GLOBAL ChunkInfo &R = glb(g.chunks)[rown * uint32_t(g.W) + chunk];
         const uint64_t fm = R.fluid, cm = R.cat;
-        const uint32_t e = R.edge;
+        const uint32_t pv = R.prev, nv = R.next;
         // bit 0: x - 1, bit 1: x, bit 2: x + 1
         uint32_t wf = uint32_t(ledge ? fm << 1 : fm >> shr) & 7u;
         uint32_t wc = uint32_t(ledge ? cm << 1 : cm >> shr) & 7u;
-        wf |= ledge ? (e & 1u) : 0u;
-        wc |= ledge ? ((e >> 1) & 1u) : 0u;
-        wf = redge ? (wf & 3u) | (((e >> 2) & 1u) << 2) : wf;
-        wc = redge ? (wc & 3u) | (((e >> 3) & 1u) << 2) : wc;
+        wf |= ledge ? (pv >> 31) : 0u;
+        wc |= ledge ? ((pv >> 30) & 1u) : 0u;
+        wf = redge ? (wf & 3u) | ((nv >> 31) << 2) : wf;
+        wc = redge ? (wc & 3u) | (((nv >> 30) & 1u) << 2) : wc;
+        // storage / interface indices of x, x - 1, x + 1 (used only where gas / interface)
         const uint32_t r0 = R.base + uint32_t(__popcll(fm & below));
-        const uint32_t rm = ledge ? R.prev_rank : r0 - 1u;
-        const uint32_t rp = redge ? R.next_rank : r0 + ((wf >> 1) & 1u);
-        const uint32_t rv = rown * uint32_t(g.nx);
+        const uint32_t rm = ledge ? (pv & NB_IDX) : r0 - 1u;
+        const uint32_t rp = redge ? (nv & NB_IDX) : r0 + ((wf >> 1) & 1u);
+        const uint32_t i0 = R.ibase + uint32_t(__popcll(cm & below));
+        const uint32_t im = ledge ? (pv & NB_IDX) : i0 - 1u;
+        const uint32_t ip = redge ? (nv & NB_IDX) : i0 + ((wc >> 1) & 1u);
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
             const int i = ORDER[k];
@@ -449,10 +457,8 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             r_b = SF ? s_b : r_b;
             opaque(r_b);
             rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
-            uint32_t xs = uint32_t(x - cx);
-            if (cx == 1) xs = first_x ? uint32_t(g.nx - 1) : xs;
-            if (cx == -1) xs = last_x ? 0u : xs;
-            uint32_t v_b = EMIT ? (rv + xs) * SB : 0u;
+            const uint32_t irank = cx == 0 ? i0 : (cx == 1 ? im : ip);
+            uint32_t v_b = EMIT ? irank * SB : 0u;
             opaque(v_b);
             re[i] = ld_at(emit, v_b);
             cat_bits |= CAT ? (1u << i) : 0u;
@@ -741,7 +747,7 @@ __global__ __launch_bounds__(256) void k_sweep_c(Geometry g, PhysK<typename Stor
 }
 
 template <int ST, int SP>
-__global__ __launch_bounds__(256) void k_sweep(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
+__global__ __launch_bounds__(256, ST == ST_F64 ? 1 : 6) void k_sweep(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
                                                 const typename Store<ST>::S *__restrict__ emit,
                                                 double *__restrict__ part) {
     sweep_block<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
@@ -865,7 +871,7 @@ __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::
             if (mask & (1u << j)) in += double(wgt<T>(j) * (Store<ST>::cv(raw[j]) + ph.cref));
         glb(it.acc)[k] += in;
         if (ph.sputter != SP_BOUNCEBACK)
-            st_at(emit, glb(it.vox)[k] * uint32_t(sizeof(S)),
+            st_at(emit, uint32_t(k) * uint32_t(sizeof(S)),
                   Store<ST>::enc(T(double(ph.keep) * in * glb(it.scale)[k])));
         arrived[0] = in;
     }
