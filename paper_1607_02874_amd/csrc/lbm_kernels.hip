@@ -216,6 +216,14 @@ template <typename S>
 __device__ __forceinline__ void st_at(S *base, uint32_t byte_off, S v) {
     *(LBM_GLOBAL S *)((LBM_GLOBAL char *)(base) + byte_off) = v;
 }
+// Streaming store: the populations written by a sweep are not read again
+// before the next sweep, so they need not stay in the caches.  Used where
+// every store of a wavefront covers whole lines (the node-compact sweep);
+// the chunk sweep's partial-line stores lose write combining with it.
+template <typename S>
+__device__ __forceinline__ void st_stream(S *base, uint32_t byte_off, S v) {
+    __builtin_nontemporal_store(v, (LBM_GLOBAL S *)((LBM_GLOBAL char *)(base) + byte_off));
+}
 
 // A population buffer: 38 direction arrays (carrier slots 0..18, reactant
 // 19..37) of `stride` bytes each from `base`.  A direction's base address is
@@ -721,9 +729,9 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             opaque(own_b);
-            st_at(static_cast<S *>(out.p(dslot(i))), own_b, Store<ST>::enc(hC[i]));
+            st_stream(static_cast<S *>(out.p(dslot(i))), own_b, Store<ST>::enc(hC[i]));
             opaque(own_b);
-            st_at(static_cast<S *>(out.p(19 + dslot(i))), own_b, Store<ST>::enc(hR[i]));
+            st_stream(static_cast<S *>(out.p(19 + dslot(i))), own_b, Store<ST>::enc(hR[i]));
         }
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
             S *link = static_cast<S *>(g.link);
