@@ -64,8 +64,7 @@ struct lbm_ctx {
     uint32_t *d_order = nullptr;
     uint32_t *d_iface_vox = nullptr, *d_iface_mask = nullptr;
     double *d_iface_scale = nullptr, *d_acc = nullptr;
-    uint32_t *d_iface_start = nullptr, *d_link_map = nullptr, *d_link_base = nullptr;
-    void *d_link = nullptr;
+    unsigned long long *d_inacc = nullptr;  // In(k) of the sweep in progress (fixed point)
     void *d_emit = nullptr;
     void *d_pop[2] = {nullptr, nullptr};
     double *d_part = nullptr;
@@ -74,9 +73,9 @@ struct lbm_ctx {
     int64_t step = 0;
     int64_t blocks_sweep = 0, blocks_iface = 0;
     int ytile = 16;       // rows per y-tile of the sweep traversal
-    // node-compact sweep: per-node coordinates, wave launch order, per-wave
-    // link base; compact = 1 selects it (needs ny, nz <= 1024)
-    uint32_t *d_pos = nullptr, *d_worder = nullptr, *d_wlink = nullptr;
+    // node-compact sweep: per-node coordinates and wave launch order;
+    // compact = 1 selects it (needs ny, nz <= 1024)
+    uint32_t *d_pos = nullptr, *d_worder = nullptr;
     int64_t nwaves = 0;
     bool compact_ok = false;
     int compact = 0;
@@ -142,8 +141,7 @@ Geometry geometry(const lbm_ctx *c) {
     Geometry g;
     g.chunks = c->d_chunks;
     g.order = c->d_order;
-    g.link_base = c->d_link_base;
-    g.link = c->d_link;
+    g.inacc = c->d_inacc;
     g.nx = c->nx;
     g.ny = c->ny;
     g.nz = c->nz;
@@ -154,7 +152,6 @@ Geometry geometry(const lbm_ctx *c) {
     g.nfluid = c->nfluid;
     g.pos = c->d_pos;
     g.worder = c->d_worder;
-    g.wlink = c->d_wlink;
     g.nwaves = uint32_t(c->nwaves);
     g.pad2 = 0;
     return g;
@@ -195,9 +192,7 @@ Interface interface_list(const lbm_ctx *c) {
     it.mask = c->d_iface_mask;
     it.scale = c->d_iface_scale;
     it.acc = c->d_acc;
-    it.start = c->d_iface_start;
-    it.map = c->d_link_map;
-    it.link = c->d_link;
+    it.inacc = c->d_inacc;
     it.n = c->niface;
     return it;
 }
@@ -283,47 +278,6 @@ void build_interface(lbm_ctx *c, std::vector<uint32_t> &vox, std::vector<uint32_
             }
 }
 
-// Link-buffer layout.  The sweep exports every reactant population that
-// heads into a catalytic node: gas nodes in storage order ((z, y, x)), each
-// node's links in ascending direction.  link_base[chunk] is the first slot of
-// each 64-voxel chunk; map lists, per interface node and active link j
-// (ascending), the slot its arriving population is written to.
-void build_links(const lbm_ctx *c, const std::vector<uint32_t> &ivox, const std::vector<uint32_t> &imask,
-                 std::vector<uint32_t> &start, std::vector<uint32_t> &map, std::vector<uint32_t> &link_base,
-                 std::vector<uint32_t> &wlink) {
-    const bool xper = c->ph.species_x == XB_PERIODIC;
-    std::vector<int32_t> iface_of(size_t(c->n), -1);
-    for (size_t k = 0; k < ivox.size(); ++k) iface_of[ivox[k]] = int32_t(k);
-    start.assign(ivox.size() + 1, 0);
-    for (size_t k = 0; k < ivox.size(); ++k) start[k + 1] = start[k] + uint32_t(__builtin_popcount(imask[k]));
-    map.assign(start.back(), 0);
-    link_base.assign(size_t(int64_t(c->ny) * c->nz * c->W), 0);
-    wlink.assign(size_t((c->nfluid + 63) / 64), 0);
-    uint32_t slot = 0;
-    int64_t rank = 0;
-    for (int z = 0; z < c->nz; ++z)
-        for (int y = 0; y < c->ny; ++y)
-            for (int x = 0; x < c->nx; ++x) {
-                if ((x & 63) == 0) link_base[size_t((int64_t(z) * c->ny + y) * c->W + (x >> 6))] = slot;
-                if (c->vox[size_t((int64_t(z) * c->ny + y) * c->nx + x)] != LBM_FLUID) continue;
-                if ((rank & 63) == 0) wlink[size_t(rank >> 6)] = slot;
-                ++rank;
-                for (int i = 1; i < 19; ++i) {
-                    int xs = x - CX[i];
-                    if (xs < 0 || xs >= c->nx) {
-                        if (!xper) continue;  // reservoir ghost, not a catalytic source
-                        xs = (xs + c->nx) % c->nx;
-                    }
-                    const int ys = (y - CY[i] + c->ny) % c->ny, zs = (z - CZ[i] + c->nz) % c->nz;
-                    const int64_t src = (int64_t(zs) * c->ny + ys) * c->nx + xs;
-                    if (c->vox[size_t(src)] != LBM_CATALYTIC) continue;
-                    const int32_t k = iface_of[size_t(src)];
-                    const int j = opp(i);
-                    const uint32_t m = imask[size_t(k)];
-                    map[start[size_t(k)] + uint32_t(__builtin_popcount(m & ((1u << j) - 1u)))] = slot++;
-                }
-            }
-}
 
 lbm_status check_pending_flag(lbm_ctx *c) {
     if (c->flag_pending && hipEventQuery(c->flag_event) == hipSuccess) {
@@ -489,6 +443,15 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     // concentration is depleted next to the catalyst, and a shift would cost
     // relative precision exactly where the conversion is decided.
     c->ph.c_ref = bc->c_ref >= 0.0 ? bc->c_ref : 0.0;
+    // Fixed-point scale 2^S of the In(k) sums: reactant populations are of the
+    // order of the largest of c_inlet, c0 and c_ref, and 2^S leaves about 2^11
+    // of headroom above 18 such terms in a signed 64-bit sum.
+    {
+        const double c_scale = std::max(std::max(c->ph.c_inlet, bc->c0), std::max(c->ph.c_ref, 1e-30));
+        const int shift = std::min(62, std::max(0, 47 - int(std::ceil(std::log2(c_scale)))));
+        c->ph.in_scale = std::ldexp(1.0, shift);
+        c->ph.in_unscale = std::ldexp(1.0, -shift);
+    }
     c->ph.p_stick = bc->p_stick;
     c->ph.p = p;
     c->ph.sputter = bc->sputter;
@@ -516,9 +479,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         }
         std::vector<ChunkInfo> chunks;
         build_chunks(c, ivox, chunks);
-        std::vector<uint32_t> istart, lmap, lbase, wlink;
         c->nwaves = (c->nfluid + 63) / 64;
-        build_links(c, ivox, imask, istart, lmap, lbase, wlink);
         // node-compact sweep tables (coordinates packed as x | y << 12 | z << 22)
         c->compact_ok = c->ny <= 1024 && c->nz <= 1024 && c->nfluid > 0;
         std::vector<uint32_t> pos, worder;
@@ -535,13 +496,11 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         }
 
         // The kernels address every buffer with 32-bit byte offsets from a
-        // scalar base: a population pair (2 nfp elements), the emission array
-        // (one element per interface node) and the link buffer must each stay
-        // below 4 GiB.
+        // scalar base: a population pair (2 nfp elements) and the emission
+        // array (one element per interface node) must each stay below 4 GiB.
         {
             const uint64_t sbytes = uint64_t(storage_bytes(c->ph.storage)), lim = uint64_t(1) << 32;
-            if (2 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(c->niface) * sbytes >= lim ||
-                uint64_t(lmap.size()) * sbytes >= lim) {
+            if (2 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(c->niface) * sbytes >= lim) {
                 release(c);
                 delete c;
                 return fail(nullptr, LBM_EUNSUPPORTED,
@@ -562,14 +521,10 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         c->d_iface_mask = static_cast<uint32_t *>(dev_alloc(c, imask.size() * 4));
         c->d_iface_scale = static_cast<double *>(dev_alloc(c, iscale.size() * 8));
         c->d_acc = static_cast<double *>(dev_alloc(c, size_t(c->niface) * 8));
-        c->d_iface_start = static_cast<uint32_t *>(dev_alloc(c, istart.size() * 4));
-        c->d_link_map = static_cast<uint32_t *>(dev_alloc(c, lmap.size() * 4));
-        c->d_link_base = static_cast<uint32_t *>(dev_alloc(c, lbase.size() * 4));
-        c->d_link = dev_alloc(c, lmap.size() * size_t(storage_bytes(c->ph.storage)));
+        c->d_inacc = static_cast<unsigned long long *>(dev_alloc(c, size_t(c->niface) * 8));
         if (c->compact_ok) {
             c->d_pos = static_cast<uint32_t *>(dev_alloc(c, pos.size() * 4));
             c->d_worder = static_cast<uint32_t *>(dev_alloc(c, worder.size() * 4));
-            c->d_wlink = static_cast<uint32_t *>(dev_alloc(c, wlink.size() * 4));
         }
         // One pool: population buffers A and B, then the emission array (one
         // element per interface node, indexed by interface index).
@@ -582,10 +537,9 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         const int64_t nparts = 4 * c->blocks_sweep + c->blocks_iface + FOLD_BLOCKS * NPART;
         c->d_part = static_cast<double *>(dev_alloc(c, size_t(nparts) * 8));
         c->d_tot = static_cast<DevTotals *>(dev_alloc(c, sizeof(DevTotals)));
-        if (!c->d_chunks || !c->d_order || !c->d_iface_start || !c->d_link_map || !c->d_link_base ||
-            !c->d_link || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
+        if (!c->d_chunks || !c->d_order || !c->d_inacc || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
             !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot ||
-            (c->compact_ok && (!c->d_pos || !c->d_worder || !c->d_wlink))) {
+            (c->compact_ok && (!c->d_pos || !c->d_worder))) {
             release(c);
             delete c;
             return fail(nullptr, LBM_ENOMEM, "device allocation failed");
@@ -599,13 +553,10 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         up(c->d_iface_vox, ivox.data(), ivox.size() * 4);
         up(c->d_iface_mask, imask.data(), imask.size() * 4);
         up(c->d_iface_scale, iscale.data(), iscale.size() * 8);
-        up(c->d_iface_start, istart.data(), istart.size() * 4);
-        up(c->d_link_map, lmap.data(), lmap.size() * 4);
-        up(c->d_link_base, lbase.data(), lbase.size() * 4);
+
         if (c->compact_ok) {
             up(c->d_pos, pos.data(), pos.size() * 4);
             up(c->d_worder, worder.data(), worder.size() * 4);
-            up(c->d_wlink, wlink.data(), wlink.size() * 4);
         }
         if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
         if (e == hipSuccess && c->niface) e = hipMemsetAsync(c->d_emit, 0, size_t(c->niface) * sb, c->stream);
@@ -614,7 +565,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         t0.mass_species = double(c->nfluid) * bc->c0;
         up(c->d_tot, &t0, sizeof(t0));
         if (e == hipSuccess) e = launch_init(geometry(c), c->ph, c->d_pop[1], c->d_pop[0], c->stream);
-        if (e == hipSuccess) e = launch_export(geometry(c), c->ph, interface_list(c), c->d_pop[0], c->stream);
+        if (e == hipSuccess) e = launch_in_init(geometry(c), c->ph, interface_list(c), c->d_pop[0], c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host vectors go out of scope
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->h_flag), sizeof(int32_t));
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->flag_event, hipEventDisableTiming);
@@ -999,8 +950,9 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_tot, &h.tot, sizeof(DevTotals), hipMemcpyHostToDevice, c->stream);
     c->step = h.step;
     c->cur = int(h.cur);
-    // the link buffer is derived state: rebuild it from the current populations
-    if (e == hipSuccess) e = launch_export(geometry(c), c->ph, interface_list(c), c->d_pop[c->cur], c->stream);
+    // In(k) of the pending interface is derived state: rebuild it from the
+    // current post-collision populations (the same integer terms the sweep adds)
+    if (e == hipSuccess) e = launch_in_init(geometry(c), c->ph, interface_list(c), c->d_pop[c->cur], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "checkpoint upload");
     c->flag_pending = false;
@@ -1011,7 +963,7 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
 // Autotuner: time the sweep for every candidate (sweep variant x y-tile)
 // in place, then restore what the trial sweeps overwrote.  A sweep reads the
 // current post-collision buffer and the emission array and writes only the
-// other population buffer, the link buffer and its partial sums, so saving
+// other population buffer, the In(k) accumulators and its partial sums, so saving
 // and restoring the first two leaves the state exactly as it was.
 }  // extern "C"
 
@@ -1037,26 +989,26 @@ std::vector<Candidate> tuning_candidates(bool compact_ok, int ny) {
 }
 
 struct Saved {
-    void *pop = nullptr, *link = nullptr;
+    void *pop = nullptr, *link = nullptr;  // saved population buffer and In(k) accumulators
 };
 
 lbm_status save_written(lbm_ctx *c, Saved &sv, void *(*alloc)(lbm_ctx *, size_t)) {
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t link = size_t(c->nlinks) * storage_bytes(c->ph.storage);
+    const size_t link = size_t(c->niface) * 8;
     sv.pop = alloc(c, pop);
     sv.link = alloc(c, std::max<size_t>(link, 256));
     if (!sv.pop || !sv.link) return fail(c, LBM_ENOMEM, "autotune scratch allocation failed");
     hipError_t e = hipMemcpyAsync(sv.pop, c->d_pop[1 - c->cur], pop, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess && link) e = hipMemcpyAsync(sv.link, c->d_link, link, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && link) e = hipMemcpyAsync(sv.link, c->d_inacc, link, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "autotune save");
     return LBM_OK;
 }
 
 lbm_status restore_written(lbm_ctx *c, Saved &sv) {
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t link = size_t(c->nlinks) * storage_bytes(c->ph.storage);
+    const size_t link = size_t(c->niface) * 8;
     hipError_t e = hipMemcpyAsync(c->d_pop[1 - c->cur], sv.pop, pop, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess && link) e = hipMemcpyAsync(c->d_link, sv.link, link, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && link) e = hipMemcpyAsync(c->d_inacc, sv.link, link, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "autotune restore");
     return LBM_OK;

@@ -63,8 +63,7 @@ struct DevTotals {
 struct Geometry {
     const ChunkInfo *chunks;  // rows * W records, row = z * ny + y
     const uint32_t *order;    // sweep traversal: per wave y | z << 12 | chunk << 24
-    const uint32_t *link_base;  // per chunk (row * W + chunk): first link-buffer slot it exports
-    void *link;               // link buffer (storage type), see Interface
+    unsigned long long *inacc;  // per interface node: In(k) of the sweep in progress, fixed point (see Interface)
     int32_t nx, ny, nz, W;    // W = ceil(nx / 64)
     uint32_t units;           // ny * nz * W waves
     int32_t pad;
@@ -74,7 +73,6 @@ struct Geometry {
     // indices per wave); null when the lattice is too large for `pos`.
     const uint32_t *pos;      // per gas node: x | y << 12 | z << 22
     const uint32_t *worder;   // launch order of the 64-node waves
-    const uint32_t *wlink;    // per 64-node wave: first link-buffer slot it exports
     uint32_t nwaves;          // ceil(nfluid / 64)
     int32_t pad2;
 };
@@ -86,6 +84,7 @@ struct Physics {
     double rho_ref, c_ref;       // storage shifts of the two lattices
     double rho0, c0, c_inlet;
     double p_stick, p;
+    double in_scale, in_unscale;  // 2^S and 2^-S of the fixed-point In(k) sums
     int32_t sputter, coupling, species_x, storage;
 };
 
@@ -95,9 +94,10 @@ struct Interface {
     const uint32_t *mask;   // bit j (kernel direction numbering): j is an active link
     const double *scale;    // 1/b(k) (UNIFORM) or 1/sum_{active} w_opp(j) (WEIGHTED)
     double *acc;            // sum_t In(k, t)
-    const uint32_t *start;  // node k's links are map[start[k] .. start[k + 1]) (n + 1 entries)
-    const uint32_t *map;    // link-buffer slot of each (node, active link), links in ascending j
-    void *link;             // link buffer: arriving populations f*_j(k - c_j), stored form
+    // In(k) = sum_j f*_j(k - c_j) of the last sweep, accumulated by that sweep
+    // with integer atomics as round(term * 2^S) (two's complement); an
+    // integer sum is the same in any order, so results are deterministic.
+    unsigned long long *inacc;
     int64_t n;
 };
 
@@ -114,10 +114,12 @@ void build_order(int nx, int ny, int nz, int ytile, uint32_t *order);
 hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *post, hipStream_t s);
 hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, void *emit, double *part,
                             int64_t blocks, hipStream_t s);
-hipError_t launch_export(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s);
+// In(k) of every interface node from a post-collision population buffer (after
+// create and after a checkpoint load; during stepping the sweep accumulates it).
+hipError_t launch_in_init(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s);
 hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
                         double *part, hipStream_t s);
-// The node-compact sweep (same results; needs g.pos, g.worder, g.wlink).
+// The node-compact sweep (same results; needs g.pos and g.worder).
 hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
                           double *part, hipStream_t s);
 int64_t sweep_blocks_c(const Geometry &g);

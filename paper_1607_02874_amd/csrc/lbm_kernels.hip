@@ -95,6 +95,7 @@ struct PhysK {
     T keep;           // 1 - p_stick
     T h0c, h0r;       // initial state, normalised: rho0 - rho_ref, c0 - c_ref
     double c_in;      // reservoir concentration (influx tally)
+    double in_scale, in_unscale;  // fixed-point scale of the In(k) sums and its inverse
     int32_t sputter, coupling, species_x;
 };
 
@@ -114,10 +115,24 @@ PhysK<T> to_kernel(const Physics &p) {
     k.h0c = T(p.rho0 - p.rho_ref);
     k.h0r = T(p.c0 - p.c_ref);
     k.c_in = p.c_inlet;
+    k.in_scale = p.in_scale;
+    k.in_unscale = p.in_unscale;
     k.sputter = p.sputter;
     k.coupling = p.coupling;
     k.species_x = p.species_x;
     return k;
+}
+
+// One term of an In(k) sum, f*_j = w_j (h_j + c_ref) of the stored value, in
+// fixed point: adding 1.5 * 2^52 to term * 2^S (|term * 2^S| < 2^51) leaves
+// round-to-nearest(term * 2^S) in the low mantissa bits, so the bit pattern
+// is MAGIC_BITS + that integer.  The sums add bit patterns; the reader
+// subtracts b(k) * MAGIC_BITS.
+constexpr double MAGIC = 6755399441055744.0;  // 1.5 * 2^52
+constexpr unsigned long long MAGIC_BITS = 0x4338000000000000ull;
+template <typename T>
+__device__ __forceinline__ unsigned long long in_term(T w, T h_stored, T cref, double scale) {
+    return static_cast<unsigned long long>(__double_as_longlong(fma(double(w * (h_stored + cref)), scale, MAGIC)));
 }
 
 // ------------------------------------------------------------ helpers --
@@ -258,11 +273,14 @@ __device__ __forceinline__ uint32_t rank_of_mask(uint64_t m, uint32_t add) {
 
 // Pull both lattices into registers: hC[i], hR[i] are the normalised
 // populations of this node after streaming (the pre-collision state).
+// kidx (LDS, may be null): receives, per direction i and lane, the
+// interface index of the lane's source x - c_i (meaningful where it is an
+// interface node), for the sweep's In(k) accumulation.
 template <int ST, int SP>
 __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
                                      const typename Store<ST>::S *__restrict__ emit, const WaveUnit &u,
                                      typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
-                                     uint32_t &cat_out) {
+                                     uint32_t &cat_out, uint32_t *kidx = nullptr) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     constexpr uint32_t SB = sizeof(S);
@@ -361,6 +379,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
         // emission of a catalytic source, by interface index (element 0 when not used)
         re[i] = ld_at(emit, lane_in(EMIT) ? irank * SB : 0u);
+        if (kidx) kidx[(i - 1) * 256 + threadIdx.x] = irank;
         cat_bits |= lane_in(CAT) ? (1u << i) : 0u;
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -389,7 +408,7 @@ template <int ST, int SP>
 __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
                                        const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
                                        int z, typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
-                                       uint32_t &cat_out) {
+                                       uint32_t &cat_out, uint32_t *kidx) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     constexpr uint32_t SB = sizeof(S);
@@ -466,6 +485,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             opaque(r_b);
             rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
             const uint32_t irank = cx == 0 ? i0 : (cx == 1 ? im : ip);
+            kidx[(i - 1) * 256 + threadIdx.x] = irank;
             uint32_t v_b = EMIT ? irank * SB : 0u;
             opaque(v_b);
             re[i] = ld_at(emit, v_b);
@@ -590,26 +610,22 @@ struct InOut {
     double in, out;
 };
 
-// Sum over the lanes below this one of a small per-lane count (< 32): the
-// count's bits are ballotted and counted below the lane.
-__device__ __forceinline__ uint32_t lanes_below_sum(uint32_t count) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int b = 0; b < 5; ++b) s += rank_of_mask(__builtin_amdgcn_ballot_w64((count >> b) & 1u), 0u) << b;
-    return s;
-}
-
-// Write this lane's catalytic-link populations (ascending direction) to
-// consecutive link slots starting at `slot`.
+// Add this lane's post-collision reactant populations that head into
+// interface nodes (the reversed catalytic-source directions) to In(k) of
+// their targets, as fixed-point integers; kidx holds each direction's target.
 template <int ST>
-__device__ __forceinline__ void export_links(typename Store<ST>::S *link, uint32_t slot, uint32_t cat_bits,
-                                             const typename Store<ST>::T (&hR)[19]) {
-    using S = typename Store<ST>::S;
+__device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const uint32_t *kidx, uint32_t cat_bits,
+                                              const PhysK<typename Store<ST>::T> &ph,
+                                              const typename Store<ST>::T (&hR)[19]) {
+    using T = typename Store<ST>::T;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         if ((cat_bits >> i) & 1u) {
-            st_at(link, slot * uint32_t(sizeof(S)), Store<ST>::enc(hR[opp(i)]));
-            ++slot;
+            const int j = opp(i);  // the link direction as seen from the interface node
+            const T stored = Store<ST>::cv(Store<ST>::enc(hR[j]));
+            (void)__hip_atomic_fetch_add(&glb(inacc)[kidx[(i - 1) * 256 + threadIdx.x]],
+                                         in_term<T>(wgt<T>(j), stored, ph.cref, ph.in_scale), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -641,12 +657,13 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
     using S = typename Store<ST>::S;
     using T = typename Store<ST>::T;
     const WaveUnit u = locate(g, block);
+    __shared__ uint32_t kidx[18 * 256];
     // per-block partials: carrier mass, reactant mass, influx, outflux
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (u.active) {
         T hC[19], hR[19];
         uint32_t cat_bits;
-        pull<ST, SP>(g, ph, in, emit, u, hC, hR, cat_bits);
+        pull<ST, SP>(g, ph, in, emit, u, hC, hR, cat_bits, kidx);
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
@@ -672,16 +689,8 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
             opaque(own_b);
             st_at(static_cast<S *>(out.p(19 + dslot(i))), own_b, Store<ST>::enc(hR[i]));
         }
-        // Export the reactant populations that head into catalytic nodes
-        // (the reversed catalytic-source directions) to the link buffer for
-        // the next step's interface sum, as the same stored bits.  Layout:
-        // gas nodes in storage order, each node's links in ascending
-        // direction; this chunk's first slot comes from the host.
-        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
-            S *link = static_cast<S *>(g.link);
-            const uint32_t lb = glb(g.link_base)[uint32_t(u.row) * uint32_t(g.W) + uint32_t(u.chunk)];
-            export_links<ST>(link, lb + lanes_below_sum(uint32_t(__popc(cat_bits))), cat_bits, hR);
-        }
+        // In(k) of the next step's interface: what leaves towards interface nodes
+        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR);
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p(19)) + u.idx, nfp, first_x,
                                                last_x);
@@ -707,13 +716,14 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
     const uint32_t w = glb(g.worder)[wvalid ? slot : 0u];
     const uint32_t idx = w * 64u + (threadIdx.x & 63u);
     const bool active = wvalid && int64_t(idx) < g.nfluid;
+    __shared__ uint32_t kidx[18 * 256];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (active) {
         const uint32_t p = glb(g.pos)[idx];
         const int x = int(p & 0xfffu), y = int((p >> 12) & 0x3ffu), z = int(p >> 22);
         T hC[19], hR[19];
         uint32_t cat_bits;
-        pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits);
+        pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx);
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
@@ -733,10 +743,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
             opaque(own_b);
             st_stream(static_cast<S *>(out.p(19 + dslot(i))), own_b, Store<ST>::enc(hR[i]));
         }
-        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
-            S *link = static_cast<S *>(g.link);
-            export_links<ST>(link, glb(g.wlink)[w] + lanes_below_sum(uint32_t(__popc(cat_bits))), cat_bits, hR);
-        }
+        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR);
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p(19)) + idx, g.nfp,
                                                first_x, last_x);
@@ -748,7 +755,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
 }
 
 template <int ST, int SP>
-__global__ __launch_bounds__(256) void k_sweep_c(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in,
+__global__ __launch_bounds__(256, ST == ST_F64 ? 1 : 5) void k_sweep_c(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in,
                                                   OutSlots out, const typename Store<ST>::S *__restrict__ emit,
                                                   double *__restrict__ part) {
     sweep_block_c<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
@@ -846,11 +853,11 @@ __device__ __forceinline__ uint32_t rank_of(const Geometry &g, int row, int x, b
     return I.base + uint32_t(__popcll(below));
 }
 
-// Sputtering sum: In(k) = sum_j f*_j(k - c_j) over the active links of each
-// interface node (first line of the sputtering equations).  The arriving
-// populations were written to the link buffer by the sweep that produced
-// them (or by k_export); node k's links sit at map[start[k] .. start[k+1])
-// in ascending direction order, so the sum order is fixed.
+// Sputtering boundary at each interface node (first line of the sputtering
+// equations): In(k) = sum_j f*_j(k - c_j) over its active links was summed by
+// the sweep that produced those populations (fixed point, any order); here it
+// is read and cleared for the next sweep, added to Acc(k), and re-emitted as
+// E(k) = (1 - p_S) In(k) scale(k).
 template <int ST>
 __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::T> &ph, const Interface &it,
                                                 typename Store<ST>::S *__restrict__ emit, double *__restrict__ part,
@@ -860,23 +867,14 @@ __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::
     const int64_t k = int64_t(block) * blockDim.x + threadIdx.x;
     double arrived[1] = {0.0};
     if (k < it.n) {
-        const LBM_GLOBAL S *link = glb(static_cast<const S *>(it.link));
-        const uint32_t mask = glb(it.mask)[k];
-        const uint32_t s0 = glb(it.start)[k];
-        // all slot indices, then all values (latency paid twice, not per link)
-        uint32_t slot[19];
-        uint32_t t = s0;
-#pragma unroll
-        for (int j = 1; j < 19; ++j)
-            if (mask & (1u << j)) slot[j] = glb(it.map)[t++];
-        S raw[19];
-#pragma unroll
-        for (int j = 1; j < 19; ++j)
-            if (mask & (1u << j)) raw[j] = link[slot[j]];
-        double in = 0.0;
-#pragma unroll
-        for (int j = 1; j < 19; ++j)
-            if (mask & (1u << j)) in += double(wgt<T>(j) * (Store<ST>::cv(raw[j]) + ph.cref));
+        const uint32_t b = uint32_t(__popc(glb(it.mask)[k]));
+        const unsigned long long raw = glb(it.inacc)[k] - uint64_t(b) * MAGIC_BITS;
+        glb(it.inacc)[k] = 0ull;
+        const long long fixed = static_cast<long long>(raw);
+        // a term outside the fixed-point range (|term| >= 2^51 / 2^S) cannot
+        // come from a bounded state; report it through the NaN watchdog
+        const double in = (fixed > (1ll << 55) || fixed < -(1ll << 55)) ? __builtin_nan("")
+                                                                         : double(fixed) * ph.in_unscale;
         glb(it.acc)[k] += in;
         if (ph.sputter != SP_BOUNCEBACK)
             st_at(emit, uint32_t(k) * uint32_t(sizeof(S)),
@@ -932,11 +930,13 @@ __global__ __launch_bounds__(256) void k_populations(Geometry g, PhysK<typename 
     }
 }
 
-// Fill the link buffer from a population buffer (after create and after a
-// checkpoint load; during stepping the sweep writes it).
+// In(k) of every interface node from a post-collision population buffer,
+// the same fixed-point terms the sweep accumulates (after create and after a
+// checkpoint load).
 template <int ST>
-__global__ __launch_bounds__(256) void k_export(Geometry g, PhysK<typename Store<ST>::T> ph, Interface it,
-                                                 const typename Store<ST>::S *__restrict__ fin) {
+__global__ __launch_bounds__(256) void k_in_init(Geometry g, PhysK<typename Store<ST>::T> ph, Interface it,
+                                                  const typename Store<ST>::S *__restrict__ fin) {
+    using T = typename Store<ST>::T;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= it.n) return;
     const uint32_t v = it.vox[k];
@@ -944,8 +944,7 @@ __global__ __launch_bounds__(256) void k_export(Geometry g, PhysK<typename Store
     const int x = int(v % uint32_t(g.nx));
     const int row = int(v / uint32_t(g.nx));
     const int y = row % g.ny, z = row / g.ny;
-    typename Store<ST>::S *link = static_cast<typename Store<ST>::S *>(it.link);
-    uint32_t t = it.start[k];
+    unsigned long long sum = 0ull;
 #pragma unroll
     for (int j = 1; j < 19; ++j) {
         if (mask & (1u << j)) {
@@ -955,9 +954,10 @@ __global__ __launch_bounds__(256) void k_export(Geometry g, PhysK<typename Store
             zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
             bool fl;
             const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
-            link[it.map[t++]] = fin[(19 + dslot(j)) * g.nfp + r];
+            sum += in_term<T>(wgt<T>(j), Store<ST>::ld(fin + (19 + dslot(j)) * g.nfp + r), ph.cref, ph.in_scale);
         }
     }
+    it.inacc[k] = sum;
 }
 
 // Fixed-order sum over rows [r0, r1) of column `col` of a row-major
@@ -1146,14 +1146,14 @@ hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interfac
     });
 }
 
-hipError_t launch_export(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s) {
+hipError_t launch_in_init(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s) {
     const int64_t blocks = interface_blocks(it.n);
     if (blocks == 0) return hipSuccess;
     return dispatch(ph.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         using SS = typename Store<ST>::S;
         using T = typename Store<ST>::T;
-        hipLaunchKernelGGL(k_export<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph), it,
+        hipLaunchKernelGGL(k_in_init<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph), it,
                            static_cast<const SS *>(fin));
         return hipGetLastError();
     });
