@@ -37,15 +37,15 @@ def algorithmic_bytes(info, s):
     """Bytes the method must move per step (per launch for each kernel).
 
     Sweep: every population of both lattices written once (38 s per gas node)
-    and read once (38 s), except the reactant populations heading into
-    catalytic solid, which the interface kernel reads instead (L_K s); plus one
-    4-byte emission read per interface node and the 32-byte chunk record per
-    64 voxels.  Interface: the L_K gathered populations, plus per interface
-    node its voxel index, link mask, scale (4 + 4 + 8), the FP64 accumulator
+    and read once (38 s), except the L_K reactant populations whose source is
+    a catalytic node, which come from the emission array (4 bytes per
+    interface node); plus the 8-byte In(k) sum per interface node and the
+    32-byte chunk record per 64 voxels.  Interface: per interface node, In(k)
+    read and clear (16), mask and scale (4 + 8), the FP64 accumulator
     read-modify-write (16) and the emission write (4)."""
     nf, n, nk, lk = info["n_fluid"], info["n_nodes"], info["n_interface"], info["n_catalytic_links"]
-    sweep = (76 * nf - lk) * s + 4 * nk + n // 2
-    iface = lk * s + nk * (4 + 4 + 8 + 16 + 4)
+    sweep = (76 * nf - lk) * s + 12 * nk + n // 2
+    iface = nk * (16 + 4 + 8 + 16 + 4)
     return {"sweep": sweep, "interface": iface, "step": sweep + iface}
 
 

@@ -444,11 +444,12 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     // relative precision exactly where the conversion is decided.
     c->ph.c_ref = bc->c_ref >= 0.0 ? bc->c_ref : 0.0;
     // Fixed-point scale 2^S of the In(k) sums: reactant populations are of the
-    // order of the largest of c_inlet, c0 and c_ref, and 2^S leaves about 2^11
-    // of headroom above 18 such terms in a signed 64-bit sum.
+    // order of the largest of c_inlet, c0 and c_ref (c); with S = 47 -
+    // ceil(log2 c) a term up to 16 c stays below the 2^51 the rounding allows,
+    // and 18 such terms below 2^56 in the signed 64-bit sum.
     {
-        const double c_scale = std::max(std::max(c->ph.c_inlet, bc->c0), std::max(c->ph.c_ref, 1e-30));
-        const int shift = std::min(62, std::max(0, 47 - int(std::ceil(std::log2(c_scale)))));
+        const double c_scale = std::max(std::max(c->ph.c_inlet, bc->c0), std::max(c->ph.c_ref, 1e-300));
+        const int shift = std::min(900, std::max(-900, 47 - int(std::ceil(std::log2(c_scale)))));
         c->ph.in_scale = std::ldexp(1.0, shift);
         c->ph.in_unscale = std::ldexp(1.0, -shift);
     }

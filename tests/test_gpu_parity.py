@@ -358,3 +358,20 @@ def test_autotune_leaves_state_unchanged():
         assert abs(ta[k] - tb[k]) <= 1e-12 * max(abs(tb[k]), abs(tb["mass_gas"])), k
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("c_inlet,c0", [(1000.0, 200.0), (1e-6, 0.0), (0.0, 0.0)])
+def test_fixed_point_in_sums_across_concentration_scales(c_inlet, c0):
+    """The In(k) sums are fixed point with a scale taken from the
+    concentration scale: the FP64 build still meets 1e-12 against the oracle
+    for large, tiny and zero concentrations."""
+    c = plain_case(steps=60, c_inlet=c_inlet, c0=c0)
+    ref = run_oracle(c)
+    gpu = run_gpu(c, F64)
+    e = errors(gpu, ref, c["vox"])
+    _report(f"fixed point c_in={c_inlet}", e)
+    if c_inlet == 0.0 and c0 == 0.0:
+        assert np.abs(gpu["conc"]).max() == 0.0 and np.abs(gpu["conv"]).max() == 0.0
+        return
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < 1e-12, (k, e[k])
