@@ -12,6 +12,7 @@ sweep of both lattices + FP64 reduction.  Prints one JSON line.
     python bench.py [--steps K] [--warmup W] [--storage f32|f16|bf16|f64]
     python bench.py --workload batch [--steps K]   (64-sample batch vs sequential)
     python bench.py --workload precision [--steps K]   (512^3, FP32/FP16/BF16 vs the FP64 build)
+    python bench.py --workload membrane [--steps K]    (1024x512x512 layer, Da 10 and 0.1, FP32 and FP16)
 """
 
 import argparse
@@ -291,6 +292,87 @@ def run_precision(args):
     print(json.dumps(line), flush=True)
 
 
+def run_membrane(args):
+    """1024x512x512 thin membrane (porous layer x in [384, 640), porosity 0.65,
+    correlation length 10, seed 1004): Da = 10 (reaction-limited under the
+    paper's convention) and Da = 0.1 (transport-limited), FP32 and FP16
+    storage, reactant initially at c_in everywhere.  Per case the throughput
+    and the conversion profile through the layer, reported as the ratio of
+    what the front and the rear quarter of the layer converted."""
+    import torch
+
+    from paper_1607_02874_amd import inputs, lbm
+
+    w = inputs.MEMBRANE_1024
+    t0 = time.perf_counter()
+    vox = w.voxels()
+    log(f"geometry {w.nx}x{w.ny}x{w.nz} porosity {inputs.porosity(vox):.4f} ({time.perf_counter() - t0:.1f} s)")
+    lo, hi = w.x_lo, w.x_hi
+    q = (hi - lo) // 4
+    results = {}
+    storages = [args.storage] if args.storage != "f32" else ["f32", "f16"]
+    for name in storages:
+        for da in (10.0, 0.1):
+            # reactant everywhere from the start (c0 = c_in): the inlet alone
+            # would not reach a layer 384 nodes downstream within the run
+            sim = lbm.Sim(vox, da=da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                          c_inlet=w.c_inlet, c0=w.c_inlet, storage=STORAGES[name])
+            info = sim.info()
+            if not args.no_autotune:
+                sim.autotune(2)
+            sim.step(args.warmup)
+            sim.synchronize()
+            sim.set_timing(True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sim.step(args.steps)
+            sim.synchronize()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            kt = sim.kernel_times()
+            conv = sim.conversion_map()
+            tot = sim.totals()
+            prof = conv[:, :, lo:hi].sum(axis=(0, 1))
+            ab = algorithmic_bytes(info, lbm.STORAGE_BYTES[STORAGES[name]])
+            t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
+            key = f"{name}_da{da:g}"
+            results[key] = {"mlups": round(vox.size * args.steps / el / 1e6, 1),
+                            "ms_per_step": round(el / args.steps * 1e3, 3),
+                            "sweep_us": round(t_sweep * 1e6, 1),
+                            "sweep_GBps": round(ab["sweep"] / t_sweep / 1e9, 1),
+                            "p": round(info["p"], 6),
+                            "sweep": "node-compact" if sim.get_tunable(lbm.TUNE_SWEEP) == 1 else "64-voxel chunks",
+                            "ytile": sim.get_tunable(lbm.TUNE_YTILE),
+                            "converted": tot["converted"], "lost": tot["lost"],
+                            "front_rear_ratio": float(prof[:q].sum() / max(prof[-q:].sum(), 1e-300))}
+            sim.close()
+            del conv
+            log(f"{key}: {results[key]}")
+    first = f"{storages[0]}_da10"
+    line = {
+        "metric": "MLUPS (flow+species) and % of HBM roofline at stated error vs FP64 oracle",
+        "value": results[first]["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": results[first]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32", "f64": "f64"}[storages[0]],
+        "data": "synthetic (seeded Gaussian-random-field porous layer)",
+        "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz}, porous layer x in [{lo}, {hi}), porosity {w.phi}, "
+                               f"correlation length {w.ell}, seed {w.seed}, tau {w.tau}; Da 10 and 0.1",
+                   "n_nodes": int(vox.size), "cases": results},
+        "roofline": {"bound": "hbm", "kernel": f"sweep ({first})", "achieved": results[first]["sweep_GBps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(results[first]["sweep_GBps"] / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,9 +387,9 @@ def main():
     ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
     ap.add_argument("--sweep", type=int, default=None, choices=(0, 1),
                     help="sweep variant: 1 node-compact (library default), 0 one wave per 64-voxel chunk")
-    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision"),
+    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision", "membrane"),
                     help="single: the 256^3 sample; batch: the 64-sample mixed batch; precision: 512^3 "
-                         "with FP32/FP16/BF16 storage against the FP64 build")
+                         "with FP32/FP16/BF16 storage against the FP64 build; membrane: 1024x512x512 layer")
     ap.add_argument("--no-graph", action="store_true", help="batch: launch directly instead of graph replays")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape instead of autotuning it before timing")
@@ -330,6 +412,9 @@ def main():
         return
     if args.workload == "precision":
         run_precision(args)
+        return
+    if args.workload == "membrane":
+        run_membrane(args)
         return
     w = inputs.SINGLE_256
     if args.da is not None:

@@ -182,6 +182,16 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
                          const lbm_bc *bc, const lbm_device *dev, lbm_ctx **out);
 
 /*
+ * lbm_inspect - what lbm_create would build, without a device: the same
+ * argument checks (same errors) and parameter maps (tau, Kn, p, p_clamped),
+ * the node, interface-node and catalytic-link counts, and the device bytes the
+ * context would allocate (populations, emission, tables, partial sums; within
+ * 256 B per buffer).  Host memory only; usable on a machine without a GPU.
+ */
+lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double tau[2],
+                       const lbm_bc *bc, lbm_info *info);
+
+/*
  * lbm_step - advance n >= 0 time steps (Eq. LBE for both lattices plus the
  * sputtering boundary condition).  Asynchronous on the context stream.
  * Returns LBM_ENONFINITE if a total of an earlier, completed step was found

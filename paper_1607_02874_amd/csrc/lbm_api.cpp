@@ -390,13 +390,18 @@ lbm_status lbm_create(const lbm_geometry *g, double kn, double da, const double 
     return lbm_create_on(g, kn, da, tau, bc, nullptr, out);
 }
 
-lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const double tau[2], const lbm_bc *bc,
-                         const lbm_device *dev, lbm_ctx **out) {
-    lbm_status st = validate(g, kn, da, tau, bc, out);
-    if (st != LBM_OK) return st;
+}  // extern "C"
 
-    // Parameter maps: Eq. (knudsen) and Eq. (Da_def) with tau_ch = 1/p,
-    // tau_tr = delta / cs.
+namespace {
+
+// Parameter maps: Eq. (knudsen) and Eq. (Da_def) with tau_ch = 1/p and
+// tau_tr = delta / cs.
+struct ParamMap {
+    double tau_gas, tau_species, kn, p;
+    int clamped;
+};
+
+lbm_status param_map(const lbm_geometry *g, double kn, double da, const double tau[2], ParamMap *m) {
     const double delta = g->pore_size;
     double tau_gas = tau[0];
     if (tau_gas == 0.0) tau_gas = 0.5 + kn * delta / CS;
@@ -404,10 +409,87 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     if (tau[0] != 0.0 && kn != 0.0 && std::fabs(kn - kn_of_tau) > 1e-9 * std::max(1.0, kn))
         return fail(nullptr, LBM_EINVAL, "kn and tau[0] disagree");
     if (!(tau_gas > 0.5)) return fail(nullptr, LBM_EINVAL, "derived tau_gas must be > 1/2");
-    const double tau_species = tau[1] != 0.0 ? tau[1] : tau_gas;
+    m->tau_gas = tau_gas;
+    m->tau_species = tau[1] != 0.0 ? tau[1] : tau_gas;
+    m->kn = kn_of_tau;
     double p = std::isinf(da) ? 0.0 : CS / (da * delta);
-    const int clamped = p > 1.0;
-    if (clamped) p = 1.0;
+    m->clamped = p > 1.0;
+    m->p = m->clamped ? 1.0 : p;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double tau[2], const lbm_bc *bc,
+                       lbm_info *info) {
+    lbm_ctx *unused = nullptr;
+    lbm_status st = validate(g, kn, da, tau, bc, &unused);
+    if (st != LBM_OK) return st;
+    if (!info) return fail(nullptr, LBM_EINVAL, "info is NULL");
+    ParamMap m;
+    st = param_map(g, kn, da, tau, &m);
+    if (st != LBM_OK) return st;
+    try {
+        lbm_ctx c;
+        c.nx = g->nx;
+        c.ny = g->ny;
+        c.nz = g->nz;
+        c.W = (g->nx + 63) / 64;
+        c.n = int64_t(g->nx) * g->ny * g->nz;
+        c.ph.species_x = bc->species_x;
+        c.ph.sputter = bc->sputter;
+        c.vox.assign(g->voxels, g->voxels + c.n);
+        for (uint8_t v : c.vox) c.nfluid += v == LBM_FLUID;
+        std::vector<uint32_t> ivox, imask;
+        std::vector<double> iscale;
+        build_interface(&c, ivox, imask, iscale);
+        const int64_t nfp = (c.nfluid + 1 + 127) / 128 * 128;
+        const int64_t sb = storage_bytes(bc->storage);
+        const int64_t niface = int64_t(ivox.size());
+        const int64_t rows = int64_t(g->ny) * g->nz;
+        info->tau_gas = m.tau_gas;
+        info->tau_species = m.tau_species;
+        info->kn = m.kn;
+        info->p = m.p;
+        info->da = da;
+        info->pore_size = g->pore_size;
+        info->p_clamped = m.clamped;
+        info->storage = bc->storage;
+        info->n_nodes = c.n;
+        info->n_fluid = c.nfluid;
+        info->n_interface = niface;
+        info->n_catalytic_links = c.nlinks;
+        // the buffers lbm_create allocates (populations and emission, chunk
+        // records and traversal tables, interface arrays, coordinates and wave
+        // order of the compact sweep, partial sums), each rounded up to 256 B
+        auto r256 = [](int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); };
+        const int64_t chunks = rows * c.W;
+        const int64_t blocks = ((chunks + 3) / 4 + 7) / 8 * 8;
+        const bool compact = g->ny <= 1024 && g->nz <= 1024 && c.nfluid > 0;
+        int64_t bytes = r256((76 * nfp + niface) * sb) + r256(chunks * int64_t(sizeof(ChunkInfo))) +
+                        r256(chunks * 4) + 2 * r256(niface * 4) + 3 * r256(niface * 8) +
+                        r256((4 * blocks + (niface + 255) / 256 + FOLD_BLOCKS * NPART) * 8) +
+                        r256(int64_t(sizeof(DevTotals)));
+        if (compact) bytes += r256(nfp * 4) + r256((c.nfluid + 63) / 64 * 4);
+        info->device_bytes = bytes;
+    } catch (const std::bad_alloc &) {
+        return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const double tau[2], const lbm_bc *bc,
+                         const lbm_device *dev, lbm_ctx **out) {
+    lbm_status st = validate(g, kn, da, tau, bc, out);
+    if (st != LBM_OK) return st;
+    ParamMap m;
+    st = param_map(g, kn, da, tau, &m);
+    if (st != LBM_OK) return st;
+    const double delta = g->pore_size;
+    const double tau_gas = m.tau_gas, tau_species = m.tau_species, kn_of_tau = m.kn, p = m.p;
+    const int clamped = m.clamped;
 
     int device = 0;
     hipError_t e = hipGetDevice(&device);

@@ -104,6 +104,8 @@ def _load():
         "lbm_create_on": (st, [P(lbm_geometry), ctypes.c_double, ctypes.c_double, P(ctypes.c_double), P(lbm_bc),
                                P(lbm_device), P(ctx)]),
         "lbm_step": (st, [ctx, ctypes.c_int64]),
+        "lbm_inspect": (st, [P(lbm_geometry), ctypes.c_double, ctypes.c_double, P(ctypes.c_double), P(lbm_bc),
+                             P(lbm_info)]),
         "lbm_fields": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_fields_device": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_conversion_map": (st, [ctx, ctypes.c_void_p]),
@@ -229,6 +231,17 @@ def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc
     _check(_LIB.lbm_create_on(ctypes.byref(g), float(kn), float(da), t, ctypes.byref(bc), dev,
                               ctypes.byref(out)))
     return out
+
+
+def inspect(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, **bc_kw):
+    """lbm_inspect: parameter maps, node/interface/link counts and planned
+    device bytes of a context, computed on the host (no GPU needed)."""
+    vox, g = _geometry(vox, pore_size)
+    bc = _bc(**bc_kw)
+    t = (ctypes.c_double * 2)(float(tau[0]), float(tau[1]))
+    info = lbm_info()
+    _check(_LIB.lbm_inspect(ctypes.byref(g), float(kn), float(da), t, ctypes.byref(bc), ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in lbm_info._fields_}
 
 
 class Sim:
