@@ -275,3 +275,32 @@ def test_results_independent_of_thread_count(orc, tmp_path):
         out.append(subprocess.run([sys.executable, "-c", code], env=env, check=True,
                                   capture_output=True, text=True).stdout.strip())
     assert out[0] == out[1]
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.3])
+def test_steady_bulk_diffusion_is_exact_fick_law(orc, tau):
+    """Steady 1-D diffusion of the reactant towards a fully absorbing wall
+    (no flow): the flux carried across a link in one step, the mean of the
+    pre- and post-collision first moments, (1 - 1/(2 tau)) j, equals
+    -D dc/dx with D = c_s^2 (tau - 1/2) and a centred difference, exactly
+    (the Appendix's diffusion of the species across the carrier, BGK with
+    equal-velocity equilibrium)."""
+    n = 20
+    vox = inputs.reactive_slab(n, ny=2, nz=2)
+    p, clamped = orc.p_from_da(1e-6, 1.0)
+    assert clamped and p == 1.0
+    o = orc.Oracle(vox, tau=(0.9, tau), p=p, p_stick=1.0, c_inlet=1.0, force=(0.0, 0.0, 0.0))
+    o.step(30000)
+    _, fR = o.get_state()
+    o.close()
+    c, _, _ = orc.d3q19()
+    f = fR.reshape(2, 2, n + 1, 19)
+    rho = f.sum(axis=3)
+    j = (f * c[:, 0]).sum(axis=3)
+    D = (tau - 0.5) / 3.0
+    flux = (1.0 - 0.5 / tau) * j[..., 2:n - 2]
+    grad = (rho[..., 3:n - 1] - rho[..., 1:n - 3]) / 2.0
+    assert np.abs(flux + D * grad).max() < 1e-12 * np.abs(flux).max()
+    # steady: the same flux through every plane, and a linear profile
+    assert np.ptp(flux) < 1e-12 * np.abs(flux).max()
+    assert np.abs(np.diff(rho[..., 1:n - 1], 2)).max() < 1e-12
