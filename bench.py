@@ -13,6 +13,7 @@ sweep of both lattices + FP64 reduction.  Prints one JSON line.
     python bench.py --workload batch [--steps K]   (64-sample batch vs sequential)
     python bench.py --workload precision [--steps K]   (512^3, FP32/FP16/BF16 vs the FP64 build)
     python bench.py --workload membrane [--steps K]    (1024x512x512 layer, Da 10 and 0.1, FP32 and FP16)
+    python bench.py --workload shard [--steps K]       (one 128x512x512 x-slab of the membrane)
 """
 
 import argparse
@@ -373,6 +374,72 @@ def run_membrane(args):
     print(json.dumps(line), flush=True)
 
 
+def run_shard(args):
+    """One rank's share of the 1024x512x512 membrane on 8 GPUs: the central
+    128x512x512 x-slab of the porous layer (x in [448, 576) of the membrane
+    geometry), stepped alone with periodic x for both lattices as an interior
+    slab sees its neighbours.  Reports the sweep time next to the bytes the
+    x-face halo exchange would move per step."""
+    import torch
+
+    from paper_1607_02874_amd import inputs, lbm
+
+    w = inputs.MEMBRANE_1024
+    t0 = time.perf_counter()
+    vox = np.ascontiguousarray(w.voxels()[:, :, 448:576])
+    log(f"shard 128x512x512 porosity {inputs.porosity(vox):.4f} ({time.perf_counter() - t0:.1f} s)")
+    storage = STORAGES[args.storage]
+    sim = lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                  c_inlet=w.c_inlet, c0=w.c_inlet, species_x=lbm.XBC_PERIODIC, storage=storage)
+    info = sim.info()
+    if not args.no_autotune:
+        sim.autotune(3)
+    sim.step(args.warmup)
+    sim.synchronize()
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sim.step(args.steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    kt = sim.kernel_times()
+    sweep_variant = sim.get_tunable(lbm.TUNE_SWEEP)
+    ytile = sim.get_tunable(lbm.TUNE_YTILE)
+    sim.close()
+    s_bytes = lbm.STORAGE_BYTES[storage]
+    ab = algorithmic_bytes(info, s_bytes)
+    t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
+    face_nodes = int((vox[:, :, 0] == 0).sum())
+    halo = 2 * 5 * s_bytes * face_nodes  # per face and direction: 5 populations of each lattice
+    line = {
+        "metric": "MLUPS (flow+species) and % of HBM roofline at stated error vs FP64 oracle",
+        "value": round(vox.size * args.steps / el / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f32", 1: "f16-storage/f32", 2: "bf16-storage/f32", 3: "f64"}[storage],
+        "data": "synthetic (seeded Gaussian-random-field porous layer)",
+        "config": {"workload": "membrane shard: x in [448, 576) of the 1024x512x512 membrane (one of 8 x-slabs), "
+                               "periodic x",
+                   "n_nodes": int(vox.size), "n_fluid": info["n_fluid"],
+                   "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks", "ytile": ytile,
+                   "sweep_us": round(t_sweep * 1e6, 1),
+                   "halo_bytes_per_face_per_direction": halo,
+                   "halo_us_at_153GBps": round(halo / 153e9 * 1e6, 1)},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_c" if sweep_variant == 1 else "k_sweep",
+                     "achieved": round(ab["sweep"] / t_sweep / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ab["sweep"] / t_sweep / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,9 +454,10 @@ def main():
     ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
     ap.add_argument("--sweep", type=int, default=None, choices=(0, 1),
                     help="sweep variant: 1 node-compact (library default), 0 one wave per 64-voxel chunk")
-    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision", "membrane"),
+    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision", "membrane", "shard"),
                     help="single: the 256^3 sample; batch: the 64-sample mixed batch; precision: 512^3 "
-                         "with FP32/FP16/BF16 storage against the FP64 build; membrane: 1024x512x512 layer")
+                         "with FP32/FP16/BF16 storage against the FP64 build; membrane: 1024x512x512 layer; "
+                         "shard: one 128x512x512 x-slab of the membrane")
     ap.add_argument("--no-graph", action="store_true", help="batch: launch directly instead of graph replays")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape instead of autotuning it before timing")
@@ -415,6 +483,9 @@ def main():
         return
     if args.workload == "membrane":
         run_membrane(args)
+        return
+    if args.workload == "shard":
+        run_shard(args)
         return
     w = inputs.SINGLE_256
     if args.da is not None:

@@ -210,6 +210,24 @@ def test_reactive_slab_closed_form_on_gpu(storage, sputter):
     assert err < (1e-10 if storage == F64 else 5e-5)
 
 
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_reaction_probability_only_scales_conversion(storage):
+    """Only (1 - p_S^R) multiplies the re-emitted reactant, so two runs that
+    differ only in Da (hence p) hold bit-identical fields, and their
+    conversion maps differ by the factor p."""
+    runs = [run_gpu(plain_case(steps=50, da=da, c0=0.4), storage) for da in (10.0, 0.1)]
+    (a, b) = runs
+    for k in ("rho", "u", "conc"):
+        assert np.array_equal(a[k], b[k]), k
+    pa, pb = a["info"]["p"], b["info"]["p"]
+    assert pa < 0.01 < 0.5 < pb
+    assert a["conv"].any()
+    assert np.allclose(a["conv"] / pa, b["conv"] / pb, rtol=1e-14, atol=0.0)
+    ta, tb = a["totals"], b["totals"]
+    assert ta["mass_species"] == tb["mass_species"]
+    assert ta["converted"] + ta["lost"] == pytest.approx(tb["converted"] + tb["lost"], rel=1e-13)
+
+
 def test_runs_are_bit_identical():
     c = plain_case(steps=50)
     a, b = run_gpu(c, F32), run_gpu(c, F32)

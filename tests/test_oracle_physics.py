@@ -196,6 +196,34 @@ def test_zero_reaction_probability_converts_nothing(orc, porous32):
     assert not o.conversion_map().any()
 
 
+@pytest.mark.parametrize("coupling", ["PASSIVE", "BARYCENTRIC"])
+def test_reactant_field_depends_on_sticking_not_reaction(orc, porous32, coupling):
+    """In the reactant sputtering equation only (1 - p_S^R) multiplies the
+    re-emitted reactant; p enters the product equation alone.  So runs that
+    differ only in p hold the same state bit for bit, and their conversion
+    maps differ by the factor p."""
+    kw = dict(tau=(0.8, 0.7), p_stick=0.95, c0=0.4, force=inputs.body_force(4.0, 0.8),
+              coupling=getattr(orc, coupling))
+    runs = []
+    for p in (0.05, 0.7):
+        o = orc.Oracle(porous32, p=p, **kw)
+        o.step(40)
+        runs.append((p, o.get_state(), o.conversion_map(), o.totals()))
+        o.close()
+    (pa, (ca, ra), ma, ta), (pb, (cb, rb), mb, tb) = runs
+    assert np.array_equal(ca, cb) and np.array_equal(ra, rb)
+    assert ta["mass_species"] == tb["mass_species"]
+    assert ma.any()
+    assert np.allclose(ma / pa, mb / pb, rtol=1e-14, atol=0.0)
+    absorbed_a = ta["converted"] + ta["lost"]
+    assert absorbed_a == pytest.approx(tb["converted"] + tb["lost"], rel=1e-14)
+    # a change of p_S^R does change the field
+    o = orc.Oracle(porous32, p=pa, **dict(kw, p_stick=0.5))
+    o.step(40)
+    assert not np.array_equal(o.get_state()[1], ra)
+    o.close()
+
+
 def test_full_sticking_and_reaction_absorbs_everything(orc):
     """p_S^R = p = 1: nothing is re-emitted, all arrivals are converted."""
     n = 9
