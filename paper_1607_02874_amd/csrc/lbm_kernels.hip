@@ -404,6 +404,13 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
 // catalytic masks; the chunk's edge bits and periodic neighbour ranks stand
 // in where x -+ 1 leaves the chunk.  Same sources, same arithmetic and same
 // decode as pull() above.
+//
+// Three phases keep a wave to two dependent memory round trips: all nine
+// records are requested first; the windows and ranks are then worked out
+// (interface indices go to kidx in LDS); then every population and emission
+// load is issued before any is waited on.  Vector loads retire in order, so a
+// record requested after population loads could not be waited on without
+// waiting for those too.
 template <int ST, int SP>
 __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
                                        const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
@@ -412,6 +419,9 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     constexpr uint32_t SB = sizeof(S);
+    // source row class (cy, cz) of each group of directions in ORDER
+    constexpr int CYS[9] = {0, 1, -1, 0, 0, 1, 1, -1, -1};
+    constexpr int CZS[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
     const int64_t nfp = g.nfp;
     const uint32_t nfp_b = uint32_t(nfp) * SB;
     const uint32_t slot_b = uint32_t(nfp - 1) * SB;
@@ -427,21 +437,32 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     const uint32_t shr = ledge ? 0u : xl - 1u;
     const uint64_t below = (uint64_t(1) << xl) - 1u;
 
-    S rc[19], rr[19], re[19];
-    uint32_t cat_bits = 0;
-    rc[0] = ld_at(base(dslot(0)), own_b);
-    rr[0] = ld_at(base(19 + dslot(0)), own_b);
+    // phase 1: the nine records
+    ChunkInfo rec[9];
 #pragma unroll
     for (int cls = 0; cls < 9; ++cls) {
-        // source row class (cy, cz) of directions ORDER[..] in this group
-        constexpr int CYS[9] = {0, 1, -1, 0, 0, 1, 1, -1, -1};
-        constexpr int CZS[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
-        const int cy = CYS[cls], cz = CZS[cls];
-        int ys = y - cy, zs = z - cz;
+        int ys = y - CYS[cls], zs = z - CZS[cls];
         ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
         zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
         const uint32_t rown = uint32_t(zs) * uint32_t(g.ny) + uint32_t(ys);
-        const LBM_GLOBAL ChunkInfo &R = glb(g.chunks)[rown * uint32_t(g.W) + chunk];
+        const LBM_GLOBAL ChunkInfo &src = glb(g.chunks)[rown * uint32_t(g.W) + chunk];
+        rec[cls].fluid = src.fluid;
+        rec[cls].cat = src.cat;
+        rec[cls].base = src.base;
+        rec[cls].ibase = src.ibase;
+        rec[cls].prev = src.prev;
+        rec[cls].next = src.next;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // phase 2: windows, ranks, catalytic links; interface indices to kidx
+    uint32_t wins = 0;  // three gas bits (x - 1, x, x + 1) per class
+    uint32_t rk[9][3];  // storage index of x - 1, x, x + 1 in each source row (where gas)
+    uint32_t cat_bits = 0;
+#pragma unroll
+    for (int cls = 0; cls < 9; ++cls) {
+        const int cy = CYS[cls], cz = CZS[cls];
+        const ChunkInfo &R = rec[cls];
         const uint64_t fm = R.fluid, cm = R.cat;
         const uint32_t pv = R.prev, nv = R.next;
         // bit 0: x - 1, bit 1: x, bit 2: x + 1
@@ -451,13 +472,14 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         wc |= ledge ? ((pv >> 30) & 1u) : 0u;
         wf = redge ? (wf & 3u) | ((nv >> 31) << 2) : wf;
         wc = redge ? (wc & 3u) | (((nv >> 30) & 1u) << 2) : wc;
-        // storage / interface indices of x, x - 1, x + 1 (used only where gas / interface)
         const uint32_t r0 = R.base + uint32_t(__popcll(fm & below));
-        const uint32_t rm = ledge ? (pv & NB_IDX) : r0 - 1u;
-        const uint32_t rp = redge ? (nv & NB_IDX) : r0 + ((wf >> 1) & 1u);
+        rk[cls][1] = r0;
+        rk[cls][0] = ledge ? (pv & NB_IDX) : r0 - 1u;
+        rk[cls][2] = redge ? (nv & NB_IDX) : r0 + ((wf >> 1) & 1u);
         const uint32_t i0 = R.ibase + uint32_t(__popcll(cm & below));
         const uint32_t im = ledge ? (pv & NB_IDX) : i0 - 1u;
         const uint32_t ip = redge ? (nv & NB_IDX) : i0 + ((wc >> 1) & 1u);
+        wins |= wf << (3 * cls);
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
             const int i = ORDER[k];
@@ -465,7 +487,32 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             const int cx = CX[i];
             const uint32_t bit = uint32_t(1 - cx);
             const bool F = (wf >> bit) & 1u, C = (wc >> bit) & 1u;
-            const uint32_t rank = cx == 0 ? r0 : (cx == 1 ? rm : rp);
+            const bool inlet = reservoir && cx == 1 && first_x;
+            const bool outlet = reservoir && cx == -1 && last_x;
+            const bool CAT = !F && C && !inlet && !outlet;
+            const uint32_t irank = cx == 0 ? i0 : (cx == 1 ? im : ip);
+            kidx[(i - 1) * 256 + threadIdx.x] = CAT ? irank : 0u;
+            cat_bits |= CAT ? (1u << i) : 0u;
+        }
+    }
+
+    // phase 3: every population and emission load
+    S rc[19], rr[19], re[19];
+    rc[0] = ld_at(base(dslot(0)), own_b);
+    rr[0] = ld_at(base(19 + dslot(0)), own_b);
+#pragma unroll
+    for (int cls = 0; cls < 9; ++cls) {
+        const int cy = CYS[cls], cz = CZS[cls];
+        const uint32_t wf = (wins >> (3 * cls)) & 7u;
+#pragma unroll
+        for (int k = 0; k < 18; ++k) {
+            const int i = ORDER[k];
+            if (CY[i] != cy || CZ[i] != cz) continue;
+            const int cx = CX[i];
+            const uint32_t bit = uint32_t(1 - cx);
+            const bool F = (wf >> bit) & 1u;
+            const bool CAT = (cat_bits >> i) & 1u;
+            const uint32_t rank = rk[cls][bit];
             const uint32_t half = dslot(i) < dslot(opp(i)) ? 0u : nfp_b;
             const uint32_t bb_b = own_b + (nfp_b - half);
             const uint32_t pull_b = rank * SB + half;
@@ -476,20 +523,16 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             const bool outlet = reservoir && cx == -1 && last_x;  // copies plane nx - 1
             const bool F0 = (wf >> 1) & 1u;
             const bool SF = outlet ? F0 : (F && !inlet);
-            const bool CAT = !F && C && !inlet && !outlet;
             const bool EMIT = !bounce && CAT;
-            const uint32_t s_b = outlet ? r0 * SB + half : pull_b;
+            const uint32_t s_b = outlet ? rk[cls][1] * SB + half : pull_b;
             uint32_t r_b = EMIT ? 0u : bb_b;
             r_b = inlet ? slot_b + half : r_b;
             r_b = SF ? s_b : r_b;
             opaque(r_b);
             rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
-            const uint32_t irank = cx == 0 ? i0 : (cx == 1 ? im : ip);
-            kidx[(i - 1) * 256 + threadIdx.x] = irank;
-            uint32_t v_b = EMIT ? irank * SB : 0u;
+            uint32_t v_b = bounce ? 0u : kidx[(i - 1) * 256 + threadIdx.x] * SB;
             opaque(v_b);
             re[i] = ld_at(emit, v_b);
-            cat_bits |= CAT ? (1u << i) : 0u;
         }
     }
     __builtin_amdgcn_sched_barrier(0);
