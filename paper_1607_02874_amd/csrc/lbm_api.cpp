@@ -25,7 +25,7 @@ thread_local std::string g_create_error;
 
 constexpr double CS = 0.57735026918962576451;  // lattice sound speed 1/sqrt(3)
 constexpr int TIMING_RING = 512;
-constexpr uint64_t CKPT_MAGIC = 0x3247504b434d424cull;  // "LBMCKPG2"
+constexpr uint64_t CKPT_MAGIC = 0x3347504b434d424cull;  // "LBMCKPG3"
 
 struct StepEvents {
     hipEvent_t ev[8];  // start/stop of interface, xflux, sweep, reduce
@@ -579,11 +579,12 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         }
 
         // The kernels address every buffer with 32-bit byte offsets from a
-        // scalar base: a population pair (2 nfp elements) and the emission
-        // array (one element per interface node) must each stay below 4 GiB.
+        // scalar base: two adjacent direction arrays (2 nfp elements of two
+        // populations each) and the emission array (one population per
+        // interface node) must each stay below 4 GiB.
         {
             const uint64_t sbytes = uint64_t(storage_bytes(c->ph.storage)), lim = uint64_t(1) << 32;
-            if (2 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(c->niface) * sbytes >= lim) {
+            if (4 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(c->niface) * sbytes >= lim) {
                 release(c);
                 delete c;
                 return fail(nullptr, LBM_EUNSUPPORTED,

@@ -46,6 +46,7 @@ struct Store;
 template <>
 struct Store<ST_F32> {
     using S = float;
+    using P = float __attribute__((ext_vector_type(2)));  // carrier and reactant of one direction
     using T = float;
     __device__ static T cv(S v) { return v; }
     __device__ static S enc(T v) { return v; }
@@ -55,6 +56,7 @@ struct Store<ST_F32> {
 template <>
 struct Store<ST_F16> {
     using S = _Float16;
+    using P = _Float16 __attribute__((ext_vector_type(2)));
     using T = float;
     __device__ static T cv(S v) { return static_cast<float>(v); }
     __device__ static T ld(const S *p) { return static_cast<float>(*p); }
@@ -64,6 +66,7 @@ struct Store<ST_F16> {
 template <>
 struct Store<ST_BF16> {
     using S = uint16_t;
+    using P = uint16_t __attribute__((ext_vector_type(2)));
     using T = float;
     __device__ static T cv(S v) { return __uint_as_float(uint32_t(v) << 16); }
     __device__ static T ld(const S *p) { return __uint_as_float(uint32_t(*p) << 16); }
@@ -77,6 +80,7 @@ struct Store<ST_BF16> {
 template <>
 struct Store<ST_F64> {
     using S = double;
+    using P = double __attribute__((ext_vector_type(2)));
     using T = double;
     __device__ static T cv(S v) { return v; }
     __device__ static S enc(T v) { return v; }
@@ -227,6 +231,26 @@ template <typename S>
 __device__ __forceinline__ S ld_at(const S *base, uint32_t byte_off) {
     return *(const LBM_GLOBAL S *)((const LBM_GLOBAL char *)(base) + byte_off);
 }
+// One element of a direction array (carrier and reactant population) in a
+// single load.  With 16-bit storage the loads bypass the cache allocation:
+// every element is read once per sweep.  (Measured: the streaming form slows
+// the FP32 sweep, whose row-edge lines are shared by two readers.)
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::P ld_pop(const void *base, uint32_t byte_off) {
+    using P = typename Store<ST>::P;
+    const LBM_GLOBAL P *a = (const LBM_GLOBAL P *)((const LBM_GLOBAL char *)(base) + byte_off);
+    if constexpr (sizeof(typename Store<ST>::S) == 2)
+        return __builtin_nontemporal_load(a);
+    else
+        return *a;
+}
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::P pop_pair(typename Store<ST>::T c, typename Store<ST>::T r) {
+    typename Store<ST>::P v;
+    v.x = Store<ST>::enc(c);
+    v.y = Store<ST>::enc(r);
+    return v;
+}
 template <typename S>
 __device__ __forceinline__ void st_at(S *base, uint32_t byte_off, S v) {
     *(LBM_GLOBAL S *)((LBM_GLOBAL char *)(base) + byte_off) = v;
@@ -240,12 +264,14 @@ __device__ __forceinline__ void st_stream(S *base, uint32_t byte_off, S v) {
     __builtin_nontemporal_store(v, (LBM_GLOBAL S *)((LBM_GLOBAL char *)(base) + byte_off));
 }
 
-// A population buffer: 38 direction arrays (carrier slots 0..18, reactant
-// 19..37) of `stride` bytes each from `base`.  A direction's base address is
-// formed in scalar registers where it is used (one 64-bit multiply-add), so
-// the kernels do not hold 76 pointers in scalar registers.
-// (The create path guarantees that two direction arrays span less than
-// 4 GiB, so the stride fits in 32 bits.)
+// A population buffer: 19 direction arrays (slots dslot(i)) of `stride`
+// bytes each from `base`.  Element n of a direction array is the pair
+// (carrier, reactant) of gas node n, so the common pull, where both lattices
+// take the same source, is one load and the store of a direction one store.
+// A direction's base address is formed in scalar registers where it is used
+// (one 64-bit multiply-add), so the kernels do not hold 38 pointers in scalar
+// registers.  (The create path guarantees that two direction arrays span
+// less than 4 GiB, so the stride fits in 32 bits.)
 struct Slots {
     const char *base;
     uint32_t stride, pad;
@@ -283,26 +309,26 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
                                      uint32_t &cat_out, uint32_t *kidx = nullptr) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
-    constexpr uint32_t SB = sizeof(S);
+    using P = typename Store<ST>::P;
+    constexpr uint32_t SB = sizeof(S), PB = 2 * SB;
     const int64_t nfp = g.nfp;
-    const uint32_t nfp_b = uint32_t(nfp) * SB;   // one direction array, in bytes
-    const uint32_t slot_b = uint32_t(nfp - 1) * SB;  // reserved last element of each array
+    const uint32_t nfp_b = uint32_t(nfp) * PB;   // one direction array, in bytes
     const bool reservoir = ph.species_x == XB_RESERVOIR;
     const int sputter = SP >= 0 ? SP : ph.sputter;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
-    auto base = [&](int slot) { return static_cast<const S *>(in.p(slot)); };
-    const uint32_t own_b = u.idx * SB;
+    auto base = [&](int slot) { return in.p(slot); };
+    const uint32_t own_b = u.idx * PB;
     // wave-uniform shape of the chunk
     const int nvalid = min(64, g.nx - 64 * u.chunk);
     const int last_lane = nvalid - 1;
     const bool first_chunk = u.chunk == 0, last_chunk = u.chunk == g.W - 1;
     const uint64_t lane0 = 1ull, lane_last = 1ull << last_lane;
 
-    // Phase 1: every address, then every load (56 loads in flight per lane).
-    S rc[19], rr[19], re[19];
+    // Phase 1: every address, then every load (up to 42 in flight per lane).
+    P pc[19];
+    S re[19], ro[19];
     uint32_t cat_bits = 0;
-    rc[0] = ld_at(base(dslot(0)), own_b);
-    rr[0] = ld_at(base(19 + dslot(0)), own_b);
+    pc[0] = ld_pop<ST>(base(dslot(0)), own_b);
     // the nine source rows (wave-uniform): chunk record and first voxel
     const LBM_GLOBAL ChunkInfo *recs[9];
 #pragma unroll
@@ -359,37 +385,37 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         // or the bounce-back is an offset of 0 or nfp elements plus a node.
         const uint32_t half = dslot(i) < dslot(opp(i)) ? 0u : nfp_b;  // i's array inside the pair
         const uint32_t bb_b = own_b + (nfp_b - half);                   // own opp(i) entry
-        const uint32_t pull_b = rank * SB + half;
-        rc[i] = ld_at(base(pair_slot(i)), lane_in(F) ? pull_b : bb_b);
-        // Reactant: reservoir ghosts at the x-ends, the reactive pull at
-        // catalytic sources.
+        const uint32_t pull_b = rank * PB + half;
+        // both lattices from the gas source, or both bounced back
+        pc[i] = ld_pop<ST>(base(pair_slot(i)), lane_in(F) ? pull_b : bb_b);
+        // Reactant exceptions: the reservoir planes and catalytic sources.
         const uint64_t inlet = (reservoir && cx == 1 && first_chunk) ? lane0 : 0ull;
-        const uint64_t outlet = (reservoir && cx == -1 && last_chunk) ? lane_last : 0ull;  // copies plane nx - 1
-        // inlet lanes take the reserved slot even though their periodic
-        // carrier source is gas; outlet lanes read the copy of plane nx - 1
-        const uint64_t SF = (F & ~outlet & ~inlet) | (I.fluid & outlet);
+        const uint64_t outlet = (reservoir && cx == -1 && last_chunk) ? lane_last : 0ull;
         const uint64_t CAT = ~F & C & ~inlet & ~outlet;
         const uint64_t EMIT = bounce ? 0ull : CAT;
-        uint32_t srank_b = pull_b;
-        if (outlet) srank_b = lane_in(outlet) ? rank_of_mask(I.fluid, I.base) * SB + half : srank_b;
-        // the inlet ghost value sits in the reserved last element of the array
-        uint32_t r_b = lane_in(EMIT) ? 0u : bb_b;
-        r_b = lane_in(inlet) ? slot_b + half : r_b;
-        r_b = lane_in(SF) ? srank_b : r_b;
-        rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
+        // the outlet lane copies plane nx - 1 of the source row (bounce-back
+        // where that voxel is solid)
+        ro[i] = S(0);
+        if (outlet)
+            ro[i] = ld_at(static_cast<const S *>(base(pair_slot(i))),
+                          (lane_in(outlet & I.fluid) ? rank_of_mask(I.fluid, I.base) * PB + half : bb_b) + SB);
         // emission of a catalytic source, by interface index (element 0 when not used)
         re[i] = ld_at(emit, lane_in(EMIT) ? irank * SB : 0u);
         if (kidx) kidx[(i - 1) * 256 + threadIdx.x] = irank;
         cat_bits |= lane_in(CAT) ? (1u << i) : 0u;
     }
     __builtin_amdgcn_sched_barrier(0);
-    // Phase 2: decode and apply the sputtering rule.
-    hC[0] = Store<ST>::cv(rc[0]);
-    hR[0] = Store<ST>::cv(rr[0]);
+    // Phase 2: decode and apply the reservoir and sputtering rules.  The inlet
+    // lane takes the reservoir population w_i c_in (as stored).
+    const T h_in = Store<ST>::cv(Store<ST>::enc(ph.h_inlet));
+    hC[0] = Store<ST>::cv(pc[0].x);
+    hR[0] = Store<ST>::cv(pc[0].y);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
-        hC[i] = Store<ST>::cv(rc[i]);
-        const T v = Store<ST>::cv(rr[i]);
+        hC[i] = Store<ST>::cv(pc[i].x);
+        T v = Store<ST>::cv(pc[i].y);
+        if (CX[i] == 1 && reservoir && first_chunk) v = lane_in(lane0) ? h_in : v;
+        if (CX[i] == -1 && reservoir && last_chunk) v = lane_in(lane_last) ? Store<ST>::cv(ro[i]) : v;
         const T e = Store<ST>::cv(re[i]);
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
@@ -418,18 +444,18 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
                                        uint32_t &cat_out, uint32_t *kidx) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
-    constexpr uint32_t SB = sizeof(S);
+    using P = typename Store<ST>::P;
+    constexpr uint32_t SB = sizeof(S), PB = 2 * SB;
     // source row class (cy, cz) of each group of directions in ORDER
     constexpr int CYS[9] = {0, 1, -1, 0, 0, 1, 1, -1, -1};
     constexpr int CZS[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
     const int64_t nfp = g.nfp;
-    const uint32_t nfp_b = uint32_t(nfp) * SB;
-    const uint32_t slot_b = uint32_t(nfp - 1) * SB;
+    const uint32_t nfp_b = uint32_t(nfp) * PB;
     const bool reservoir = ph.species_x == XB_RESERVOIR;
     const int sputter = SP >= 0 ? SP : ph.sputter;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
-    auto base = [&](int slot) { return static_cast<const S *>(in.p(slot)); };
-    const uint32_t own_b = idx * SB;
+    auto base = [&](int slot) { return in.p(slot); };
+    const uint32_t own_b = idx * PB;
     const uint32_t xl = uint32_t(x) & 63u, chunk = uint32_t(x) >> 6;
     const bool ledge = xl == 0u;                       // x - 1 lies in the previous chunk (or wraps)
     const bool redge = xl == 63u || x == g.nx - 1;     // x + 1 lies in the next chunk (or wraps)
@@ -496,10 +522,15 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         }
     }
 
-    // phase 3: every population and emission load
-    S rc[19], rr[19], re[19];
-    rc[0] = ld_at(base(dslot(0)), own_b);
-    rr[0] = ld_at(base(19 + dslot(0)), own_b);
+    // phase 3: every population and emission load.  One load per direction
+    // gives both lattices (same gas source, or both bounced back); the
+    // reactant differs only at catalytic sources (emission), at the inlet
+    // plane (the reservoir value) and at the outlet plane (a copy of plane
+    // nx - 1, loaded only by wavefronts that hold an outlet lane).
+    P pc[19];
+    S re[19], ro[19];
+    pc[0] = ld_pop<ST>(base(dslot(0)), own_b);
+    const bool any_outlet = reservoir && __builtin_amdgcn_ballot_w64(last_x) != 0u;
 #pragma unroll
     for (int cls = 0; cls < 9; ++cls) {
         const int cy = CYS[cls], cz = CZS[cls];
@@ -511,37 +542,35 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             const int cx = CX[i];
             const uint32_t bit = uint32_t(1 - cx);
             const bool F = (wf >> bit) & 1u;
-            const bool CAT = (cat_bits >> i) & 1u;
-            const uint32_t rank = rk[cls][bit];
             const uint32_t half = dslot(i) < dslot(opp(i)) ? 0u : nfp_b;
             const uint32_t bb_b = own_b + (nfp_b - half);
-            const uint32_t pull_b = rank * SB + half;
+            const uint32_t pull_b = rk[cls][bit] * PB + half;
             uint32_t c_b = F ? pull_b : bb_b;
             opaque(c_b);
-            rc[i] = ld_at(base(pair_slot(i)), c_b);
-            const bool inlet = reservoir && cx == 1 && first_x;
-            const bool outlet = reservoir && cx == -1 && last_x;  // copies plane nx - 1
-            const bool F0 = (wf >> 1) & 1u;
-            const bool SF = outlet ? F0 : (F && !inlet);
-            const bool EMIT = !bounce && CAT;
-            const uint32_t s_b = outlet ? rk[cls][1] * SB + half : pull_b;
-            uint32_t r_b = EMIT ? 0u : bb_b;
-            r_b = inlet ? slot_b + half : r_b;
-            r_b = SF ? s_b : r_b;
-            opaque(r_b);
-            rr[i] = ld_at(base(19 + pair_slot(i)), r_b);
+            pc[i] = ld_pop<ST>(base(pair_slot(i)), c_b);
             uint32_t v_b = bounce ? 0u : kidx[(i - 1) * 256 + threadIdx.x] * SB;
             opaque(v_b);
             re[i] = ld_at(emit, v_b);
+            ro[i] = S(0);
+            if (cx == -1 && any_outlet) {
+                const bool F0 = (wf >> 1) & 1u;
+                uint32_t o_b = (last_x && F0 ? rk[cls][1] * PB + half : bb_b) + SB;
+                opaque(o_b);
+                ro[i] = ld_at(static_cast<const S *>(base(pair_slot(i))), o_b);
+            }
         }
     }
     __builtin_amdgcn_sched_barrier(0);
-    hC[0] = Store<ST>::cv(rc[0]);
-    hR[0] = Store<ST>::cv(rr[0]);
+    const T h_in = Store<ST>::cv(Store<ST>::enc(ph.h_inlet));
+    const bool inlet = reservoir && first_x, outlet = reservoir && last_x;
+    hC[0] = Store<ST>::cv(pc[0].x);
+    hR[0] = Store<ST>::cv(pc[0].y);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
-        hC[i] = Store<ST>::cv(rc[i]);
-        const T v = Store<ST>::cv(rr[i]);
+        hC[i] = Store<ST>::cv(pc[i].x);
+        T v = Store<ST>::cv(pc[i].y);
+        if (CX[i] == 1) v = inlet ? h_in : v;
+        if (CX[i] == -1) v = outlet ? Store<ST>::cv(ro[i]) : v;
         const T ev = Store<ST>::cv(re[i]);
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? ev * inv_wgt<T>(i) : ev) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
@@ -674,18 +703,20 @@ __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const u
 }
 
 template <int ST>
-__device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double c_in,
-                                             const typename Store<ST>::S *own, int64_t nfp, bool first_x,
-                                             bool last_x) {
+__device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double c_in, const char *pop,
+                                             uint32_t stride, uint32_t idx, bool first_x, bool last_x) {
     using T = typename Store<ST>::T;
+    using S = typename Store<ST>::S;
+    // the node's own reactant population of direction i
+    auto own = [&](int i) { return Store<ST>::ld(reinterpret_cast<const S *>(pop + dslot(i) * stride) + 2 * idx + 1); };
     double fin = 0.0, fout = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         if (CX[i] == 1) {
             if (first_x) fin += double(wgt<T>(i)) * c_in;
-            if (last_x) fout += double(wgt<T>(i) * (Store<ST>::ld(own + dslot(i) * nfp) + c_ref));
+            if (last_x) fout += double(wgt<T>(i) * (own(i) + c_ref));
         }
-        if (CX[i] == -1 && first_x) fout += double(wgt<T>(i) * (Store<ST>::ld(own + dslot(i) * nfp) + c_ref));
+        if (CX[i] == -1 && first_x) fout += double(wgt<T>(i) * (own(i) + c_ref));
     }
     return InOut{fin, fout};
 }
@@ -697,7 +728,6 @@ template <int ST, int SP>
 __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
                                             const OutSlots &out, const typename Store<ST>::S *__restrict__ emit,
                                             double *__restrict__ part, uint32_t block) {
-    using S = typename Store<ST>::S;
     using T = typename Store<ST>::T;
     const WaveUnit u = locate(g, block);
     __shared__ uint32_t kidx[18 * 256];
@@ -721,22 +751,19 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
                 if (CX[i] == -1) acc[3] -= double(wgt<T>(i) * (hR[i] + ph.cref));
         }
         collide(ph, m, hC, hR);
-        const int64_t nfp = g.nfp;
-        uint32_t own_b = u.idx * uint32_t(sizeof(typename Store<ST>::S));
+        using P = typename Store<ST>::P;
+        uint32_t own_b = u.idx * uint32_t(sizeof(P));
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             // opaque per store: keeps each store in the scalar-base form instead
             // of a shared 64-bit vector address plus per-store 64-bit adds
             opaque(own_b);
-            st_at(static_cast<S *>(out.p(dslot(i))), own_b, Store<ST>::enc(hC[i]));
-            opaque(own_b);
-            st_at(static_cast<S *>(out.p(19 + dslot(i))), own_b, Store<ST>::enc(hR[i]));
+            st_at(static_cast<P *>(out.p(dslot(i))), own_b, pop_pair<ST>(hC[i], hR[i]));
         }
         // In(k) of the next step's interface: what leaves towards interface nodes
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR);
         if (reservoir && (first_x || last_x)) {
-            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p(19)) + u.idx, nfp, first_x,
-                                               last_x);
+            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, in.base, in.stride, u.idx, first_x, last_x);
             acc[2] += f.in;
             acc[3] += f.out;
         }
@@ -751,7 +778,6 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
                                               const Slots &in, const OutSlots &out,
                                               const typename Store<ST>::S *__restrict__ emit,
                                               double *__restrict__ part, uint32_t block) {
-    using S = typename Store<ST>::S;
     using T = typename Store<ST>::T;
     const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
     const uint32_t slot = block * 4u + wave;
@@ -778,18 +804,16 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
                 if (CX[i] == -1) acc[3] -= double(wgt<T>(i) * (hR[i] + ph.cref));
         }
         collide(ph, m, hC, hR);
-        uint32_t own_b = idx * uint32_t(sizeof(S));
+        using P = typename Store<ST>::P;
+        uint32_t own_b = idx * uint32_t(sizeof(P));
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             opaque(own_b);
-            st_stream(static_cast<S *>(out.p(dslot(i))), own_b, Store<ST>::enc(hC[i]));
-            opaque(own_b);
-            st_stream(static_cast<S *>(out.p(19 + dslot(i))), own_b, Store<ST>::enc(hR[i]));
+            st_stream(static_cast<P *>(out.p(dslot(i))), own_b, pop_pair<ST>(hC[i], hR[i]));
         }
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR);
         if (reservoir && (first_x || last_x)) {
-            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, static_cast<const S *>(in.p(19)) + idx, g.nfp,
-                                               first_x, last_x);
+            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, in.base, in.stride, idx, first_x, last_x);
             acc[2] += f.in;
             acc[3] += f.out;
         }
@@ -825,8 +849,9 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
         if (LOCAL) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                hC[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p(dslot(i))) + u.idx);
-                hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p(19 + dslot(i))) + u.idx);
+                const typename Store<ST>::P v = static_cast<const typename Store<ST>::P *>(in.p(dslot(i)))[u.idx];
+                hC[i] = Store<ST>::cv(v.x);
+                hR[i] = Store<ST>::cv(v.y);
             }
         } else {
             uint32_t cat_bits;
@@ -859,16 +884,16 @@ __global__ __launch_bounds__(256) void k_init(Geometry g, PhysK<typename Store<S
     using T = typename Store<ST>::T;
     const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (n >= g.nfp) return;
+    using P = typename Store<ST>::P;
+    P *pre2 = reinterpret_cast<P *>(pre), *post2 = reinterpret_cast<P *>(post);
     T hC[19], hR[19];
     if (n >= g.nfluid) {
-        // padding; the last element of each reactant array holds the inlet
-        // ghost population (normalised), which the sweep pulls at x = 0
+        // padding (the last element of every array holds the normalised
+        // reservoir population, which no kernel needs to read)
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            Store<ST>::st(pre + dslot(i) * g.nfp + n, T(0));
-            Store<ST>::st(post + dslot(i) * g.nfp + n, T(0));
-            Store<ST>::st(pre + (19 + dslot(i)) * g.nfp + n, ph.h_inlet);
-            Store<ST>::st(post + (19 + dslot(i)) * g.nfp + n, ph.h_inlet);
+            pre2[dslot(i) * g.nfp + n] = pop_pair<ST>(T(0), ph.h_inlet);
+            post2[dslot(i) * g.nfp + n] = pop_pair<ST>(T(0), ph.h_inlet);
         }
         return;
     }
@@ -876,16 +901,12 @@ __global__ __launch_bounds__(256) void k_init(Geometry g, PhysK<typename Store<S
     for (int i = 0; i < 19; ++i) {
         hC[i] = ph.h0c;
         hR[i] = ph.h0r;
-        Store<ST>::st(pre + dslot(i) * g.nfp + n, hC[i]);
-        Store<ST>::st(pre + (19 + dslot(i)) * g.nfp + n, hR[i]);
+        pre2[dslot(i) * g.nfp + n] = pop_pair<ST>(hC[i], hR[i]);
     }
     const Mom<T> m = moments(ph, hC, hR);
     collide(ph, m, hC, hR);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        Store<ST>::st(post + dslot(i) * g.nfp + n, hC[i]);
-        Store<ST>::st(post + (19 + dslot(i)) * g.nfp + n, hR[i]);
-    }
+    for (int i = 0; i < 19; ++i) post2[dslot(i) * g.nfp + n] = pop_pair<ST>(hC[i], hR[i]);
 }
 
 __device__ __forceinline__ uint32_t rank_of(const Geometry &g, int row, int x, bool *fluid) {
@@ -955,8 +976,9 @@ __global__ __launch_bounds__(256) void k_populations(Geometry g, PhysK<typename 
         if (LOCAL) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                hC[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p(dslot(i))) + u.idx);
-                hR[i] = Store<ST>::ld(static_cast<const typename Store<ST>::S *>(in.p(19 + dslot(i))) + u.idx);
+                const typename Store<ST>::P v = static_cast<const typename Store<ST>::P *>(in.p(dslot(i)))[u.idx];
+                hC[i] = Store<ST>::cv(v.x);
+                hR[i] = Store<ST>::cv(v.y);
             }
         } else {
             uint32_t cat_bits;
@@ -997,7 +1019,7 @@ __global__ __launch_bounds__(256) void k_in_init(Geometry g, PhysK<typename Stor
             zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
             bool fl;
             const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
-            sum += in_term<T>(wgt<T>(j), Store<ST>::ld(fin + (19 + dslot(j)) * g.nfp + r), ph.cref, ph.in_scale);
+            sum += in_term<T>(wgt<T>(j), Store<ST>::ld(fin + 2 * (dslot(j) * g.nfp + r) + 1), ph.cref, ph.in_scale);
         }
     }
     it.inacc[k] = sum;
@@ -1207,7 +1229,7 @@ Slots slots_of(const Geometry &g, const void *buf) {
     Slots sl;
     using S = typename Store<ST>::S;
     sl.base = static_cast<const char *>(buf);
-    sl.stride = uint32_t(uint64_t(g.nfp) * sizeof(S));
+    sl.stride = uint32_t(uint64_t(g.nfp) * 2 * sizeof(S));
     sl.pad = 0;
     return sl;
 }
@@ -1221,7 +1243,7 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
         const Slots in = slots_of<ST>(g, fin);
         OutSlots out;
         out.base = static_cast<char *>(fout);
-        out.stride = uint32_t(uint64_t(g.nfp) * sizeof(SS));
+        out.stride = uint32_t(uint64_t(g.nfp) * 2 * sizeof(SS));
         out.pad = 0;
         const dim3 grid(unsigned(sweep_blocks(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
@@ -1247,7 +1269,7 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
         const Slots in = slots_of<ST>(g, fin);
         OutSlots out;
         out.base = static_cast<char *>(fout);
-        out.stride = uint32_t(uint64_t(g.nfp) * sizeof(SS));
+        out.stride = uint32_t(uint64_t(g.nfp) * 2 * sizeof(SS));
         out.pad = 0;
         const dim3 grid(static_cast<unsigned>(sweep_blocks_c(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
