@@ -829,7 +829,7 @@ __global__ __launch_bounds__(256, ST == ST_F64 ? 1 : 5) void k_sweep_c(Geometry 
 }
 
 template <int ST, int SP>
-__global__ __launch_bounds__(256, ST == ST_F64 ? 1 : 6) void k_sweep(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
+__global__ __launch_bounds__(256, ST == ST_F64 ? 1 : (sizeof(typename Store<ST>::S) == 2 ? 5 : 6)) void k_sweep(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
                                                 const typename Store<ST>::S *__restrict__ emit,
                                                 double *__restrict__ part) {
     sweep_block<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
