@@ -173,8 +173,12 @@ typedef struct {
  * Errors: LBM_EINVAL for NULL pointers, sizes < 1, nx > 4096, a voxel > 2,
  * tau <= 1/2, kn < 0, da <= 0 or NaN, inconsistent kn/tau, p_stick outside
  * [0, 1], c_inlet/c0 < 0, rho0 <= 0, nonzero reserved fields;
- * LBM_EUNSUPPORTED for an unknown enum value; LBM_EDEVICE without a usable
- * gfx950 device; LBM_ENOMEM when a buffer cannot be allocated.
+ * LBM_EUNSUPPORTED for an unknown enum value, or for a lattice whose
+ * buffers exceed the kernels' 32-bit offsets (4 * nfp * s >= 2^32 bytes with
+ * nfp = gas nodes + 1 rounded up to 128 and s the bytes per stored
+ * population, an emission array of 2^32 bytes or more, or 2^30 gas or
+ * interface nodes); LBM_EDEVICE without a usable gfx950 device; LBM_ENOMEM
+ * when a buffer cannot be allocated.
  */
 lbm_status lbm_create(const lbm_geometry *g, double kn, double da, const double tau[2],
                       const lbm_bc *bc, lbm_ctx **out);
