@@ -144,7 +144,15 @@ typedef struct {
     int64_t device_bytes;          /* device memory held by the context */
 } lbm_info;
 
-/* Per-kernel device time accumulated while timing is enabled. */
+/* Per-kernel device time accumulated while timing is enabled.
+ * sweep: the fused stream-collide sweep, once per step.
+ * interface: the launch before each sweep, which runs the interface kernel of
+ *   the step together with the first reduction stage of the previous step and
+ *   the final stage of the one before (when those belong to the same
+ *   lbm_step call).
+ * reduce: the reductions that close an lbm_step call (after its last sweep);
+ *   n_reduce counts calls.
+ * xflux: unused (the sweep tallies the reservoir planes), always 0. */
 typedef struct {
     double ms_sweep, ms_interface, ms_xflux, ms_reduce;
     int64_t n_sweep, n_interface, n_xflux, n_reduce;
@@ -271,7 +279,7 @@ lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value);
  * candidate (sweep variant x y-tile in {4, 8, 16, 32, 64, 128}, clamped to
  * ny) in two interleaved rounds and keep the candidate with the fastest
  * round.  The trial sweeps run in place; the population
- * buffer and link buffer they overwrite are saved to temporary device memory
+ * buffer and In(k) accumulators they overwrite are saved to temporary device memory
  * first and restored afterwards, so the state (and every later result) is
  * exactly as before the call.  best_ms (may be NULL) receives the mean sweep
  * time of the winner.  Synchronises the stream.

@@ -28,8 +28,9 @@ constexpr int TIMING_RING = 512;
 constexpr uint64_t CKPT_MAGIC = 0x3347504b434d424cull;  // "LBMCKPG3"
 
 struct StepEvents {
-    hipEvent_t ev[8];  // start/stop of interface, xflux, sweep, reduce
+    hipEvent_t ev[8];  // start/stop of the front launch, xflux, sweep, closing reduction
     bool pending;
+    bool flushed;      // the slot's step closed an lbm_step call (ev[6..7] time that reduction)
 };
 
 uint64_t fnv1a(const uint8_t *p, size_t n) {
@@ -301,18 +302,32 @@ void drain_slot(lbm_ctx *c, StepEvents &r) {
     }
     c->times.ms_sweep += ms[2];
     c->times.n_sweep += 1;
-    c->times.ms_reduce += ms[3];
-    c->times.n_reduce += 1;
+    if (r.flushed) {
+        c->times.ms_reduce += ms[3];
+        c->times.n_reduce += 1;
+    }
     r.pending = false;
 }
 
-lbm_status one_step(lbm_ctx *c) {
+// Partial-sum layout in d_part: sweep partials (4 per sweep block), then the
+// interface partials and the fold outputs, two of each alternating with the
+// step's parity (a front launch writes step t's while it reads step t - 1's).
+double *part_iface(const lbm_ctx *c, int64_t t) { return c->d_part + 4 * c->blocks_sweep + (t & 1) * c->blocks_iface; }
+double *part_fold(const lbm_ctx *c, int64_t t) {
+    return c->d_part + 4 * c->blocks_sweep + 2 * c->blocks_iface + (t & 1) * int64_t(FOLD_BLOCKS) * NPART;
+}
+
+// One step t = c->step: the front launch (interface of t, and the reduction
+// stages of t - 1 and t - 2 when those steps belong to the same lbm_step
+// call: `fold`, `reduce`), then the sweep.  `last` closes the call: the
+// remaining reduction stages of t - 1 and t follow the sweep.
+lbm_status one_step(lbm_ctx *c, bool fold, bool reduce, bool last) {
     const Geometry g = geometry(c);
     const void *fin = c->d_pop[c->cur];
     void *fout = c->d_pop[1 - c->cur];
+    const int64_t t = c->step;
     double *ps = c->d_part;
-    double *pi = ps + 4 * c->blocks_sweep;
-    double *fold = pi + c->blocks_iface;
+    const int64_t ns = active_sweep_blocks(c), ni = c->blocks_iface;
     StepEvents *r = nullptr;
     if (c->timing) {
         r = &c->ring[size_t(c->ring_next)];
@@ -321,7 +336,9 @@ lbm_status one_step(lbm_ctx *c) {
     }
     hipError_t e;
     if (r) (void)hipEventRecord(r->ev[0], c->stream);
-    e = launch_interface(g, c->ph, interface_list(c), c->d_emit, pi, c->blocks_iface, c->stream);
+    e = launch_front(c->ph, interface_list(c), c->d_emit, c->blocks_iface, part_iface(c, t), ps, ns,
+                     part_iface(c, t - 1), ni, part_fold(c, t - 1), fold, part_fold(c, t - 2), reduce, c->d_tot,
+                     c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "interface kernel launch");
     if (r) (void)hipEventRecord(r->ev[1], c->stream);
     if (r) (void)hipEventRecord(r->ev[2], c->stream);  // no separate boundary-flux kernel:
@@ -332,12 +349,19 @@ lbm_status one_step(lbm_ctx *c) {
     if (e != hipSuccess) return hip_fail(c, e, "sweep kernel launch");
     if (r) (void)hipEventRecord(r->ev[5], c->stream);
     if (r) (void)hipEventRecord(r->ev[6], c->stream);
-    e = launch_reduce(ps, active_sweep_blocks(c), pi, c->blocks_iface, fold, c->ph.p, c->ph.p_stick, c->d_tot,
-                      c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+    if (last) {
+        // fold of t (with the final stage of t - 1 when pending), then the final stage of t
+        e = launch_front(c->ph, interface_list(c), c->d_emit, 0, nullptr, ps, ns, part_iface(c, t), ni,
+                         part_fold(c, t), true, part_fold(c, t - 1), fold, c->d_tot, c->stream);
+        if (e == hipSuccess)
+            e = launch_front(c->ph, interface_list(c), c->d_emit, 0, nullptr, ps, ns, nullptr, ni, nullptr, false,
+                             part_fold(c, t), true, c->d_tot, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+    }
     if (r) {
         (void)hipEventRecord(r->ev[7], c->stream);
         r->pending = true;
+        r->flushed = last;
     }
     c->cur = 1 - c->cur;
     c->step += 1;
@@ -470,7 +494,7 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
         const bool compact = g->ny <= 1024 && g->nz <= 1024 && c.nfluid > 0;
         int64_t bytes = r256((76 * nfp + niface) * sb) + r256(chunks * int64_t(sizeof(ChunkInfo))) +
                         r256(chunks * 4) + 2 * r256(niface * 4) + 3 * r256(niface * 8) +
-                        r256((4 * blocks + (niface + 255) / 256 + FOLD_BLOCKS * NPART) * 8) +
+                        r256((4 * blocks + 2 * ((niface + 255) / 256) + 2 * FOLD_BLOCKS * NPART) * 8) +
                         r256(int64_t(sizeof(DevTotals)));
         if (compact) bytes += r256(nfp * 4) + r256((c.nfluid + 63) / 64 * 4);
         info->device_bytes = bytes;
@@ -618,7 +642,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
             c->d_pop[1] = pool + size_t(38) * c->nfp * sb;
             c->d_emit = pool + size_t(76) * c->nfp * sb;
         }
-        const int64_t nparts = 4 * c->blocks_sweep + c->blocks_iface + FOLD_BLOCKS * NPART;
+        const int64_t nparts = 4 * c->blocks_sweep + 2 * c->blocks_iface + 2 * FOLD_BLOCKS * NPART;
         c->d_part = static_cast<double *>(dev_alloc(c, size_t(nparts) * 8));
         c->d_tot = static_cast<DevTotals *>(dev_alloc(c, sizeof(DevTotals)));
         if (!c->d_chunks || !c->d_order || !c->d_inacc || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
@@ -675,8 +699,10 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n) {
     if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
     lbm_status st = check_pending_flag(c);
     if (st != LBM_OK) return st;
+    // the reductions of step s run in the front launches of steps s + 1 and
+    // s + 2 of this call; the last step closes the call's own
     for (int64_t s = 0; s < n; ++s) {
-        st = one_step(c);
+        st = one_step(c, s >= 1, s >= 2, s == n - 1);
         if (st != LBM_OK) return st;
     }
     if (n > 0) {
@@ -904,6 +930,7 @@ lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable) {
         c->ring.resize(TIMING_RING);
         for (auto &r : c->ring) {
             r.pending = false;
+            r.flushed = false;
             for (auto &ev : r.ev) {
                 hipError_t e = hipEventCreate(&ev);
                 if (e != hipSuccess) return hip_fail(c, e, "event create");
@@ -1330,7 +1357,7 @@ lbm_status batch_tables(lbm_batch *b) {
         s.pop[1] = c->d_pop[1];
         s.emit = c->d_emit;
         s.part_sweep = c->d_part;
-        s.part_iface = c->d_part + 4 * c->blocks_sweep;
+        s.part_iface = part_iface(c, 0);
         s.block0 = uint32_t(nb);
         s.iblock0 = uint32_t(ni);
         nb += active_sweep_blocks(c);
@@ -1340,7 +1367,7 @@ lbm_status batch_tables(lbm_batch *b) {
         r.ns = active_sweep_blocks(c);
         r.pi = s.part_iface;
         r.ni = c->blocks_iface;
-        r.fold = s.part_iface + c->blocks_iface;
+        r.fold = part_fold(c, 0);
         r.p = c->ph.p;
         r.p_stick = c->ph.p_stick;
         r.tot = c->d_tot;

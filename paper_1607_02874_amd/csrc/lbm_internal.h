@@ -142,6 +142,14 @@ hipError_t launch_populations(const Geometry &g, const Physics &ph, const void *
 constexpr int FOLD_BLOCKS = 256;
 hipError_t launch_reduce(const double *part_sweep, int64_t n_sweep, const double *part_iface, int64_t n_iface,
                          double *fold, double p, double p_stick, DevTotals *tot, hipStream_t s);
+// One launch for everything of a step but the sweep: the interface kernel of
+// step t (iface_blocks blocks, partials to pi_now), when `fold` the first
+// reduction stage of step t - 1 (sweep partials ps, interface partials
+// pi_prev, into fold_prev), and when `reduce` the final stage of step t - 2
+// (from fold_prev2 into tot).  Zero blocks: nothing is launched.
+hipError_t launch_front(const Physics &ph, const Interface &it, void *emit, int64_t iface_blocks, double *pi_now,
+                        const double *ps, int64_t ns, const double *pi_prev, int64_t ni, double *fold_prev,
+                        bool fold, const double *fold_prev2, bool reduce, DevTotals *tot, hipStream_t s);
 
 int64_t sweep_blocks(const Geometry &g);
 int64_t interface_blocks(int64_t n);

@@ -1091,6 +1091,28 @@ __global__ __launch_bounds__(256) void k_reduce(const double *folded, int64_t nb
     reduce_block(folded, nb, p, p_stick, tot);
 }
 
+// Everything of a step but the sweep, in one launch: the interface of step t
+// (the first `iface_blocks` blocks), the first reduction stage of step t - 1
+// (the next `fold_blocks`, 0 or FOLD_BLOCKS) and the final stage of step
+// t - 2 (one last block, when `reduce`).  The parts touch disjoint buffers
+// (interface partials and fold outputs alternate with the step's parity), and
+// each runs exactly the code of its own kernel, so the totals are the same.
+template <int ST>
+__global__ __launch_bounds__(256) void k_front(PhysK<typename Store<ST>::T> ph, Interface it,
+                                                typename Store<ST>::S *__restrict__ emit, double *pi_now,
+                                                const double *ps, int64_t ns, const double *pi_prev, int64_t ni,
+                                                double *fold_prev, const double *fold_prev2, double p, double p_stick,
+                                                DevTotals *tot, int32_t iface_blocks, int32_t fold_blocks) {
+    const int32_t b = int32_t(blockIdx.x);
+    if (b < iface_blocks) {
+        interface_block<ST>(ph, it, emit, pi_now, uint32_t(b));
+    } else if (b - iface_blocks < fold_blocks) {
+        fold_block(ps, ns, pi_prev, ni, fold_prev, b - iface_blocks, FOLD_BLOCKS);
+    } else {
+        reduce_block(fold_prev2, FOLD_BLOCKS, p, p_stick, tot);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched kernels: one launch covers every sample of a batch.  Each sample
 // owns a contiguous range of logical blocks (first block in its record); a
@@ -1325,6 +1347,22 @@ hipError_t launch_populations(const Geometry &g, const Physics &ph, const void *
             hipLaunchKernelGGL((k_populations<ST, true>), grid, block, 0, s, g, k, f, e, win, fC, fR);
         else
             hipLaunchKernelGGL((k_populations<ST, false>), grid, block, 0, s, g, k, f, e, win, fC, fR);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_front(const Physics &ph, const Interface &it, void *emit, int64_t iface_blocks, double *pi_now,
+                        const double *ps, int64_t ns, const double *pi_prev, int64_t ni, double *fold_prev,
+                        bool fold, const double *fold_prev2, bool reduce, DevTotals *tot, hipStream_t s) {
+    const int64_t blocks = iface_blocks + (fold ? FOLD_BLOCKS : 0) + (reduce ? 1 : 0);
+    if (blocks == 0) return hipSuccess;
+    return dispatch(ph.storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        using SS = typename Store<ST>::S;
+        using T = typename Store<ST>::T;
+        hipLaunchKernelGGL(k_front<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, to_kernel<T>(ph), it,
+                           static_cast<SS *>(emit), pi_now, ps, ns, pi_prev, ni, fold_prev, fold_prev2, ph.p,
+                           ph.p_stick, tot, int32_t(iface_blocks), int32_t(fold ? FOLD_BLOCKS : 0));
         return hipGetLastError();
     });
 }
