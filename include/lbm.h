@@ -286,7 +286,11 @@ lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value);
  */
 lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms);
 
-/* Per-kernel HIP-event timing: enable (1) / disable (0) and read; reading
+/* Per-kernel HIP-event timing on the context's stream: 1 times every launch
+ * (eight events per step), 2 the sweep only (two events per step; the other
+ * fields stay 0), 0 disables; other values are LBM_EINVAL.  Events between
+ * launches cost step time (about 30 us per step with 1 at 256^3 on MI355X),
+ * so 2 is the level to use around a throughput measurement.  Reading
  * synchronises the stream.  Reset on enable. */
 lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable);
 lbm_status lbm_kernel_times(lbm_ctx *c, lbm_kernel_times_t *t);

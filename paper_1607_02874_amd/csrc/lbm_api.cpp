@@ -31,6 +31,7 @@ struct StepEvents {
     hipEvent_t ev[8];  // start/stop of the front launch, xflux, sweep, closing reduction
     bool pending;
     bool flushed;      // the slot's step closed an lbm_step call (ev[6..7] time that reduction)
+    bool sweep_only;   // only ev[4..5] were recorded
 };
 
 uint64_t fnv1a(const uint8_t *p, size_t n) {
@@ -87,7 +88,7 @@ struct lbm_ctx {
     bool flag_pending = false;
 
     // timing
-    bool timing = false;
+    int timing = 0;  // 0 off, 1 every launch, 2 the sweep only
     std::vector<StepEvents> ring;
     int ring_next = 0;
     lbm_kernel_times_t times{};
@@ -290,19 +291,20 @@ lbm_status check_pending_flag(lbm_ctx *c) {
 
 void drain_slot(lbm_ctx *c, StepEvents &r) {
     if (!r.pending) return;
-    (void)hipEventSynchronize(r.ev[7]);
+    (void)hipEventSynchronize(r.ev[r.sweep_only ? 5 : 7]);
     float ms[4];
     for (int k = 0; k < 4; ++k) {
         ms[k] = 0.0f;
-        if (hipEventElapsedTime(&ms[k], r.ev[2 * k], r.ev[2 * k + 1]) != hipSuccess) ms[k] = 0.0f;
+        if ((!r.sweep_only || k == 2) && hipEventElapsedTime(&ms[k], r.ev[2 * k], r.ev[2 * k + 1]) != hipSuccess)
+            ms[k] = 0.0f;
     }
-    if (c->blocks_iface > 0) {
+    if (c->blocks_iface > 0 && !r.sweep_only) {
         c->times.ms_interface += ms[0];
         c->times.n_interface += 1;
     }
     c->times.ms_sweep += ms[2];
     c->times.n_sweep += 1;
-    if (r.flushed) {
+    if (r.flushed && !r.sweep_only) {
         c->times.ms_reduce += ms[3];
         c->times.n_reduce += 1;
     }
@@ -328,27 +330,28 @@ lbm_status one_step(lbm_ctx *c, bool fold, bool reduce, bool last) {
     const int64_t t = c->step;
     double *ps = c->d_part;
     const int64_t ns = active_sweep_blocks(c), ni = c->blocks_iface;
-    StepEvents *r = nullptr;
+    StepEvents *r = nullptr, *all = nullptr;  // all: every launch is timed
     if (c->timing) {
         r = &c->ring[size_t(c->ring_next)];
         c->ring_next = (c->ring_next + 1) % TIMING_RING;
         drain_slot(c, *r);
+        if (c->timing == 1) all = r;
     }
     hipError_t e;
-    if (r) (void)hipEventRecord(r->ev[0], c->stream);
+    if (all) (void)hipEventRecord(r->ev[0], c->stream);
     e = launch_front(c->ph, interface_list(c), c->d_emit, c->blocks_iface, part_iface(c, t), ps, ns,
                      part_iface(c, t - 1), ni, part_fold(c, t - 1), fold, part_fold(c, t - 2), reduce, c->d_tot,
                      c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "interface kernel launch");
-    if (r) (void)hipEventRecord(r->ev[1], c->stream);
-    if (r) (void)hipEventRecord(r->ev[2], c->stream);  // no separate boundary-flux kernel:
-    if (r) (void)hipEventRecord(r->ev[3], c->stream);  // the sweep tallies the x-planes
+    if (all) (void)hipEventRecord(r->ev[1], c->stream);
+    if (all) (void)hipEventRecord(r->ev[2], c->stream);  // no separate boundary-flux kernel:
+    if (all) (void)hipEventRecord(r->ev[3], c->stream);  // the sweep tallies the x-planes
     if (r) (void)hipEventRecord(r->ev[4], c->stream);
     e = c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, ps, c->stream)
                    : launch_sweep(g, c->ph, fin, fout, c->d_emit, ps, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "sweep kernel launch");
     if (r) (void)hipEventRecord(r->ev[5], c->stream);
-    if (r) (void)hipEventRecord(r->ev[6], c->stream);
+    if (all) (void)hipEventRecord(r->ev[6], c->stream);
     if (last) {
         // fold of t (with the final stage of t - 1 when pending), then the final stage of t
         e = launch_front(c->ph, interface_list(c), c->d_emit, 0, nullptr, ps, ns, part_iface(c, t), ni,
@@ -359,9 +362,10 @@ lbm_status one_step(lbm_ctx *c, bool fold, bool reduce, bool last) {
         if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
     }
     if (r) {
-        (void)hipEventRecord(r->ev[7], c->stream);
+        if (all) (void)hipEventRecord(r->ev[7], c->stream);
         r->pending = true;
         r->flushed = last;
+        r->sweep_only = !all;
     }
     c->cur = 1 - c->cur;
     c->step += 1;
@@ -926,6 +930,7 @@ lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value) {
 
 lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable) {
     if (!c) return LBM_EINVAL;
+    if (enable < 0 || enable > 2) return fail(c, LBM_EINVAL, "timing must be 0, 1 or 2");
     if (enable && c->ring.empty()) {
         c->ring.resize(TIMING_RING);
         for (auto &r : c->ring) {
@@ -941,7 +946,7 @@ lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable) {
         for (auto &r : c->ring) r.pending = false;
         c->times = lbm_kernel_times_t{};
     }
-    c->timing = enable != 0;
+    c->timing = enable;
     return LBM_OK;
 }
 

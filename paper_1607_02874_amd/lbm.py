@@ -342,7 +342,9 @@ class Sim:
         return v.value
 
     def set_timing(self, on=True):
-        _check(_LIB.lbm_set_timing(self._h, 1 if on else 0), self._h)
+        """True or 1: time every launch; 2: the sweep only; False or 0: off."""
+        level = 1 if on is True else (0 if on is False else int(on))
+        _check(_LIB.lbm_set_timing(self._h, level), self._h)
 
     def autotune(self, reps=5):
         """Time the sweep for every launch-shape candidate and keep the

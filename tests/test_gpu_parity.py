@@ -228,6 +228,41 @@ def test_reaction_probability_only_scales_conversion(storage):
     assert ta["converted"] + ta["lost"] == pytest.approx(tb["converted"] + tb["lost"], rel=1e-13)
 
 
+def test_totals_do_not_depend_on_how_steps_are_split():
+    """The reductions of a step run in the launches of the next two steps of
+    the same lbm_step call, and a call closes its own: the totals after 7
+    steps are the same in one call or in three."""
+    c = plain_case(steps=7)
+    a, b = make_sim(c, F32), make_sim(c, F32)
+    a.step(7)
+    for n in (3, 1, 3):
+        b.step(n)
+    assert a.totals() == b.totals()
+    assert all(np.array_equal(x, y) for x, y in zip(a.fields(), b.fields()))
+    a.close()
+    b.close()
+
+
+def test_timing_levels():
+    from paper_1607_02874_amd import lbm
+
+    s = make_sim(plain_case(steps=5), F32)
+    s.set_timing(2)  # the sweep only
+    s.step(5)
+    kt = s.kernel_times()
+    assert kt["n_sweep"] == 5 and kt["ms_sweep"] > 0
+    assert kt["n_interface"] == kt["n_reduce"] == 0 and kt["ms_interface"] == kt["ms_reduce"] == 0.0
+    s.set_timing(1)  # every launch; the closing reductions once per call
+    s.step(3)
+    s.step(2)
+    kt = s.kernel_times()
+    assert kt["n_sweep"] == kt["n_interface"] == 5 and kt["n_reduce"] == 2
+    with pytest.raises(lbm.LbmError) as e:
+        s.set_timing(3)
+    assert e.value.status == lbm.LBM_EINVAL
+    s.close()
+
+
 def test_runs_are_bit_identical():
     c = plain_case(steps=50)
     a, b = run_gpu(c, F32), run_gpu(c, F32)
