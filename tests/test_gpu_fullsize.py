@@ -152,12 +152,54 @@ def test_256_bookkeeping_and_carrier_mass_every_step(vox256):
         assert t["step"] == 30 and t["nonfinite"] == 0
 
 
-def test_membrane_1024x512x512_sampled_boxes_one_step():
+@pytest.fixture(scope="module")
+def vox_membrane():
+    print("membrane: geometry", flush=True)
+    return inputs.MEMBRANE_1024.voxels()
+
+
+# FP16 storage: density and conversion meet 1e-3; velocity and concentration
+# do not.  In the free-gas reservoirs no wall drag damps momentum, so the
+# rounding of the stored populations accumulates (measured at 300 steps:
+# u 1.3e-2, c 5.5e-3, the same before and after every layout change); the
+# bounds below guard that level.
+COLUMN_TOL = {F32: dict(rho=1e-5, u=1e-5, conc=1e-5, conv=1e-5),
+              F16: dict(rho=1e-3, u=2e-2, conc=1e-2, conv=1e-3)}
+
+
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_membrane_column_crop_matches_oracle(vox_membrane, storage):
+    """A full-length column of the membrane geometry (1024 x 16 x 16: both
+    reservoirs and the porous layer, y and z periodic) run 300 steps by the
+    oracle and by the GPU, reactant at c_in everywhere from the start."""
+    from parity import errors
+
+    w = inputs.MEMBRANE_1024
+    vox = np.ascontiguousarray(vox_membrane[:16, :16, :])
+    steps = 300
+    p, _ = oracle.p_from_da(w.da, w.pore_size)
+    print(f"membrane column 1024x16x16, storage {storage}: oracle {steps} steps", flush=True)
+    o = oracle.Oracle(vox, tau=w.tau, p=p, p_stick=w.p_stick, c_inlet=w.c_inlet, c0=w.c_inlet, force=w.force())
+    o.step(steps)
+    rho, u, conc = o.fields()
+    ref = dict(rho=rho, u=u, conc=conc, conv=o.conversion_map())
+    o.close()
+    with workload_sim(w, vox, storage, c0=w.c_inlet) as s:
+        s.step(steps)
+        rho, u, conc = s.fields()
+        gpu = dict(rho=rho, u=u, conc=conc, conv=s.conversion_map())
+    e = errors(gpu, ref, vox)
+    print("membrane column", storage, {k: f"{v:.2e}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+    assert ref["conv"].sum() > 0
+    for k, tol in COLUMN_TOL[storage].items():
+        assert e[k] < tol, (k, e[k])
+
+
+def test_membrane_1024x512x512_sampled_boxes_one_step(vox_membrane):
     """The largest single-GPU case (268 M nodes, FP32): boxes across the
     porous layer x in [384, 640)."""
     w = inputs.MEMBRANE_1024
-    print("membrane: geometry", flush=True)
-    vox = w.voxels()
+    vox = vox_membrane
     print("membrane: create and 20 steps", flush=True)
     with workload_sim(w, vox, F32, c0=0.5) as s:
         s.step(20)
