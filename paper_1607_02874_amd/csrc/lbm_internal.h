@@ -112,8 +112,6 @@ void build_order(int nx, int ny, int nz, int ytile, uint32_t *order);
 
 // All launchers queue on `stream` and return the launch status.
 hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *post, hipStream_t s);
-hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, void *emit, double *part,
-                            int64_t blocks, hipStream_t s);
 // In(k) of every interface node from a post-collision population buffer (after
 // create and after a checkpoint load; during stepping the sweep accumulates it).
 hipError_t launch_in_init(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s);
@@ -140,8 +138,6 @@ hipError_t launch_populations(const Geometry &g, const Physics &ph, const void *
 // blocks fold contiguous slices into `fold` (FOLD_BLOCKS * NPART doubles),
 // then one block sums those and updates the totals.
 constexpr int FOLD_BLOCKS = 256;
-hipError_t launch_reduce(const double *part_sweep, int64_t n_sweep, const double *part_iface, int64_t n_iface,
-                         double *fold, double p, double p_stick, DevTotals *tot, hipStream_t s);
 // One launch for everything of a step but the sweep: the interface kernel of
 // step t (iface_blocks blocks, partials to pi_now), when `fold` the first
 // reduction stage of step t - 1 (sweep partials ps, interface partials
@@ -167,7 +163,7 @@ struct BatchSample {
     uint32_t block0, iblock0;
 };
 
-// Per-sample inputs of the batched reduction (same two stages as launch_reduce).
+// Per-sample inputs of the batched reduction (the same two stages as in launch_front).
 struct ReduceK {
     const double *ps;
     int64_t ns;

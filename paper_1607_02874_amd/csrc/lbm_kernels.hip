@@ -1,26 +1,26 @@
 // HIP kernels of the reactive two-lattice lattice-Boltzmann step for gfx950.
 //
-// One time step (Falcucci et al., Appendix "Numerical Method"):
-//   k_interface  sputtering boundary condition: every catalytic node k sums
-//                the reactant arriving along its active links,
-//                In(k) = sum_j f*_j(k - c_j) (first line of the sputtering
-//                equations), accumulates it and stores the re-emission
-//                (1 - p_S^R) In(k) scale(k);
-//   k_xflux      species crossing the x reservoir planes (bookkeeping);
-//   k_sweep      fused pull-streaming + BGK collision of both lattices,
-//                Eq. LBE with the second-order equilibrium, Guo body force on
+// One time step (Falcucci et al., Appendix "Numerical Method"), two launches:
+//   k_front      the sputtering boundary condition: every catalytic node k
+//                takes In(k) = sum_j f*_j(k - c_j) over its active links
+//                (first line of the sputtering equations; the sweep that
+//                produced those populations summed it), accumulates it and
+//                stores the re-emission (1 - p_S^R) In(k) scale(k); in the same
+//                launch, the fixed-order FP64 reductions of the two previous
+//                steps;
+//   k_sweep_c /  fused pull-streaming + BGK collision of both lattices,
+//   k_sweep      Eq. LBE with the second-order equilibrium, Guo body force on
 //                the carrier, halfway bounce-back at solid links, the reactive
-//                pull at catalytic sources and the reservoir ghosts;
-//   k_reduce     fixed-order FP64 totals.
+//                pull at catalytic sources and the reservoir planes; one lane
+//                per gas node (k_sweep_c) or per voxel of a 64-voxel chunk.
 //
-// Storage: populations of gas nodes only, structure of arrays
-// f[lattice][direction][gas node] in (z, y, x) order, as the normalised
-// deviation h_i = f_i / w_i - rho_ref (rho_ref = rho0 for the carrier, c_ref
-// for the reactant).  A wavefront owns one 64-voxel chunk of an x-row; lanes
-// on solid voxels idle.  A gas neighbour's storage index is its chunk base
-// plus a popcount of the chunk's gas bits, so no per-node neighbour table is
-// read: the 32-byte chunk records of the nine source rows are scalar loads.
-// Memory traffic is therefore close to 2 x 38 populations per gas node.
+// Storage: populations of gas nodes only, in (z, y, x) order, one array per
+// direction whose element n is the pair (carrier, reactant) of node n, each
+// as the normalised deviation h_i = f_i / w_i - rho_ref (rho_ref = rho0 for
+// the carrier, c_ref for the reactant).  A gas neighbour's storage index is
+// its chunk base plus a popcount of the chunk's gas bits, so no per-node
+// neighbour table is read, only the 32-byte chunk records of the nine source
+// rows.  Memory traffic is therefore close to 2 x 38 populations per gas node.
 
 #include <hip/hip_runtime.h>
 
@@ -948,12 +948,6 @@ __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::
     block_sum<1>(arrived, part + block);
 }
 
-template <int ST>
-__global__ __launch_bounds__(256) void k_interface(PhysK<typename Store<ST>::T> ph, Interface it,
-                                                    typename Store<ST>::S *__restrict__ emit,
-                                                    double *__restrict__ part) {
-    interface_block<ST>(ph, it, emit, part, blockIdx.x);
-}
 
 // Pre-collision populations of both lattices in a box of voxels (the same
 // pull as the sweep and the field kernels), as FP64 f_i = w_i (h_i + ref),
@@ -1064,10 +1058,6 @@ __device__ void fold_block(const double *ps, int64_t ns, const double *pi, int64
         for (int k = 0; k < NPART; ++k) out[b * NPART + k] = v[k];
 }
 
-__global__ __launch_bounds__(256) void k_fold(const double *ps, int64_t ns, const double *pi, int64_t ni,
-                                              double *out) {
-    fold_block(ps, ns, pi, ni, out, blockIdx.x, gridDim.x);
-}
 
 __device__ void reduce_block(const double *folded, int64_t nb, double p, double p_stick, DevTotals *tot) {
     double v[NPART];
@@ -1086,10 +1076,6 @@ __device__ void reduce_block(const double *folded, int64_t nb, double p, double 
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const double *folded, int64_t nb, double p, double p_stick,
-                                                 DevTotals *tot) {
-    reduce_block(folded, nb, p, p_stick, tot);
-}
 
 // Everything of a step but the sweep, in one launch: the interface of step t
 // (the first `iface_blocks` blocks), the first reduction stage of step t - 1
@@ -1216,19 +1202,6 @@ hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *po
         const int64_t blocks = (g.nfp + 255) / 256;
         hipLaunchKernelGGL(k_init<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph),
                            static_cast<SS *>(pre), static_cast<SS *>(post));
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_interface(const Geometry &g, const Physics &ph, const Interface &it, void *emit, double *part,
-                            int64_t blocks, hipStream_t s) {
-    if (blocks == 0) return hipSuccess;
-    return dispatch(ph.storage, [&](auto st) {
-        constexpr int ST = decltype(st)::value;
-        using SS = typename Store<ST>::S;
-        using T = typename Store<ST>::T;
-        hipLaunchKernelGGL(k_interface<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, to_kernel<T>(ph), it,
-                           static_cast<SS *>(emit), part);
         return hipGetLastError();
     });
 }
@@ -1365,15 +1338,6 @@ hipError_t launch_front(const Physics &ph, const Interface &it, void *emit, int6
                            ph.p_stick, tot, int32_t(iface_blocks), int32_t(fold ? FOLD_BLOCKS : 0));
         return hipGetLastError();
     });
-}
-
-hipError_t launch_reduce(const double *part_sweep, int64_t n_sweep, const double *part_iface, int64_t n_iface,
-                         double *fold, double p, double p_stick, DevTotals *tot, hipStream_t s) {
-    hipLaunchKernelGGL(k_fold, dim3(FOLD_BLOCKS), dim3(256), 0, s, part_sweep, n_sweep, part_iface, n_iface, fold);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, fold, int64_t(FOLD_BLOCKS), p, p_stick, tot);
-    return hipGetLastError();
 }
 
 size_t batch_record_bytes(int storage) {
