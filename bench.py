@@ -40,14 +40,14 @@ def algorithmic_bytes(info, s):
 
     Sweep: every population of both lattices written once (38 s per gas node)
     and read once (38 s), except the L_K reactant populations whose source is
-    a catalytic node, which come from the emission array (4 bytes per
+    a catalytic node, which come from the emission array (s bytes per
     interface node); plus the 8-byte In(k) sum per interface node and the
     32-byte chunk record per 64 voxels.  Interface: per interface node, In(k)
     read and clear (16), mask and scale (4 + 8), the FP64 accumulator
-    read-modify-write (16) and the emission write (4)."""
+    read-modify-write (16) and the emission write (s)."""
     nf, n, nk, lk = info["n_fluid"], info["n_nodes"], info["n_interface"], info["n_catalytic_links"]
-    sweep = (76 * nf - lk) * s + 12 * nk + n // 2
-    iface = nk * (16 + 4 + 8 + 16 + 4)
+    sweep = (76 * nf - lk) * s + (8 + s) * nk + n // 2
+    iface = nk * (16 + 4 + 8 + 16 + s)
     return {"sweep": sweep, "interface": iface, "step": sweep + iface}
 
 
