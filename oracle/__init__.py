@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 UNIFORM, WEIGHTED, BOUNCEBACK = 0, 1, 2
 PASSIVE, BARYCENTRIC = 0, 1
-XPERIODIC, XRESERVOIR = 0, 1
+XPERIODIC, XRESERVOIR, XINFLOW = 0, 1, 2
 
 
 def build(force=True):

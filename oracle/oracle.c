@@ -50,6 +50,11 @@
  *   - species x-boundaries: RESERVOIR puts an inlet ghost plane at x = -1
  *     holding w_i c_in and an outlet ghost plane at x = nx that copies plane
  *     nx - 1 (zero gradient; a solid copy reflects as inert solid);
+ *     INFLOW is the same except that the inlet ghost holds the equilibrium
+ *     of c_in moving with the carrier: f_i^eq(c_in, u) with
+ *     u = (sum_i c_i f_i^C + F/2) / sum_i f_i^C of the node it feeds, from
+ *     the carrier populations that node has just pulled (reactant injected
+ *     with the flow, as at the paper's inlet);
  *     PERIODIC wraps x like y and z.  The gas is periodic in x, y and z.
  */
 
@@ -76,7 +81,7 @@ static const int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16,
 enum { ORC_FLUID = 0, ORC_INERT = 1, ORC_CATALYTIC = 2 };
 enum { ORC_UNIFORM = 0, ORC_WEIGHTED = 1, ORC_BOUNCEBACK = 2 };
 enum { ORC_PASSIVE = 0, ORC_BARYCENTRIC = 1 };
-enum { ORC_XPERIODIC = 0, ORC_XRESERVOIR = 1 };
+enum { ORC_XPERIODIC = 0, ORC_XRESERVOIR = 1, ORC_XINFLOW = 2 };
 
 typedef struct {
     double tau_gas, tau_species; /* relaxation times of C and R */
@@ -422,7 +427,7 @@ static double interface(orc *o)
 static void stream(orc *o)
 {
     const orc_params *P = &o->prm;
-    int res = P->species_x == ORC_XRESERVOIR;
+    int res = P->species_x != ORC_XPERIODIC;
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < o->nz; ++z) {
         for (int y = 0; y < o->ny; ++y) {
@@ -436,11 +441,26 @@ static void stream(orc *o)
                     source(o, x, y, z, i, 1, &sx, &sy, &sz);
                     long s = node(o, sx, sy, sz);
                     o->fC[n * Q + i] = o->vox[s] == ORC_FLUID ? o->pC[s * Q + i] : o->pC[n * Q + OPP[i]];
+                }
+                /* the inlet ghost of INFLOW moves with the carrier velocity of this node */
+                double ghost[Q];
+                for (int i = 0; i < Q; ++i)
+                    ghost[i] = WT[i] * P->c_inlet;
+                if (P->species_x == ORC_XINFLOW && x == 0) {
+                    double rho, j[3], u[3];
+                    moments(o->fC + n * Q, &rho, j);
+                    for (int d = 0; d < 3; ++d)
+                        u[d] = (j[d] + 0.5 * P->force[d]) / rho;
+                    orc_equilibrium(P->c_inlet, u, ghost);
+                }
+                for (int i = 0; i < Q; ++i) {
+                    int sx, sy, sz;
+                    long s;
                     /* reactant */
                     source(o, x, y, z, i, !res, &sx, &sy, &sz);
                     double v;
                     if (sx < 0) {
-                        v = WT[i] * P->c_inlet;                          /* inlet ghost */
+                        v = ghost[i];                                    /* inlet ghost */
                     } else if (sx >= o->nx) {
                         long m = node(o, o->nx - 1, sy, sz);             /* outlet ghost */
                         v = o->vox[m] == ORC_FLUID ? o->pR[m * Q + i] : o->pR[n * Q + OPP[i]];
@@ -466,7 +486,7 @@ static void boundary_flux(orc *o, double *in_flux, double *out_flux)
     ksum fin = {0.0, 0.0}, fout = {0.0, 0.0};
     *in_flux = 0.0;
     *out_flux = 0.0;
-    if (o->prm.species_x != ORC_XRESERVOIR)
+    if (o->prm.species_x == ORC_XPERIODIC)
         return;
     for (int z = 0; z < o->nz; ++z)
         for (int y = 0; y < o->ny; ++y) {
@@ -474,7 +494,7 @@ static void boundary_flux(orc *o, double *in_flux, double *out_flux)
             if (o->vox[n0] == ORC_FLUID)
                 for (int i = 1; i < Q; ++i) {
                     if (CX[i] == 1)
-                        kadd(&fin, WT[i] * o->prm.c_inlet);        /* pulled from the inlet ghost */
+                        kadd(&fin, o->fR[n0 * Q + i]);             /* pulled from the inlet ghost */
                     if (CX[i] == -1)
                         kadd(&fout, o->pR[n0 * Q + i]);           /* left through the inlet */
                 }

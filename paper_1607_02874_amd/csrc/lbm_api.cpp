@@ -388,7 +388,7 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
         return fail(nullptr, LBM_EINVAL, "pore_size must be finite and > 0");
     if (bc->sputter < 0 || bc->sputter > 2) return fail(nullptr, LBM_EUNSUPPORTED, "unknown sputter mode");
     if (bc->coupling < 0 || bc->coupling > 1) return fail(nullptr, LBM_EUNSUPPORTED, "unknown coupling mode");
-    if (bc->species_x < 0 || bc->species_x > 1) return fail(nullptr, LBM_EUNSUPPORTED, "unknown species x-boundary");
+    if (bc->species_x < 0 || bc->species_x > 2) return fail(nullptr, LBM_EUNSUPPORTED, "unknown species x-boundary");
     if (bc->storage < 0 || bc->storage > 3) return fail(nullptr, LBM_EUNSUPPORTED, "unknown storage format");
     if (!(bc->p_stick >= 0.0 && bc->p_stick <= 1.0)) return fail(nullptr, LBM_EINVAL, "p_stick must be in [0, 1]");
     if (!(bc->c_inlet >= 0.0) || !std::isfinite(bc->c_inlet)) return fail(nullptr, LBM_EINVAL, "c_inlet must be >= 0");
@@ -547,7 +547,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     for (int a = 0; a < 3; ++a) c->ph.force[a] = bc->force[a];
     c->ph.rho0 = bc->rho0;
     c->ph.c0 = bc->c0;
-    c->ph.c_inlet = bc->species_x == LBM_XBC_RESERVOIR ? bc->c_inlet : 0.0;
+    c->ph.c_inlet = bc->species_x != LBM_XBC_PERIODIC ? bc->c_inlet : 0.0;
     c->ph.rho_ref = bc->rho0;
     // Species populations are stored unshifted by default (c_ref = 0): the
     // concentration is depleted next to the catalyst, and a shift would cost

@@ -45,7 +45,7 @@ static_assert(sizeof(ChunkInfo) == 32, "ChunkInfo must stay 32 bytes (one scalar
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_F64 = 3 };
 enum { SP_UNIFORM = 0, SP_WEIGHTED = 1, SP_BOUNCEBACK = 2 };
 enum { CP_PASSIVE = 0, CP_BARYCENTRIC = 1 };
-enum { XB_PERIODIC = 0, XB_RESERVOIR = 1 };
+enum { XB_PERIODIC = 0, XB_RESERVOIR = 1, XB_INFLOW = 2 };
 
 // Slots of the per-step partial sums (FP64).  The sweep writes four per
 // block (carrier mass, reactant mass, influx, outflux), the interface kernel

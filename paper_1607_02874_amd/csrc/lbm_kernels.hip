@@ -283,6 +283,28 @@ struct OutSlots {
     __device__ __forceinline__ void *p(int slot) const { return base + uint64_t(uint32_t(slot)) * stride; }
 };
 
+// INFLOW species x-boundary: the inlet ghost populations pulled by a node at
+// x = 0 (directions with c_x = +1) are the equilibrium of c_in moving with the
+// carrier velocity of that node, u = (j_C + F/2) / rho_C from the carrier
+// populations it has just pulled.
+template <typename T>
+__device__ __forceinline__ void weighted_moments(const T (&h)[19], T &d, T &jx, T &jy, T &jz);
+template <typename T>
+__device__ __forceinline__ void inflow_ghost(const PhysK<T> &ph, const T (&hC)[19], T (&hR)[19]) {
+    T d, jx, jy, jz;
+    weighted_moments(hC, d, jx, jy, jz);
+    const T inv = T(1) / (ph.rref + d);
+    const T ux = (jx + T(0.5) * ph.fx) * inv, uy = (jy + T(0.5) * ph.fy) * inv, uz = (jz + T(0.5) * ph.fz) * inv;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T cin = T(ph.c_in);
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        if (CX[i] != 1) continue;
+        const T cu = ux + T(CY[i]) * uy + T(CZ[i]) * uz;
+        hR[i] = cin * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu) - ph.cref;
+    }
+}
+
 // Directions grouped by source row (cy, cz), so each row's chunk record is
 // needed for one stretch of the pull only.
 constexpr int ORDER[18] = {1, 10, 2, 4, 14, 11, 13, 5, 3, 6, 16, 12, 15, 7, 8, 9, 17, 18};
@@ -313,7 +335,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     constexpr uint32_t SB = sizeof(S), PB = 2 * SB;
     const int64_t nfp = g.nfp;
     const uint32_t nfp_b = uint32_t(nfp) * PB;   // one direction array, in bytes
-    const bool reservoir = ph.species_x == XB_RESERVOIR;
+    const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
     const int sputter = SP >= 0 ? SP : ph.sputter;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
     auto base = [&](int slot) { return in.p(slot); };
@@ -420,6 +442,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
+    if (ph.species_x == XB_INFLOW && first_chunk && lane_in(lane0)) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
 
@@ -451,7 +474,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     constexpr int CZS[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
     const int64_t nfp = g.nfp;
     const uint32_t nfp_b = uint32_t(nfp) * PB;
-    const bool reservoir = ph.species_x == XB_RESERVOIR;
+    const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
     const int sputter = SP >= 0 ? SP : ph.sputter;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
     auto base = [&](int slot) { return in.p(slot); };
@@ -575,6 +598,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? ev * inv_wgt<T>(i) : ev) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
+    if (ph.species_x == XB_INFLOW && __builtin_amdgcn_ballot_w64(first_x) != 0u && first_x) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
 
@@ -743,12 +767,18 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
         // Reactant crossing the reservoir planes in this streaming: what the
         // outlet ghost returned to x = nx - 1 (pulled along c_x = -1) counts
         // against what left there (below).
-        const bool reservoir = ph.species_x == XB_RESERVOIR;
+        const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
+        const bool inflow = ph.species_x == XB_INFLOW;
         const bool first_x = u.x == 0, last_x = u.x == g.nx - 1;
         if (reservoir && last_x) {
 #pragma unroll
             for (int i = 1; i < 19; ++i)
                 if (CX[i] == -1) acc[3] -= double(wgt<T>(i) * (hR[i] + ph.cref));
+        }
+        if (inflow && first_x) {  // what the moving inlet ghost supplied
+#pragma unroll
+            for (int i = 1; i < 19; ++i)
+                if (CX[i] == 1) acc[2] += double(wgt<T>(i) * (hR[i] + ph.cref));
         }
         collide(ph, m, hC, hR);
         using P = typename Store<ST>::P;
@@ -763,7 +793,8 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
         // In(k) of the next step's interface: what leaves towards interface nodes
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR);
         if (reservoir && (first_x || last_x)) {
-            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, in.base, in.stride, u.idx, first_x, last_x);
+            const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, u.idx, first_x,
+                                               last_x);
             acc[2] += f.in;
             acc[3] += f.out;
         }
@@ -796,12 +827,18 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
-        const bool reservoir = ph.species_x == XB_RESERVOIR;
+        const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
+        const bool inflow = ph.species_x == XB_INFLOW;
         const bool first_x = x == 0, last_x = x == g.nx - 1;
         if (reservoir && last_x) {
 #pragma unroll
             for (int i = 1; i < 19; ++i)
                 if (CX[i] == -1) acc[3] -= double(wgt<T>(i) * (hR[i] + ph.cref));
+        }
+        if (inflow && first_x) {  // what the moving inlet ghost supplied
+#pragma unroll
+            for (int i = 1; i < 19; ++i)
+                if (CX[i] == 1) acc[2] += double(wgt<T>(i) * (hR[i] + ph.cref));
         }
         collide(ph, m, hC, hR);
         using P = typename Store<ST>::P;
@@ -813,7 +850,8 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         }
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR);
         if (reservoir && (first_x || last_x)) {
-            const InOut f = boundary_tally<ST>(ph.cref, ph.c_in, in.base, in.stride, idx, first_x, last_x);
+            const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, idx, first_x,
+                                               last_x);
             acc[2] += f.in;
             acc[3] += f.out;
         }

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "LBM_OK", 1: "LBM_EINVAL", 2: "LBM_ENOMEM", 3: "LBM_EDEVICE",
 FLUID, INERT, CATALYTIC = 0, 1, 2
 SPUTTER_UNIFORM, SPUTTER_WEIGHTED, SPUTTER_BOUNCEBACK = 0, 1, 2
 COUPLE_PASSIVE, COUPLE_BARYCENTRIC = 0, 1
-XBC_PERIODIC, XBC_RESERVOIR = 0, 1
+XBC_PERIODIC, XBC_RESERVOIR, XBC_INFLOW = 0, 1, 2
 STORE_F32, STORE_F16, STORE_BF16, STORE_F64 = 0, 1, 2, 3
 TUNE_YTILE, TUNE_SWEEP = 0, 1
 STORAGE_BYTES = {STORE_F32: 4, STORE_F16: 2, STORE_BF16: 2, STORE_F64: 8}

@@ -8,7 +8,7 @@ from paper_1607_02874_amd import inputs
 
 SPUTTER = {"UNIFORM": 0, "WEIGHTED": 1, "BOUNCEBACK": 2}
 COUPLING = {"PASSIVE": 0, "BARYCENTRIC": 1}
-XBC = {"PERIODIC": 0, "RESERVOIR": 1}
+XBC = {"PERIODIC": 0, "RESERVOIR": 1, "INFLOW": 2}
 
 
 def case(vox, steps, da=1.0, tau=(0.8, 0.7), pore_size=4.0, p_stick=0.95, c_inlet=1.0, c0=0.0, rho0=1.0,

@@ -97,6 +97,8 @@ def test_geometry_bookkeeping_is_exact(plain_ref):
     ("UNIFORM", "BARYCENTRIC", "RESERVOIR"),
     ("UNIFORM", "PASSIVE", "PERIODIC"),
     ("WEIGHTED", "BARYCENTRIC", "PERIODIC"),
+    ("UNIFORM", "PASSIVE", "INFLOW"),
+    ("BOUNCEBACK", "BARYCENTRIC", "INFLOW"),
 ])
 def test_modes_fp64_match_oracle(sputter, coupling, species_x):
     c = plain_case(steps=60, sputter=sputter, coupling=coupling, species_x=species_x, c0=0.2, p_stick=0.6)
@@ -130,7 +132,7 @@ def test_ragged_shapes_fp64_and_fp32(name, shape):
     vox[rng.random(shape) < 0.1] = 1
     if nx > 2:
         vox[:, :, 0] = 0
-    for species_x in ("RESERVOIR", "PERIODIC"):
+    for species_x in ("RESERVOIR", "PERIODIC", "INFLOW"):
         c = case(vox, 25, da=0.3, tau=(0.9, 0.75), pore_size=2.0, force=(1e-4, 2e-5, -1e-5), c0=0.1,
                  p_stick=0.7, species_x=species_x)
         ref = run_oracle(c)
@@ -360,7 +362,8 @@ SHAPES_SWEEP = {
 @pytest.mark.parametrize("sputter,coupling,species_x", [("UNIFORM", "PASSIVE", "RESERVOIR"),
                                                         ("WEIGHTED", "BARYCENTRIC", "PERIODIC"),
                                                         ("BOUNCEBACK", "PASSIVE", "PERIODIC"),
-                                                        ("UNIFORM", "BARYCENTRIC", "RESERVOIR")])
+                                                        ("UNIFORM", "BARYCENTRIC", "RESERVOIR"),
+                                                        ("WEIGHTED", "PASSIVE", "INFLOW")])
 def test_compact_and_chunk_sweeps_agree(shape, sputter, coupling, species_x):
     """The node-compact sweep (default) and the 64-voxel-chunk sweep compute
     the same populations: fields and conversion map bit-identical, totals to
