@@ -1240,7 +1240,7 @@ struct lbm_batch {
     std::vector<lbm_ctx *> ctx;
     lbm_device dev{};
     hipStream_t stream = nullptr;
-    int storage = 0, sputter = 0;
+    int storage = 0, sputter = 0, species_x = 0;  // shared by every sample
     bool compact = false;  // node-compact sweep for every sample (all support it)
     std::vector<void *> allocations;
     void *d_records = nullptr;
@@ -1297,7 +1297,7 @@ void *batch_alloc(lbm_batch *b, size_t bytes) {
 }
 
 lbm_status batch_launch(lbm_batch *b, int parity, hipStream_t s) {
-    hipError_t e = launch_batch_step(b->storage, b->sputter, b->compact, b->d_records, b->d_sweep_sample,
+    hipError_t e = launch_batch_step(b->storage, b->sputter, b->species_x, b->compact, b->d_records, b->d_sweep_sample,
                                      b->sweep_blocks_total, b->d_iface_sample, b->iface_blocks_total, b->d_reduce,
                                      int(b->ctx.size()), parity, s);
     if (e != hipSuccess) return bfail(b, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
@@ -1426,6 +1426,7 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
     b->stream = static_cast<hipStream_t>(b->dev.stream);
     b->storage = bc[0].storage;
     b->sputter = bc[0].sputter;
+    b->species_x = bc[0].species_x;
     try {
         b->ctx.reserve(size_t(n));
         for (int32_t i = 0; i < n; ++i) {
@@ -1633,7 +1634,8 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, double *best_ms) {
             const int parity = b->parity;
             float ms = 0.0f;
             st = time_launches(b->stream, reps, [&]() {
-                return launch_batch_sweep(b->storage, b->sputter, b->compact, b->d_records, b->d_sweep_sample,
+                return launch_batch_sweep(b->storage, b->sputter, b->species_x, b->compact, b->d_records,
+                                          b->d_sweep_sample,
                                           b->sweep_blocks_total, parity, b->stream);
             }, &ms, &b->err);
             if (st != LBM_OK) break;

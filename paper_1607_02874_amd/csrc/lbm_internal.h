@@ -179,11 +179,11 @@ struct ReduceK {
 size_t batch_record_bytes(int storage);
 hipError_t batch_upload(int storage, const BatchSample *smp, int n, void *d_records, hipStream_t s);
 // The batched sweep alone (reads buffer `parity` of every sample).
-hipError_t launch_batch_sweep(int storage, int sputter, bool compact, const void *d_records,
+hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool compact, const void *d_records,
                               const uint32_t *sweep_sample, int64_t sweep_blocks_total, int parity, hipStream_t s);
 // One step of every sample: batched interface, sweep (reading population
 // buffer `parity` of every sample, writing the other) and reduction.
-hipError_t launch_batch_step(int storage, int sputter, bool compact, const void *d_records,
+hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compact, const void *d_records,
                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, const uint32_t *iface_sample,
                              int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s);
 

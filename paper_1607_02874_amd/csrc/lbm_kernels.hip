@@ -283,6 +283,10 @@ struct OutSlots {
     __device__ __forceinline__ void *p(int slot) const { return base + uint64_t(uint32_t(slot)) * stride; }
 };
 
+// Template code of a sweep: the sputter mode, plus this flag for INFLOW, so
+// the kernels of the other boundaries carry none of its code.
+constexpr int SP_INFLOW_FLAG = 4;
+
 // INFLOW species x-boundary: the inlet ghost populations pulled by a node at
 // x = 0 (directions with c_x = +1) are the equilibrium of c_in moving with the
 // carrier velocity of that node, u = (j_C + F/2) / rho_C from the carrier
@@ -336,7 +340,10 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     const int64_t nfp = g.nfp;
     const uint32_t nfp_b = uint32_t(nfp) * PB;   // one direction array, in bytes
     const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
-    const int sputter = SP >= 0 ? SP : ph.sputter;
+    // SP: the sputter mode (bits 0-1) and the INFLOW flag, fixed at compile
+    // time for the sweeps, or -1 to read both from ph
+    const int sputter = SP >= 0 ? (SP & 3) : ph.sputter;
+    const bool inflow = SP >= 0 ? (SP & SP_INFLOW_FLAG) != 0 : ph.species_x == XB_INFLOW;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
     auto base = [&](int slot) { return in.p(slot); };
     const uint32_t own_b = u.idx * PB;
@@ -442,7 +449,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
-    if (ph.species_x == XB_INFLOW && first_chunk && lane_in(lane0)) inflow_ghost(ph, hC, hR);
+    if (inflow && first_chunk && lane_in(lane0)) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
 
@@ -475,7 +482,10 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     const int64_t nfp = g.nfp;
     const uint32_t nfp_b = uint32_t(nfp) * PB;
     const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
-    const int sputter = SP >= 0 ? SP : ph.sputter;
+    // SP: the sputter mode (bits 0-1) and the INFLOW flag, fixed at compile
+    // time for the sweeps, or -1 to read both from ph
+    const int sputter = SP >= 0 ? (SP & 3) : ph.sputter;
+    const bool inflow = SP >= 0 ? (SP & SP_INFLOW_FLAG) != 0 : ph.species_x == XB_INFLOW;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
     auto base = [&](int slot) { return in.p(slot); };
     const uint32_t own_b = idx * PB;
@@ -598,7 +608,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? ev * inv_wgt<T>(i) : ev) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
-    if (ph.species_x == XB_INFLOW && __builtin_amdgcn_ballot_w64(first_x) != 0u && first_x) inflow_ghost(ph, hC, hR);
+    if (inflow && __builtin_amdgcn_ballot_w64(first_x) != 0u && first_x) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
 
@@ -768,7 +778,7 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
         // outlet ghost returned to x = nx - 1 (pulled along c_x = -1) counts
         // against what left there (below).
         const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
-        const bool inflow = ph.species_x == XB_INFLOW;
+        const bool inflow = (SP & SP_INFLOW_FLAG) != 0;
         const bool first_x = u.x == 0, last_x = u.x == g.nx - 1;
         if (reservoir && last_x) {
 #pragma unroll
@@ -828,7 +838,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
         const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
-        const bool inflow = ph.species_x == XB_INFLOW;
+        const bool inflow = (SP & SP_INFLOW_FLAG) != 0;
         const bool first_x = x == 0, last_x = x == g.nx - 1;
         if (reservoir && last_x) {
 #pragma unroll
@@ -1194,6 +1204,22 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const ReduceK *__restrict_
     reduce_block(d.fold, FOLD_BLOCKS, d.p, d.p_stick, d.tot);
 }
 
+// The sweep template code of a sputter mode and species x-boundary.
+int sweep_code(int sputter, int species_x) { return sputter | (species_x == XB_INFLOW ? SP_INFLOW_FLAG : 0); }
+
+template <typename F>
+hipError_t dispatch_sp(int code, F &&f) {
+    switch (code) {
+        case SP_UNIFORM: return f(std::integral_constant<int, SP_UNIFORM>{});
+        case SP_WEIGHTED: return f(std::integral_constant<int, SP_WEIGHTED>{});
+        case SP_BOUNCEBACK: return f(std::integral_constant<int, SP_BOUNCEBACK>{});
+        case SP_UNIFORM | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_UNIFORM | SP_INFLOW_FLAG>{});
+        case SP_WEIGHTED | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_WEIGHTED | SP_INFLOW_FLAG>{});
+        case SP_BOUNCEBACK | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_BOUNCEBACK | SP_INFLOW_FLAG>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename F>
 hipError_t dispatch(int storage, F &&f) {
     switch (storage) {
@@ -1281,13 +1307,10 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
         const dim3 grid(unsigned(sweep_blocks(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
         const PhysK<T> k = to_kernel<T>(ph);
-        if (ph.sputter == SP_UNIFORM)
-            hipLaunchKernelGGL((k_sweep<ST, SP_UNIFORM>), grid, block, 0, s, g, k, in, out, e, part);
-        else if (ph.sputter == SP_WEIGHTED)
-            hipLaunchKernelGGL((k_sweep<ST, SP_WEIGHTED>), grid, block, 0, s, g, k, in, out, e, part);
-        else
-            hipLaunchKernelGGL((k_sweep<ST, SP_BOUNCEBACK>), grid, block, 0, s, g, k, in, out, e, part);
-        return hipGetLastError();
+        return dispatch_sp(sweep_code(ph.sputter, ph.species_x), [&](auto sp) {
+            hipLaunchKernelGGL((k_sweep<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -1307,13 +1330,10 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
         const dim3 grid(static_cast<unsigned>(sweep_blocks_c(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
         const PhysK<T> k = to_kernel<T>(ph);
-        if (ph.sputter == SP_UNIFORM)
-            hipLaunchKernelGGL((k_sweep_c<ST, SP_UNIFORM>), grid, block, 0, s, g, k, in, out, e, part);
-        else if (ph.sputter == SP_WEIGHTED)
-            hipLaunchKernelGGL((k_sweep_c<ST, SP_WEIGHTED>), grid, block, 0, s, g, k, in, out, e, part);
-        else
-            hipLaunchKernelGGL((k_sweep_c<ST, SP_BOUNCEBACK>), grid, block, 0, s, g, k, in, out, e, part);
-        return hipGetLastError();
+        return dispatch_sp(sweep_code(ph.sputter, ph.species_x), [&](auto sp) {
+            hipLaunchKernelGGL((k_sweep_c<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -1414,32 +1434,24 @@ hipError_t batch_upload(int storage, const BatchSample *smp, int n, void *d_reco
     });
 }
 
-hipError_t launch_batch_sweep(int storage, int sputter, bool compact, const void *d_records,
+hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool compact, const void *d_records,
                               const uint32_t *sweep_sample, int64_t sweep_blocks_total, int parity, hipStream_t s) {
     return dispatch(storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         const SampleK<ST> *rec = static_cast<const SampleK<ST> *>(d_records);
         const dim3 grid(static_cast<unsigned>(sweep_blocks_total)), block(256);
-        if (compact) {
-            if (sputter == SP_UNIFORM)
-                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP_UNIFORM>), grid, block, 0, s, rec, sweep_sample, parity);
-            else if (sputter == SP_WEIGHTED)
-                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP_WEIGHTED>), grid, block, 0, s, rec, sweep_sample, parity);
+        return dispatch_sp(sweep_code(sputter, species_x), [&](auto sp) {
+            constexpr int SP = decltype(sp)::value;
+            if (compact)
+                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP>), grid, block, 0, s, rec, sweep_sample, parity);
             else
-                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP_BOUNCEBACK>), grid, block, 0, s, rec, sweep_sample,
-                                   parity);
-        } else if (sputter == SP_UNIFORM) {
-            hipLaunchKernelGGL((k_sweep_batch<ST, SP_UNIFORM>), grid, block, 0, s, rec, sweep_sample, parity);
-        } else if (sputter == SP_WEIGHTED) {
-            hipLaunchKernelGGL((k_sweep_batch<ST, SP_WEIGHTED>), grid, block, 0, s, rec, sweep_sample, parity);
-        } else {
-            hipLaunchKernelGGL((k_sweep_batch<ST, SP_BOUNCEBACK>), grid, block, 0, s, rec, sweep_sample, parity);
-        }
-        return hipGetLastError();
+                hipLaunchKernelGGL((k_sweep_batch<ST, SP>), grid, block, 0, s, rec, sweep_sample, parity);
+            return hipGetLastError();
+        });
     });
 }
 
-hipError_t launch_batch_step(int storage, int sputter, bool compact, const void *d_records,
+hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compact, const void *d_records,
                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, const uint32_t *iface_sample,
                              int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s) {
     return dispatch(storage, [&](auto st) {
@@ -1451,8 +1463,8 @@ hipError_t launch_batch_step(int storage, int sputter, bool compact, const void 
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        hipError_t e = launch_batch_sweep(storage, sputter, compact, d_records, sweep_sample, sweep_blocks_total,
-                                          parity, s);
+        hipError_t e = launch_batch_sweep(storage, sputter, species_x, compact, d_records, sweep_sample,
+                                          sweep_blocks_total, parity, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_fold_batch, dim3(FOLD_BLOCKS, unsigned(n)), dim3(256), 0, s, d_reduce);
         e = hipGetLastError();
