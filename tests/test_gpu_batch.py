@@ -76,6 +76,24 @@ def test_batch_barycentric_periodic_matches_single():
             assert_same(b, i, single(smp, 17))
 
 
+@pytest.mark.parametrize("variant", [1, 0])
+def test_batch_inflow_matches_single(variant):
+    """The moving-inlet boundary (INFLOW) in a batch, both sweep variants:
+    every sample bit-identical to the same sample alone."""
+    samples = mixed_samples(species_x=lbm.XBC_INFLOW)
+    with lbm.Batch(samples) as b:
+        b.set_tunable(lbm.TUNE_SWEEP, variant)
+        b.set_tunable(lbm.TUNE_YTILE, 4)
+        b.step(13)
+        for i, smp in enumerate(samples):
+            kw = {k: v for k, v in smp.items() if k not in ("vox", "da", "tau", "pore_size")}
+            with lbm.Sim(smp["vox"], da=smp["da"], tau=smp["tau"], pore_size=smp["pore_size"], **kw) as s:
+                s.set_tunable(lbm.TUNE_SWEEP, variant)
+                s.set_tunable(lbm.TUNE_YTILE, min(4, smp["vox"].shape[1]))
+                s.step(13)
+                assert_same(b, i, (s.fields(), s.conversion_map(), s.totals()))
+
+
 def test_batch_graph_replays_match_eager():
     samples = mixed_samples()
     with lbm.Batch(samples) as eager, lbm.Batch(samples, graph=True) as graphed:
