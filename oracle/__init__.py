@@ -39,7 +39,9 @@ class Params(ctypes.Structure):
                 ("c_inlet", ctypes.c_double), ("rho0", ctypes.c_double), ("c0", ctypes.c_double),
                 ("force", ctypes.c_double * 3),
                 ("sputter", ctypes.c_int32), ("coupling", ctypes.c_int32),
-                ("species_x", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("species_x", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("p_stick_product", ctypes.c_double),
+                ("product", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 _lib = None
@@ -66,6 +68,10 @@ def lib():
         L.orc_step_count.restype = ctypes.c_long
         L.orc_get_state.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_set_state.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_get_state_product.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_set_state_product.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_product.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_product_flux.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_link_counts.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_d3q19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_d3q19.restype = ctypes.c_int
@@ -131,10 +137,12 @@ def threads():
 
 
 class Oracle:
-    """One FP64 reference simulation of the gas + reactant lattices."""
+    """One FP64 reference simulation of the gas + reactant lattices, plus the
+    product lattice when `product` is set (p_stick_product = p_S^P)."""
 
     def __init__(self, vox, tau=(0.8, 0.7), p=0.1, p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0,
-                 force=(0.0, 0.0, 0.0), sputter=UNIFORM, coupling=PASSIVE, species_x=XRESERVOIR):
+                 force=(0.0, 0.0, 0.0), sputter=UNIFORM, coupling=PASSIVE, species_x=XRESERVOIR,
+                 product=False, p_stick_product=0.0):
         vox = np.ascontiguousarray(vox, dtype=np.uint8)
         assert vox.ndim == 3
         self.nz, self.ny, self.nx = vox.shape
@@ -147,6 +155,7 @@ class Oracle:
         for a in range(3):
             prm.force[a] = float(force[a])
         prm.sputter, prm.coupling, prm.species_x = int(sputter), int(coupling), int(species_x)
+        prm.product, prm.p_stick_product = int(bool(product)), float(p_stick_product)
         self.params = prm
         h = lib().orc_create(self.nx, self.ny, self.nz, vox.ctypes.data, ctypes.byref(prm))
         if not h:
@@ -189,6 +198,31 @@ class Oracle:
         lib().orc_totals(self._h, t.ctypes.data)
         keys = ("mass_gas", "mass_species", "converted", "lost", "influx", "outflux")
         return dict(zip(keys, t.tolist()))
+
+    def product(self):
+        """(rho_P field, totals dict, stuck map p_S^P sum_t In_P(k, t))."""
+        shape = (self.nz, self.ny, self.nx)
+        c = np.zeros(self.n)
+        t = np.zeros(4)
+        st = np.zeros(self.n)
+        lib().orc_product(self._h, c.ctypes.data, t.ctypes.data, st.ctypes.data)
+        keys = ("mass_product", "lost_product", "product_out_inlet", "product_out_outlet")
+        return c.reshape(shape), dict(zip(keys, t.tolist())), st.reshape(shape)
+
+    def product_flux(self):
+        """Phi_P(x): sum over each cross-section of rho_P u_x."""
+        phi = np.zeros(self.nx)
+        lib().orc_product_flux(self._h, phi.ctypes.data)
+        return phi
+
+    def get_state_product(self):
+        fP = np.zeros((self.n, 19))
+        lib().orc_get_state_product(self._h, fP.ctypes.data)
+        return fP
+
+    def set_state_product(self, fP):
+        a = np.ascontiguousarray(fP, dtype=np.float64)
+        lib().orc_set_state_product(self._h, a.ctypes.data)
 
     def link_counts(self):
         b = np.zeros(self.n, dtype=np.uint8)

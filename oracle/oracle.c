@@ -33,10 +33,22 @@
  *     (1 - p) p_S^R is lost, so total (R + P) mass is not conserved unless the
  *     sticking probability is zero (text after the eqnarray);
  *   - a body force drives the carrier ("Validation of Numerical Model"),
- *     implemented with Guo's forcing term and the half-force velocity shift.
+ *     implemented with Guo's forcing term and the half-force velocity shift;
+ *   - optionally the product lattice P (second line of the eqnarray): a
+ *     catalytic node re-emits into the gas, along the directions picked by
+ *     S, the converted reactant p p_S^R In_R(k) plus the fraction
+ *     (1 - p_S^P) of the product that arrived there, In_P(k); the fraction
+ *     p_S^P of arriving product sticks and leaves the system;
+ *   - the diagnostics of "Results & Discussion": the conversion efficiency
+ *     (Eq. eff), product mass leaving through the outlet over reactant mass
+ *     entering through the inlet, and the product flux profile Phi_P
+ *     (Eq. for Phi_P), sum over a cross-section of rho_P u along the flow.
  *
  * Readings where the paper is silent (the same readings the HIP path uses):
- *   - gas lattice C and reactant lattice R only; relaxation time per lattice;
+ *   - gas lattice C, reactant lattice R and, when enabled, product lattice P;
+ *     one relaxation time for the gas and one shared by the two species (the
+ *     paper takes tau equal for all species); P starts at zero and the
+ *     inlet ghost holds no product (only carrier and reactant are injected);
  *   - species advection velocity: PASSIVE (carrier velocity; the text says
  *     reactant and product are passively transported by the carrier) or
  *     BARYCENTRIC (the common velocity of the moment equations);
@@ -55,7 +67,8 @@
  *     u = (sum_i c_i f_i^C + F/2) / sum_i f_i^C of the node it feeds, from
  *     the carrier populations that node has just pulled (reactant injected
  *     with the flow, as at the paper's inlet);
- *     PERIODIC wraps x like y and z.  The gas is periodic in x, y and z.
+ *     PERIODIC wraps x like y and z.  The gas is periodic in x, y and z;
+ *   - BARYCENTRIC sums the moments of every lattice present (C, R and P).
  */
 
 #include <math.h>
@@ -91,6 +104,8 @@ typedef struct {
     double rho0, c0;             /* initial carrier density and concentration */
     double force[3];             /* body-force density on the carrier */
     int32_t sputter, coupling, species_x, pad;
+    double p_stick_product;      /* sticking probability p_S^P of the product */
+    int32_t product, pad2;       /* 1: evolve the product lattice P */
 } orc_params;
 
 typedef struct {
@@ -103,6 +118,11 @@ typedef struct {
     double *em;        /* emission E_i(k) of catalytic nodes, [node*Q + i] */
     double *acc;       /* accumulated arrivals sum_t In(k, t), per node */
     double tot[6];     /* mass_gas, mass_species, converted, lost, influx, outflux */
+    /* product lattice (NULL unless prm.product) */
+    double *fP, *pP, *emP, *accP;
+    /* mass_product, lost_product (p_S^P sum In_P), product leaving through
+     * the inlet face, product leaving through the outlet face (net) */
+    double totp[4];
     long step;
 } orc;
 
@@ -271,17 +291,27 @@ static void moments(const double *f, double *rho, double *j)
 
 static void totals_mass(orc *o)
 {
-    ksum mc = {0.0, 0.0}, mr = {0.0, 0.0};
+    ksum mc = {0.0, 0.0}, mr = {0.0, 0.0}, mp = {0.0, 0.0};
     for (long n = 0; n < o->n; ++n) {
         if (o->vox[n] != ORC_FLUID)
             continue;
         for (int i = 0; i < Q; ++i) {
             kadd(&mc, o->fC[n * Q + i]);
             kadd(&mr, o->fR[n * Q + i]);
+            if (o->fP)
+                kadd(&mp, o->fP[n * Q + i]);
         }
     }
     o->tot[0] = kval(&mc);
     o->tot[1] = kval(&mr);
+    o->totp[0] = kval(&mp);
+}
+
+static void free_all(orc *o)
+{
+    free(o->vox); free(o->fC); free(o->fR); free(o->pC); free(o->pR); free(o->em); free(o->acc);
+    free(o->fP); free(o->pP); free(o->emP); free(o->accP);
+    free(o);
 }
 
 orc *orc_create(int nx, int ny, int nz, const unsigned char *vox, const orc_params *prm)
@@ -303,14 +333,20 @@ orc *orc_create(int nx, int ny, int nz, const unsigned char *vox, const orc_para
     o->pR = calloc(o->n * Q, sizeof(double));
     o->em = calloc(o->n * Q, sizeof(double));
     o->acc = calloc(o->n, sizeof(double));
-    if (!o->vox || !o->fC || !o->fR || !o->pC || !o->pR || !o->em || !o->acc) {
-        free(o->vox); free(o->fC); free(o->fR); free(o->pC); free(o->pR); free(o->em); free(o->acc);
-        free(o);
+    if (prm->product) {
+        o->fP = calloc(o->n * Q, sizeof(double));
+        o->pP = calloc(o->n * Q, sizeof(double));
+        o->emP = calloc(o->n * Q, sizeof(double));
+        o->accP = calloc(o->n, sizeof(double));
+    }
+    if (!o->vox || !o->fC || !o->fR || !o->pC || !o->pR || !o->em || !o->acc ||
+        (prm->product && (!o->fP || !o->pP || !o->emP || !o->accP))) {
+        free_all(o);
         return NULL;
     }
     memcpy(o->vox, vox, o->n);
-    /* Initial state: carrier at rest with density rho0, species at c0
-     * (the paper starts with no reactant in the domain). */
+    /* Initial state: carrier at rest with density rho0, reactant at c0 (the
+     * paper starts with no reactant in the domain), no product (calloc). */
     double zero[3] = {0.0, 0.0, 0.0};
     double eqC[Q], eqR[Q];
     orc_equilibrium(prm->rho0, zero, eqC);
@@ -331,8 +367,7 @@ void orc_destroy(orc *o)
 {
     if (!o)
         return;
-    free(o->vox); free(o->fC); free(o->fR); free(o->pC); free(o->pR); free(o->em); free(o->acc);
-    free(o);
+    free_all(o);
 }
 
 /* ----------------------------------------------------------------- step -- */
@@ -350,22 +385,28 @@ static void collide(orc *o)
                 if (o->vox[n] != ORC_FLUID)
                     continue;
                 const double *fc = o->fC + n * Q, *fr = o->fR + n * Q;
-                double rc, jc[3], rr, jr[3], u[3];
+                const double *fp = o->fP ? o->fP + n * Q : NULL;
+                double rc, jc[3], rr, jr[3], rp = 0.0, jp[3] = {0.0, 0.0, 0.0}, u[3];
                 moments(fc, &rc, jc);
                 moments(fr, &rr, jr);
+                if (fp)
+                    moments(fp, &rp, jp);
                 for (int a = 0; a < 3; ++a) {
                     if (P->coupling == ORC_BARYCENTRIC)
-                        u[a] = (jc[a] + jr[a] + 0.5 * P->force[a]) / (rc + rr);
+                        u[a] = (jc[a] + jr[a] + jp[a] + 0.5 * P->force[a]) / (rc + rr + rp);
                     else
                         u[a] = (jc[a] + 0.5 * P->force[a]) / rc;
                 }
-                double eqc[Q], eqr[Q], S[Q];
+                double eqc[Q], eqr[Q], eqp[Q], S[Q];
                 orc_equilibrium(rc, u, eqc);
                 orc_equilibrium(rr, u, eqr);
+                orc_equilibrium(rp, u, eqp);
                 orc_guo_source(P->tau_gas, u, P->force, S);
                 for (int i = 0; i < Q; ++i) {
                     o->pC[n * Q + i] = fc[i] - (fc[i] - eqc[i]) / P->tau_gas + S[i];
                     o->pR[n * Q + i] = fr[i] - (fr[i] - eqr[i]) / P->tau_species;
+                    if (fp)
+                        o->pP[n * Q + i] = fp[i] - (fp[i] - eqp[i]) / P->tau_species;
                 }
             }
         }
@@ -373,12 +414,13 @@ static void collide(orc *o)
 }
 
 /* Step 5: the sputtering boundary condition at catalytic nodes.  Returns the
- * total arrival sum_k In(k) of this step. */
-static double interface(orc *o)
+ * total reactant arrival sum_k In_R(k) of this step, and the product arrival
+ * sum_k In_P(k) in *arrived_p (0 without the product lattice). */
+static double interface(orc *o, double *arrived_p)
 {
     const orc_params *P = &o->prm;
     int xper = P->species_x == ORC_XPERIODIC;
-    ksum total = {0.0, 0.0};
+    ksum total = {0.0, 0.0}, total_p = {0.0, 0.0};
     for (int z = 0; z < o->nz; ++z)
         for (int y = 0; y < o->ny; ++y)
             for (int x = 0; x < o->nx; ++x) {
@@ -391,43 +433,88 @@ static double interface(orc *o)
                     continue;
                 /* In(k): every reactant population heading into k along an
                  * active link, f*_j(k - c_j). */
-                double in = 0.0, wsum = 0.0;
+                double in = 0.0, in_p = 0.0, wsum = 0.0;
                 for (int j = 1; j < Q; ++j) {
                     if (!(act & (1u << j)))
                         continue;
                     int sx, sy, sz;
                     source(o, x, y, z, j, xper, &sx, &sy, &sz);
                     in += o->pR[node(o, sx, sy, sz) * Q + j];
+                    if (o->pP)
+                        in_p += o->pP[node(o, sx, sy, sz) * Q + j];
                     wsum += WT[OPP[j]];
                 }
                 o->acc[k] += in;
                 kadd(&total, in);
+                if (o->pP) {
+                    o->accP[k] += in_p;
+                    kadd(&total_p, in_p);
+                }
+                /* What the node sends back as product: the converted part of
+                 * the reactant plus the product that did not stick. */
+                const double a_r = P->p * P->p_stick, a_p = 1.0 - P->p_stick_product;
                 /* Re-emission (1 - p_S^R) sum_j S_ij f_j^out along i = opp(j). */
                 for (int j = 1; j < Q; ++j) {
                     if (!(act & (1u << j)))
                         continue;
                     int i = OPP[j];
-                    double e;
+                    double e, ep;
                     if (P->sputter == ORC_UNIFORM) {
                         e = (1.0 - P->p_stick) * in / b;
+                        ep = (a_r * in + a_p * in_p) / b;
                     } else if (P->sputter == ORC_WEIGHTED) {
                         e = (1.0 - P->p_stick) * in * WT[i] / wsum;
+                        ep = (a_r * in + a_p * in_p) * WT[i] / wsum;
                     } else {
                         int sx, sy, sz;
                         source(o, x, y, z, j, xper, &sx, &sy, &sz);
-                        e = (1.0 - P->p_stick) * o->pR[node(o, sx, sy, sz) * Q + j];
+                        long s = node(o, sx, sy, sz);
+                        e = (1.0 - P->p_stick) * o->pR[s * Q + j];
+                        ep = a_r * o->pR[s * Q + j] + (o->pP ? a_p * o->pP[s * Q + j] : 0.0);
                     }
                     o->em[k * Q + i] = e;
+                    if (o->emP)
+                        o->emP[k * Q + i] = ep;
                 }
             }
+    *arrived_p = kval(&total_p);
     return kval(&total);
 }
 
-/* Step 6: pull streaming of both lattices. */
+/* Pull of one species lattice into gas node (x, y, z): post-collision
+ * populations pst, catalytic emission em, inlet ghost values ghost[i]. */
+static void pull_species(orc *o, int x, int y, int z, const double *pst, const double *em,
+                         const double *ghost, double *f)
+{
+    int res = o->prm.species_x != ORC_XPERIODIC;
+    long n = node(o, x, y, z);
+    for (int i = 0; i < Q; ++i) {
+        int sx, sy, sz;
+        long s;
+        source(o, x, y, z, i, !res, &sx, &sy, &sz);
+        double v;
+        if (sx < 0) {
+            v = ghost[i];                                    /* inlet ghost */
+        } else if (sx >= o->nx) {
+            long m = node(o, o->nx - 1, sy, sz);             /* outlet ghost */
+            v = o->vox[m] == ORC_FLUID ? pst[m * Q + i] : pst[n * Q + OPP[i]];
+        } else {
+            s = node(o, sx, sy, sz);
+            if (o->vox[s] == ORC_FLUID)
+                v = pst[s * Q + i];
+            else if (o->vox[s] == ORC_INERT)
+                v = pst[n * Q + OPP[i]];
+            else
+                v = em[s * Q + i];
+        }
+        f[n * Q + i] = v;
+    }
+}
+
+/* Step 6: pull streaming of every lattice. */
 static void stream(orc *o)
 {
     const orc_params *P = &o->prm;
-    int res = P->species_x != ORC_XPERIODIC;
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < o->nz; ++z) {
         for (int y = 0; y < o->ny; ++y) {
@@ -453,39 +540,27 @@ static void stream(orc *o)
                         u[d] = (j[d] + 0.5 * P->force[d]) / rho;
                     orc_equilibrium(P->c_inlet, u, ghost);
                 }
-                for (int i = 0; i < Q; ++i) {
-                    int sx, sy, sz;
-                    long s;
-                    /* reactant */
-                    source(o, x, y, z, i, !res, &sx, &sy, &sz);
-                    double v;
-                    if (sx < 0) {
-                        v = ghost[i];                                    /* inlet ghost */
-                    } else if (sx >= o->nx) {
-                        long m = node(o, o->nx - 1, sy, sz);             /* outlet ghost */
-                        v = o->vox[m] == ORC_FLUID ? o->pR[m * Q + i] : o->pR[n * Q + OPP[i]];
-                    } else {
-                        s = node(o, sx, sy, sz);
-                        if (o->vox[s] == ORC_FLUID)
-                            v = o->pR[s * Q + i];
-                        else if (o->vox[s] == ORC_INERT)
-                            v = o->pR[n * Q + OPP[i]];
-                        else
-                            v = o->em[s * Q + i];
-                    }
-                    o->fR[n * Q + i] = v;
+                pull_species(o, x, y, z, o->pR, o->em, ghost, o->fR);
+                if (o->fP) {
+                    double none[Q] = {0.0};                              /* no product is injected */
+                    pull_species(o, x, y, z, o->pP, o->emP, none, o->fP);
                 }
             }
         }
     }
 }
 
-/* Species crossing the x-boundaries during the streaming just done. */
-static void boundary_flux(orc *o, double *in_flux, double *out_flux)
+/* A species crossing the x-boundaries during the streaming just done: in_flux
+ * pulled from the inlet ghost; out_in left through the inlet face; out_out
+ * sent to the outlet ghost net of what it returned.  f / pst: pre- and
+ * post-collision populations of that species. */
+static void boundary_flux(orc *o, const double *f, const double *pst, double *in_flux, double *out_in,
+                          double *out_out)
 {
-    ksum fin = {0.0, 0.0}, fout = {0.0, 0.0};
+    ksum fin = {0.0, 0.0}, foi = {0.0, 0.0}, foo = {0.0, 0.0};
     *in_flux = 0.0;
-    *out_flux = 0.0;
+    *out_in = 0.0;
+    *out_out = 0.0;
     if (o->prm.species_x == ORC_XPERIODIC)
         return;
     for (int z = 0; z < o->nz; ++z)
@@ -494,21 +569,22 @@ static void boundary_flux(orc *o, double *in_flux, double *out_flux)
             if (o->vox[n0] == ORC_FLUID)
                 for (int i = 1; i < Q; ++i) {
                     if (CX[i] == 1)
-                        kadd(&fin, o->fR[n0 * Q + i]);             /* pulled from the inlet ghost */
+                        kadd(&fin, f[n0 * Q + i]);                 /* pulled from the inlet ghost */
                     if (CX[i] == -1)
-                        kadd(&fout, o->pR[n0 * Q + i]);           /* left through the inlet */
+                        kadd(&foi, pst[n0 * Q + i]);              /* left through the inlet */
                 }
             long n1 = node(o, o->nx - 1, y, z);
             if (o->vox[n1] == ORC_FLUID)
                 for (int i = 1; i < Q; ++i) {
                     if (CX[i] == 1)
-                        kadd(&fout, o->pR[n1 * Q + i]);           /* sent to the outlet ghost */
+                        kadd(&foo, pst[n1 * Q + i]);              /* sent to the outlet ghost */
                     if (CX[i] == -1)
-                        kadd(&fout, -o->fR[n1 * Q + i]);          /* came back from it */
+                        kadd(&foo, -f[n1 * Q + i]);               /* came back from it */
                 }
         }
     *in_flux = kval(&fin);
-    *out_flux = kval(&fout);
+    *out_in = kval(&foi);
+    *out_out = kval(&foo);
 }
 
 void orc_step(orc *o, long nsteps)
@@ -516,15 +592,23 @@ void orc_step(orc *o, long nsteps)
     const orc_params *P = &o->prm;
     for (long t = 0; t < nsteps; ++t) {
         collide(o);
-        double arrived = interface(o);
+        double arrived_p;
+        double arrived = interface(o, &arrived_p);
         stream(o);
-        double fin, fout;
-        boundary_flux(o, &fin, &fout);
+        double fin, foi, foo;
+        boundary_flux(o, o->fR, o->pR, &fin, &foi, &foo);
         totals_mass(o);
         o->tot[2] += P->p * P->p_stick * arrived;
         o->tot[3] += (1.0 - P->p) * P->p_stick * arrived;
         o->tot[4] += fin;
-        o->tot[5] += fout;
+        o->tot[5] += foi + foo;
+        if (o->fP) {
+            double pin;
+            boundary_flux(o, o->fP, o->pP, &pin, &foi, &foo);
+            o->totp[1] += P->p_stick_product * arrived_p;
+            o->totp[2] += foi;
+            o->totp[3] += foo;
+        }
         o->step += 1;
     }
 }
@@ -538,12 +622,15 @@ void orc_fields(const orc *o, double *rho, double *u, double *conc)
     const orc_params *P = &o->prm;
     for (long n = 0; n < o->n; ++n) {
         double rc = 0.0, jc[3] = {0, 0, 0}, rr = 0.0, jr[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+        double rp = 0.0, jp[3] = {0, 0, 0};
         if (o->vox[n] == ORC_FLUID) {
             moments(o->fC + n * Q, &rc, jc);
             moments(o->fR + n * Q, &rr, jr);
+            if (o->fP)
+                moments(o->fP + n * Q, &rp, jp);
             for (int a = 0; a < 3; ++a) {
                 if (P->coupling == ORC_BARYCENTRIC)
-                    v[a] = (jc[a] + jr[a] + 0.5 * P->force[a]) / (rc + rr);
+                    v[a] = (jc[a] + jr[a] + jp[a] + 0.5 * P->force[a]) / (rc + rr + rp);
                 else
                     v[a] = (jc[a] + 0.5 * P->force[a]) / rc;
             }
@@ -569,6 +656,56 @@ void orc_totals(const orc *o, double *t)
         t[k] = o->tot[k];
 }
 
+/* Product diagnostics (zeros without the product lattice): conc[node] =
+ * rho_P of the pre-collision populations (solid 0); tot = {mass_product,
+ * lost_product, product out through the inlet face, product out through the
+ * outlet face}; conv_p[node] = p_S^P sum_t In_P(k, t), the product that stuck
+ * at catalytic node k. */
+void orc_product(const orc *o, double *conc, double *tot, double *stuck)
+{
+    for (long n = 0; n < o->n; ++n) {
+        double r = 0.0;
+        if (o->fP && o->vox[n] == ORC_FLUID)
+            for (int i = 0; i < Q; ++i)
+                r += o->fP[n * Q + i];
+        if (conc) conc[n] = r;
+        if (stuck)
+            stuck[n] = o->accP && o->vox[n] == ORC_CATALYTIC ? o->prm.p_stick_product * o->accP[n] : 0.0;
+    }
+    if (tot)
+        for (int k = 0; k < 4; ++k)
+            tot[k] = o->fP ? o->totp[k] : 0.0;
+}
+
+/* Product flux profile along the flow (Eq. for Phi_P, with x the streamwise
+ * axis here): phi[x] = sum over the (y, z) cross-section of rho_P u_x, the
+ * moments of the pre-collision populations, u the species advection
+ * velocity. */
+void orc_product_flux(const orc *o, double *phi)
+{
+    const orc_params *P = &o->prm;
+    for (int x = 0; x < o->nx; ++x) {
+        ksum s = {0.0, 0.0};
+        if (o->fP)
+            for (int z = 0; z < o->nz; ++z)
+                for (int y = 0; y < o->ny; ++y) {
+                    long n = node(o, x, y, z);
+                    if (o->vox[n] != ORC_FLUID)
+                        continue;
+                    double rc, jc[3], rr, jr[3], rp, jp[3], ux;
+                    moments(o->fC + n * Q, &rc, jc);
+                    moments(o->fR + n * Q, &rr, jr);
+                    moments(o->fP + n * Q, &rp, jp);
+                    if (P->coupling == ORC_BARYCENTRIC)
+                        ux = (jc[0] + jr[0] + jp[0] + 0.5 * P->force[0]) / (rc + rr + rp);
+                    else
+                        ux = (jc[0] + 0.5 * P->force[0]) / rc;
+                    kadd(&s, rp * ux);
+                }
+        phi[x] = kval(&s);
+    }
+}
+
 long orc_step_count(const orc *o)
 {
     return o->step;
@@ -585,6 +722,18 @@ void orc_set_state(orc *o, const double *fC, const double *fR)
 {
     if (fC) memcpy(o->fC, fC, sizeof(double) * o->n * Q);
     if (fR) memcpy(o->fR, fR, sizeof(double) * o->n * Q);
+    totals_mass(o);
+}
+
+/* The same for the product lattice (no-ops without it). */
+void orc_get_state_product(const orc *o, double *fP)
+{
+    if (fP && o->fP) memcpy(fP, o->fP, sizeof(double) * o->n * Q);
+}
+
+void orc_set_state_product(orc *o, const double *fP)
+{
+    if (fP && o->fP) memcpy(o->fP, fP, sizeof(double) * o->n * Q);
     totals_mass(o);
 }
 
