@@ -107,7 +107,17 @@ typedef struct {
                                  the concentration is depleted) */
     double force[3];          /* body-force density on the carrier (Guo
                                  forcing, half-force velocity shift) */
-    uint64_t reserved;        /* must be 0 */
+    int32_t product;          /* 1: also evolve the product lattice P (second
+                                 line of the sputtering equations); 0: carrier
+                                 and reactant only.  P starts at 0, no product
+                                 enters at the inlet, it relaxes with
+                                 tau_species and is advected by the carrier.
+                                 Needs PASSIVE coupling and the node-compact
+                                 sweep (ny, nz <= 1024), LBM_EUNSUPPORTED
+                                 otherwise; not available in batches */
+    int32_t reserved;         /* must be 0 */
+    double p_stick_product;   /* product sticking probability p_S^P in [0, 1]
+                                 (the paper uses 0); ignored without product */
 } lbm_bc;
 
 /* Optional device hooks.  stream: a hipStream_t all work is queued on
@@ -132,6 +142,15 @@ typedef struct {
                                  x = nx, net of what the outlet ghost returned */
     int32_t nonfinite;        /* 1 once any total was NaN or Inf */
     int32_t reserved;
+    /* product lattice (0 without it) */
+    double mass_product;      /* sum of rho_P over gas nodes at this step */
+    double lost_product;      /* cumulative p_S^P sum_t sum_k In_P(k, t): product
+                                 that stuck at the catalyst */
+    double product_out_inlet; /* cumulative product leaving through x = -1 */
+    double product_out_outlet;/* cumulative product leaving through x = nx, net
+                                 of what the outlet ghost returned; over a
+                                 window, its increase over that of influx is
+                                 the conversion efficiency of Eq. (eff) */
 } lbm_totals_t;
 
 typedef struct {
@@ -238,6 +257,22 @@ lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc);
  * of n_nodes doubles.  Synchronises the stream.
  */
 lbm_status lbm_conversion_map(lbm_ctx *c, double *conv);
+
+/*
+ * lbm_product_fields - product-lattice outputs at the current step (contexts
+ * created with bc.product = 1; LBM_EUNSUPPORTED otherwise).  Host arrays, any
+ * may be NULL:
+ *   conc  n_nodes doubles, rho_P of the pre-collision populations ([z][y][x],
+ *         solid 0);
+ *   stuck n_nodes doubles, p_S^P sum_t In_P(k, t): product that stuck at
+ *         catalytic node k (0 elsewhere);
+ *   phi   nx doubles, the product flux profile Phi_P along the flow
+ *         ("Results & Discussion"): phi[x] = sum over the (y, z)
+ *         cross-section of rho_P u_x, u the carrier velocity (j_C + F/2) /
+ *         rho_C.
+ * Synchronises the stream; allocates temporary device memory for phi.
+ */
+lbm_status lbm_product_fields(lbm_ctx *c, double *conc, double *stuck, double *phi);
 
 /*
  * lbm_populations - the pre-collision populations f_i of both lattices at the

@@ -25,7 +25,7 @@ thread_local std::string g_create_error;
 
 constexpr double CS = 0.57735026918962576451;  // lattice sound speed 1/sqrt(3)
 constexpr int TIMING_RING = 512;
-constexpr uint64_t CKPT_MAGIC = 0x3347504b434d424cull;  // "LBMCKPG3"
+constexpr uint64_t CKPT_MAGIC = 0x3447504b434d424cull;  // "LBMCKPG4"
 
 struct StepEvents {
     hipEvent_t ev[8];  // start/stop of the front launch, xflux, sweep, closing reduction
@@ -82,6 +82,15 @@ struct lbm_ctx {
     bool compact_ok = false;
     int compact = 0;
 
+    // product lattice (ph.product): populations (same parity as d_pop), E_P,
+    // In_P, Acc_P and partial sums (3 per sweep block, then 2 x interface)
+    void *d_popP[2] = {nullptr, nullptr};
+    void *d_emitP = nullptr;
+    unsigned long long *d_inaccP = nullptr;
+    double *d_accP = nullptr;
+    double *d_partP = nullptr;
+    int64_t rows_partP = 0;   // sweep-partial rows reserved in d_partP
+
     // watchdog
     int32_t *h_flag = nullptr;
     hipEvent_t flag_event = nullptr;
@@ -95,6 +104,10 @@ struct lbm_ctx {
 };
 
 namespace {
+
+// Temporary device memory through the context's allocator (defined below).
+void *scratch_alloc(lbm_ctx *c, size_t bytes);
+void scratch_free(lbm_ctx *c, void *p);
 
 lbm_status fail(lbm_ctx *c, lbm_status s, const std::string &msg) {
     if (c)
@@ -318,6 +331,23 @@ double *part_iface(const lbm_ctx *c, int64_t t) { return c->d_part + 4 * c->bloc
 double *part_fold(const lbm_ctx *c, int64_t t) {
     return c->d_part + 4 * c->blocks_sweep + 2 * c->blocks_iface + (t & 1) * int64_t(FOLD_BLOCKS) * NPART;
 }
+double *part_iface_p(const lbm_ctx *c, int64_t t) {
+    return c->d_partP + 3 * c->rows_partP + (t & 1) * c->blocks_iface;
+}
+
+// The product lattice's buffers for step t (reading d_popP[cur]).
+ProdStep prod_step(const lbm_ctx *c, int64_t t) {
+    ProdStep p{};
+    p.fin = c->d_popP[c->cur];
+    p.fout = c->d_popP[1 - c->cur];
+    p.emit = c->d_emitP;
+    p.inacc = c->d_inaccP;
+    p.acc = c->d_accP;
+    p.part_sweep = c->d_partP;
+    p.pi_now = part_iface_p(c, t);
+    p.pi_prev = part_iface_p(c, t - 1);
+    return p;
+}
 
 // One step t = c->step: the front launch (interface of t, and the reduction
 // stages of t - 1 and t - 2 when those steps belong to the same lbm_step
@@ -338,27 +368,32 @@ lbm_status one_step(lbm_ctx *c, bool fold, bool reduce, bool last) {
         if (c->timing == 1) all = r;
     }
     hipError_t e;
+    ProdStep pst = c->ph.product ? prod_step(c, t) : ProdStep{};
+    const ProdStep *prod = c->ph.product ? &pst : nullptr;
     if (all) (void)hipEventRecord(r->ev[0], c->stream);
     e = launch_front(c->ph, interface_list(c), c->d_emit, c->blocks_iface, part_iface(c, t), ps, ns,
                      part_iface(c, t - 1), ni, part_fold(c, t - 1), fold, part_fold(c, t - 2), reduce, c->d_tot,
-                     c->stream);
+                     c->stream, prod);
     if (e != hipSuccess) return hip_fail(c, e, "interface kernel launch");
     if (all) (void)hipEventRecord(r->ev[1], c->stream);
     if (all) (void)hipEventRecord(r->ev[2], c->stream);  // no separate boundary-flux kernel:
     if (all) (void)hipEventRecord(r->ev[3], c->stream);  // the sweep tallies the x-planes
     if (r) (void)hipEventRecord(r->ev[4], c->stream);
-    e = c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, ps, c->stream)
+    e = c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, ps, c->stream, prod)
                    : launch_sweep(g, c->ph, fin, fout, c->d_emit, ps, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "sweep kernel launch");
     if (r) (void)hipEventRecord(r->ev[5], c->stream);
     if (all) (void)hipEventRecord(r->ev[6], c->stream);
     if (last) {
         // fold of t (with the final stage of t - 1 when pending), then the final stage of t
+        // (the product partials of step t: the interface ones were written
+        // by this step's front launch, as pi_now)
+        if (prod) pst.pi_prev = pst.pi_now;
         e = launch_front(c->ph, interface_list(c), c->d_emit, 0, nullptr, ps, ns, part_iface(c, t), ni,
-                         part_fold(c, t), true, part_fold(c, t - 1), fold, c->d_tot, c->stream);
+                         part_fold(c, t), true, part_fold(c, t - 1), fold, c->d_tot, c->stream, prod);
         if (e == hipSuccess)
             e = launch_front(c->ph, interface_list(c), c->d_emit, 0, nullptr, ps, ns, nullptr, ni, nullptr, false,
-                             part_fold(c, t), true, c->d_tot, c->stream);
+                             part_fold(c, t), true, c->d_tot, c->stream, prod);
         if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
     }
     if (r) {
@@ -384,6 +419,11 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
     if (int64_t(g->nx) * g->ny * g->nz >= (int64_t(1) << 32))
         return fail(nullptr, LBM_EINVAL, "lattice has 2^32 nodes or more");
     if (g->reserved0 != 0 || bc->reserved != 0) return fail(nullptr, LBM_EINVAL, "reserved fields must be 0");
+    if (bc->product != 0 && bc->product != 1) return fail(nullptr, LBM_EINVAL, "product must be 0 or 1");
+    if (bc->product && !(bc->p_stick_product >= 0.0 && bc->p_stick_product <= 1.0))
+        return fail(nullptr, LBM_EINVAL, "p_stick_product must be in [0, 1]");
+    if (bc->product && bc->coupling != LBM_COUPLE_PASSIVE)
+        return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice needs PASSIVE coupling");
     if (!(g->pore_size > 0) || !std::isfinite(g->pore_size))
         return fail(nullptr, LBM_EINVAL, "pore_size must be finite and > 0");
     if (bc->sputter < 0 || bc->sputter > 2) return fail(nullptr, LBM_EUNSUPPORTED, "unknown sputter mode");
@@ -501,6 +541,13 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
                         r256((4 * blocks + 2 * ((niface + 255) / 256) + 2 * FOLD_BLOCKS * NPART) * 8) +
                         r256(int64_t(sizeof(DevTotals)));
         if (compact) bytes += r256(nfp * 4) + r256((c.nfluid + 63) / 64 * 4);
+        if (bc->product) {
+            // P buffers and E_P, In_P and Acc_P, P partial sums
+            const int64_t blocks_c = ((c.nfluid + 63) / 64 + 3) / 4;
+            const int64_t rows_p = std::max(blocks, (blocks_c + 7) / 8 * 8);
+            bytes += r256((38 * nfp + niface) * sb) + 2 * r256(niface * 8) +
+                     r256((3 * rows_p + 2 * ((niface + 255) / 256)) * 8);
+        }
         info->device_bytes = bytes;
     } catch (const std::bad_alloc &) {
         return fail(nullptr, LBM_ENOMEM, "host allocation failed");
@@ -569,6 +616,8 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.coupling = bc->coupling;
     c->ph.species_x = bc->species_x;
     c->ph.storage = bc->storage;
+    c->ph.product = bc->product;
+    c->ph.p_stick_product = bc->product ? bc->p_stick_product : 0.0;
 
     try {
         c->vox.assign(g->voxels, g->voxels + c->n);
@@ -604,6 +653,11 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
                             pos[r++] = uint32_t(x) | (uint32_t(y) << 12) | (uint32_t(z) << 22);
             build_wave_order(c, pos, std::min(c->ytile, c->ny), worder);
             c->compact = 1;
+        }
+        if (c->ph.product && !c->compact_ok) {
+            release(c);
+            delete c;
+            return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice needs the node-compact sweep (ny, nz <= 1024)");
         }
 
         // The kernels address every buffer with 32-bit byte offsets from a
@@ -649,8 +703,23 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         const int64_t nparts = 4 * c->blocks_sweep + 2 * c->blocks_iface + 2 * FOLD_BLOCKS * NPART;
         c->d_part = static_cast<double *>(dev_alloc(c, size_t(nparts) * 8));
         c->d_tot = static_cast<DevTotals *>(dev_alloc(c, sizeof(DevTotals)));
+        bool prod_ok = true;
+        if (c->ph.product) {
+            // P buffers A and B, then E_P (one element per interface node)
+            char *pp = static_cast<char *>(dev_alloc(c, (size_t(38) * c->nfp + size_t(c->niface)) * sb));
+            if (pp) {
+                c->d_popP[0] = pp;
+                c->d_popP[1] = pp + size_t(19) * c->nfp * sb;
+                c->d_emitP = pp + size_t(38) * c->nfp * sb;
+            }
+            c->d_inaccP = static_cast<unsigned long long *>(dev_alloc(c, size_t(c->niface) * 8));
+            c->d_accP = static_cast<double *>(dev_alloc(c, size_t(c->niface) * 8));
+            c->rows_partP = std::max(c->blocks_sweep, sweep_blocks_c(gtmp));
+            c->d_partP = static_cast<double *>(dev_alloc(c, size_t(3 * c->rows_partP + 2 * c->blocks_iface) * 8));
+            prod_ok = pp && c->d_inaccP && c->d_accP && c->d_partP;
+        }
         if (!c->d_chunks || !c->d_order || !c->d_inacc || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
-            !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot ||
+            !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot || !prod_ok ||
             (c->compact_ok && (!c->d_pos || !c->d_worder))) {
             release(c);
             delete c;
@@ -678,6 +747,15 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         up(c->d_tot, &t0, sizeof(t0));
         if (e == hipSuccess) e = launch_init(geometry(c), c->ph, c->d_pop[1], c->d_pop[0], c->stream);
         if (e == hipSuccess) e = launch_in_init(geometry(c), c->ph, interface_list(c), c->d_pop[0], c->stream);
+        if (c->ph.product) {
+            // no product anywhere at the start: both P buffers, E_P and Acc_P are 0
+            if (e == hipSuccess)
+                e = hipMemsetAsync(c->d_popP[0], 0, (size_t(38) * c->nfp + size_t(c->niface)) * sb, c->stream);
+            if (e == hipSuccess && c->niface) e = hipMemsetAsync(c->d_accP, 0, size_t(c->niface) * 8, c->stream);
+            if (e == hipSuccess)
+                e = launch_in_init_product(geometry(c), c->ph, interface_list(c), c->d_popP[0], c->d_inaccP,
+                                           c->stream);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host vectors go out of scope
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->h_flag), sizeof(int32_t));
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->flag_event, hipEventDisableTiming);
@@ -812,6 +890,49 @@ lbm_status lbm_conversion_map(lbm_ctx *c, double *conv) {
     return LBM_OK;
 }
 
+lbm_status lbm_product_fields(lbm_ctx *c, double *conc, double *stuck, double *phi) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (!c->ph.product) return fail(c, LBM_EUNSUPPORTED, "this context has no product lattice");
+    hipError_t e = hipSuccess;
+    if (stuck) {
+        std::vector<double> acc(size_t(c->niface));
+        if (c->niface) e = hipMemcpyAsync(acc.data(), c->d_accP, acc.size() * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "product map copy");
+        std::memset(stuck, 0, size_t(c->n) * sizeof(double));
+        for (size_t k = 0; k < acc.size(); ++k) stuck[c->iface_vox[k]] = c->ph.p_stick_product * acc[k];
+    }
+    if (!conc && !phi) return LBM_OK;
+    // device temporaries: rho_P, and for phi the carrier velocity
+    const size_t n = size_t(c->n);
+    double *d_c = static_cast<double *>(scratch_alloc(c, n * 8));
+    double *d_u = phi ? static_cast<double *>(scratch_alloc(c, 3 * n * 8)) : nullptr;
+    double *d_phi = phi ? static_cast<double *>(scratch_alloc(c, size_t(c->nx) * 8)) : nullptr;
+    if (!d_c || (phi && (!d_u || !d_phi))) {
+        scratch_free(c, d_c);
+        scratch_free(c, d_u);
+        scratch_free(c, d_phi);
+        return fail(c, LBM_ENOMEM, "product field scratch allocation failed");
+    }
+    const int mode = c->step == 0 ? 2 : 1;
+    const Geometry g = geometry(c);
+    // the buffers the last sweep pulled from (at step 0 the stored initial
+    // state), as for lbm_fields
+    const void *fin = c->d_pop[1 - c->cur];
+    const void *finp = c->d_popP[1 - c->cur];
+    e = launch_product_field(g, c->ph, fin, finp, c->d_emitP, mode, d_c, c->stream);
+    if (e == hipSuccess && phi) e = launch_fields(g, c->ph, fin, c->d_emit, mode, nullptr, d_u, nullptr, true, c->stream);
+    if (e == hipSuccess && phi) e = launch_flux_profile(g, d_c, d_u, d_phi, c->stream);
+    if (e == hipSuccess && conc) e = hipMemcpyAsync(conc, d_c, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && phi) e = hipMemcpyAsync(phi, d_phi, size_t(c->nx) * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    scratch_free(c, d_c);
+    scratch_free(c, d_u);
+    scratch_free(c, d_phi);
+    if (e != hipSuccess) return hip_fail(c, e, "product fields");
+    return LBM_OK;
+}
+
 lbm_status lbm_totals(lbm_ctx *c, lbm_totals_t *t) {
     if (!c || !t) return fail(c, LBM_EINVAL, "NULL argument");
     DevTotals d;
@@ -827,6 +948,10 @@ lbm_status lbm_totals(lbm_ctx *c, lbm_totals_t *t) {
     t->outflux = d.outflux;
     t->nonfinite = d.nonfinite;
     t->reserved = 0;
+    t->mass_product = d.mass_product;
+    t->lost_product = d.lost_product;
+    t->product_out_inlet = d.product_out_inlet;
+    t->product_out_outlet = d.product_out_outlet;
     if (d.nonfinite) return fail(c, LBM_ENONFINITE, "a global total became non-finite");
     return LBM_OK;
 }
@@ -909,6 +1034,8 @@ lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value) {
         if (value != 0 && value != 1) return fail(c, LBM_EINVAL, "sweep variant must be 0 or 1");
         if (value == 1 && !c->compact_ok)
             return fail(c, LBM_EUNSUPPORTED, "the node-compact sweep needs ny, nz <= 1024 and a gas node");
+        if (value == 0 && c->ph.product)
+            return fail(c, LBM_EUNSUPPORTED, "the product lattice runs on the node-compact sweep only");
         c->compact = int(value);
         return LBM_OK;
     }
@@ -964,12 +1091,14 @@ struct CkptHeader {
     uint64_t magic;
     int64_t nx, ny, nz, storage, step, nfluid, niface, nfp, cur;
     uint64_t geom_hash;
-    double params[16];
+    double params[18];
     DevTotals tot;
 };
 
+constexpr int NPARAMS = 18;
+
 void pack_params(const lbm_ctx *c, double *p) {
-    std::memset(p, 0, 16 * sizeof(double));
+    std::memset(p, 0, NPARAMS * sizeof(double));
     p[0] = c->ph.tau_gas;
     p[1] = c->ph.tau_species;
     p[2] = c->ph.force[0];
@@ -985,6 +1114,15 @@ void pack_params(const lbm_ctx *c, double *p) {
     p[12] = c->ph.sputter;
     p[13] = c->ph.coupling;
     p[14] = c->ph.species_x;
+    p[15] = c->ph.product;
+    p[16] = c->ph.p_stick_product;
+}
+
+// Product-lattice bytes of a checkpoint: P buffers A and B, E_P, Acc_P.
+size_t ckpt_product_bytes(const lbm_ctx *c) {
+    if (!c->ph.product) return 0;
+    const size_t sb = size_t(storage_bytes(c->ph.storage));
+    return size_t(38) * c->nfp * sb + size_t(c->niface) * sb + size_t(c->niface) * 8;
 }
 }  // namespace
 
@@ -1006,9 +1144,10 @@ lbm_status lbm_save(lbm_ctx *c, const char *path) {
     hipError_t e = hipMemcpyAsync(&h.tot, c->d_tot, sizeof(DevTotals), hipMemcpyDeviceToHost, c->stream);
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
     const size_t emit = size_t(c->niface) * storage_bytes(c->ph.storage);
+    const size_t base = 2 * pop + emit + size_t(c->niface) * 8, pbytes = ckpt_product_bytes(c);
     std::vector<char> buf;
     try {
-        buf.resize(2 * pop + emit + size_t(c->niface) * 8);
+        buf.resize(base + pbytes);
     } catch (const std::bad_alloc &) {
         return fail(c, LBM_ENOMEM, "checkpoint buffer");
     }
@@ -1018,6 +1157,14 @@ lbm_status lbm_save(lbm_ctx *c, const char *path) {
     if (e == hipSuccess && c->niface)
         e = hipMemcpyAsync(buf.data() + 2 * pop + emit, c->d_acc, size_t(c->niface) * 8, hipMemcpyDeviceToHost,
                            c->stream);
+    if (e == hipSuccess && pbytes) {
+        // d_popP[0], d_popP[1] and E_P are one contiguous block
+        const size_t pe = pbytes - size_t(c->niface) * 8;
+        e = hipMemcpyAsync(buf.data() + base, c->d_popP[0], pe, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && c->niface)
+            e = hipMemcpyAsync(buf.data() + base + pe, c->d_accP, size_t(c->niface) * 8, hipMemcpyDeviceToHost,
+                               c->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
     FILE *f = std::fopen(path, "wb");
@@ -1036,7 +1183,7 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
         std::fclose(f);
         return fail(c, LBM_EINVAL, "not a checkpoint of this library");
     }
-    double params[16];
+    double params[NPARAMS];
     pack_params(c, params);
     if (h.nx != c->nx || h.ny != c->ny || h.nz != c->nz || h.storage != c->ph.storage || h.nfluid != c->nfluid ||
         h.niface != c->niface || h.nfp != c->nfp || h.geom_hash != c->geom_hash ||
@@ -1046,9 +1193,10 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
     }
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
     const size_t emit = size_t(c->niface) * storage_bytes(c->ph.storage);
+    const size_t base = 2 * pop + emit + size_t(c->niface) * 8, pbytes = ckpt_product_bytes(c);
     std::vector<char> buf;
     try {
-        buf.resize(2 * pop + emit + size_t(c->niface) * 8);
+        buf.resize(base + pbytes);
     } catch (const std::bad_alloc &) {
         std::fclose(f);
         return fail(c, LBM_ENOMEM, "checkpoint buffer");
@@ -1063,12 +1211,21 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
     if (e == hipSuccess && c->niface)
         e = hipMemcpyAsync(c->d_acc, buf.data() + 2 * pop + emit, size_t(c->niface) * 8, hipMemcpyHostToDevice,
                            c->stream);
+    if (e == hipSuccess && pbytes) {
+        const size_t pe = pbytes - size_t(c->niface) * 8;
+        e = hipMemcpyAsync(c->d_popP[0], buf.data() + base, pe, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && c->niface)
+            e = hipMemcpyAsync(c->d_accP, buf.data() + base + pe, size_t(c->niface) * 8, hipMemcpyHostToDevice,
+                               c->stream);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_tot, &h.tot, sizeof(DevTotals), hipMemcpyHostToDevice, c->stream);
     c->step = h.step;
     c->cur = int(h.cur);
     // In(k) of the pending interface is derived state: rebuild it from the
     // current post-collision populations (the same integer terms the sweep adds)
     if (e == hipSuccess) e = launch_in_init(geometry(c), c->ph, interface_list(c), c->d_pop[c->cur], c->stream);
+    if (e == hipSuccess && c->ph.product)
+        e = launch_in_init_product(geometry(c), c->ph, interface_list(c), c->d_popP[c->cur], c->d_inaccP, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "checkpoint upload");
     c->flag_pending = false;
@@ -1089,10 +1246,10 @@ struct Candidate {
     int compact, ytile;
 };
 
-std::vector<Candidate> tuning_candidates(bool compact_ok, int ny) {
+std::vector<Candidate> tuning_candidates(bool compact_ok, int ny, bool compact_only = false) {
     std::vector<Candidate> out;
     const int ytiles[] = {4, 8, 16, 32, 64, 128};
-    for (int v = 0; v <= (compact_ok ? 1 : 0); ++v) {
+    for (int v = compact_only ? 1 : 0; v <= (compact_ok ? 1 : 0); ++v) {
         int last = -1;
         for (int yt : ytiles) {
             const int t = std::min(yt, ny);
@@ -1105,7 +1262,8 @@ std::vector<Candidate> tuning_candidates(bool compact_ok, int ny) {
 }
 
 struct Saved {
-    void *pop = nullptr, *link = nullptr;  // saved population buffer and In(k) accumulators
+    void *pop = nullptr, *link = nullptr;    // saved population buffer and In(k) accumulators
+    void *popP = nullptr, *linkP = nullptr;  // the same of the product lattice
 };
 
 lbm_status save_written(lbm_ctx *c, Saved &sv, void *(*alloc)(lbm_ctx *, size_t)) {
@@ -1114,8 +1272,17 @@ lbm_status save_written(lbm_ctx *c, Saved &sv, void *(*alloc)(lbm_ctx *, size_t)
     sv.pop = alloc(c, pop);
     sv.link = alloc(c, std::max<size_t>(link, 256));
     if (!sv.pop || !sv.link) return fail(c, LBM_ENOMEM, "autotune scratch allocation failed");
+    if (c->ph.product) {
+        sv.popP = alloc(c, pop / 2);
+        sv.linkP = alloc(c, std::max<size_t>(link, 256));
+        if (!sv.popP || !sv.linkP) return fail(c, LBM_ENOMEM, "autotune scratch allocation failed");
+    }
     hipError_t e = hipMemcpyAsync(sv.pop, c->d_pop[1 - c->cur], pop, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess && link) e = hipMemcpyAsync(sv.link, c->d_inacc, link, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && c->ph.product)
+        e = hipMemcpyAsync(sv.popP, c->d_popP[1 - c->cur], pop / 2, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && c->ph.product && link)
+        e = hipMemcpyAsync(sv.linkP, c->d_inaccP, link, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "autotune save");
     return LBM_OK;
 }
@@ -1125,6 +1292,10 @@ lbm_status restore_written(lbm_ctx *c, Saved &sv) {
     const size_t link = size_t(c->niface) * 8;
     hipError_t e = hipMemcpyAsync(c->d_pop[1 - c->cur], sv.pop, pop, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess && link) e = hipMemcpyAsync(c->d_inacc, sv.link, link, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && sv.popP)
+        e = hipMemcpyAsync(c->d_popP[1 - c->cur], sv.popP, pop / 2, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && sv.linkP && link)
+        e = hipMemcpyAsync(c->d_inaccP, sv.linkP, link, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "autotune restore");
     return LBM_OK;
@@ -1185,7 +1356,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
     const Candidate keep{c->compact, c->ytile};
     Candidate best = keep;
     float best_t = 0.0f;
-    const std::vector<Candidate> cands = tuning_candidates(c->compact_ok, c->ny);
+    const std::vector<Candidate> cands = tuning_candidates(c->compact_ok, c->ny, c->ph.product != 0);
     std::vector<float> t_min(cands.size(), 0.0f);
     // two interleaved rounds; each candidate keeps its faster round
     for (int round = 0; round < 2 && st == LBM_OK; ++round) {
@@ -1198,8 +1369,10 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
             const void *fin = c->d_pop[c->cur];
             void *fout = c->d_pop[1 - c->cur];
             float ms = 0.0f;
+            ProdStep pst = c->ph.product ? prod_step(c, c->step) : ProdStep{};
+            const ProdStep *prod = c->ph.product ? &pst : nullptr;
             st = time_launches(c->stream, reps, [&]() {
-                return c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, c->d_part, c->stream)
+                return c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, c->d_part, c->stream, prod)
                                   : launch_sweep(g, c->ph, fin, fout, c->d_emit, c->d_part, c->stream);
             }, &ms, &c->err);
             if (st != LBM_OK) break;
@@ -1214,6 +1387,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
     lbm_status rs = sv.pop ? restore_written(c, sv) : LBM_OK;
     scratch_free(c, sv.pop);
     scratch_free(c, sv.link);
+    scratch_free(c, sv.popP);
+    scratch_free(c, sv.linkP);
     const Candidate use = st == LBM_OK ? best : keep;
     lbm_status ts = lbm_set_tunable(c, LBM_TUNE_YTILE, use.ytile);
     if (ts == LBM_OK) ts = lbm_set_tunable(c, LBM_TUNE_SWEEP, use.compact);
@@ -1415,6 +1590,9 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
     *out = nullptr;
     if (n < 1) return bfail(nullptr, LBM_EINVAL, "a batch needs n >= 1 samples");
     if (!g || !da || !tau || !bc) return bfail(nullptr, LBM_EINVAL, "g, da, tau and bc must not be NULL");
+    for (int32_t i = 0; i < n; ++i)
+        if (bc[i].product != 0)
+            return bfail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available in batches");
     for (int32_t i = 1; i < n; ++i)
         if (bc[i].storage != bc[0].storage || bc[i].sputter != bc[0].sputter || bc[i].coupling != bc[0].coupling ||
             bc[i].species_x != bc[0].species_x)

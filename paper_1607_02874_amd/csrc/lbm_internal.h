@@ -49,12 +49,19 @@ enum { XB_PERIODIC = 0, XB_RESERVOIR = 1, XB_INFLOW = 2 };
 
 // Slots of the per-step partial sums (FP64).  The sweep writes four per
 // block (carrier mass, reactant mass, influx, outflux), the interface kernel
-// one (arrivals In).
-enum { PART_MASS_C = 0, PART_MASS_R = 1, PART_IN = 2, PART_INFLUX = 3, PART_OUTFLUX = 4, NPART = 5 };
+// one (arrivals In).  With the product lattice the sweep adds three per
+// block (product mass, product leaving through the inlet face and through the
+// outlet face) and the interface kernel one (product arrivals In_P).
+enum {
+    PART_MASS_C = 0, PART_MASS_R = 1, PART_IN = 2, PART_INFLUX = 3, PART_OUTFLUX = 4,
+    PART_MASS_P = 5, PART_IN_P = 6, PART_POUT_IN = 7, PART_POUT_OUT = 8, NPART = 9
+};
+constexpr int NPART_BASE = 5;  // the slots without the product lattice
 
 // Device totals: step-cumulative FP64 values and the non-finite flag.
 struct DevTotals {
     double mass_gas, mass_species, converted, lost, influx, outflux;
+    double mass_product, lost_product, product_out_inlet, product_out_outlet;
     int64_t step;
     int32_t nonfinite;
     int32_t pad;
@@ -86,6 +93,21 @@ struct Physics {
     double p_stick, p;
     double in_scale, in_unscale;  // 2^S and 2^-S of the fixed-point In(k) sums
     int32_t sputter, coupling, species_x, storage;
+    double p_stick_product;       // p_S^P
+    int32_t product, pad;         // 1: the product lattice P is evolved
+};
+
+// Device buffers of the product lattice for one step (all null / unused when
+// the lattice is off).  P populations are stored unshifted (h_i = f_i / w_i),
+// 19 direction arrays of nfp elements in the slot order of the pair buffers.
+struct ProdStep {
+    const void *fin;             // P post-collision populations the sweep pulls from
+    void *fout;                  // and the buffer it writes
+    void *emit;                  // E_P(k) per interface node (not used by BOUNCEBACK)
+    unsigned long long *inacc;   // In_P(k), fixed point like In(k)
+    double *acc;                 // sum_t In_P(k, t)
+    double *part_sweep;          // 3 per sweep block
+    double *pi_now, *pi_prev;    // interface partials (1 per interface block) of steps t and t - 1
 };
 
 // Interface list (catalytic nodes with b(k) >= 1), sorted by voxel index.
@@ -115,11 +137,14 @@ hipError_t launch_init(const Geometry &g, const Physics &ph, void *pre, void *po
 // In(k) of every interface node from a post-collision population buffer (after
 // create and after a checkpoint load; during stepping the sweep accumulates it).
 hipError_t launch_in_init(const Geometry &g, const Physics &ph, const Interface &it, const void *fin, hipStream_t s);
+// In_P(k) from a P post-collision buffer into `inacc` (same terms, unshifted).
+hipError_t launch_in_init_product(const Geometry &g, const Physics &ph, const Interface &it, const void *finP,
+                                  unsigned long long *inacc, hipStream_t s);
 hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
                         double *part, hipStream_t s);
 // The node-compact sweep (same results; needs g.pos and g.worder).
 hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
-                          double *part, hipStream_t s);
+                          double *part, hipStream_t s, const ProdStep *prod = nullptr);
 int64_t sweep_blocks_c(const Geometry &g);
 // mode 1: moments after streaming fin (fields at step >= 1); mode 2: local
 // moments of fin (the initial state, step 0).  Outputs are float arrays, or
@@ -134,6 +159,14 @@ struct Window {
 // `win`, FP64, direction-major [19][wz][wy][wx] in the library's numbering.
 hipError_t launch_populations(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
                               const Window &win, double *fC, double *fR, hipStream_t s);
+// Product concentration rho_P of every voxel (double, solid 0), from the
+// moments after streaming `finP` (mode 1) or of `finP` itself (mode 2); the
+// pair buffer `fin` supplies the reactant of reversal re-emission.
+hipError_t launch_product_field(const Geometry &g, const Physics &ph, const void *fin, const void *finP,
+                                const void *emitP, int mode, double *concP, hipStream_t s);
+// phi[x] = sum over the (y, z) plane of concP * u_x (double fields, u
+// component-major), one block per x in a fixed order.
+hipError_t launch_flux_profile(const Geometry &g, const double *concP, const double *u, double *phi, hipStream_t s);
 // Two-stage fixed-order reduction of the per-block partials: FOLD_BLOCKS
 // blocks fold contiguous slices into `fold` (FOLD_BLOCKS * NPART doubles),
 // then one block sums those and updates the totals.
@@ -145,7 +178,8 @@ constexpr int FOLD_BLOCKS = 256;
 // (from fold_prev2 into tot).  Zero blocks: nothing is launched.
 hipError_t launch_front(const Physics &ph, const Interface &it, void *emit, int64_t iface_blocks, double *pi_now,
                         const double *ps, int64_t ns, const double *pi_prev, int64_t ni, double *fold_prev,
-                        bool fold, const double *fold_prev2, bool reduce, DevTotals *tot, hipStream_t s);
+                        bool fold, const double *fold_prev2, bool reduce, DevTotals *tot, hipStream_t s,
+                        const ProdStep *prod = nullptr);
 
 int64_t sweep_blocks(const Geometry &g);
 int64_t interface_blocks(int64_t n);

@@ -97,6 +97,7 @@ struct PhysK {
     T rref, cref;     // storage shifts
     T h_inlet;        // c_inlet - c_ref: normalised inlet ghost population
     T keep;           // 1 - p_stick
+    T a_r, a_p;       // product re-emission: p p_S^R of the reactant, 1 - p_S^P of the product
     T h0c, h0r;       // initial state, normalised: rho0 - rho_ref, c0 - c_ref
     double c_in;      // reservoir concentration (influx tally)
     double in_scale, in_unscale;  // fixed-point scale of the In(k) sums and its inverse
@@ -116,6 +117,8 @@ PhysK<T> to_kernel(const Physics &p) {
     k.cref = T(p.c_ref);
     k.h_inlet = T(p.c_inlet - p.c_ref);
     k.keep = T(1.0 - p.p_stick);
+    k.a_r = T(p.p * p.p_stick);
+    k.a_p = T(1.0 - p.p_stick_product);
     k.h0c = T(p.rho0 - p.rho_ref);
     k.h0r = T(p.c0 - p.c_ref);
     k.c_in = p.c_inlet;
@@ -284,8 +287,22 @@ struct OutSlots {
 };
 
 // Template code of a sweep: the sputter mode, plus this flag for INFLOW, so
-// the kernels of the other boundaries carry none of its code.
+// the kernels of the other boundaries carry none of its code, and this one
+// for the product lattice (node-compact sweep only).
 constexpr int SP_INFLOW_FLAG = 4;
+constexpr int SP_PRODUCT_FLAG = 8;
+
+// The product lattice as the sweep sees it: P population buffers (one
+// population per element, same slot order as the pair buffers), E_P(k),
+// In_P(k) and the sweep's three P partials per block.
+template <int ST>
+struct ProdK {
+    Slots in;
+    OutSlots out;
+    const typename Store<ST>::S *emit;
+    unsigned long long *inacc;
+    double *part;
+};
 
 // INFLOW species x-boundary: the inlet ghost populations pulled by a node at
 // x = 0 (directions with c_x = +1) are the equilibrium of c_in moving with the
@@ -467,11 +484,18 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
 // load is issued before any is waited on.  Vector loads retire in order, so a
 // record requested after population loads could not be waited on without
 // waiting for those too.
+//
+// With the product flag in SP the product lattice is pulled alongside, from
+// the same sources: no product at the inlet ghost, the outlet copy, and at a
+// catalytic source E_P(k) (or, for reversal, p p_S^R times the reactant plus
+// 1 - p_S^P times the product population that arrived along the reversed
+// link: second sputtering equation).
 template <int ST, int SP>
 __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
                                        const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
                                        int z, typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
-                                       uint32_t &cat_out, uint32_t *kidx) {
+                                       uint32_t &cat_out, uint32_t *kidx, const ProdK<ST> &pk,
+                                       typename Store<ST>::T (&hP)[19]) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     using P = typename Store<ST>::P;
@@ -562,7 +586,11 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     // nx - 1, loaded only by wavefronts that hold an outlet lane).
     P pc[19];
     S re[19], ro[19];
+    constexpr bool PROD = SP >= 0 && (SP & SP_PRODUCT_FLAG) != 0;
+    S pp[PROD ? 19 : 1], pe[PROD ? 19 : 1], po[PROD ? 19 : 1];
+    const uint32_t nfpp_b = uint32_t(nfp) * SB, ownp_b = idx * SB;  // product buffer: one population per element
     pc[0] = ld_pop<ST>(base(dslot(0)), own_b);
+    if constexpr (PROD) pp[0] = ld_at(static_cast<const S *>(pk.in.p(dslot(0))), ownp_b);
     const bool any_outlet = reservoir && __builtin_amdgcn_ballot_w64(last_x) != 0u;
 #pragma unroll
     for (int cls = 0; cls < 9; ++cls) {
@@ -591,6 +619,24 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
                 opaque(o_b);
                 ro[i] = ld_at(static_cast<const S *>(base(pair_slot(i))), o_b);
             }
+            if constexpr (PROD) {
+                const uint32_t halfp = dslot(i) < dslot(opp(i)) ? 0u : nfpp_b;
+                const uint32_t bbp_b = ownp_b + (nfpp_b - halfp);
+                const S *pbase = static_cast<const S *>(pk.in.p(pair_slot(i)));
+                uint32_t p_b = F ? rk[cls][bit] * SB + halfp : bbp_b;
+                opaque(p_b);
+                pp[i] = ld_at(pbase, p_b);
+                uint32_t e_b = bounce ? 0u : kidx[(i - 1) * 256 + threadIdx.x] * SB;
+                opaque(e_b);
+                pe[i] = ld_at(pk.emit, e_b);
+                po[i] = S(0);
+                if (cx == -1 && any_outlet) {
+                    const bool F0 = (wf >> 1) & 1u;
+                    uint32_t o_b = last_x && F0 ? rk[cls][1] * SB + halfp : bbp_b;
+                    opaque(o_b);
+                    po[i] = ld_at(pbase, o_b);
+                }
+            }
         }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -606,8 +652,17 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         if (CX[i] == -1) v = outlet ? Store<ST>::cv(ro[i]) : v;
         const T ev = Store<ST>::cv(re[i]);
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? ev * inv_wgt<T>(i) : ev) - ph.cref;
+        if constexpr (PROD) {
+            T q = Store<ST>::cv(pp[i]);
+            if (CX[i] == 1) q = inlet ? T(0) : q;
+            if (CX[i] == -1) q = outlet ? Store<ST>::cv(po[i]) : q;
+            const T epv = Store<ST>::cv(pe[i]);
+            const T q_cat = bounce ? ph.a_r * (v + ph.cref) + ph.a_p * q : (uniform ? epv * inv_wgt<T>(i) : epv);
+            hP[i] = ((cat_bits >> i) & 1u) ? q_cat : q;
+        }
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
+    if constexpr (PROD) hP[0] = Store<ST>::cv(pp[0]);
     if (inflow && __builtin_amdgcn_ballot_w64(first_x) != 0u && first_x) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
@@ -722,7 +777,8 @@ struct InOut {
 template <int ST>
 __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const uint32_t *kidx, uint32_t cat_bits,
                                               const PhysK<typename Store<ST>::T> &ph,
-                                              const typename Store<ST>::T (&hR)[19]) {
+                                              const typename Store<ST>::T (&hR)[19],
+                                              typename Store<ST>::T cref) {
     using T = typename Store<ST>::T;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
@@ -730,7 +786,7 @@ __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const u
             const int j = opp(i);  // the link direction as seen from the interface node
             const T stored = Store<ST>::cv(Store<ST>::enc(hR[j]));
             (void)__hip_atomic_fetch_add(&glb(inacc)[kidx[(i - 1) * 256 + threadIdx.x]],
-                                         in_term<T>(wgt<T>(j), stored, ph.cref, ph.in_scale), __ATOMIC_RELAXED,
+                                         in_term<T>(wgt<T>(j), stored, cref, ph.in_scale), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -753,6 +809,41 @@ __device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double
         if (CX[i] == -1 && first_x) fout += double(wgt<T>(i) * (own(i) + c_ref));
     }
     return InOut{fin, fout};
+}
+
+// Product leaving through the x-faces: out_in, its own post-collision
+// populations at x = 0 along c_x = -1; out_out, those at x = nx - 1 along
+// c_x = +1 (what the outlet ghost returned is subtracted by the caller).
+template <int ST>
+__device__ __noinline__ InOut product_tally(const char *pop, uint32_t stride, uint32_t idx, bool first_x,
+                                            bool last_x) {
+    using T = typename Store<ST>::T;
+    using S = typename Store<ST>::S;
+    auto own = [&](int i) { return Store<ST>::ld(reinterpret_cast<const S *>(pop + dslot(i) * stride) + idx); };
+    double oin = 0.0, oout = 0.0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        if (CX[i] == 1 && last_x) oout += double(wgt<T>(i) * own(i));
+        if (CX[i] == -1 && first_x) oin += double(wgt<T>(i) * own(i));
+    }
+    return InOut{oin, oout};
+}
+
+// BGK collision of the product lattice with the velocity of the carrier
+// (stored unshifted: h_eq = rho (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)).
+template <typename T>
+__device__ __forceinline__ void collide_product(const PhysK<T> &ph, const Mom<T> &m, T rp, T (&hP)[19]) {
+    const T uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+    const T base = rp - T(1.5) * rp * uu;
+    hP[0] = hP[0] - ph.om_r * (hP[0] - base);
+#pragma unroll
+    for (int i = 1; i <= 9; ++i) {
+        const int j = opp(i);
+        const T cu = T(CX[i]) * m.ux + T(CY[i]) * m.uy + T(CZ[i]) * m.uz;
+        const T t = base + rp * (T(4.5) * cu * cu), sl = rp * (T(3) * cu);
+        hP[i] = hP[i] - ph.om_r * (hP[i] - (t + sl));
+        hP[j] = hP[j] - ph.om_r * (hP[j] - (t - sl));
+    }
 }
 
 // One block of the fused sweep: logical block `block` of the sample described
@@ -801,7 +892,7 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
             st_at(static_cast<P *>(out.p(dslot(i))), own_b, pop_pair<ST>(hC[i], hR[i]));
         }
         // In(k) of the next step's interface: what leaves towards interface nodes
-        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR);
+        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, u.idx, first_x,
                                                last_x);
@@ -818,8 +909,10 @@ template <int ST, int SP>
 __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph,
                                               const Slots &in, const OutSlots &out,
                                               const typename Store<ST>::S *__restrict__ emit,
-                                              double *__restrict__ part, uint32_t block) {
+                                              double *__restrict__ part, uint32_t block, const ProdK<ST> &pk) {
     using T = typename Store<ST>::T;
+    constexpr bool PROD = (SP & SP_PRODUCT_FLAG) != 0;
+    double accp[3] = {0.0, 0.0, 0.0};  // product mass, out through the inlet face, out through the outlet face
     const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
     const uint32_t slot = block * 4u + wave;
     const bool wvalid = slot < g.nwaves;
@@ -831,9 +924,9 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
     if (active) {
         const uint32_t p = glb(g.pos)[idx];
         const int x = int(p & 0xfffu), y = int((p >> 12) & 0x3ffu), z = int(p >> 22);
-        T hC[19], hR[19];
+        T hC[19], hR[19], hP[19];  // hP: product lattice (unused without it)
         uint32_t cat_bits;
-        pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx);
+        pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx, pk, hP);
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
@@ -844,6 +937,17 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
 #pragma unroll
             for (int i = 1; i < 19; ++i)
                 if (CX[i] == -1) acc[3] -= double(wgt<T>(i) * (hR[i] + ph.cref));
+        }
+        T rp = T(0);
+        if constexpr (PROD) {
+            T dpx, dpy, dpz;
+            weighted_moments(hP, rp, dpx, dpy, dpz);
+            accp[0] = double(rp);
+            if (reservoir && last_x) {
+#pragma unroll
+                for (int i = 1; i < 19; ++i)
+                    if (CX[i] == -1) accp[2] -= double(wgt<T>(i) * hP[i]);
+            }
         }
         if (inflow && first_x) {  // what the moving inlet ghost supplied
 #pragma unroll
@@ -858,7 +962,23 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
             opaque(own_b);
             st_stream(static_cast<P *>(out.p(dslot(i))), own_b, pop_pair<ST>(hC[i], hR[i]));
         }
-        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR);
+        if constexpr (PROD) {
+            using S = typename Store<ST>::S;
+            collide_product(ph, m, rp, hP);
+            uint32_t ownp_b = idx * uint32_t(sizeof(S));
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                opaque(ownp_b);
+                st_stream(static_cast<S *>(pk.out.p(dslot(i))), ownp_b, Store<ST>::enc(hP[i]));
+            }
+            if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(pk.inacc, kidx, cat_bits, ph, hP, T(0));
+            if (reservoir && (first_x || last_x)) {
+                const InOut f = product_tally<ST>(pk.in.base, pk.in.stride, idx, first_x, last_x);
+                accp[1] += f.in;
+                accp[2] += f.out;
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, idx, first_x,
                                                last_x);
@@ -867,13 +987,14 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         }
     }
     block_sum<4>(acc, part + int64_t(block) * 4);
+    if constexpr (PROD) block_sum<3>(accp, pk.part + int64_t(block) * 3);
 }
 
 template <int ST, int SP>
-__global__ __launch_bounds__(256, ST == ST_F64 ? 1 : 5) void k_sweep_c(Geometry g, PhysK<typename Store<ST>::T> ph, Slots in,
-                                                  OutSlots out, const typename Store<ST>::S *__restrict__ emit,
-                                                  double *__restrict__ part) {
-    sweep_block_c<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
+__global__ __launch_bounds__(256, ST == ST_F64 ? 1 : ((SP & SP_PRODUCT_FLAG) ? 3 : 5)) void k_sweep_c(
+    Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
+    const typename Store<ST>::S *__restrict__ emit, double *__restrict__ part, ProdK<ST> pk) {
+    sweep_block_c<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))), pk);
 }
 
 template <int ST, int SP>
@@ -969,31 +1090,54 @@ __device__ __forceinline__ uint32_t rank_of(const Geometry &g, int row, int x, b
 // equations): In(k) = sum_j f*_j(k - c_j) over its active links was summed by
 // the sweep that produced those populations (fixed point, any order); here it
 // is read and cleared for the next sweep, added to Acc(k), and re-emitted as
-// E(k) = (1 - p_S) In(k) scale(k).
+// E(k) = (1 - p_S) In(k) scale(k).  With the product lattice (pi.inacc set)
+// In_P(k) is read and cleared the same way, added to Acc_P(k), and the
+// product re-emission E_P(k) = (p p_S^R In(k) + (1 - p_S^P) In_P(k)) scale(k)
+// is written (second sputtering equation).
+struct ProdI {
+    void *emit;
+    unsigned long long *inacc;
+    double *acc;
+    double *part;
+};
+
+// In(k) from the fixed-point sum of b terms (and clear it).
+__device__ __forceinline__ double take_in(unsigned long long *inacc, int64_t k, uint32_t b, double unscale) {
+    const unsigned long long raw = glb(inacc)[k] - uint64_t(b) * MAGIC_BITS;
+    glb(inacc)[k] = 0ull;
+    const long long fixed = static_cast<long long>(raw);
+    // a term outside the fixed-point range (|term| >= 2^51 / 2^S) cannot
+    // come from a bounded state; report it through the NaN watchdog
+    return (fixed > (1ll << 55) || fixed < -(1ll << 55)) ? __builtin_nan("") : double(fixed) * unscale;
+}
+
 template <int ST>
 __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::T> &ph, const Interface &it,
                                                 typename Store<ST>::S *__restrict__ emit, double *__restrict__ part,
-                                                uint32_t block) {
+                                                uint32_t block, const ProdI &pi) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     const int64_t k = int64_t(block) * blockDim.x + threadIdx.x;
-    double arrived[1] = {0.0};
+    double arrived[1] = {0.0}, arrived_p[1] = {0.0};
     if (k < it.n) {
         const uint32_t b = uint32_t(__popc(glb(it.mask)[k]));
-        const unsigned long long raw = glb(it.inacc)[k] - uint64_t(b) * MAGIC_BITS;
-        glb(it.inacc)[k] = 0ull;
-        const long long fixed = static_cast<long long>(raw);
-        // a term outside the fixed-point range (|term| >= 2^51 / 2^S) cannot
-        // come from a bounded state; report it through the NaN watchdog
-        const double in = (fixed > (1ll << 55) || fixed < -(1ll << 55)) ? __builtin_nan("")
-                                                                         : double(fixed) * ph.in_unscale;
+        const double in = take_in(it.inacc, k, b, ph.in_unscale);
         glb(it.acc)[k] += in;
+        const double scale = glb(it.scale)[k];
         if (ph.sputter != SP_BOUNCEBACK)
-            st_at(emit, uint32_t(k) * uint32_t(sizeof(S)),
-                  Store<ST>::enc(T(double(ph.keep) * in * glb(it.scale)[k])));
+            st_at(emit, uint32_t(k) * uint32_t(sizeof(S)), Store<ST>::enc(T(double(ph.keep) * in * scale)));
         arrived[0] = in;
+        if (pi.inacc) {
+            const double inp = take_in(pi.inacc, k, b, ph.in_unscale);
+            glb(pi.acc)[k] += inp;
+            if (ph.sputter != SP_BOUNCEBACK)
+                st_at(static_cast<S *>(pi.emit), uint32_t(k) * uint32_t(sizeof(S)),
+                      Store<ST>::enc(T((double(ph.a_r) * in + double(ph.a_p) * inp) * scale)));
+            arrived_p[0] = inp;
+        }
     }
     block_sum<1>(arrived, part + block);
+    if (pi.inacc) block_sum<1>(arrived_p, pi.part + block);
 }
 
 
@@ -1067,6 +1211,123 @@ __global__ __launch_bounds__(256) void k_in_init(Geometry g, PhysK<typename Stor
     it.inacc[k] = sum;
 }
 
+// In_P(k) of every interface node from a product post-collision buffer (one
+// unshifted population per element).
+template <int ST>
+__global__ __launch_bounds__(256) void k_in_init_p(Geometry g, PhysK<typename Store<ST>::T> ph, Interface it,
+                                                    const typename Store<ST>::S *__restrict__ finp,
+                                                    unsigned long long *__restrict__ inacc) {
+    using T = typename Store<ST>::T;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= it.n) return;
+    const uint32_t v = it.vox[k];
+    const uint32_t mask = it.mask[k];
+    const int x = int(v % uint32_t(g.nx));
+    const int row = int(v / uint32_t(g.nx));
+    const int y = row % g.ny, z = row / g.ny;
+    unsigned long long sum = 0ull;
+#pragma unroll
+    for (int j = 1; j < 19; ++j) {
+        if (mask & (1u << j)) {
+            int xs = x - CX[j], ys = y - CY[j], zs = z - CZ[j];
+            xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+            ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+            zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
+            bool fl;
+            const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
+            sum += in_term<T>(wgt<T>(j), Store<ST>::ld(finp + dslot(j) * g.nfp + r), T(0), ph.in_scale);
+        }
+    }
+    inacc[k] = sum;
+}
+
+// Product concentration of every voxel (one thread per voxel): the moments
+// of the product populations after streaming finp (LOCAL: of finp itself).
+// The pull is written node by node with the same sources as the sweep: y and
+// z periodic; x periodic or the reservoir planes (no product at the inlet,
+// the copy of plane nx - 1 at the outlet); gas sources; inert sources and a
+// solid outlet copy reflect; catalytic sources re-emit E_P(k), or for
+// reversal p p_S^R times the reactant plus 1 - p_S^P times the product
+// population of the reversed link.  Off the stepping path.
+template <int ST, bool LOCAL>
+__global__ __launch_bounds__(256) void k_product_field(Geometry g, PhysK<typename Store<ST>::T> ph,
+                                                        const typename Store<ST>::S *__restrict__ fin,
+                                                        const typename Store<ST>::S *__restrict__ finp,
+                                                        const typename Store<ST>::S *__restrict__ emitp,
+                                                        double *__restrict__ conc) {
+    using T = typename Store<ST>::T;
+    const int64_t n = int64_t(g.nx) * g.ny * g.nz;
+    const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int x = int(v % g.nx);
+    const int row = int(v / g.nx);
+    const int y = row % g.ny, z = row / g.ny;
+    bool gas;
+    const uint32_t me = rank_of(g, row, x, &gas);
+    if (!gas) {
+        conc[v] = 0.0;
+        return;
+    }
+    const bool xper = ph.species_x == XB_PERIODIC;
+    auto popp = [&](int i, uint32_t r) { return Store<ST>::ld(finp + dslot(i) * g.nfp + r); };
+    auto popr = [&](int i, uint32_t r) { return Store<ST>::ld(fin + 2 * (dslot(i) * g.nfp + r) + 1); };
+    double rho = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < 19; ++i) {
+        T h;
+        if (LOCAL || i == 0) {
+            h = popp(i, me);
+        } else {
+            int xs = x - CX[i], ys = y - CY[i], zs = z - CZ[i];
+            ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+            zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
+            if (xper) xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+            const int srow = zs * g.ny + ys;
+            if (xs < 0) {
+                h = T(0);  // inlet ghost: no product injected
+            } else if (xs >= g.nx) {
+                bool fl;
+                const uint32_t r = rank_of(g, srow, g.nx - 1, &fl);
+                h = fl ? popp(i, r) : popp(opp(i), me);
+            } else {
+                const ChunkInfo &I = g.chunks[int64_t(srow) * g.W + (xs >> 6)];
+                const int b = xs & 63;
+                const uint64_t below = b ? (~0ull >> (64 - b)) : 0ull;
+                if ((I.fluid >> b) & 1u) {
+                    h = popp(i, I.base + uint32_t(__popcll(I.fluid & below)));
+                } else if (!((I.cat >> b) & 1u)) {
+                    h = popp(opp(i), me);
+                } else if (ph.sputter == SP_BOUNCEBACK) {
+                    h = ph.a_r * (popr(opp(i), me) + ph.cref) + ph.a_p * popp(opp(i), me);
+                } else {
+                    const uint32_t k = I.ibase + uint32_t(__popcll(I.cat & below));
+                    const T e = Store<ST>::ld(emitp + k);
+                    h = ph.sputter == SP_UNIFORM ? e * inv_wgt<T>(i) : e;
+                }
+            }
+        }
+        rho += double(wgt<T>(i) * h);
+    }
+    conc[v] = rho;
+}
+
+// phi[x] = sum over the (y, z) plane of conc * u_x: block x, rows strided
+// over the threads, then a fixed tree.
+__global__ __launch_bounds__(256) void k_flux_profile(int nx, int64_t rows, const double *__restrict__ conc,
+                                                       const double *__restrict__ ux, double *__restrict__ phi) {
+    __shared__ double sh[256];
+    const int x = int(blockIdx.x);
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) s += conc[r * nx + x] * ux[r * nx + x];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) phi[x] = sh[0];
+}
+
 // Fixed-order sum over rows [r0, r1) of column `col` of a row-major
 // [n][ncol] partial array, by the whole block (thread-strided, then a tree).
 __device__ double column_sum(const double *p, int64_t r0, int64_t r1, int ncol, int col) {
@@ -1086,8 +1347,10 @@ __device__ double column_sum(const double *p, int64_t r0, int64_t r1, int ncol, 
 
 // First stage of the totals: block b folds its contiguous slice of rows of
 // each partial array into one row of `out` (fixed order, so deterministic).
+// psp / pip: the product partials (3 per sweep block, 1 per interface
+// block), or null without the product lattice (its slots stay 0).
 __device__ void fold_block(const double *ps, int64_t ns, const double *pi, int64_t ni, double *out, int64_t b,
-                           int64_t nb) {
+                           int64_t nb, const double *psp = nullptr, const double *pip = nullptr) {
     auto slice = [&](int64_t n, int64_t *r0, int64_t *r1) {
         const int64_t per = (n + nb - 1) / nb;
         *r0 = b * per < n ? b * per : n;
@@ -1100,17 +1363,35 @@ __device__ void fold_block(const double *ps, int64_t ns, const double *pi, int64
     v[PART_MASS_R] = column_sum(ps, r0, r1, 4, 1);
     v[PART_INFLUX] = column_sum(ps, r0, r1, 4, 2);
     v[PART_OUTFLUX] = column_sum(ps, r0, r1, 4, 3);
+    if (psp) {
+        v[PART_MASS_P] = column_sum(psp, r0, r1, 3, 0);
+        v[PART_POUT_IN] = column_sum(psp, r0, r1, 3, 1);
+        v[PART_POUT_OUT] = column_sum(psp, r0, r1, 3, 2);
+    } else {
+        v[PART_MASS_P] = v[PART_POUT_IN] = v[PART_POUT_OUT] = 0.0;
+    }
     slice(ni, &r0, &r1);
     v[PART_IN] = column_sum(pi, r0, r1, 1, 0);
+    v[PART_IN_P] = pip ? column_sum(pip, r0, r1, 1, 0) : 0.0;
     if (threadIdx.x == 0)
         for (int k = 0; k < NPART; ++k) out[b * NPART + k] = v[k];
 }
 
 
-__device__ void reduce_block(const double *folded, int64_t nb, double p, double p_stick, DevTotals *tot) {
+// `product`: also sum the product slots into the product totals (p_stick_p =
+// p_S^P); without it only the first NPART_BASE slots are read.
+__device__ void reduce_block(const double *folded, int64_t nb, double p, double p_stick, DevTotals *tot,
+                             bool product = false, double p_stick_p = 0.0) {
     double v[NPART];
-    for (int k = 0; k < NPART; ++k) v[k] = column_sum(folded, 0, nb, NPART, k);
+    const int nk = product ? NPART : NPART_BASE;
+    for (int k = 0; k < NPART; ++k) v[k] = k < nk ? column_sum(folded, 0, nb, NPART, k) : 0.0;
     if (threadIdx.x == 0) {
+        if (product) {
+            tot->mass_product = v[PART_MASS_P];
+            tot->lost_product += p_stick_p * v[PART_IN_P];
+            tot->product_out_inlet += v[PART_POUT_IN];
+            tot->product_out_outlet += v[PART_POUT_OUT];
+        }
         tot->mass_gas = v[PART_MASS_C];
         tot->mass_species = v[PART_MASS_R];
         tot->converted += p * p_stick * v[PART_IN];
@@ -1119,7 +1400,7 @@ __device__ void reduce_block(const double *folded, int64_t nb, double p, double 
         tot->outflux += v[PART_OUTFLUX];
         tot->step += 1;
         double all = 0.0;
-        for (int k = 0; k < NPART; ++k) all += v[k];
+        for (int k = 0; k < nk; ++k) all += v[k];
         if (!(all - all == 0.0)) tot->nonfinite = 1;
     }
 }
@@ -1131,19 +1412,30 @@ __device__ void reduce_block(const double *folded, int64_t nb, double p, double 
 // t - 2 (one last block, when `reduce`).  The parts touch disjoint buffers
 // (interface partials and fold outputs alternate with the step's parity), and
 // each runs exactly the code of its own kernel, so the totals are the same.
+// The product lattice's parts of a front launch (all null without it).
+struct ProdFront {
+    ProdI iface;             // interface of step t (iface.part: its partials)
+    const double *ps;        // sweep P partials of step t - 1
+    const double *pi_prev;   // interface P partials of step t - 1
+    double p_stick;          // p_S^P
+    int32_t on, pad;
+};
+
 template <int ST>
 __global__ __launch_bounds__(256) void k_front(PhysK<typename Store<ST>::T> ph, Interface it,
                                                 typename Store<ST>::S *__restrict__ emit, double *pi_now,
                                                 const double *ps, int64_t ns, const double *pi_prev, int64_t ni,
                                                 double *fold_prev, const double *fold_prev2, double p, double p_stick,
-                                                DevTotals *tot, int32_t iface_blocks, int32_t fold_blocks) {
+                                                DevTotals *tot, int32_t iface_blocks, int32_t fold_blocks,
+                                                ProdFront pf) {
     const int32_t b = int32_t(blockIdx.x);
     if (b < iface_blocks) {
-        interface_block<ST>(ph, it, emit, pi_now, uint32_t(b));
+        interface_block<ST>(ph, it, emit, pi_now, uint32_t(b), pf.iface);
     } else if (b - iface_blocks < fold_blocks) {
-        fold_block(ps, ns, pi_prev, ni, fold_prev, b - iface_blocks, FOLD_BLOCKS);
+        fold_block(ps, ns, pi_prev, ni, fold_prev, b - iface_blocks, FOLD_BLOCKS, pf.on ? pf.ps : nullptr,
+                   pf.on ? pf.pi_prev : nullptr);
     } else {
-        reduce_block(fold_prev2, FOLD_BLOCKS, p, p_stick, tot);
+        reduce_block(fold_prev2, FOLD_BLOCKS, p, p_stick, tot, pf.on != 0, pf.p_stick);
     }
 }
 
@@ -1183,7 +1475,7 @@ __global__ __launch_bounds__(256) void k_sweep_batch_c(const SampleK<ST> *__rest
     const SampleK<ST> &d = smp[__builtin_amdgcn_readfirstlane(block_sample[b])];
     const Slots &in = d.pop[parity];
     const OutSlots &out = reinterpret_cast<const OutSlots &>(d.pop[1 - parity]);
-    sweep_block_c<ST, SP>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0);
+    sweep_block_c<ST, SP>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0, ProdK<ST>{});
 }
 
 template <int ST>
@@ -1191,7 +1483,7 @@ __global__ __launch_bounds__(256) void k_interface_batch(const SampleK<ST> *__re
                                                           const uint32_t *__restrict__ block_sample) {
     const uint32_t b = blockIdx.x;
     const SampleK<ST> &d = smp[__builtin_amdgcn_readfirstlane(block_sample[b])];
-    interface_block<ST>(d.ph, d.it, d.emit, d.part_iface, b - d.iblock0);
+    interface_block<ST>(d.ph, d.it, d.emit, d.part_iface, b - d.iblock0, ProdI{});
 }
 
 __global__ __launch_bounds__(256) void k_fold_batch(const ReduceK *__restrict__ r) {
@@ -1216,6 +1508,21 @@ hipError_t dispatch_sp(int code, F &&f) {
         case SP_UNIFORM | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_UNIFORM | SP_INFLOW_FLAG>{});
         case SP_WEIGHTED | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_WEIGHTED | SP_INFLOW_FLAG>{});
         case SP_BOUNCEBACK | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_BOUNCEBACK | SP_INFLOW_FLAG>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// The product-lattice codes (node-compact sweep only).
+template <typename F>
+hipError_t dispatch_sp_product(int code, F &&f) {
+    constexpr int P = SP_PRODUCT_FLAG, I = SP_INFLOW_FLAG;
+    switch (code) {
+        case SP_UNIFORM: return f(std::integral_constant<int, P | SP_UNIFORM>{});
+        case SP_WEIGHTED: return f(std::integral_constant<int, P | SP_WEIGHTED>{});
+        case SP_BOUNCEBACK: return f(std::integral_constant<int, P | SP_BOUNCEBACK>{});
+        case SP_UNIFORM | I: return f(std::integral_constant<int, P | I | SP_UNIFORM>{});
+        case SP_WEIGHTED | I: return f(std::integral_constant<int, P | I | SP_WEIGHTED>{});
+        case SP_BOUNCEBACK | I: return f(std::integral_constant<int, P | I | SP_BOUNCEBACK>{});
         default: return hipErrorInvalidValue;
     }
 }
@@ -1317,7 +1624,7 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
 int64_t sweep_blocks_c(const Geometry &g) { return ((int64_t(g.nwaves) + 3) / 4 + 7) / 8 * 8; }
 
 hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
-                          double *part, hipStream_t s) {
+                          double *part, hipStream_t s, const ProdStep *prod) {
     return dispatch(ph.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         using SS = typename Store<ST>::S;
@@ -1330,8 +1637,24 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
         const dim3 grid(static_cast<unsigned>(sweep_blocks_c(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
         const PhysK<T> k = to_kernel<T>(ph);
+        if (prod) {
+            ProdK<ST> pk{};
+            pk.in.base = static_cast<const char *>(prod->fin);
+            pk.in.stride = uint32_t(uint64_t(g.nfp) * sizeof(SS));
+            pk.out.base = static_cast<char *>(prod->fout);
+            pk.out.stride = pk.in.stride;
+            pk.emit = static_cast<const SS *>(prod->emit);
+            pk.inacc = prod->inacc;
+            pk.part = prod->part_sweep;
+            return dispatch_sp_product(sweep_code(ph.sputter, ph.species_x), [&](auto sp) {
+                hipLaunchKernelGGL((k_sweep_c<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part,
+                                   pk);
+                return hipGetLastError();
+            });
+        }
         return dispatch_sp(sweep_code(ph.sputter, ph.species_x), [&](auto sp) {
-            hipLaunchKernelGGL((k_sweep_c<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part);
+            hipLaunchKernelGGL((k_sweep_c<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part,
+                               ProdK<ST>{});
             return hipGetLastError();
         });
     });
@@ -1384,18 +1707,68 @@ hipError_t launch_populations(const Geometry &g, const Physics &ph, const void *
 
 hipError_t launch_front(const Physics &ph, const Interface &it, void *emit, int64_t iface_blocks, double *pi_now,
                         const double *ps, int64_t ns, const double *pi_prev, int64_t ni, double *fold_prev,
-                        bool fold, const double *fold_prev2, bool reduce, DevTotals *tot, hipStream_t s) {
+                        bool fold, const double *fold_prev2, bool reduce, DevTotals *tot, hipStream_t s,
+                        const ProdStep *prod) {
     const int64_t blocks = iface_blocks + (fold ? FOLD_BLOCKS : 0) + (reduce ? 1 : 0);
     if (blocks == 0) return hipSuccess;
+    ProdFront pf{};
+    if (prod) {
+        pf.on = 1;
+        pf.p_stick = ph.p_stick_product;
+        pf.iface.emit = prod->emit;
+        pf.iface.inacc = iface_blocks > 0 ? prod->inacc : nullptr;
+        pf.iface.acc = prod->acc;
+        pf.iface.part = prod->pi_now;
+        pf.ps = prod->part_sweep;
+        pf.pi_prev = prod->pi_prev;
+    }
     return dispatch(ph.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         using SS = typename Store<ST>::S;
         using T = typename Store<ST>::T;
         hipLaunchKernelGGL(k_front<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, to_kernel<T>(ph), it,
                            static_cast<SS *>(emit), pi_now, ps, ns, pi_prev, ni, fold_prev, fold_prev2, ph.p,
-                           ph.p_stick, tot, int32_t(iface_blocks), int32_t(fold ? FOLD_BLOCKS : 0));
+                           ph.p_stick, tot, int32_t(iface_blocks), int32_t(fold ? FOLD_BLOCKS : 0), pf);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_in_init_product(const Geometry &g, const Physics &ph, const Interface &it, const void *finP,
+                                  unsigned long long *inacc, hipStream_t s) {
+    const int64_t blocks = interface_blocks(it.n);
+    if (blocks == 0) return hipSuccess;
+    return dispatch(ph.storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        using SS = typename Store<ST>::S;
+        using T = typename Store<ST>::T;
+        hipLaunchKernelGGL(k_in_init_p<ST>, dim3(unsigned(blocks)), dim3(256), 0, s, g, to_kernel<T>(ph), it,
+                           static_cast<const SS *>(finP), inacc);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_product_field(const Geometry &g, const Physics &ph, const void *fin, const void *finP,
+                                const void *emitP, int mode, double *concP, hipStream_t s) {
+    const int64_t n = int64_t(g.nx) * g.ny * g.nz;
+    const dim3 grid(unsigned((n + 255) / 256)), block(256);
+    return dispatch(ph.storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        using SS = typename Store<ST>::S;
+        using T = typename Store<ST>::T;
+        const SS *a = static_cast<const SS *>(fin), *b = static_cast<const SS *>(finP),
+                 *e = static_cast<const SS *>(emitP);
+        if (mode == 2)
+            hipLaunchKernelGGL((k_product_field<ST, true>), grid, block, 0, s, g, to_kernel<T>(ph), a, b, e, concP);
+        else
+            hipLaunchKernelGGL((k_product_field<ST, false>), grid, block, 0, s, g, to_kernel<T>(ph), a, b, e, concP);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_flux_profile(const Geometry &g, const double *concP, const double *u, double *phi, hipStream_t s) {
+    hipLaunchKernelGGL(k_flux_profile, dim3(unsigned(g.nx)), dim3(256), 0, s, g.nx, int64_t(g.ny) * g.nz, concP, u,
+                       phi);
+    return hipGetLastError();
 }
 
 size_t batch_record_bytes(int storage) {

@@ -51,7 +51,8 @@ class lbm_bc(ctypes.Structure):
     _fields_ = [("sputter", ctypes.c_int32), ("coupling", ctypes.c_int32), ("species_x", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("p_stick", ctypes.c_double), ("c_inlet", ctypes.c_double),
                 ("rho0", ctypes.c_double), ("c0", ctypes.c_double), ("c_ref", ctypes.c_double),
-                ("force", ctypes.c_double * 3), ("reserved", ctypes.c_uint64)]
+                ("force", ctypes.c_double * 3), ("product", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("p_stick_product", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -65,7 +66,9 @@ class lbm_device(ctypes.Structure):
 class lbm_totals_t(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("mass_gas", ctypes.c_double), ("mass_species", ctypes.c_double),
                 ("converted", ctypes.c_double), ("lost", ctypes.c_double), ("influx", ctypes.c_double),
-                ("outflux", ctypes.c_double), ("nonfinite", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("outflux", ctypes.c_double), ("nonfinite", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mass_product", ctypes.c_double), ("lost_product", ctypes.c_double),
+                ("product_out_inlet", ctypes.c_double), ("product_out_outlet", ctypes.c_double)]
 
 
 class lbm_info(ctypes.Structure):
@@ -109,6 +112,7 @@ def _load():
         "lbm_fields": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_fields_device": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_conversion_map": (st, [ctx, ctypes.c_void_p]),
+        "lbm_product_fields": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_populations": (st, [ctx, P(ctypes.c_int32), P(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_totals": (st, [ctx, P(lbm_totals_t)]),
         "lbm_query": (st, [ctx, P(lbm_info)]),
@@ -212,16 +216,19 @@ def _geometry(vox, pore_size):
 
 
 def _bc(sputter=SPUTTER_UNIFORM, coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32,
-        p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0)):
+        p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0), product=False,
+        p_stick_product=0.0):
     return lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
-                  float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]), 0)
+                  float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]),
+                  int(bool(product)), 0, float(p_stick_product))
 
 
 def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc_kw):
     """Call lbm_create_on.  vox is a (nz, ny, nx) uint8 array; device is an
     lbm_device struct holder (see use_torch) or None for hipMalloc and the
     null stream; bc_kw are the lbm_bc fields (sputter, coupling, species_x,
-    storage, p_stick, c_inlet, rho0, c0, c_ref, force).  Returns the raw
+    storage, p_stick, c_inlet, rho0, c0, c_ref, force, product,
+    p_stick_product).  Returns the raw
     context handle."""
     vox, g = _geometry(vox, pore_size)
     bc = _bc(**bc_kw)
@@ -317,6 +324,14 @@ class Sim:
         out = np.zeros(self.n)
         _check(_LIB.lbm_conversion_map(self._h, out.ctypes.data), self._h)
         return out.reshape(self.shape)
+
+    def product_fields(self):
+        """lbm_product_fields: (rho_P field, stuck-product map, Phi_P(x))."""
+        conc = np.zeros(self.n)
+        stuck = np.zeros(self.n)
+        phi = np.zeros(self.shape[2])
+        _check(_LIB.lbm_product_fields(self._h, conc.ctypes.data, stuck.ctypes.data, phi.ctypes.data), self._h)
+        return conc.reshape(self.shape), stuck.reshape(self.shape), phi
 
     def totals(self):
         t = lbm_totals_t()

@@ -20,8 +20,8 @@ def test_every_declared_function_is_exported():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_geometry) == 32
-    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8
-    assert ctypes.sizeof(lbm.lbm_totals_t) == 8 + 6 * 8 + 8
+    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8
+    assert ctypes.sizeof(lbm.lbm_totals_t) == 8 + 6 * 8 + 8 + 4 * 8
     assert ctypes.sizeof(lbm.lbm_device) == 32
 
 
@@ -46,6 +46,8 @@ def _create(vox, **kw):
     (dict(kn=-0.5), "kn"),
     (dict(tau=(0.8, 0.7), kn=0.3), "disagree"),
     (dict(force=(float("inf"), 0, 0)), "force"),
+    (dict(product=True, p_stick_product=1.5), "p_stick_product"),
+    (dict(product=True, p_stick_product=-0.1), "p_stick_product"),
 ])
 def test_invalid_parameters_are_rejected(kw, msg):
     vox = np.zeros((4, 4, 8), np.uint8)
@@ -110,3 +112,27 @@ def test_batch_rejects_invalid_arguments_before_device_work():
     assert L.lbm_batch_step(None, 1) == lbm.LBM_EINVAL
     assert L.lbm_batch_set_graph(None, 1) == lbm.LBM_EINVAL
     L.lbm_batch_destroy(None)  # no-op
+
+
+def test_product_lattice_needs_passive_coupling():
+    """The product lattice is advected by the carrier (PASSIVE); asking for it
+    with BARYCENTRIC coupling is rejected before any device work."""
+    vox = np.zeros((4, 4, 8), np.uint8)
+    with pytest.raises(lbm.LbmError) as e:
+        _create(vox, product=True, coupling=lbm.COUPLE_BARYCENTRIC)
+    assert e.value.status == lbm.LBM_EUNSUPPORTED
+    assert "PASSIVE" in str(e.value)
+
+
+def test_inspect_counts_the_product_buffers():
+    """The planned device bytes grow by the product lattice's buffers: two
+    population buffers of 19 nfp elements, E_P, In_P, Acc_P and partials."""
+    from paper_1607_02874_amd import inputs
+
+    vox = inputs.PLAIN_32.voxels()
+    a = lbm.inspect(vox, 1.0, tau=(0.8, 0.7), pore_size=4.0)
+    b = lbm.inspect(vox, 1.0, tau=(0.8, 0.7), pore_size=4.0, product=True, p_stick_product=0.2)
+    nfp = (a["n_fluid"] + 1 + 127) // 128 * 128
+    grow = b["device_bytes"] - a["device_bytes"]
+    assert grow >= (38 * nfp + a["n_interface"]) * 4 + 2 * a["n_interface"] * 8
+    assert grow < (38 * nfp + a["n_interface"]) * 4 + 2 * a["n_interface"] * 8 + 64 * 1024
