@@ -14,6 +14,8 @@ sweep of both lattices + FP64 reduction.  Prints one JSON line.
     python bench.py --workload precision [--steps K]   (512^3, FP32/FP16/BF16 vs the FP64 build)
     python bench.py --workload membrane [--steps K]    (1024x512x512 layer, Da 10 and 0.1, FP32 and FP16)
     python bench.py --workload shard [--steps K]       (one 128x512x512 x-slab of the membrane)
+    python bench.py --workload product [--steps K]     (256^3 with the product lattice P)
+    python bench.py --workload reactor2d               (the paper's 2-D reactor: efficiency vs p and w/h)
 """
 
 import argparse
@@ -35,7 +37,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(info, s):
+def algorithmic_bytes(info, s, product=False):
     """Bytes the method must move per step (per launch for each kernel).
 
     Sweep: every population of both lattices written once (38 s per gas node)
@@ -44,10 +46,18 @@ def algorithmic_bytes(info, s):
     interface node); plus the 8-byte In(k) sum per interface node and the
     32-byte chunk record per 64 voxels.  Interface: per interface node, In(k)
     read and clear (16), mask and scale (4 + 8), the FP64 accumulator
-    read-modify-write (16) and the emission write (s)."""
+    read-modify-write (16) and the emission write (s).
+
+    With the product lattice the sweep also reads and writes every product
+    population once (38 s per gas node, less the L_K that come from E_P),
+    reads E_P and adds In_P (s + 8 per interface node); the interface also
+    reads and clears In_P (16), updates Acc_P (16) and writes E_P (s)."""
     nf, n, nk, lk = info["n_fluid"], info["n_nodes"], info["n_interface"], info["n_catalytic_links"]
     sweep = (76 * nf - lk) * s + (8 + s) * nk + n // 2
     iface = nk * (16 + 4 + 8 + 16 + s)
+    if product:
+        sweep += (38 * nf - lk) * s + (8 + s) * nk
+        iface += nk * (16 + 16 + s)
     return {"sweep": sweep, "interface": iface, "step": sweep + iface}
 
 
@@ -440,6 +450,155 @@ def run_shard(args):
     print(json.dumps(line), flush=True)
 
 
+def run_product(args):
+    """The 256^3 porous sample with the product lattice P (three D3Q19
+    lattices: carrier, reactant, product; p_S^P = 0 as in the paper), FP32
+    unless --storage says otherwise.  Reports lattice updates per second (one
+    update covers all three lattices), the sweep's share of the HBM roofline,
+    the product totals and the conversion efficiency of Eq. (eff) over the
+    timed window."""
+    import torch
+
+    from paper_1607_02874_amd import inputs, lbm
+
+    w = inputs.SINGLE_256
+    vox = w.voxels()
+    storage = STORAGES[args.storage]
+    sim = lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                  c_inlet=w.c_inlet, storage=storage, product=True, p_stick_product=0.0)
+    info = sim.info()
+    if args.ytile:
+        sim.set_tunable(lbm.TUNE_YTILE, args.ytile)
+    if not args.no_autotune and args.ytile is None:
+        sim.autotune(3)
+    sim.step(args.warmup)
+    sim.synchronize()
+    t0 = sim.totals()
+    sim.set_timing(2)  # events around the sweeps only
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sim.step(args.steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    kt = sim.kernel_times()
+    t1 = sim.totals()
+    sweep_variant = sim.get_tunable(lbm.TUNE_SWEEP)
+    ytile = sim.get_tunable(lbm.TUNE_YTILE)
+    sim.close()
+    s_bytes = lbm.STORAGE_BYTES[storage]
+    ab = algorithmic_bytes(info, s_bytes, product=True)
+    t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
+    d_in = t1["influx"] - t0["influx"]
+    eta = (t1["product_out_outlet"] - t0["product_out_outlet"]) / d_in if d_in else None
+    storage_name = {0: "f32", 1: "f16", 2: "bf16", 3: "f64"}[storage]
+    line = {
+        "metric": "MLUPS (flow+species) and % of HBM roofline at stated error vs FP64 oracle",
+        "value": round(vox.size * args.steps / el / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f32", 1: "f16-storage/f32", 2: "bf16-storage/f32", 3: "f64"}[storage],
+        "data": "synthetic (seeded Gaussian-random-field porous sample)",
+        "config": {"workload": f"{w.name} with the product lattice: {w.nx}x{w.ny}x{w.nz}, carrier, reactant and "
+                               f"product D3Q19 lattices, p_S^P = 0",
+                   "n_nodes": int(vox.size), "n_fluid": info["n_fluid"], "n_interface": info["n_interface"],
+                   "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks", "ytile": ytile,
+                   "sweep_us": round(t_sweep * 1e6, 1),
+                   "mass_product": t1["mass_product"], "converted": t1["converted"],
+                   "conversion_efficiency_window": eta},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_c",
+                     "achieved": round(ab["sweep"] / t_sweep / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ab["sweep"] / t_sweep / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("k_sweep_c", w.name + "_product", storage_name, "node-compact",
+                                                 ytile),
+                     "algorithmic_bytes": ab["sweep"]},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_reactor2d(args):
+    """The paper's 2-D reactor ("Results & Discussion", Table 1, the p and
+    w/h sweep of Fig. 6) on one z-plane of D3Q19, whose populations project
+    exactly onto D2Q9's weights (4/9, 1/9, 1/36): L = 250 along the flow,
+    H = 500 across, a horizontal ingot h = 200 wide and w = 6, 10, 20, 30
+    thick carved to porosity 0.70 with 3-unit disks, tau 4 for every lattice,
+    rho_C = 0.8, reactant injected with the flow at 0.2 (INFLOW), no product
+    at the inlet, p_S^R = 0.95 (Table 1), p_S^P = 0, p = 0.35 ... 0.65.  The
+    gas is periodic and driven by a body force; the mean inlet speed it
+    reaches is reported (the paper imposes 0.08).  The conversion efficiency
+    of Eq. (eff), product mass leaving through the outlet over reactant mass
+    entering through the inlet, is taken over the last 20000 of 60000 steps
+    with the reactant inflow c_in sum_y u_x(0, y) per step (the inlet flow;
+    the ghost populations' gross influx, mostly diffusion that returns, is
+    reported beside it)."""
+    import torch
+
+    from paper_1607_02874_amd import inputs, lbm
+
+    steps, window = 60000, 20000
+    tau, rho0, c_in = 4.0, 0.8, 0.2
+    force = 4.0e-5
+    ps = (0.35, 0.45, 0.55, 0.65)
+    ws = (6, 10, 20, 30)
+    eta, eta_gross, u_mean = {}, {}, {}
+    n_updates, t_total = 0, 0.0
+    for w in ws:
+        vox = inputs.disk_ingot(w, seed=w)
+        for p in ps:
+            da = np.sqrt(1.0 / 3.0) / (p * 3.0)  # p = cs / (Da delta), delta = 3
+            with lbm.Sim(vox, da=da, tau=(tau, tau), pore_size=3.0, force=(force, 0.0, 0.0), rho0=rho0,
+                         c_inlet=c_in, p_stick=0.95, species_x=lbm.XBC_INFLOW, product=True,
+                         p_stick_product=0.0, storage=STORAGES[args.storage]) as sim:
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                gas = vox[0, :, 0] == inputs.FLUID
+                sim.step(steps - window)
+                t0 = sim.totals()
+                q0 = float(sim.fields()[1][0, 0, gas, 0].sum())
+                sim.step(window)
+                t1 = sim.totals()
+                q1 = float(sim.fields()[1][0, 0, gas, 0].sum())
+                t_total += time.perf_counter() - t
+                n_updates += vox.size * steps
+                d_out = t1["product_out_outlet"] - t0["product_out_outlet"]
+                key = f"p={p}"
+                eta.setdefault(key, {})[f"w={w}"] = round(d_out / (window * c_in * 0.5 * (q0 + q1)), 4)
+                eta_gross.setdefault(key, {})[f"w={w}"] = round(d_out / (t1["influx"] - t0["influx"]), 5)
+                if p == ps[0]:
+                    u_mean[f"w={w}"] = round(0.5 * (q0 + q1) / int(gas.sum()), 4)
+            log(f"w {w} p {p}: eta {eta[f'p={p}'][f'w={w}']}")
+    line = {
+        "metric": "conversion efficiency eta (Eq. eff) of the paper's 2-D reactor vs p and w/h",
+        "value": round(n_updates / t_total / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": round(t_total / (len(ps) * len(ws) * steps) * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f32", 1: "f16-storage/f32", 2: "bf16-storage/f32", 3: "f64"}[STORAGES[args.storage]],
+        "data": "synthetic (seeded disk-carved porous ingot, the paper's recipe)",
+        "config": {"workload": "reactor2d: 250 x 500 x 1 (D3Q19 on one plane = D2Q9), ingot h = 200, porosity 0.70, "
+                               "tau 4, rho_C 0.8, c_in 0.2 (INFLOW), p_S^R 0.95, p_S^P 0, 60000 steps, eta over the "
+                               "last 20000",
+                   "body_force": force, "inlet_mean_u": u_mean, "eta": eta,
+                   "eta_over_gross_ghost_influx": eta_gross,
+                   "paper": "eta = 0.2 at p = 0.45, w = 10 (the experimental value the paper matches)"},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,7 +613,7 @@ def main():
     ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
     ap.add_argument("--sweep", type=int, default=None, choices=(0, 1),
                     help="sweep variant: 1 node-compact (library default), 0 one wave per 64-voxel chunk")
-    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision", "membrane", "shard"),
+    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision", "membrane", "shard", "product", "reactor2d"),
                     help="single: the 256^3 sample; batch: the 64-sample mixed batch; precision: 512^3 "
                          "with FP32/FP16/BF16 storage against the FP64 build; membrane: 1024x512x512 layer; "
                          "shard: one 128x512x512 x-slab of the membrane")
@@ -484,6 +643,10 @@ def main():
     if args.workload == "membrane":
         run_membrane(args)
         return
+    if args.workload == "product":
+        return run_product(args)
+    if args.workload == "reactor2d":
+        return run_reactor2d(args)
     if args.workload == "shard":
         run_shard(args)
         return

@@ -536,7 +536,7 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
         const int64_t chunks = rows * c.W;
         const int64_t blocks = ((chunks + 3) / 4 + 7) / 8 * 8;
         const bool compact = g->ny <= 1024 && g->nz <= 1024 && c.nfluid > 0;
-        int64_t bytes = r256((76 * nfp + niface) * sb) + r256(chunks * int64_t(sizeof(ChunkInfo))) +
+        int64_t bytes = r256((76 * nfp + niface + 1) * sb) + r256(chunks * int64_t(sizeof(ChunkInfo))) +
                         r256(chunks * 4) + 2 * r256(niface * 4) + 3 * r256(niface * 8) +
                         r256((4 * blocks + 2 * ((niface + 255) / 256) + 2 * FOLD_BLOCKS * NPART) * 8) +
                         r256(int64_t(sizeof(DevTotals)));
@@ -545,7 +545,7 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
             // P buffers and E_P, In_P and Acc_P, P partial sums
             const int64_t blocks_c = ((c.nfluid + 63) / 64 + 3) / 4;
             const int64_t rows_p = std::max(blocks, (blocks_c + 7) / 8 * 8);
-            bytes += r256((38 * nfp + niface) * sb) + 2 * r256(niface * 8) +
+            bytes += r256((38 * nfp + niface + 1) * sb) + 2 * r256(niface * 8) +
                      r256((3 * rows_p + 2 * ((niface + 255) / 256)) * 8);
         }
         info->device_bytes = bytes;
@@ -693,8 +693,10 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
             c->d_worder = static_cast<uint32_t *>(dev_alloc(c, worder.size() * 4));
         }
         // One pool: population buffers A and B, then the emission array (one
-        // element per interface node, indexed by interface index).
-        char *pool = static_cast<char *>(dev_alloc(c, (size_t(76) * c->nfp + size_t(c->niface)) * sb));
+        // element per interface node, indexed by interface index, plus one:
+        // the sweeps load element 0 for lanes without a catalytic source,
+        // which must exist when there is no interface node).
+        char *pool = static_cast<char *>(dev_alloc(c, (size_t(76) * c->nfp + size_t(c->niface) + 1) * sb));
         if (pool) {
             c->d_pop[0] = pool;
             c->d_pop[1] = pool + size_t(38) * c->nfp * sb;
@@ -706,7 +708,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         bool prod_ok = true;
         if (c->ph.product) {
             // P buffers A and B, then E_P (one element per interface node)
-            char *pp = static_cast<char *>(dev_alloc(c, (size_t(38) * c->nfp + size_t(c->niface)) * sb));
+            char *pp = static_cast<char *>(dev_alloc(c, (size_t(38) * c->nfp + size_t(c->niface) + 1) * sb));
             if (pp) {
                 c->d_popP[0] = pp;
                 c->d_popP[1] = pp + size_t(19) * c->nfp * sb;
@@ -740,7 +742,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
             up(c->d_worder, worder.data(), worder.size() * 4);
         }
         if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
-        if (e == hipSuccess && c->niface) e = hipMemsetAsync(c->d_emit, 0, size_t(c->niface) * sb, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, (size_t(c->niface) + 1) * sb, c->stream);
         DevTotals t0{};
         t0.mass_gas = double(c->nfluid) * bc->rho0;
         t0.mass_species = double(c->nfluid) * bc->c0;
@@ -750,7 +752,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         if (c->ph.product) {
             // no product anywhere at the start: both P buffers, E_P and Acc_P are 0
             if (e == hipSuccess)
-                e = hipMemsetAsync(c->d_popP[0], 0, (size_t(38) * c->nfp + size_t(c->niface)) * sb, c->stream);
+                e = hipMemsetAsync(c->d_popP[0], 0, (size_t(38) * c->nfp + size_t(c->niface) + 1) * sb, c->stream);
             if (e == hipSuccess && c->niface) e = hipMemsetAsync(c->d_accP, 0, size_t(c->niface) * 8, c->stream);
             if (e == hipSuccess)
                 e = launch_in_init_product(geometry(c), c->ph, interface_list(c), c->d_popP[0], c->d_inaccP,

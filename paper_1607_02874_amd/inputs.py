@@ -71,6 +71,31 @@ def porous_slab(nx, ny, nz, phi, ell, seed, x_lo=4, x_hi=None, solid_flag=CATALY
     return vox
 
 
+def disk_ingot(w, h=200, length=250, width=500, phi=0.70, diameter=3.0, seed=0, tol=0.005):
+    """The paper's 2-D reactor ("Experimental details and Nanoporous Catalyst
+    reconstruction"; Table 1): a (1, width, length) voxel map, flow along x,
+    with a rectangular catalytic ingot w along the flow and h across it,
+    centred in the domain, made porous by carving disks of the given
+    diameter (30 nm = 3 lattice units) around uniformly random centres inside
+    the rectangle until its porosity reaches phi within tol.  One inert wall
+    row at y = 0 bounds the tube (y is periodic, so it bounds both sides).
+    """
+    rng = np.random.default_rng(seed)
+    vox = np.zeros((1, width, length), dtype=np.uint8)
+    x0, y0 = (length - w) // 2, (width - h) // 2
+    block = np.ones((h, w), dtype=bool)  # True = solid
+    yy, xx = np.mgrid[0:h, 0:w]
+    r2 = (diameter / 2.0) ** 2
+    n = h * w
+    while 1.0 - block.sum() / n < phi - tol:
+        cy, cx = rng.uniform(0, h), rng.uniform(0, w)
+        # pixel centres at (i + 1/2, j + 1/2)
+        block[(yy + 0.5 - cy) ** 2 + (xx + 0.5 - cx) ** 2 <= r2] = False
+    vox[0, y0:y0 + h, x0:x0 + w][block] = CATALYTIC
+    vox[0, 0, :] = INERT
+    return vox
+
+
 def crop(vox, nx, ny, nz, outlet_planes=4):
     """Crop voxels [0:nz, 0:ny, 0:nx] and force the last outlet planes to gas."""
     c = np.ascontiguousarray(vox[:nz, :ny, :nx]).copy()

@@ -79,3 +79,42 @@ def test_leveque_reactive_channel(storage, species_x):
     else:
         assert 0.7 < entering < 0.9, entering
     assert mae < 0.06, mae
+
+
+def reactor_eta(w, p, steps=60000, window=20000):
+    """The paper's 2-D reactor (Table 1; the p and w/h sweep of "Results &
+    Discussion") on one z-plane: efficiency of Eq. (eff) as product leaving
+    through the outlet over the reactant inlet flow c_in sum_y u_x(0, y),
+    over the last `window` steps, and the mean inlet speed."""
+    vox = inputs.disk_ingot(w, seed=w)
+    gas = vox[0, :, 0] == inputs.FLUID
+    c_in = 0.2
+    with lbm.Sim(vox, da=math.sqrt(1.0 / 3.0) / (p * 3.0), tau=(4.0, 4.0), pore_size=3.0, force=(4e-5, 0.0, 0.0),
+                 rho0=0.8, c_inlet=c_in, p_stick=0.95, species_x=lbm.XBC_INFLOW, product=True,
+                 p_stick_product=0.0) as s:
+        s.step(steps - window)
+        t0, q0 = s.totals(), float(s.fields()[1][0, 0, gas, 0].sum())
+        s.step(window)
+        t1, q1 = s.totals(), float(s.fields()[1][0, 0, gas, 0].sum())
+    q = 0.5 * (q0 + q1)
+    return (t1["product_out_outlet"] - t0["product_out_outlet"]) / (window * c_in * q), q / int(gas.sum())
+
+
+def test_reactor2d_efficiency_trends():
+    """The paper's qualitative findings on its 2-D reactor: the efficiency
+    grows with the reaction probability, and the ingot thickness matters
+    little next to its perimeter (a five times thicker ingot, five times the
+    area, changes eta by far less than five times; eta stays finite as
+    w/h -> 0).  The absolute level is not compared: the gas here is periodic
+    and force-driven instead of the paper's velocity inlet, and the paper
+    gives p_S^R as 0.95 (Table 1) and as about 0.5 (text)."""
+    res = {(w, p): reactor_eta(w, p) for w in (6, 30) for p in (0.35, 0.65)}
+    for (w, p), (eta, u) in res.items():
+        print(f"w {w} p {p}: eta {eta:.4f}, inlet mean speed {u:.4f}", flush=True)
+        assert 0.05 < u < 0.1  # the paper's inlet speed is 0.08
+        assert eta > 0.0
+    for w in (6, 30):
+        assert res[(w, 0.65)][0] > 1.3 * res[(w, 0.35)][0]
+    for p in (0.35, 0.65):
+        ratio = res[(30, p)][0] / res[(6, p)][0]
+        assert 0.5 < ratio < 2.0, ratio
