@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-UNIFORM, WEIGHTED, BOUNCEBACK = 0, 1, 2
+UNIFORM, WEIGHTED, BOUNCEBACK, STOCHASTIC = 0, 1, 2, 3
 PASSIVE, BARYCENTRIC = 0, 1
 XPERIODIC, XRESERVOIR, XINFLOW = 0, 1, 2
 
@@ -41,7 +41,8 @@ class Params(ctypes.Structure):
                 ("sputter", ctypes.c_int32), ("coupling", ctypes.c_int32),
                 ("species_x", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("p_stick_product", ctypes.c_double),
-                ("product", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+                ("product", ctypes.c_int32), ("pad2", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def lib():
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.orc_guo_source.argtypes = [ctypes.c_double, dp, dp, dp]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_philox4x32_10.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -132,6 +134,15 @@ def guo_source(tau, u, F):
     return out
 
 
+def philox4x32_10(ctr, key):
+    """The oracle's Philox4x32-10 on one counter (4 words) and key (2 words)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
 def threads():
     return lib().orc_threads()
 
@@ -142,7 +153,7 @@ class Oracle:
 
     def __init__(self, vox, tau=(0.8, 0.7), p=0.1, p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0,
                  force=(0.0, 0.0, 0.0), sputter=UNIFORM, coupling=PASSIVE, species_x=XRESERVOIR,
-                 product=False, p_stick_product=0.0):
+                 product=False, p_stick_product=0.0, seed=0):
         vox = np.ascontiguousarray(vox, dtype=np.uint8)
         assert vox.ndim == 3
         self.nz, self.ny, self.nx = vox.shape
@@ -156,6 +167,7 @@ class Oracle:
             prm.force[a] = float(force[a])
         prm.sputter, prm.coupling, prm.species_x = int(sputter), int(coupling), int(species_x)
         prm.product, prm.p_stick_product = int(bool(product)), float(p_stick_product)
+        prm.seed = int(seed)
         self.params = prm
         h = lib().orc_create(self.nx, self.ny, self.nz, vox.ctypes.data, ctypes.byref(prm))
         if not h:

@@ -58,7 +58,18 @@
  *     along the reversed active links at the next streaming (link-wise,
  *     one step, like halfway bounce-back);
  *   - S as an expectation: UNIFORM (each active direction 1/b), WEIGHTED
- *     (proportional to w_i) or BOUNCEBACK (reversal);
+ *     (proportional to w_i) or BOUNCEBACK (reversal); or S drawn at random
+ *     (STOCHASTIC, the paper's random discrete orientation): each arrival at
+ *     catalytic node k along active link j leaves whole along one of the b(k)
+ *     exit directions {opp(j') : j' active}, picked with probability 1/b(k)
+ *     (so the expectation is UNIFORM).  The draw is a pure function of
+ *     (seed, step, k, j): Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+ *     "Parallel random numbers: as easy as 1, 2, 3", SC 2011) with key
+ *     (seed low, seed high) and counter (step, k, code(j), 0), where code(c)
+ *     = 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1) labels a velocity independently
+ *     of any direction numbering; the first output word r picks the exit
+ *     floor(r b / 2^32) in ascending code order.  The step is the one whose
+ *     collision produced the arriving populations;
  *   - species x-boundaries: RESERVOIR puts an inlet ghost plane at x = -1
  *     holding w_i c_in and an outlet ghost plane at x = nx that copies plane
  *     nx - 1 (zero gradient; a solid copy reflects as inert solid);
@@ -92,7 +103,7 @@ static const double WT[Q] = {1.0 / 3.0,
 static const int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 
 enum { ORC_FLUID = 0, ORC_INERT = 1, ORC_CATALYTIC = 2 };
-enum { ORC_UNIFORM = 0, ORC_WEIGHTED = 1, ORC_BOUNCEBACK = 2 };
+enum { ORC_UNIFORM = 0, ORC_WEIGHTED = 1, ORC_BOUNCEBACK = 2, ORC_STOCHASTIC = 3 };
 enum { ORC_PASSIVE = 0, ORC_BARYCENTRIC = 1 };
 enum { ORC_XPERIODIC = 0, ORC_XRESERVOIR = 1, ORC_XINFLOW = 2 };
 
@@ -106,6 +117,7 @@ typedef struct {
     int32_t sputter, coupling, species_x, pad;
     double p_stick_product;      /* sticking probability p_S^P of the product */
     int32_t product, pad2;       /* 1: evolve the product lattice P */
+    uint64_t seed;               /* key of the STOCHASTIC sputter draws */
 } orc_params;
 
 typedef struct {
@@ -413,6 +425,46 @@ static void collide(orc *o)
     }
 }
 
+/* Philox4x32-10 (Salmon et al. 2011): ten rounds of two 32 x 32 -> 64-bit
+ * products, the high halves xored with the other counter words and the key,
+ * the key bumped by the Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1, n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static int vcode(int i)
+{
+    return 9 * (CX[i] + 1) + 3 * (CY[i] + 1) + (CZ[i] + 1);
+}
+
+/* STOCHASTIC: the exit direction of the arrival at node k along active link
+ * j produced by the collision of step t (see the header). */
+static int random_exit(const orc *o, long k, int j, unsigned act, int b, long t)
+{
+    int exits[Q], n = 0;
+    for (int code = 0; code < 27; ++code)
+        for (int e = 1; e < Q; ++e)
+            if (vcode(e) == code && (act & (1u << OPP[e])))
+                exits[n++] = e;
+    uint32_t ctr[4] = {(uint32_t)t, (uint32_t)k, (uint32_t)vcode(j), 0u};
+    uint32_t key[2] = {(uint32_t)o->prm.seed, (uint32_t)(o->prm.seed >> 32)}, out[4];
+    orc_philox4x32_10(ctr, key, out);
+    (void)n;
+    return exits[(int)(((uint64_t)out[0] * (uint64_t)b) >> 32)];
+}
+
 /* Step 5: the sputtering boundary condition at catalytic nodes.  Returns the
  * total reactant arrival sum_k In_R(k) of this step, and the product arrival
  * sum_k In_P(k) in *arrived_p (0 without the product lattice). */
@@ -453,6 +505,26 @@ static double interface(orc *o, double *arrived_p)
                 /* What the node sends back as product: the converted part of
                  * the reactant plus the product that did not stick. */
                 const double a_r = P->p * P->p_stick, a_p = 1.0 - P->p_stick_product;
+                if (P->sputter == ORC_STOCHASTIC) {
+                    /* each arrival leaves whole along one random exit */
+                    for (int i = 0; i < Q; ++i) {
+                        o->em[k * Q + i] = 0.0;
+                        if (o->emP)
+                            o->emP[k * Q + i] = 0.0;
+                    }
+                    for (int j = 1; j < Q; ++j) {
+                        if (!(act & (1u << j)))
+                            continue;
+                        int sx, sy, sz;
+                        source(o, x, y, z, j, xper, &sx, &sy, &sz);
+                        long s = node(o, sx, sy, sz);
+                        int e = random_exit(o, k, j, act, b, o->step);
+                        o->em[k * Q + e] += (1.0 - P->p_stick) * o->pR[s * Q + j];
+                        if (o->emP)
+                            o->emP[k * Q + e] += a_r * o->pR[s * Q + j] + a_p * o->pP[s * Q + j];
+                    }
+                    continue;
+                }
                 /* Re-emission (1 - p_S^R) sum_j S_ij f_j^out along i = opp(j). */
                 for (int j = 1; j < Q; ++j) {
                     if (!(act & (1u << j)))

@@ -132,7 +132,7 @@ def porous32():
     return inputs.PLAIN_32.voxels()
 
 
-@pytest.mark.parametrize("sputter", ["UNIFORM", "WEIGHTED", "BOUNCEBACK"])
+@pytest.mark.parametrize("sputter", ["UNIFORM", "WEIGHTED", "BOUNCEBACK", "STOCHASTIC"])
 def test_closed_box_conserves_mass(orc, porous32, sputter):
     """Periodic box, porous catalytic solid, p_S^R = 0: the sputtering
     condition conserves what it re-emits, so both lattices keep their mass
@@ -148,7 +148,7 @@ def test_closed_box_conserves_mass(orc, porous32, sputter):
     assert t1["converted"] == 0.0 and t1["lost"] == 0.0
 
 
-@pytest.mark.parametrize("sputter", ["UNIFORM", "WEIGHTED", "BOUNCEBACK"])
+@pytest.mark.parametrize("sputter", ["UNIFORM", "WEIGHTED", "BOUNCEBACK", "STOCHASTIC"])
 @pytest.mark.parametrize("coupling", ["PASSIVE", "BARYCENTRIC"])
 def test_species_bookkeeping_per_step(orc, porous32, sputter, coupling):
     """M_R(t+1) - M_R(t) = influx - outflux - p_S^R sum_k In(k) each step, and

@@ -23,7 +23,7 @@ import pytest
 
 from paper_1607_02874_amd import inputs
 
-SPUTTERS = ["UNIFORM", "WEIGHTED", "BOUNCEBACK"]
+SPUTTERS = ["UNIFORM", "WEIGHTED", "BOUNCEBACK", "STOCHASTIC"]
 
 
 @pytest.fixture(scope="module")
