@@ -16,6 +16,7 @@ sweep of both lattices + FP64 reduction.  Prints one JSON line.
     python bench.py --workload shard [--steps K]       (one 128x512x512 x-slab of the membrane)
     python bench.py --workload product [--steps K]     (256^3 with the product lattice P)
     python bench.py --workload reactor2d               (the paper's 2-D reactor: efficiency vs p and w/h)
+    python bench.py --workload stochastic [--steps K]  (256^3 with the random sputtering matrix)
 """
 
 import argparse
@@ -37,7 +38,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(info, s, product=False):
+def algorithmic_bytes(info, s, product=False, stochastic=False):
     """Bytes the method must move per step (per launch for each kernel).
 
     Sweep: every population of both lattices written once (38 s per gas node)
@@ -58,6 +59,11 @@ def algorithmic_bytes(info, s, product=False):
     if product:
         sweep += (38 * nf - lk) * s + (8 + s) * nk
         iface += nk * (16 + 16 + s)
+    if stochastic:
+        # one In sum and one emission value per exit slot (L_K of them)
+        # instead of one per interface node
+        sweep += (lk - nk) * (8 + s)
+        iface = nk * (4 + 16) + lk * (16 + s)
     return {"sweep": sweep, "interface": iface, "step": sweep + iface}
 
 
@@ -523,6 +529,68 @@ def run_product(args):
     print(json.dumps(line), flush=True)
 
 
+def run_stochastic(args):
+    """The 256^3 porous sample with the random sputtering matrix
+    (STOCHASTIC: each arrival leaves along one exit drawn by Philox4x32-10),
+    otherwise the default workload.  Reports lattice updates per second and
+    the sweep's share of the HBM roofline."""
+    import torch
+
+    from paper_1607_02874_amd import inputs, lbm
+
+    w = inputs.SINGLE_256
+    vox = w.voxels()
+    storage = STORAGES[args.storage]
+    sim = lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                  c_inlet=w.c_inlet, storage=storage, sputter=lbm.SPUTTER_STOCHASTIC, seed=2016)
+    info = sim.info()
+    if args.ytile:
+        sim.set_tunable(lbm.TUNE_YTILE, args.ytile)
+    if not args.no_autotune and args.ytile is None:
+        sim.autotune(3)
+    sim.step(args.warmup)
+    sim.synchronize()
+    sim.set_timing(2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sim.step(args.steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    kt = sim.kernel_times()
+    tot = sim.totals()
+    sweep_variant = sim.get_tunable(lbm.TUNE_SWEEP)
+    ytile = sim.get_tunable(lbm.TUNE_YTILE)
+    sim.close()
+    s_bytes = lbm.STORAGE_BYTES[storage]
+    ab = algorithmic_bytes(info, s_bytes, stochastic=True)
+    t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
+    line = {
+        "metric": "MLUPS (flow+species) and % of HBM roofline at stated error vs FP64 oracle",
+        "value": round(vox.size * args.steps / el / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f32", 1: "f16-storage/f32", 2: "bf16-storage/f32", 3: "f64"}[storage],
+        "data": "synthetic (seeded Gaussian-random-field porous sample)",
+        "config": {"workload": f"{w.name} with STOCHASTIC sputtering (Philox4x32-10 draws, seed 2016)",
+                   "n_nodes": int(vox.size), "n_fluid": info["n_fluid"], "n_interface": info["n_interface"],
+                   "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks", "ytile": ytile,
+                   "sweep_us": round(t_sweep * 1e6, 1), "converted": tot["converted"]},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_c" if sweep_variant == 1 else "k_sweep",
+                     "achieved": round(ab["sweep"] / t_sweep / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ab["sweep"] / t_sweep / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes": ab["sweep"]},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_reactor2d(args):
     """The paper's 2-D reactor ("Results & Discussion", Table 1, the p and
     w/h sweep of Fig. 6) on one z-plane of D3Q19, whose populations project
@@ -613,7 +681,7 @@ def main():
     ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
     ap.add_argument("--sweep", type=int, default=None, choices=(0, 1),
                     help="sweep variant: 1 node-compact (library default), 0 one wave per 64-voxel chunk")
-    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision", "membrane", "shard", "product", "reactor2d"),
+    ap.add_argument("--workload", default="single", choices=("single", "batch", "precision", "membrane", "shard", "product", "reactor2d", "stochastic"),
                     help="single: the 256^3 sample; batch: the 64-sample mixed batch; precision: 512^3 "
                          "with FP32/FP16/BF16 storage against the FP64 build; membrane: 1024x512x512 layer; "
                          "shard: one 128x512x512 x-slab of the membrane")
@@ -647,6 +715,8 @@ def main():
         return run_product(args)
     if args.workload == "reactor2d":
         return run_reactor2d(args)
+    if args.workload == "stochastic":
+        return run_stochastic(args)
     if args.workload == "shard":
         run_shard(args)
         return

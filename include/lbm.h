@@ -52,11 +52,21 @@ enum { LBM_FLUID = 0, LBM_INERT = 1, LBM_CATALYTIC = 2 };
 
 /* Sputtering matrix S_ij (probability that reactant arriving along j
  * re-enters along i, with sum_i S_ij = 1; Appendix, text after the
- * sputtering equations).  The paper calls S random; the library evolves its
- * expectation: UNIFORM gives each active direction of the node 1/b(k),
- * WEIGHTED gives direction i the share w_i / sum_{active} w, BOUNCEBACK
- * reverses each arrival (S = reversal). */
-typedef enum { LBM_SPUTTER_UNIFORM = 0, LBM_SPUTTER_WEIGHTED = 1, LBM_SPUTTER_BOUNCEBACK = 2 } lbm_sputter;
+ * sputtering equations).  The paper calls S random.  UNIFORM, WEIGHTED and
+ * BOUNCEBACK evolve an expectation: UNIFORM gives each active direction of
+ * the node 1/b(k), WEIGHTED gives direction i the share w_i / sum_{active} w,
+ * BOUNCEBACK reverses each arrival (S = reversal).  STOCHASTIC draws S: each
+ * arrival at node k along active link j leaves whole along one of the b(k)
+ * exit directions, each with probability 1/b(k) (expectation: UNIFORM), by
+ * Philox4x32-10 (Salmon et al., SC 2011) with key (seed low 32 bits, seed
+ * high 32 bits) and counter (step whose collision produced the arrival,
+ * voxel index of k, code(j), 0); the first output word r picks exit number
+ * floor(r b / 2^32) in ascending code order, code(c) = 9 (c_x + 1) +
+ * 3 (c_y + 1) + (c_z + 1).  Runs are reproducible for a given seed.  Not with
+ * the product lattice or in batches (LBM_EUNSUPPORTED). */
+typedef enum {
+    LBM_SPUTTER_UNIFORM = 0, LBM_SPUTTER_WEIGHTED = 1, LBM_SPUTTER_BOUNCEBACK = 2, LBM_SPUTTER_STOCHASTIC = 3
+} lbm_sputter;
 
 /* Velocity in the species equilibrium.  PASSIVE: the carrier velocity
  * (j_C + F/2) / rho_C (reactant passively transported by the carrier,
@@ -118,6 +128,7 @@ typedef struct {
     int32_t reserved;         /* must be 0 */
     double p_stick_product;   /* product sticking probability p_S^P in [0, 1]
                                  (the paper uses 0); ignored without product */
+    uint64_t seed;            /* key of the STOCHASTIC draws; ignored otherwise */
 } lbm_bc;
 
 /* Optional device hooks.  stream: a hipStream_t all work is queued on

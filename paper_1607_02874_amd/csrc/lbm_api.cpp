@@ -162,15 +162,21 @@ Geometry geometry(const lbm_ctx *c) {
     g.nz = c->nz;
     g.W = c->W;
     g.units = uint32_t(int64_t(c->ny) * c->nz * c->W);
-    g.pad = 0;
+    g.niface = uint32_t(c->niface);
     g.nfp = c->nfp;
     g.nfluid = c->nfluid;
     g.pos = c->d_pos;
     g.worder = c->d_worder;
     g.nwaves = uint32_t(c->nwaves);
     g.pad2 = 0;
+    g.ivox = c->d_iface_vox;
+    g.imask = c->d_iface_mask;
     return g;
 }
+
+// In and emission slots per interface node: one, or one per exit direction
+// for STOCHASTIC.
+int64_t nslot(const lbm_ctx *c) { return c->ph.sputter == SP_STOCHASTIC ? NSLOT : 1; }
 
 // Sweep blocks of the variant in use (the partial sums have one row each).
 int64_t active_sweep_blocks(const lbm_ctx *c) {
@@ -379,6 +385,7 @@ lbm_status one_step(lbm_ctx *c, bool fold, bool reduce, bool last) {
     if (all) (void)hipEventRecord(r->ev[2], c->stream);  // no separate boundary-flux kernel:
     if (all) (void)hipEventRecord(r->ev[3], c->stream);  // the sweep tallies the x-planes
     if (r) (void)hipEventRecord(r->ev[4], c->stream);
+    c->ph.step_ctr = uint32_t(t + 1);  // this sweep's collision makes the arrivals of step t + 1
     e = c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, ps, c->stream, prod)
                    : launch_sweep(g, c->ph, fin, fout, c->d_emit, ps, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "sweep kernel launch");
@@ -426,7 +433,9 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
         return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice needs PASSIVE coupling");
     if (!(g->pore_size > 0) || !std::isfinite(g->pore_size))
         return fail(nullptr, LBM_EINVAL, "pore_size must be finite and > 0");
-    if (bc->sputter < 0 || bc->sputter > 2) return fail(nullptr, LBM_EUNSUPPORTED, "unknown sputter mode");
+    if (bc->sputter < 0 || bc->sputter > 3) return fail(nullptr, LBM_EUNSUPPORTED, "unknown sputter mode");
+    if (bc->product && bc->sputter == LBM_SPUTTER_STOCHASTIC)
+        return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available with STOCHASTIC sputtering");
     if (bc->coupling < 0 || bc->coupling > 1) return fail(nullptr, LBM_EUNSUPPORTED, "unknown coupling mode");
     if (bc->species_x < 0 || bc->species_x > 2) return fail(nullptr, LBM_EUNSUPPORTED, "unknown species x-boundary");
     if (bc->storage < 0 || bc->storage > 3) return fail(nullptr, LBM_EUNSUPPORTED, "unknown storage format");
@@ -536,8 +545,9 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
         const int64_t chunks = rows * c.W;
         const int64_t blocks = ((chunks + 3) / 4 + 7) / 8 * 8;
         const bool compact = g->ny <= 1024 && g->nz <= 1024 && c.nfluid > 0;
-        int64_t bytes = r256((76 * nfp + niface + 1) * sb) + r256(chunks * int64_t(sizeof(ChunkInfo))) +
-                        r256(chunks * 4) + 2 * r256(niface * 4) + 3 * r256(niface * 8) +
+        const int64_t ns = bc->sputter == LBM_SPUTTER_STOCHASTIC ? NSLOT : 1;
+        int64_t bytes = r256((76 * nfp + ns * niface + 1) * sb) + r256(chunks * int64_t(sizeof(ChunkInfo))) +
+                        r256(chunks * 4) + 2 * r256(niface * 4) + 2 * r256(niface * 8) + r256(ns * niface * 8) +
                         r256((4 * blocks + 2 * ((niface + 255) / 256) + 2 * FOLD_BLOCKS * NPART) * 8) +
                         r256(int64_t(sizeof(DevTotals)));
         if (compact) bytes += r256(nfp * 4) + r256((c.nfluid + 63) / 64 * 4);
@@ -618,6 +628,8 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.storage = bc->storage;
     c->ph.product = bc->product;
     c->ph.p_stick_product = bc->product ? bc->p_stick_product : 0.0;
+    c->ph.seed = bc->seed;
+    c->ph.step_ctr = 0;  // the initial state is the collision of step 0
 
     try {
         c->vox.assign(g->voxels, g->voxels + c->n);
@@ -666,7 +678,8 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         // interface node) must each stay below 4 GiB.
         {
             const uint64_t sbytes = uint64_t(storage_bytes(c->ph.storage)), lim = uint64_t(1) << 32;
-            if (4 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(c->niface) * sbytes >= lim) {
+            if (4 * uint64_t(c->nfp) * sbytes >= lim || uint64_t(nslot(c) * c->niface) * sbytes >= lim ||
+                uint64_t(nslot(c) * c->niface) >= (uint64_t(1) << 32)) {
                 release(c);
                 delete c;
                 return fail(nullptr, LBM_EUNSUPPORTED,
@@ -687,7 +700,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         c->d_iface_mask = static_cast<uint32_t *>(dev_alloc(c, imask.size() * 4));
         c->d_iface_scale = static_cast<double *>(dev_alloc(c, iscale.size() * 8));
         c->d_acc = static_cast<double *>(dev_alloc(c, size_t(c->niface) * 8));
-        c->d_inacc = static_cast<unsigned long long *>(dev_alloc(c, size_t(c->niface) * 8));
+        c->d_inacc = static_cast<unsigned long long *>(dev_alloc(c, size_t(nslot(c) * c->niface) * 8));
         if (c->compact_ok) {
             c->d_pos = static_cast<uint32_t *>(dev_alloc(c, pos.size() * 4));
             c->d_worder = static_cast<uint32_t *>(dev_alloc(c, worder.size() * 4));
@@ -696,7 +709,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         // element per interface node, indexed by interface index, plus one:
         // the sweeps load element 0 for lanes without a catalytic source,
         // which must exist when there is no interface node).
-        char *pool = static_cast<char *>(dev_alloc(c, (size_t(76) * c->nfp + size_t(c->niface) + 1) * sb));
+        char *pool = static_cast<char *>(dev_alloc(c, (size_t(76) * c->nfp + size_t(nslot(c) * c->niface) + 1) * sb));
         if (pool) {
             c->d_pop[0] = pool;
             c->d_pop[1] = pool + size_t(38) * c->nfp * sb;
@@ -742,7 +755,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
             up(c->d_worder, worder.data(), worder.size() * 4);
         }
         if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, (size_t(c->niface) + 1) * sb, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, (size_t(nslot(c) * c->niface) + 1) * sb, c->stream);
         DevTotals t0{};
         t0.mass_gas = double(c->nfluid) * bc->rho0;
         t0.mass_species = double(c->nfluid) * bc->c0;
@@ -1145,7 +1158,7 @@ lbm_status lbm_save(lbm_ctx *c, const char *path) {
     pack_params(c, h.params);
     hipError_t e = hipMemcpyAsync(&h.tot, c->d_tot, sizeof(DevTotals), hipMemcpyDeviceToHost, c->stream);
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t emit = size_t(c->niface) * storage_bytes(c->ph.storage);
+    const size_t emit = size_t(nslot(c) * c->niface) * storage_bytes(c->ph.storage);
     const size_t base = 2 * pop + emit + size_t(c->niface) * 8, pbytes = ckpt_product_bytes(c);
     std::vector<char> buf;
     try {
@@ -1194,7 +1207,7 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
         return fail(c, LBM_EINVAL, "checkpoint does not match this context's geometry or parameters");
     }
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t emit = size_t(c->niface) * storage_bytes(c->ph.storage);
+    const size_t emit = size_t(nslot(c) * c->niface) * storage_bytes(c->ph.storage);
     const size_t base = 2 * pop + emit + size_t(c->niface) * 8, pbytes = ckpt_product_bytes(c);
     std::vector<char> buf;
     try {
@@ -1223,6 +1236,7 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_tot, &h.tot, sizeof(DevTotals), hipMemcpyHostToDevice, c->stream);
     c->step = h.step;
     c->cur = int(h.cur);
+    c->ph.step_ctr = uint32_t(c->step);
     // In(k) of the pending interface is derived state: rebuild it from the
     // current post-collision populations (the same integer terms the sweep adds)
     if (e == hipSuccess) e = launch_in_init(geometry(c), c->ph, interface_list(c), c->d_pop[c->cur], c->stream);
@@ -1270,7 +1284,7 @@ struct Saved {
 
 lbm_status save_written(lbm_ctx *c, Saved &sv, void *(*alloc)(lbm_ctx *, size_t)) {
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t link = size_t(c->niface) * 8;
+    const size_t link = size_t(nslot(c) * c->niface) * 8;
     sv.pop = alloc(c, pop);
     sv.link = alloc(c, std::max<size_t>(link, 256));
     if (!sv.pop || !sv.link) return fail(c, LBM_ENOMEM, "autotune scratch allocation failed");
@@ -1291,7 +1305,7 @@ lbm_status save_written(lbm_ctx *c, Saved &sv, void *(*alloc)(lbm_ctx *, size_t)
 
 lbm_status restore_written(lbm_ctx *c, Saved &sv) {
     const size_t pop = size_t(38) * c->nfp * storage_bytes(c->ph.storage);
-    const size_t link = size_t(c->niface) * 8;
+    const size_t link = size_t(nslot(c) * c->niface) * 8;
     hipError_t e = hipMemcpyAsync(c->d_pop[1 - c->cur], sv.pop, pop, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess && link) e = hipMemcpyAsync(c->d_inacc, sv.link, link, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess && sv.popP)
@@ -1373,6 +1387,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
             float ms = 0.0f;
             ProdStep pst = c->ph.product ? prod_step(c, c->step) : ProdStep{};
             const ProdStep *prod = c->ph.product ? &pst : nullptr;
+            c->ph.step_ctr = uint32_t(c->step + 1);
             st = time_launches(c->stream, reps, [&]() {
                 return c->compact ? launch_sweep_c(g, c->ph, fin, fout, c->d_emit, c->d_part, c->stream, prod)
                                   : launch_sweep(g, c->ph, fin, fout, c->d_emit, c->d_part, c->stream);
@@ -1595,6 +1610,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
     for (int32_t i = 0; i < n; ++i)
         if (bc[i].product != 0)
             return bfail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available in batches");
+        else if (bc[i].sputter == LBM_SPUTTER_STOCHASTIC)
+            return bfail(nullptr, LBM_EUNSUPPORTED, "STOCHASTIC sputtering is not available in batches");
     for (int32_t i = 1; i < n; ++i)
         if (bc[i].storage != bc[0].storage || bc[i].sputter != bc[0].sputter || bc[i].coupling != bc[0].coupling ||
             bc[i].species_x != bc[0].species_x)

@@ -43,7 +43,12 @@ constexpr uint32_t NB_GAS = 1u << 31, NB_CAT = 1u << 30, NB_IDX = NB_CAT - 1u;
 static_assert(sizeof(ChunkInfo) == 32, "ChunkInfo must stay 32 bytes (one scalar load)");
 
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_F64 = 3 };
-enum { SP_UNIFORM = 0, SP_WEIGHTED = 1, SP_BOUNCEBACK = 2 };
+enum { SP_UNIFORM = 0, SP_WEIGHTED = 1, SP_BOUNCEBACK = 2, SP_STOCHASTIC = 3 };
+// STOCHASTIC keeps one In and one emission slot per exit direction of each
+// interface node, direction-major: slot (e - 1) * n_interface + k for exit
+// direction e, so lanes that pull from neighbouring interface nodes along
+// one direction read neighbouring slots.
+constexpr int NSLOT = 18;
 enum { CP_PASSIVE = 0, CP_BARYCENTRIC = 1 };
 enum { XB_PERIODIC = 0, XB_RESERVOIR = 1, XB_INFLOW = 2 };
 
@@ -73,7 +78,7 @@ struct Geometry {
     unsigned long long *inacc;  // per interface node: In(k) of the sweep in progress, fixed point (see Interface)
     int32_t nx, ny, nz, W;    // W = ceil(nx / 64)
     uint32_t units;           // ny * nz * W waves
-    int32_t pad;
+    uint32_t niface;          // interface nodes (stride of the STOCHASTIC slot arrays)
     int64_t nfp;              // elements per direction in a population buffer
     int64_t nfluid;
     // Node-compact sweep (one lane per gas node, 64 consecutive storage
@@ -82,6 +87,9 @@ struct Geometry {
     const uint32_t *worder;   // launch order of the 64-node waves
     uint32_t nwaves;          // ceil(nfluid / 64)
     int32_t pad2;
+    // interface list (voxel index and active-link mask per interface node),
+    // read by the STOCHASTIC sweeps to key and resolve each draw
+    const uint32_t *ivox, *imask;
 };
 
 // Physical parameters in FP64; kernels convert to their compute type.
@@ -95,6 +103,9 @@ struct Physics {
     int32_t sputter, coupling, species_x, storage;
     double p_stick_product;       // p_S^P
     int32_t product, pad;         // 1: the product lattice P is evolved
+    uint64_t seed;                // STOCHASTIC: Philox key
+    uint32_t step_ctr;            // STOCHASTIC: step whose collision produces the arrivals a launch sums
+    uint32_t pad3;
 };
 
 // Device buffers of the product lattice for one step (all null / unused when

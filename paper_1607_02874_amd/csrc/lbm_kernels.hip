@@ -102,6 +102,7 @@ struct PhysK {
     double c_in;      // reservoir concentration (influx tally)
     double in_scale, in_unscale;  // fixed-point scale of the In(k) sums and its inverse
     int32_t sputter, coupling, species_x;
+    uint32_t seed_lo, seed_hi, step_ctr;  // STOCHASTIC draws
 };
 
 template <typename T>
@@ -127,7 +128,72 @@ PhysK<T> to_kernel(const Physics &p) {
     k.sputter = p.sputter;
     k.coupling = p.coupling;
     k.species_x = p.species_x;
+    k.seed_lo = uint32_t(p.seed);
+    k.seed_hi = uint32_t(p.seed >> 32);
+    k.step_ctr = p.step_ctr;
     return k;
+}
+
+// ------------------------------------------------- random sputtering --
+// STOCHASTIC: each arrival at interface node k along active link j leaves
+// whole along one of the b(k) exit directions {opp(j')}, picked with
+// probability 1/b by Philox4x32-10 (Salmon et al., SC 2011): key (seed low,
+// seed high), counter (step, voxel index of k, code(j), 0), first output word
+// r, exit number floor(r b / 2^32) in ascending code order, where code(c) =
+// 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1) labels a velocity independently of
+// the direction numbering.
+__host__ __device__ constexpr int vcode(int i) { return 9 * (CX[i] + 1) + 3 * (CY[i] + 1) + (CZ[i] + 1); }
+
+// Directions 1..18 in ascending velocity code.
+struct CodeOrder {
+    int d[18];
+};
+__host__ __device__ constexpr CodeOrder code_order() {
+    CodeOrder o{};
+    int n = 0;
+    for (int code = 0; code < 27; ++code)
+        for (int i = 1; i < 19; ++i)
+            if (vcode(i) == code) o.d[n++] = i;
+    return o;
+}
+constexpr CodeOrder CODE_ORDER = code_order();
+
+__device__ __forceinline__ uint32_t philox_first(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return c0;
+}
+
+// The exit direction (library numbering) of an arrival along link j at the
+// interface node with voxel index vox and active-link mask `mask`.
+template <typename T>
+__device__ __forceinline__ int random_exit(const PhysK<T> &ph, uint32_t vox, uint32_t mask, int j) {
+    const uint32_t b = uint32_t(__popc(mask));
+    const uint32_t r = philox_first(ph.step_ctr, vox, uint32_t(vcode(j)), 0u, ph.seed_lo, ph.seed_hi);
+    const uint32_t pick = uint32_t((uint64_t(r) * b) >> 32);
+    int e = 0;
+    uint32_t n = 0;
+#pragma unroll
+    for (int t = 0; t < 18; ++t) {
+        const int d = CODE_ORDER.d[t];
+        const bool exit = (mask >> opp(d)) & 1u;
+        e = (exit && n == pick) ? d : e;
+        n += exit ? 1u : 0u;
+    }
+    return e;
 }
 
 // One term of an In(k) sum, f*_j = w_j (h_j + c_ref) of the stored value, in
@@ -362,6 +428,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     const int sputter = SP >= 0 ? (SP & 3) : ph.sputter;
     const bool inflow = SP >= 0 ? (SP & SP_INFLOW_FLAG) != 0 : ph.species_x == XB_INFLOW;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
+    const bool stoch = sputter == SP_STOCHASTIC;  // per-exit emission slots (already divided by w_i)
     auto base = [&](int slot) { return in.p(slot); };
     const uint32_t own_b = u.idx * PB;
     // wave-uniform shape of the chunk
@@ -446,7 +513,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
             ro[i] = ld_at(static_cast<const S *>(base(pair_slot(i))),
                           (lane_in(outlet & I.fluid) ? rank_of_mask(I.fluid, I.base) * PB + half : bb_b) + SB);
         // emission of a catalytic source, by interface index (element 0 when not used)
-        re[i] = ld_at(emit, lane_in(EMIT) ? irank * SB : 0u);
+        re[i] = ld_at(emit, lane_in(EMIT) ? (stoch ? uint32_t(i - 1) * g.niface + irank : irank) * SB : 0u);
         if (kidx) kidx[(i - 1) * 256 + threadIdx.x] = irank;
         cat_bits |= lane_in(CAT) ? (1u << i) : 0u;
     }
@@ -511,6 +578,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     const int sputter = SP >= 0 ? (SP & 3) : ph.sputter;
     const bool inflow = SP >= 0 ? (SP & SP_INFLOW_FLAG) != 0 : ph.species_x == XB_INFLOW;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
+    const bool stoch = sputter == SP_STOCHASTIC;  // per-exit emission slots (already divided by w_i)
     auto base = [&](int slot) { return in.p(slot); };
     const uint32_t own_b = idx * PB;
     const uint32_t xl = uint32_t(x) & 63u, chunk = uint32_t(x) >> 6;
@@ -609,7 +677,9 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             uint32_t c_b = F ? pull_b : bb_b;
             opaque(c_b);
             pc[i] = ld_pop<ST>(base(pair_slot(i)), c_b);
-            uint32_t v_b = bounce ? 0u : kidx[(i - 1) * 256 + threadIdx.x] * SB;
+            uint32_t v_b = bounce ? 0u
+                                  : (stoch ? uint32_t(i - 1) * g.niface + kidx[(i - 1) * 256 + threadIdx.x]
+                                           : kidx[(i - 1) * 256 + threadIdx.x]) * SB;
             opaque(v_b);
             re[i] = ld_at(emit, v_b);
             ro[i] = S(0);
@@ -792,6 +862,30 @@ __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const u
     }
 }
 
+// STOCHASTIC: the same terms, each added to the In slot of the exit its draw
+// picks.  Slots receive a random number of terms, so the terms are plain
+// two's-complement integers (the fixed-point pattern minus MAGIC_BITS) and
+// the reader subtracts nothing.
+template <int ST>
+__device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned long long *inacc,
+                                                     const uint32_t *kidx, uint32_t cat_bits,
+                                                     const PhysK<typename Store<ST>::T> &ph,
+                                                     const typename Store<ST>::T (&hR)[19]) {
+    using T = typename Store<ST>::T;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        if ((cat_bits >> i) & 1u) {
+            const int j = opp(i);  // the link direction as seen from the interface node
+            const uint32_t k = kidx[(i - 1) * 256 + threadIdx.x];
+            const int e = random_exit(ph, glb(g.ivox)[k], glb(g.imask)[k], j);
+            const T stored = Store<ST>::cv(Store<ST>::enc(hR[j]));
+            const unsigned long long term = in_term<T>(wgt<T>(j), stored, ph.cref, ph.in_scale) - MAGIC_BITS;
+            (void)__hip_atomic_fetch_add(&glb(inacc)[uint64_t(uint32_t(e - 1)) * g.niface + k], term,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <int ST>
 __device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double c_in, const char *pop,
                                              uint32_t stride, uint32_t idx, bool first_x, bool last_x) {
@@ -892,7 +986,12 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
             st_at(static_cast<P *>(out.p(dslot(i))), own_b, pop_pair<ST>(hC[i], hR[i]));
         }
         // In(k) of the next step's interface: what leaves towards interface nodes
-        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
+        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
+            if constexpr ((SP & 3) == SP_STOCHASTIC)
+                accumulate_in_random<ST>(g, g.inacc, kidx, cat_bits, ph, hR);
+            else
+                accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
+        }
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, u.idx, first_x,
                                                last_x);
@@ -978,7 +1077,12 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
                 accp[2] += f.out;
             }
         }
-        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
+        if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
+            if constexpr ((SP & 3) == SP_STOCHASTIC)
+                accumulate_in_random<ST>(g, g.inacc, kidx, cat_bits, ph, hR);
+            else
+                accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
+        }
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, idx, first_x,
                                                last_x);
@@ -1119,7 +1223,27 @@ __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::
     using S = typename Store<ST>::S;
     const int64_t k = int64_t(block) * blockDim.x + threadIdx.x;
     double arrived[1] = {0.0}, arrived_p[1] = {0.0};
-    if (k < it.n) {
+    if (k < it.n && ph.sputter == SP_STOCHASTIC) {
+        // one In slot per exit direction; each re-emits (1 - p_S) of its sum
+        // along its own exit (stored divided by w_e, like WEIGHTED's E)
+        const uint32_t m = glb(it.mask)[k];
+        double in = 0.0;
+#pragma unroll
+        for (int e = 1; e < 19; ++e) {
+            if ((m >> opp(e)) & 1u) {
+                const uint64_t slot = uint64_t(uint32_t(e - 1)) * uint64_t(it.n) + uint64_t(k);
+                const long long fixed = static_cast<long long>(glb(it.inacc)[slot]);
+                glb(it.inacc)[slot] = 0ull;
+                const double ine = (fixed > (1ll << 55) || fixed < -(1ll << 55)) ? __builtin_nan("")
+                                                                                 : double(fixed) * ph.in_unscale;
+                in += ine;
+                st_at(emit, uint32_t(slot) * uint32_t(sizeof(S)),
+                      Store<ST>::enc(T(double(ph.keep) * ine * inv_wgt<double>(e))));
+            }
+        }
+        glb(it.acc)[k] += in;
+        arrived[0] = in;
+    } else if (k < it.n) {
         const uint32_t b = uint32_t(__popc(glb(it.mask)[k]));
         const double in = take_in(it.inacc, k, b, ph.in_unscale);
         glb(it.acc)[k] += in;
@@ -1195,7 +1319,9 @@ __global__ __launch_bounds__(256) void k_in_init(Geometry g, PhysK<typename Stor
     const int x = int(v % uint32_t(g.nx));
     const int row = int(v / uint32_t(g.nx));
     const int y = row % g.ny, z = row / g.ny;
-    unsigned long long sum = 0ull;
+    unsigned long long sum = 0ull, slots[NSLOT];
+#pragma unroll
+    for (int e = 0; e < NSLOT; ++e) slots[e] = 0ull;
 #pragma unroll
     for (int j = 1; j < 19; ++j) {
         if (mask & (1u << j)) {
@@ -1205,10 +1331,23 @@ __global__ __launch_bounds__(256) void k_in_init(Geometry g, PhysK<typename Stor
             zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
             bool fl;
             const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
-            sum += in_term<T>(wgt<T>(j), Store<ST>::ld(fin + 2 * (dslot(j) * g.nfp + r) + 1), ph.cref, ph.in_scale);
+            const unsigned long long term =
+                in_term<T>(wgt<T>(j), Store<ST>::ld(fin + 2 * (dslot(j) * g.nfp + r) + 1), ph.cref, ph.in_scale);
+            sum += term;
+            if (ph.sputter == SP_STOCHASTIC) {
+                const int e = random_exit(ph, v, mask, j);
+#pragma unroll
+                for (int d = 1; d < 19; ++d)
+                    if (d == e) slots[d - 1] += term - MAGIC_BITS;
+            }
         }
     }
-    it.inacc[k] = sum;
+    if (ph.sputter == SP_STOCHASTIC) {
+#pragma unroll
+        for (int e = 0; e < NSLOT; ++e) it.inacc[uint64_t(uint32_t(e)) * uint64_t(it.n) + uint64_t(k)] = slots[e];
+    } else {
+        it.inacc[k] = sum;
+    }
 }
 
 // In_P(k) of every interface node from a product post-collision buffer (one
@@ -1508,6 +1647,8 @@ hipError_t dispatch_sp(int code, F &&f) {
         case SP_UNIFORM | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_UNIFORM | SP_INFLOW_FLAG>{});
         case SP_WEIGHTED | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_WEIGHTED | SP_INFLOW_FLAG>{});
         case SP_BOUNCEBACK | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_BOUNCEBACK | SP_INFLOW_FLAG>{});
+        case SP_STOCHASTIC: return f(std::integral_constant<int, SP_STOCHASTIC>{});
+        case SP_STOCHASTIC | SP_INFLOW_FLAG: return f(std::integral_constant<int, SP_STOCHASTIC | SP_INFLOW_FLAG>{});
         default: return hipErrorInvalidValue;
     }
 }

@@ -23,7 +23,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_ENONFINITE, LBM_EUN
 STATUS_NAMES = {0: "LBM_OK", 1: "LBM_EINVAL", 2: "LBM_ENOMEM", 3: "LBM_EDEVICE", 4: "LBM_ESTATE",
                 5: "LBM_ENONFINITE", 6: "LBM_EUNSUPPORTED"}
 FLUID, INERT, CATALYTIC = 0, 1, 2
-SPUTTER_UNIFORM, SPUTTER_WEIGHTED, SPUTTER_BOUNCEBACK = 0, 1, 2
+SPUTTER_UNIFORM, SPUTTER_WEIGHTED, SPUTTER_BOUNCEBACK, SPUTTER_STOCHASTIC = 0, 1, 2, 3
 COUPLE_PASSIVE, COUPLE_BARYCENTRIC = 0, 1
 XBC_PERIODIC, XBC_RESERVOIR, XBC_INFLOW = 0, 1, 2
 STORE_F32, STORE_F16, STORE_BF16, STORE_F64 = 0, 1, 2, 3
@@ -52,7 +52,7 @@ class lbm_bc(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("p_stick", ctypes.c_double), ("c_inlet", ctypes.c_double),
                 ("rho0", ctypes.c_double), ("c0", ctypes.c_double), ("c_ref", ctypes.c_double),
                 ("force", ctypes.c_double * 3), ("product", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("p_stick_product", ctypes.c_double)]
+                ("p_stick_product", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -217,10 +217,10 @@ def _geometry(vox, pore_size):
 
 def _bc(sputter=SPUTTER_UNIFORM, coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32,
         p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0), product=False,
-        p_stick_product=0.0):
+        p_stick_product=0.0, seed=0):
     return lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
                   float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]),
-                  int(bool(product)), 0, float(p_stick_product))
+                  int(bool(product)), 0, float(p_stick_product), int(seed))
 
 
 def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc_kw):

@@ -20,7 +20,7 @@ def test_every_declared_function_is_exported():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_geometry) == 32
-    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8
+    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8 + 8
     assert ctypes.sizeof(lbm.lbm_totals_t) == 8 + 6 * 8 + 8 + 4 * 8
     assert ctypes.sizeof(lbm.lbm_device) == 32
 
@@ -136,3 +136,21 @@ def test_inspect_counts_the_product_buffers():
     grow = b["device_bytes"] - a["device_bytes"]
     assert grow >= (38 * nfp + a["n_interface"]) * 4 + 2 * a["n_interface"] * 8
     assert grow < (38 * nfp + a["n_interface"]) * 4 + 2 * a["n_interface"] * 8 + 64 * 1024
+
+
+def test_stochastic_sputter_without_product_lattice():
+    vox = np.zeros((4, 4, 8), np.uint8)
+    with pytest.raises(lbm.LbmError) as e:
+        _create(vox, product=True, sputter=lbm.SPUTTER_STOCHASTIC)
+    assert e.value.status == lbm.LBM_EUNSUPPORTED
+
+
+def test_inspect_counts_the_stochastic_slots():
+    """STOCHASTIC keeps 18 In and emission slots per interface node."""
+    from paper_1607_02874_amd import inputs
+
+    vox = inputs.PLAIN_32.voxels()
+    a = lbm.inspect(vox, 1.0, tau=(0.8, 0.7), pore_size=4.0)
+    b = lbm.inspect(vox, 1.0, tau=(0.8, 0.7), pore_size=4.0, sputter=lbm.SPUTTER_STOCHASTIC)
+    grow = b["device_bytes"] - a["device_bytes"]
+    assert abs(grow - 17 * a["n_interface"] * (8 + 4)) < 1024

@@ -1,0 +1,161 @@
+"""Parity of the random sputtering matrix (STOCHASTIC) on the HIP path,
+called through the C ABI, with the FP64 oracle.  Both sides draw each exit
+with Philox4x32-10 keyed by (seed, step, voxel, velocity code of the link), so
+the draws are the same integers and the fields agree to the usual bars: FP64
+build 1e-12, FP32 1e-5 (L2-relative over the gas nodes)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_02874_amd import inputs, lbm
+
+from parity import XBC, l2rel
+
+pytestmark = pytest.mark.gpu
+
+F32, F16, BF16, F64 = 0, 1, 2, 3
+PLAIN = inputs.PLAIN_32
+SEED = 0x0123_4567_89AB_CDEF
+
+
+def scase(vox, steps, **kw):
+    c = dict(vox=np.ascontiguousarray(vox, np.uint8), steps=steps, da=0.3, tau=(0.8, 0.7), pore_size=4.0,
+             p_stick=0.6, c_inlet=1.0, c0=0.1, force=(2e-4, 3e-5, -2e-5), species_x="RESERVOIR", seed=SEED)
+    c.update(kw)
+    return c
+
+
+def run_oracle(c):
+    p, _ = oracle.p_from_da(c["da"], c["pore_size"])
+    o = oracle.Oracle(c["vox"], tau=c["tau"], p=p, p_stick=c["p_stick"], c_inlet=c["c_inlet"], c0=c["c0"],
+                      force=c["force"], sputter=oracle.STOCHASTIC, species_x=XBC[c["species_x"]], seed=c["seed"])
+    o.step(c["steps"])
+    rho, u, conc = o.fields()
+    out = dict(rho=rho, u=u, conc=conc, conv=o.conversion_map(), totals=o.totals())
+    o.close()
+    return out
+
+
+def make_sim(c, storage):
+    return lbm.Sim(c["vox"], da=c["da"], tau=c["tau"], pore_size=c["pore_size"], p_stick=c["p_stick"],
+                   c_inlet=c["c_inlet"], c0=c["c0"], force=c["force"], sputter=lbm.SPUTTER_STOCHASTIC,
+                   species_x=XBC[c["species_x"]], storage=storage, seed=c["seed"])
+
+
+def run_gpu(c, storage, variant=None, steps=None):
+    with make_sim(c, storage) as s:
+        if variant is not None:
+            s.set_tunable(lbm.TUNE_SWEEP, variant)
+        if steps is None:
+            s.step(c["steps"])
+        else:
+            for n in steps:
+                s.step(n)
+        rho, u, conc = s.fields()
+        return dict(rho=rho, u=u, conc=conc, conv=s.conversion_map(), totals=s.totals())
+
+
+def errs(g, r, vox):
+    gas, cat = vox == inputs.FLUID, vox == inputs.CATALYTIC
+    e = {k: l2rel(g[k], r[k], gas) for k in ("rho", "u", "conc")}
+    e["conv"] = l2rel(g["conv"], r["conv"], cat)
+    mass = abs(r["totals"]["mass_gas"])
+    for k in ("mass_species", "converted", "lost", "influx", "outflux"):
+        a, b = g["totals"][k], r["totals"][k]
+        e["t_" + k] = abs(a - b) / max(abs(b), mass * 1e-9, 1e-300)
+    print({k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    return e
+
+
+@pytest.mark.parametrize("species_x", ["RESERVOIR", "INFLOW", "PERIODIC"])
+@pytest.mark.parametrize("variant", [1, 0])
+def test_stochastic_fp64_matches_oracle(species_x, variant):
+    c = scase(PLAIN.voxels(), 50, species_x=species_x)
+    ref = run_oracle(c)
+    e = errs(run_gpu(c, F64, variant), ref, c["vox"])
+    for k, v in e.items():
+        assert v < (1e-11 if k.startswith("t_") else 1e-12), (k, v)
+
+
+def test_stochastic_fp32_matches_oracle():
+    c = scase(PLAIN.voxels(), 120, species_x="INFLOW")
+    ref = run_oracle(c)
+    e = errs(run_gpu(c, F32), ref, c["vox"])
+    for k, v in e.items():
+        assert v < 1e-5, (k, v)
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 1), (5, 6, 63), (4, 3, 65), (3, 4, 130), (9, 2, 7)])
+def test_stochastic_ragged_shapes(shape):
+    rng = np.random.default_rng(11 * sum(shape))
+    vox = np.where(rng.random(shape) < 0.3, 2, 0).astype(np.uint8)
+    vox[rng.random(shape) < 0.1] = 1
+    if shape[2] > 2:
+        vox[:, :, 0] = 0
+    for species_x in ("RESERVOIR", "PERIODIC"):
+        c = scase(vox, 25, pore_size=2.0, species_x=species_x)
+        ref = run_oracle(c)
+        for variant in (1, 0):
+            e = errs(run_gpu(c, F64, variant), ref, vox)
+            for k, v in e.items():
+                assert v < (1e-11 if k.startswith("t_") else 1e-12), (shape, species_x, variant, k, v)
+
+
+def test_stochastic_draws_depend_on_step_not_on_call_split():
+    """The draw of an arrival is keyed by the step that produced it, so
+    splitting the steps over calls changes nothing, bit for bit."""
+    c = scase(PLAIN.voxels(), 23)
+    a = run_gpu(c, F32)
+    b = run_gpu(c, F32, steps=(1, 2, 7, 13))
+    for k in ("rho", "u", "conc", "conv"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["totals"] == b["totals"]
+
+
+def test_stochastic_seed_reproducible_and_effective():
+    c = scase(PLAIN.voxels(), 30)
+    a, b = run_gpu(c, F32), run_gpu(c, F32)
+    d = run_gpu(dict(c, seed=SEED + 1), F32)
+    assert np.array_equal(a["conc"], b["conc"]) and a["totals"] == b["totals"]
+    assert not np.array_equal(a["conc"], d["conc"])
+
+
+def test_stochastic_checkpoint_resume_is_bit_identical(tmp_path):
+    c = scase(PLAIN.voxels(), 0, species_x="INFLOW")
+    path = str(tmp_path / "s.ckpt")
+    with make_sim(c, F32) as a:
+        a.step(17)
+        a.save(path)
+        a.step(19)
+        want = (a.fields(), a.totals(), a.conversion_map())
+    with make_sim(c, F32) as b:
+        b.load(path)
+        b.step(19)
+        got = (b.fields(), b.totals(), b.conversion_map())
+    for x, y in zip(want[0], got[0]):
+        assert np.array_equal(x, y)
+    assert want[1] == got[1]
+    assert np.array_equal(want[2], got[2])
+
+
+def test_stochastic_autotune_leaves_state_unchanged():
+    c = scase(PLAIN.voxels(), 0)
+    with make_sim(c, F32) as a, make_sim(c, F32) as b:
+        a.step(11)
+        b.step(11)
+        a.autotune(reps=2)
+        for w in (lbm.TUNE_SWEEP, lbm.TUNE_YTILE):
+            b.set_tunable(w, a.get_tunable(w))
+        a.step(9)
+        b.step(9)
+        assert np.array_equal(a.fields()[2], b.fields()[2])
+        assert a.totals() == b.totals()
+
+
+def test_stochastic_requests_the_library_rejects():
+    c = scase(PLAIN.voxels(), 0)
+    smp = dict(vox=c["vox"], da=c["da"], tau=c["tau"], pore_size=c["pore_size"], sputter=lbm.SPUTTER_STOCHASTIC)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Batch([smp, smp])
+    assert e.value.status == lbm.LBM_EUNSUPPORTED
