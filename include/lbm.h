@@ -62,8 +62,9 @@ enum { LBM_FLUID = 0, LBM_INERT = 1, LBM_CATALYTIC = 2 };
  * high 32 bits) and counter (step whose collision produced the arrival,
  * voxel index of k, code(j), 0); the first output word r picks exit number
  * floor(r b / 2^32) in ascending code order, code(c) = 9 (c_x + 1) +
- * 3 (c_y + 1) + (c_z + 1).  Runs are reproducible for a given seed.  Not with
- * the product lattice or in batches (LBM_EUNSUPPORTED). */
+ * 3 (c_y + 1) + (c_z + 1).  Runs are reproducible for a given seed; the
+ * step enters the counter modulo 2^32.  Not with the product lattice or in
+ * batches (LBM_EUNSUPPORTED). */
 typedef enum {
     LBM_SPUTTER_UNIFORM = 0, LBM_SPUTTER_WEIGHTED = 1, LBM_SPUTTER_BOUNCEBACK = 2, LBM_SPUTTER_STOCHASTIC = 3
 } lbm_sputter;
@@ -347,11 +348,12 @@ lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable);
 lbm_status lbm_kernel_times(lbm_ctx *c, lbm_kernel_times_t *t);
 
 /*
- * Checkpoint of the full state (populations, emission and accumulator
- * arrays, totals, step) with a header that records the geometry hash and the
- * parameters; lbm_load requires a context created with the same geometry and
- * parameters (LBM_EINVAL otherwise) and makes the next steps bit-identical to
- * an uninterrupted run.  Synchronise the stream.
+ * Checkpoint of the full state (populations of every lattice, emission and
+ * accumulator arrays, totals, step) with a header that records the geometry
+ * hash and the parameters (product lattice and STOCHASTIC seed included);
+ * lbm_load requires a context created with the same geometry and parameters
+ * (LBM_EINVAL otherwise) and makes the next steps bit-identical to an
+ * uninterrupted run.  Synchronise the stream.
  */
 lbm_status lbm_save(lbm_ctx *c, const char *path);
 lbm_status lbm_load(lbm_ctx *c, const char *path);

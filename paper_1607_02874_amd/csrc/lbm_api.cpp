@@ -1131,6 +1131,8 @@ void pack_params(const lbm_ctx *c, double *p) {
     p[14] = c->ph.species_x;
     p[15] = c->ph.product;
     p[16] = c->ph.p_stick_product;
+    // the STOCHASTIC key, bit for bit (the checks compare bytes)
+    std::memcpy(&p[17], &c->ph.seed, sizeof(uint64_t));
 }
 
 // Product-lattice bytes of a checkpoint: P buffers A and B, E_P, Acc_P.

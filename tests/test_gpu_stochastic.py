@@ -137,6 +137,10 @@ def test_stochastic_checkpoint_resume_is_bit_identical(tmp_path):
         assert np.array_equal(x, y)
     assert want[1] == got[1]
     assert np.array_equal(want[2], got[2])
+    # the seed is part of the state: another seed's context does not load it
+    with make_sim(dict(c, seed=SEED + 1), F32) as d:
+        with pytest.raises(lbm.LbmError):
+            d.load(path)
 
 
 def test_stochastic_autotune_leaves_state_unchanged():
