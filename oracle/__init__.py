@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
                 ("species_x", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("p_stick_product", ctypes.c_double),
                 ("product", ctypes.c_int32), ("pad2", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("wall_diffuse", ctypes.c_double)]
 
 
 _lib = None
@@ -153,7 +153,7 @@ class Oracle:
 
     def __init__(self, vox, tau=(0.8, 0.7), p=0.1, p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0,
                  force=(0.0, 0.0, 0.0), sputter=UNIFORM, coupling=PASSIVE, species_x=XRESERVOIR,
-                 product=False, p_stick_product=0.0, seed=0):
+                 product=False, p_stick_product=0.0, seed=0, wall_diffuse=0.0):
         vox = np.ascontiguousarray(vox, dtype=np.uint8)
         assert vox.ndim == 3
         self.nz, self.ny, self.nx = vox.shape
@@ -168,6 +168,7 @@ class Oracle:
         prm.sputter, prm.coupling, prm.species_x = int(sputter), int(coupling), int(species_x)
         prm.product, prm.p_stick_product = int(bool(product)), float(p_stick_product)
         prm.seed = int(seed)
+        prm.wall_diffuse = float(wall_diffuse)
         self.params = prm
         h = lib().orc_create(self.nx, self.ny, self.nz, vox.ctypes.data, ctypes.byref(prm))
         if not h:

@@ -53,7 +53,14 @@
  *     reactant and product are passively transported by the carrier) or
  *     BARYCENTRIC (the common velocity of the moment equations);
  *   - halfway bounce-back at every solid link of the gas, and at inert-solid
- *     links of the species;
+ *     links of the species; optionally the gas wall reflects a fraction
+ *     sigma diffusely (Maxwell's accommodation model; in lattice Boltzmann
+ *     form, Ansumali and Karlin, Phys. Rev. E 66, 026311 (2002)): at a gas
+ *     node, the populations pulled from solid sources share the mass the node
+ *     sends into the wall, M, in proportion to w_i (the equilibrium of a wall
+ *     at rest), f_i = (1 - sigma) f*_opp(i) + sigma w_i M / W, with W the sum
+ *     of w_i over those directions; sigma = 0 is bounce-back.  The rarefaction
+ *     (Kn) enters through tau; sigma is the wall's accommodation;
  *   - sputter timing: what arrives at a catalytic node during a step leaves it
  *     along the reversed active links at the next streaming (link-wise,
  *     one step, like halfway bounce-back);
@@ -118,6 +125,7 @@ typedef struct {
     double p_stick_product;      /* sticking probability p_S^P of the product */
     int32_t product, pad2;       /* 1: evolve the product lattice P */
     uint64_t seed;               /* key of the STOCHASTIC sputter draws */
+    double wall_diffuse;         /* sigma: diffuse fraction of the gas wall reflection */
 } orc_params;
 
 typedef struct {
@@ -594,13 +602,26 @@ static void stream(orc *o)
                 long n = node(o, x, y, z);
                 if (o->vox[n] != ORC_FLUID)
                     continue;
+                double M = 0.0, W = 0.0;
                 for (int i = 0; i < Q; ++i) {
                     int sx, sy, sz;
                     /* carrier: periodic in x; every solid reflects */
                     source(o, x, y, z, i, 1, &sx, &sy, &sz);
                     long s = node(o, sx, sy, sz);
                     o->fC[n * Q + i] = o->vox[s] == ORC_FLUID ? o->pC[s * Q + i] : o->pC[n * Q + OPP[i]];
+                    if (o->vox[s] != ORC_FLUID) {
+                        M += o->pC[n * Q + OPP[i]];
+                        W += WT[i];
+                    }
                 }
+                if (P->wall_diffuse != 0.0 && W > 0.0)
+                    for (int i = 0; i < Q; ++i) {
+                        int sx, sy, sz;
+                        source(o, x, y, z, i, 1, &sx, &sy, &sz);
+                        if (o->vox[node(o, sx, sy, sz)] != ORC_FLUID)
+                            o->fC[n * Q + i] = (1.0 - P->wall_diffuse) * o->pC[n * Q + OPP[i]] +
+                                               P->wall_diffuse * WT[i] * M / W;
+                    }
                 /* the inlet ghost of INFLOW moves with the carrier velocity of this node */
                 double ghost[Q];
                 for (int i = 0; i < Q; ++i)
