@@ -130,6 +130,17 @@ typedef struct {
     double p_stick_product;   /* product sticking probability p_S^P in [0, 1]
                                  (the paper uses 0); ignored without product */
     uint64_t seed;            /* key of the STOCHASTIC draws; ignored otherwise */
+    double wall_diffuse;      /* sigma in [0, 1]: diffuse fraction of the carrier's
+                                 reflection at solid walls (Maxwell's
+                                 accommodation; lattice Boltzmann form of
+                                 Ansumali and Karlin, Phys. Rev. E 66, 026311,
+                                 2002).  A gas node's populations pulled from
+                                 solid sources keep 1 - sigma of their
+                                 bounce-back values and take sigma of the mass
+                                 the node sent into the wall, in proportion to
+                                 w_i; 0 = halfway bounce-back.  Rarefaction (Kn)
+                                 enters through tau_gas.  Not with the product
+                                 lattice or in batches (LBM_EUNSUPPORTED) */
 } lbm_bc;
 
 /* Optional device hooks.  stream: a hipStream_t all work is queued on

@@ -434,6 +434,10 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
     if (!(g->pore_size > 0) || !std::isfinite(g->pore_size))
         return fail(nullptr, LBM_EINVAL, "pore_size must be finite and > 0");
     if (bc->sputter < 0 || bc->sputter > 3) return fail(nullptr, LBM_EUNSUPPORTED, "unknown sputter mode");
+    if (!(bc->wall_diffuse >= 0.0 && bc->wall_diffuse <= 1.0))
+        return fail(nullptr, LBM_EINVAL, "wall_diffuse must be in [0, 1]");
+    if (bc->product && bc->wall_diffuse != 0.0)
+        return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available with a diffuse wall");
     if (bc->product && bc->sputter == LBM_SPUTTER_STOCHASTIC)
         return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available with STOCHASTIC sputtering");
     if (bc->coupling < 0 || bc->coupling > 1) return fail(nullptr, LBM_EUNSUPPORTED, "unknown coupling mode");
@@ -629,6 +633,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.product = bc->product;
     c->ph.p_stick_product = bc->product ? bc->p_stick_product : 0.0;
     c->ph.seed = bc->seed;
+    c->ph.wall_diffuse = bc->wall_diffuse;
     c->ph.step_ctr = 0;  // the initial state is the collision of step 0
 
     try {
@@ -1106,11 +1111,11 @@ struct CkptHeader {
     uint64_t magic;
     int64_t nx, ny, nz, storage, step, nfluid, niface, nfp, cur;
     uint64_t geom_hash;
-    double params[18];
+    double params[19];
     DevTotals tot;
 };
 
-constexpr int NPARAMS = 18;
+constexpr int NPARAMS = 19;
 
 void pack_params(const lbm_ctx *c, double *p) {
     std::memset(p, 0, NPARAMS * sizeof(double));
@@ -1133,6 +1138,7 @@ void pack_params(const lbm_ctx *c, double *p) {
     p[16] = c->ph.p_stick_product;
     // the STOCHASTIC key, bit for bit (the checks compare bytes)
     std::memcpy(&p[17], &c->ph.seed, sizeof(uint64_t));
+    p[18] = c->ph.wall_diffuse;
 }
 
 // Product-lattice bytes of a checkpoint: P buffers A and B, E_P, Acc_P.
@@ -1614,6 +1620,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
             return bfail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available in batches");
         else if (bc[i].sputter == LBM_SPUTTER_STOCHASTIC)
             return bfail(nullptr, LBM_EUNSUPPORTED, "STOCHASTIC sputtering is not available in batches");
+        else if (bc[i].wall_diffuse != 0.0)
+            return bfail(nullptr, LBM_EUNSUPPORTED, "the diffuse wall is not available in batches");
     for (int32_t i = 1; i < n; ++i)
         if (bc[i].storage != bc[0].storage || bc[i].sputter != bc[0].sputter || bc[i].coupling != bc[0].coupling ||
             bc[i].species_x != bc[0].species_x)

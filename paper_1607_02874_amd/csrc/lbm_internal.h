@@ -103,6 +103,7 @@ struct Physics {
     int32_t sputter, coupling, species_x, storage;
     double p_stick_product;       // p_S^P
     int32_t product, pad;         // 1: the product lattice P is evolved
+    double wall_diffuse;          // sigma: diffuse fraction of the carrier's wall reflection
     uint64_t seed;                // STOCHASTIC: Philox key
     uint32_t step_ctr;            // STOCHASTIC: step whose collision produces the arrivals a launch sums
     uint32_t pad3;

@@ -98,6 +98,7 @@ struct PhysK {
     T h_inlet;        // c_inlet - c_ref: normalised inlet ghost population
     T keep;           // 1 - p_stick
     T a_r, a_p;       // product re-emission: p p_S^R of the reactant, 1 - p_S^P of the product
+    T sigma;          // diffuse fraction of the carrier's wall reflection
     T h0c, h0r;       // initial state, normalised: rho0 - rho_ref, c0 - c_ref
     double c_in;      // reservoir concentration (influx tally)
     double in_scale, in_unscale;  // fixed-point scale of the In(k) sums and its inverse
@@ -120,6 +121,7 @@ PhysK<T> to_kernel(const Physics &p) {
     k.keep = T(1.0 - p.p_stick);
     k.a_r = T(p.p * p.p_stick);
     k.a_p = T(1.0 - p.p_stick_product);
+    k.sigma = T(p.wall_diffuse);
     k.h0c = T(p.rho0 - p.rho_ref);
     k.h0r = T(p.c0 - p.c_ref);
     k.c_in = p.c_inlet;
@@ -357,6 +359,29 @@ struct OutSlots {
 // for the product lattice (node-compact sweep only).
 constexpr int SP_INFLOW_FLAG = 4;
 constexpr int SP_PRODUCT_FLAG = 8;
+// and this one for a diffuse carrier wall (single-context sweeps only)
+constexpr int SP_DIFFUSE_FLAG = 16;
+
+// Diffuse carrier wall (Maxwell accommodation; lattice Boltzmann form of
+// Ansumali and Karlin, Phys. Rev. E 66, 026311 (2002)): the populations a gas
+// node pulls from solid sources (its own reversed populations, h = f/w -
+// rho_ref) keep 1 - sigma of themselves and take sigma of the mass the node
+// sent into the wall, spread as w_i: h_i += sigma (sum_s w_s h_s / sum_s w_s -
+// h_i) over the solid-source directions s.
+template <typename T>
+__device__ __forceinline__ void diffuse_wall(T sigma, uint32_t solid_bits, T (&hC)[19]) {
+    T m = 0, w = 0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const bool s = (solid_bits >> i) & 1u;
+        m += s ? wgt<T>(i) * hC[i] : T(0);
+        w += s ? wgt<T>(i) : T(0);
+    }
+    const T mh = w > T(0) ? m / w : T(0);
+#pragma unroll
+    for (int i = 1; i < 19; ++i)
+        if ((solid_bits >> i) & 1u) hC[i] = hC[i] + sigma * (mh - hC[i]);
+}
 
 // The product lattice as the sweep sees it: P population buffers (one
 // population per element, same slot order as the pair buffers), E_P(k),
@@ -429,6 +454,8 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     const bool inflow = SP >= 0 ? (SP & SP_INFLOW_FLAG) != 0 : ph.species_x == XB_INFLOW;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
     const bool stoch = sputter == SP_STOCHASTIC;  // per-exit emission slots (already divided by w_i)
+    const bool diffuse = SP >= 0 ? (SP & SP_DIFFUSE_FLAG) != 0 : ph.sigma != T(0);
+    uint32_t solid_bits = 0;  // directions whose source is solid (the carrier reflects there)
     auto base = [&](int slot) { return in.p(slot); };
     const uint32_t own_b = u.idx * PB;
     // wave-uniform shape of the chunk
@@ -501,6 +528,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const uint32_t pull_b = rank * PB + half;
         // both lattices from the gas source, or both bounced back
         pc[i] = ld_pop<ST>(base(pair_slot(i)), lane_in(F) ? pull_b : bb_b);
+        solid_bits |= lane_in(F) ? 0u : (1u << i);
         // Reactant exceptions: the reservoir planes and catalytic sources.
         const uint64_t inlet = (reservoir && cx == 1 && first_chunk) ? lane0 : 0ull;
         const uint64_t outlet = (reservoir && cx == -1 && last_chunk) ? lane_last : 0ull;
@@ -533,6 +561,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
+    if (diffuse && solid_bits != 0u) diffuse_wall(ph.sigma, solid_bits, hC);
     if (inflow && first_chunk && lane_in(lane0)) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
@@ -579,6 +608,8 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     const bool inflow = SP >= 0 ? (SP & SP_INFLOW_FLAG) != 0 : ph.species_x == XB_INFLOW;
     const bool bounce = sputter == SP_BOUNCEBACK, uniform = sputter == SP_UNIFORM;
     const bool stoch = sputter == SP_STOCHASTIC;  // per-exit emission slots (already divided by w_i)
+    const bool diffuse = SP >= 0 ? (SP & SP_DIFFUSE_FLAG) != 0 : ph.sigma != T(0);
+    uint32_t solid_bits = 0;  // directions whose source is solid (the carrier reflects there)
     auto base = [&](int slot) { return in.p(slot); };
     const uint32_t own_b = idx * PB;
     const uint32_t xl = uint32_t(x) & 63u, chunk = uint32_t(x) >> 6;
@@ -675,6 +706,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             const uint32_t bb_b = own_b + (nfp_b - half);
             const uint32_t pull_b = rk[cls][bit] * PB + half;
             uint32_t c_b = F ? pull_b : bb_b;
+            solid_bits |= F ? 0u : (1u << i);
             opaque(c_b);
             pc[i] = ld_pop<ST>(base(pair_slot(i)), c_b);
             uint32_t v_b = bounce ? 0u
@@ -733,6 +765,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
     if constexpr (PROD) hP[0] = Store<ST>::cv(pp[0]);
+    if (diffuse && solid_bits != 0u) diffuse_wall(ph.sigma, solid_bits, hC);
     if (inflow && __builtin_amdgcn_ballot_w64(first_x) != 0u && first_x) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
@@ -1653,6 +1686,23 @@ hipError_t dispatch_sp(int code, F &&f) {
     }
 }
 
+// The diffuse-wall codes (single-context sweeps).
+template <typename F>
+hipError_t dispatch_sp_diffuse(int code, F &&f) {
+    constexpr int D = SP_DIFFUSE_FLAG, I = SP_INFLOW_FLAG;
+    switch (code) {
+        case SP_UNIFORM: return f(std::integral_constant<int, D | SP_UNIFORM>{});
+        case SP_WEIGHTED: return f(std::integral_constant<int, D | SP_WEIGHTED>{});
+        case SP_BOUNCEBACK: return f(std::integral_constant<int, D | SP_BOUNCEBACK>{});
+        case SP_STOCHASTIC: return f(std::integral_constant<int, D | SP_STOCHASTIC>{});
+        case SP_UNIFORM | I: return f(std::integral_constant<int, D | I | SP_UNIFORM>{});
+        case SP_WEIGHTED | I: return f(std::integral_constant<int, D | I | SP_WEIGHTED>{});
+        case SP_BOUNCEBACK | I: return f(std::integral_constant<int, D | I | SP_BOUNCEBACK>{});
+        case SP_STOCHASTIC | I: return f(std::integral_constant<int, D | I | SP_STOCHASTIC>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // The product-lattice codes (node-compact sweep only).
 template <typename F>
 hipError_t dispatch_sp_product(int code, F &&f) {
@@ -1755,10 +1805,12 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
         const dim3 grid(unsigned(sweep_blocks(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
         const PhysK<T> k = to_kernel<T>(ph);
-        return dispatch_sp(sweep_code(ph.sputter, ph.species_x), [&](auto sp) {
+        auto go = [&](auto sp) {
             hipLaunchKernelGGL((k_sweep<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part);
             return hipGetLastError();
-        });
+        };
+        if (ph.wall_diffuse != 0.0) return dispatch_sp_diffuse(sweep_code(ph.sputter, ph.species_x), go);
+        return dispatch_sp(sweep_code(ph.sputter, ph.species_x), go);
     });
 }
 
@@ -1793,11 +1845,13 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
                 return hipGetLastError();
             });
         }
-        return dispatch_sp(sweep_code(ph.sputter, ph.species_x), [&](auto sp) {
+        auto go = [&](auto sp) {
             hipLaunchKernelGGL((k_sweep_c<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part,
                                ProdK<ST>{});
             return hipGetLastError();
-        });
+        };
+        if (ph.wall_diffuse != 0.0) return dispatch_sp_diffuse(sweep_code(ph.sputter, ph.species_x), go);
+        return dispatch_sp(sweep_code(ph.sputter, ph.species_x), go);
     });
 }
 

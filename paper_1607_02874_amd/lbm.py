@@ -52,7 +52,8 @@ class lbm_bc(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("p_stick", ctypes.c_double), ("c_inlet", ctypes.c_double),
                 ("rho0", ctypes.c_double), ("c0", ctypes.c_double), ("c_ref", ctypes.c_double),
                 ("force", ctypes.c_double * 3), ("product", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("p_stick_product", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("p_stick_product", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("wall_diffuse", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -217,10 +218,10 @@ def _geometry(vox, pore_size):
 
 def _bc(sputter=SPUTTER_UNIFORM, coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32,
         p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0), product=False,
-        p_stick_product=0.0, seed=0):
+        p_stick_product=0.0, seed=0, wall_diffuse=0.0):
     return lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
                   float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]),
-                  int(bool(product)), 0, float(p_stick_product), int(seed))
+                  int(bool(product)), 0, float(p_stick_product), int(seed), float(wall_diffuse))
 
 
 def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc_kw):
