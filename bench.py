@@ -674,6 +674,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
     ap.add_argument("--da", type=float, default=None)
+    ap.add_argument("--wall-diffuse", type=float, default=0.0,
+                    help="diffuse fraction of the carrier's wall reflection (default 0: bounce-back)")
     ap.add_argument("--cpu-steps", type=int, default=300, help="oracle steps on the 64^3 crop (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 4 GiB device copy (counter calibration)")
@@ -731,7 +733,7 @@ def main():
     log(f"geometry {w.nx}x{w.ny}x{w.nz} porosity {inputs.porosity(vox):.4f} ({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
     sim = lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
-                  c_inlet=w.c_inlet, storage=storage)
+                  c_inlet=w.c_inlet, storage=storage, wall_diffuse=args.wall_diffuse)
     info = sim.info()
     log(f"create {time.perf_counter() - t0:.1f} s, info {info}")
 
@@ -811,7 +813,9 @@ def main():
         kernels = {k: round(kt["ms_" + k] / max(kt["n_" + k], 1) * 1e3, 2) for k in ("sweep", "interface", "reduce")}
 
     cpu, errs = None, None
-    if args.cpu_steps > 0:
+    if args.cpu_steps > 0 and args.wall_diffuse:
+        log("the oracle crop check runs the default workload only; skipped with --wall-diffuse")
+    if args.cpu_steps > 0 and not args.wall_diffuse:
         log(f"oracle {args.cpu_steps} steps on the 64^3 crop")
         crop, ref, cpu = cpu_baseline(vox, w, args.cpu_steps)
         errs = crop_errors(crop, ref, w, args.cpu_steps, storage)
@@ -832,7 +836,8 @@ def main():
         "data": "synthetic (seeded Gaussian-random-field porous geometry)",
         "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} porous membrane, porosity {w.phi}, "
                                f"correlation length {w.ell}, seed {w.seed}, tau {w.tau}, Da {w.da}, "
-                               f"p_S {w.p_stick}, UNIFORM sputter, PASSIVE coupling, reservoir x-BC",
+                               f"p_S {w.p_stick}, UNIFORM sputter, PASSIVE coupling, reservoir x-BC"
+                               + (f", diffuse wall fraction {args.wall_diffuse}" if args.wall_diffuse else ""),
                    "n_nodes": n, "n_fluid": info["n_fluid"], "n_interface": info["n_interface"],
                    "n_catalytic_links": info["n_catalytic_links"], "mflups": round(mlups * info["n_fluid"] / n, 1),
                    "step_bytes": ab["step"], "step_GBps": round(ab["step"] / (ms_step * 1e-3) / 1e9, 1),
