@@ -25,7 +25,7 @@ thread_local std::string g_create_error;
 
 constexpr double CS = 0.57735026918962576451;  // lattice sound speed 1/sqrt(3)
 constexpr int TIMING_RING = 512;
-constexpr uint64_t CKPT_MAGIC = 0x3447504b434d424cull;  // "LBMCKPG4"
+constexpr uint64_t CKPT_MAGIC = 0x3547504b434d424cull;  // "LBMCKPG5"
 
 struct StepEvents {
     hipEvent_t ev[8];  // start/stop of the front launch, xflux, sweep, closing reduction
