@@ -253,7 +253,13 @@ def inspect(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, **bc_kw):
 
 
 class Sim:
-    """One context: the carrier and reactant lattices over a voxel map."""
+    """One context: the carrier and reactant lattices over a voxel map.
+
+    Keyword arguments are the lbm_bc fields (see _bc).  Options beyond the
+    default method: product=True with p_stick_product (the product lattice;
+    product_fields() and the product totals), sputter=SPUTTER_STOCHASTIC with
+    seed (random sputtering matrix), wall_diffuse=sigma (diffuse carrier
+    wall)."""
 
     def __init__(self, vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, use_torch=True, stream=None, **kw):
         self._h = None
