@@ -163,3 +163,15 @@ def test_stochastic_requests_the_library_rejects():
     with pytest.raises(lbm.LbmError) as e:
         lbm.Batch([smp, smp])
     assert e.value.status == lbm.LBM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("storage,bar", [(F16, 1e-3), (BF16, 1e-2)])
+def test_stochastic_16bit_storage(storage, bar):
+    """16-bit storage with the random sputtering matrix: the per-exit
+    emission slots are stored in the population format; the same bars as the
+    deterministic modes (FP16 1e-3, BF16 1e-2)."""
+    c = scase(PLAIN.voxels(), 120, da=PLAIN.da, tau=PLAIN.tau, force=PLAIN.force())
+    ref = run_oracle(c)
+    e = errs(run_gpu(c, storage), ref, c["vox"])
+    for k in ("rho", "u", "conc", "conv", "t_converted"):
+        assert e[k] < bar, (k, e[k])

@@ -121,3 +121,13 @@ def test_diffuse_wall_requests_the_library_rejects():
     with pytest.raises(lbm.LbmError) as e:
         lbm.Batch([smp, smp])
     assert e.value.status == lbm.LBM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("storage,bar", [(1, 1e-3), (2, 1e-2)])
+def test_diffuse_wall_16bit_storage(storage, bar):
+    """16-bit storage with the diffuse wall (FP16 1e-3, BF16 1e-2)."""
+    p32 = inputs.PLAIN_32
+    c = wcase(p32.voxels(), 120, da=p32.da, tau=p32.tau, force=p32.force(), sigma=0.8)
+    e = errs(run_gpu(c, storage, 1), run_oracle(c), c["vox"])
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < bar, (k, e[k])
