@@ -694,8 +694,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
-              "multi-GPU sharding is a design in DESIGN.md, not an implementation", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for {max(args.gpus, world)}); "
+              "sharding across GPUs (x-slabs with a population halo) is designed but not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
