@@ -584,7 +584,11 @@ def run_stochastic(args):
                    "sweep_us": round(t_sweep * 1e6, 1), "converted": tot["converted"]},
         "roofline": {"bound": "hbm", "kernel": "k_sweep_c" if sweep_variant == 1 else "k_sweep",
                      "achieved": round(ab["sweep"] / t_sweep / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ab["sweep"] / t_sweep / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ab["sweep"] / t_sweep / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("k_sweep_c" if sweep_variant == 1 else "k_sweep",
+                                                 w.name + "_stochastic", {0: "f32", 1: "f16", 2: "bf16",
+                                                                          3: "f64"}[storage],
+                                                 "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile),
                      "algorithmic_bytes": ab["sweep"]},
         "cpu_baseline": None,
     }
