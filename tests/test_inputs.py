@@ -44,3 +44,20 @@ def test_crop_forces_outlet_gas():
     assert c.shape == (12, 16, 24)
     assert (c[:, :, -4:] == 0).all()
     assert np.array_equal(c[:, :, :20], v[:12, :16, :20])
+
+
+@pytest.mark.parametrize("w", [6, 10, 20, 30])
+def test_disk_ingot_follows_the_papers_recipe(w):
+    """The 2-D reactor geometry: a (1, 500, 250) map, a catalytic ingot w
+    along x and 200 across, centred, porosity 0.70 +- 0.005 inside it, one
+    inert wall row, gas elsewhere; seeded, so deterministic."""
+    vox = inputs.disk_ingot(w, seed=w)
+    assert vox.shape == (1, 500, 250)
+    x0, y0 = (250 - w) // 2, 150
+    block = vox[0, y0:y0 + 200, x0:x0 + w]
+    assert abs((block == inputs.FLUID).mean() - 0.70) <= 0.005 + 1e-12
+    assert set(np.unique(block)) <= {inputs.FLUID, inputs.CATALYTIC}
+    outside = vox[0].copy()
+    outside[y0:y0 + 200, x0:x0 + w] = inputs.FLUID
+    assert (outside[0] == inputs.INERT).all() and (outside[1:] == inputs.FLUID).all()
+    assert np.array_equal(vox, inputs.disk_ingot(w, seed=w))
