@@ -179,12 +179,13 @@ __device__ __forceinline__ uint32_t philox_first(uint32_t c0, uint32_t c1, uint3
     return c0;
 }
 
-// The exit direction (library numbering) of an arrival along link j at the
-// interface node with voxel index vox and active-link mask `mask`.
-template <typename T>
-__device__ __forceinline__ int random_exit(const PhysK<T> &ph, uint32_t vox, uint32_t mask, int j) {
+// The exit direction (library numbering) of an arrival along the link with
+// velocity code `code` at the interface node with voxel index vox and
+// active-link mask `mask`.
+__device__ __forceinline__ int random_exit(uint32_t step, uint32_t seed_lo, uint32_t seed_hi, uint32_t vox,
+                                           uint32_t mask, uint32_t code) {
     const uint32_t b = uint32_t(__popc(mask));
-    const uint32_t r = philox_first(ph.step_ctr, vox, uint32_t(vcode(j)), 0u, ph.seed_lo, ph.seed_hi);
+    const uint32_t r = philox_first(step, vox, code, 0u, seed_lo, seed_hi);
     const uint32_t pick = uint32_t((uint64_t(r) * b) >> 32);
     int e = 0;
     uint32_t n = 0;
@@ -899,23 +900,97 @@ __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const u
 // picks.  Slots receive a random number of terms, so the terms are plain
 // two's-complement integers (the fixed-point pattern minus MAGIC_BITS) and
 // the reader subtracts nothing.
+//
+// The draws are made densely: each wavefront queues its arrivals (term,
+// interface node, link code) in LDS, direction by direction, and draws the
+// exits of 64 queued arrivals per pass, so a wavefront runs the generator
+// about once instead of once per direction in which any of its lanes has a
+// catalytic source.  Integer sums do not depend on the order, so the slots
+// hold the same values.
+struct QueuedArrival {
+    unsigned long long term;
+    uint32_t k, code;
+};
+constexpr uint32_t ARRIVAL_QUEUE = 128;  // per wavefront: < 64 waiting + up to one per live lane added
+
+// The entries are dealt over the lanes active here (the calling sweep runs
+// only its gas-node lanes), by their rank among them.
+__device__ __forceinline__ void draw_queued(const QueuedArrival *q, uint32_t n, const uint32_t *ivox,
+                                         const uint32_t *imask, unsigned long long *inacc, uint32_t niface,
+                                         uint32_t step, uint32_t seed_lo, uint32_t seed_hi) {
+    const uint64_t live = __builtin_amdgcn_read_exec();
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(live >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(live), 0u));
+    const uint32_t lanes = uint32_t(__popcll(live));
+    for (uint32_t t = rank; t < n; t += lanes) {
+        const QueuedArrival a = q[t];
+        const int e = random_exit(step, seed_lo, seed_hi, glb(ivox)[a.k], glb(imask)[a.k], a.code);
+        (void)__hip_atomic_fetch_add(&glb(inacc)[uint64_t(uint32_t(e - 1)) * niface + a.k], a.term,
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The direct form (a draw in place per direction), for the chunk sweep,
+// whose register budget the queue would exceed.
 template <int ST>
-__device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned long long *inacc,
-                                                     const uint32_t *kidx, uint32_t cat_bits,
-                                                     const PhysK<typename Store<ST>::T> &ph,
-                                                     const typename Store<ST>::T (&hR)[19]) {
+__device__ __forceinline__ void accumulate_in_random_direct(const Geometry &g, unsigned long long *inacc,
+                                                            const uint32_t *kidx, uint32_t cat_bits,
+                                                            const PhysK<typename Store<ST>::T> &ph,
+                                                            const typename Store<ST>::T (&hR)[19]) {
     using T = typename Store<ST>::T;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         if ((cat_bits >> i) & 1u) {
             const int j = opp(i);  // the link direction as seen from the interface node
             const uint32_t k = kidx[(i - 1) * 256 + threadIdx.x];
-            const int e = random_exit(ph, glb(g.ivox)[k], glb(g.imask)[k], j);
+            const int e = random_exit(ph.step_ctr, ph.seed_lo, ph.seed_hi, glb(g.ivox)[k], glb(g.imask)[k],
+                                      uint32_t(vcode(j)));
             const T stored = Store<ST>::cv(Store<ST>::enc(hR[j]));
             const unsigned long long term = in_term<T>(wgt<T>(j), stored, ph.cref, ph.in_scale) - MAGIC_BITS;
             (void)__hip_atomic_fetch_add(&glb(inacc)[uint64_t(uint32_t(e - 1)) * g.niface + k], term,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned long long *inacc,
+                                                     const uint32_t *kidx, uint32_t cat_bits,
+                                                     const PhysK<typename Store<ST>::T> &ph,
+                                                     const typename Store<ST>::T (&hR)[19]) {
+    using T = typename Store<ST>::T;
+    __shared__ QueuedArrival queue[4][ARRIVAL_QUEUE];
+    QueuedArrival *q = queue[threadIdx.x >> 6];
+    uint32_t qn = 0;  // the same in every lane of the wavefront
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const bool act = (cat_bits >> i) & 1u;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(act);
+        if (bal == 0u) continue;
+        if (act) {
+            const int j = opp(i);  // the link direction as seen from the interface node
+            const T stored = Store<ST>::cv(Store<ST>::enc(hR[j]));
+            QueuedArrival a;
+            a.term = in_term<T>(wgt<T>(j), stored, ph.cref, ph.in_scale) - MAGIC_BITS;
+            a.k = kidx[(i - 1) * 256 + threadIdx.x];
+            a.code = uint32_t(vcode(j));
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+            q[qn + below] = a;
+        }
+        qn += uint32_t(__popcll(bal));
+        if (qn >= 64u) {
+            // the wavefront's queue writes before its reads, and its reads
+            // before the next writes (LDS accesses of one wavefront)
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            draw_queued(q, qn, g.ivox, g.imask, inacc, g.niface, ph.step_ctr, ph.seed_lo, ph.seed_hi);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            qn = 0;
+        }
+    }
+    if (qn > 0u) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        draw_queued(q, qn, g.ivox, g.imask, inacc, g.niface, ph.step_ctr, ph.seed_lo, ph.seed_hi);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
 
@@ -1021,7 +1096,7 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
         // In(k) of the next step's interface: what leaves towards interface nodes
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
             if constexpr ((SP & 3) == SP_STOCHASTIC)
-                accumulate_in_random<ST>(g, g.inacc, kidx, cat_bits, ph, hR);
+                accumulate_in_random_direct<ST>(g, g.inacc, kidx, cat_bits, ph, hR);
             else
                 accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
         }
@@ -1368,7 +1443,7 @@ __global__ __launch_bounds__(256) void k_in_init(Geometry g, PhysK<typename Stor
                 in_term<T>(wgt<T>(j), Store<ST>::ld(fin + 2 * (dslot(j) * g.nfp + r) + 1), ph.cref, ph.in_scale);
             sum += term;
             if (ph.sputter == SP_STOCHASTIC) {
-                const int e = random_exit(ph, v, mask, j);
+                const int e = random_exit(ph.step_ctr, ph.seed_lo, ph.seed_hi, v, mask, uint32_t(vcode(j)));
 #pragma unroll
                 for (int d = 1; d < 19; ++d)
                     if (d == e) slots[d - 1] += term - MAGIC_BITS;
