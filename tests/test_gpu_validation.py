@@ -118,3 +118,43 @@ def test_reactor2d_efficiency_trends():
     for p in (0.35, 0.65):
         ratio = res[(30, p)][0] / res[(6, p)][0]
         assert 0.5 < ratio < 2.0, ratio
+
+
+def test_reactor2d_setup_matches_oracle():
+    """The exact 2-D reactor configuration behind the efficiency figures
+    (disk-carved ingot w = 10, tau 4, INFLOW at 0.2, product lattice,
+    p = 0.45), 600 steps, the FP64 build against the oracle.  The carrier and
+    reactant fields agree to 1e-12 relative.  The product is made only from
+    the In(k) sums, which the library adds in fixed point with absolute
+    resolution 2^-S (S = 47 - ceil(log2 c_in) = 49 here, each term rounded to
+    half of that); while the product is still minute a relative comparison
+    measures that resolution, so it is held to the absolute bound
+    steps * 18 terms * 2^-(S + 1)."""
+    import oracle
+
+    vox = inputs.disk_ingot(10, seed=10)
+    p, steps, c_in = 0.45, 600, 0.2
+    kw = dict(tau=(4.0, 4.0), force=(4e-5, 0.0, 0.0), rho0=0.8, c_inlet=c_in, p_stick=0.95)
+    o = oracle.Oracle(vox, p=p, species_x=oracle.XINFLOW, product=True, p_stick_product=0.0, **kw)
+    o.step(steps)
+    ref_rho, ref_u, ref_c = o.fields()
+    ref_cp, ref_tp, _ = o.product()
+    with lbm.Sim(vox, da=math.sqrt(1.0 / 3.0) / (p * 3.0), pore_size=3.0, species_x=lbm.XBC_INFLOW, product=True,
+                 p_stick_product=0.0, storage=3, **kw) as s:
+        s.step(steps)
+        rho, u, c = s.fields()
+        cp, _, _ = s.product_fields()
+        t = s.totals()
+    gas = vox == inputs.FLUID
+
+    def rel(a, b):
+        d, r = ((a - b)[:, gas], b[:, gas]) if a.ndim == 4 else ((a - b)[gas], b[gas])
+        return np.linalg.norm(d) / np.linalg.norm(r)
+
+    for a, b in ((rho, ref_rho), (u, ref_u), (c, ref_c)):
+        assert rel(a, b) < 1e-12
+    shift = 47 - math.ceil(math.log2(c_in))
+    bound = steps * 18 * 2.0 ** -(shift + 1)
+    assert np.abs(cp - ref_cp).max() < bound
+    assert np.abs(ref_cp).max() > 1e3 * bound  # the product is well resolved by then
+    assert abs(t["mass_product"] - ref_tp["mass_product"]) < bound * int(gas.sum())
