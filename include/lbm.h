@@ -92,8 +92,20 @@ typedef enum { LBM_XBC_PERIODIC = 0, LBM_XBC_RESERVOIR = 1, LBM_XBC_INFLOW = 2 }
  * h_i = f_i / w_i - rho_ref of each population from the rest equilibrium of
  * the reference density (rho_ref = rho0 for the carrier, c_ref for the
  * species).  F32, F16 and BF16 compute in FP32; F64 stores and computes in
- * FP64 (a reference build).  16-bit formats round to nearest even. */
+ * FP64 (a reference build).  16-bit formats round as lbm_bc.rounding says. */
 typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2, LBM_STORE_F64 = 3 } lbm_storage;
+
+/* Rounding of 16-bit stores (F16, BF16; FP32 and FP64 storage ignore it).
+ * NEAREST rounds every stored population and emission value to nearest
+ * (ties away from zero).  STOCHASTIC rounds each one up with probability
+ * equal to the discarded fraction of its last place, so the stored value is
+ * right on average: a steady flow no longer sees the same rounding error at
+ * the same node every step, which would act on it like a small persistent
+ * body force.  The random words are a hash of (step, storage index of the
+ * node or interface node, lbm_bc.seed), so runs are reproducible and the
+ * In(k) sums still count exactly the stored values.  Not available in batches
+ * (LBM_EUNSUPPORTED), whose captured graphs replay the step key. */
+typedef enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 } lbm_rounding;
 
 typedef struct {
     int32_t nx, ny, nz;       /* lattice size, each >= 1; nx <= 4096 */
@@ -126,10 +138,11 @@ typedef struct {
                                  Needs PASSIVE coupling and the node-compact
                                  sweep (ny, nz <= 1024), LBM_EUNSUPPORTED
                                  otherwise; not available in batches */
-    int32_t reserved;         /* must be 0 */
+    int32_t rounding;         /* lbm_rounding of 16-bit stores (0 = NEAREST) */
     double p_stick_product;   /* product sticking probability p_S^P in [0, 1]
                                  (the paper uses 0); ignored without product */
-    uint64_t seed;            /* key of the STOCHASTIC draws; ignored otherwise */
+    uint64_t seed;            /* key of the STOCHASTIC draws and of the
+                                 stochastic rounding words; ignored otherwise */
     double wall_diffuse;      /* sigma in [0, 1]: diffuse fraction of the carrier's
                                  reflection at solid walls (Maxwell's
                                  accommodation; lattice Boltzmann form of
@@ -227,7 +240,8 @@ typedef struct {
  *
  * Errors: LBM_EINVAL for NULL pointers, sizes < 1, nx > 4096, a voxel > 2,
  * tau <= 1/2, kn < 0, da <= 0 or NaN, inconsistent kn/tau, p_stick outside
- * [0, 1], c_inlet/c0 < 0, rho0 <= 0, nonzero reserved fields;
+ * [0, 1], c_inlet/c0 < 0, rho0 <= 0, an unknown rounding, nonzero reserved
+ * fields;
  * LBM_EUNSUPPORTED for an unknown enum value, or for a lattice whose
  * buffers exceed the kernels' 32-bit offsets (4 * nfp * s >= 2^32 bytes with
  * nfp = gas nodes + 1 rounded up to 128 and s the bytes per stored

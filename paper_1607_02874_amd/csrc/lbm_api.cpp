@@ -25,7 +25,7 @@ thread_local std::string g_create_error;
 
 constexpr double CS = 0.57735026918962576451;  // lattice sound speed 1/sqrt(3)
 constexpr int TIMING_RING = 512;
-constexpr uint64_t CKPT_MAGIC = 0x3547504b434d424cull;  // "LBMCKPG5"
+constexpr uint64_t CKPT_MAGIC = 0x3647504b434d424cull;  // "LBMCKPG6"
 
 struct StepEvents {
     hipEvent_t ev[8];  // start/stop of the front launch, xflux, sweep, closing reduction
@@ -425,7 +425,9 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
         return fail(nullptr, LBM_EINVAL, "nx, ny and nz must be <= 4096");
     if (int64_t(g->nx) * g->ny * g->nz >= (int64_t(1) << 32))
         return fail(nullptr, LBM_EINVAL, "lattice has 2^32 nodes or more");
-    if (g->reserved0 != 0 || bc->reserved != 0) return fail(nullptr, LBM_EINVAL, "reserved fields must be 0");
+    if (g->reserved0 != 0) return fail(nullptr, LBM_EINVAL, "reserved fields must be 0");
+    if (bc->rounding != LBM_ROUND_NEAREST && bc->rounding != LBM_ROUND_STOCHASTIC)
+        return fail(nullptr, LBM_EINVAL, "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC");
     if (bc->product != 0 && bc->product != 1) return fail(nullptr, LBM_EINVAL, "product must be 0 or 1");
     if (bc->product && !(bc->p_stick_product >= 0.0 && bc->p_stick_product <= 1.0))
         return fail(nullptr, LBM_EINVAL, "p_stick_product must be in [0, 1]");
@@ -634,6 +636,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.p_stick_product = bc->product ? bc->p_stick_product : 0.0;
     c->ph.seed = bc->seed;
     c->ph.wall_diffuse = bc->wall_diffuse;
+    c->ph.rounding = bc->rounding;
     c->ph.step_ctr = 0;  // the initial state is the collision of step 0
 
     try {
@@ -1107,15 +1110,15 @@ lbm_status lbm_kernel_times(lbm_ctx *c, lbm_kernel_times_t *t) {
 }
 
 namespace {
+constexpr int NPARAMS = 20;
+
 struct CkptHeader {
     uint64_t magic;
     int64_t nx, ny, nz, storage, step, nfluid, niface, nfp, cur;
     uint64_t geom_hash;
-    double params[19];
+    double params[NPARAMS];
     DevTotals tot;
 };
-
-constexpr int NPARAMS = 19;
 
 void pack_params(const lbm_ctx *c, double *p) {
     std::memset(p, 0, NPARAMS * sizeof(double));
@@ -1139,6 +1142,8 @@ void pack_params(const lbm_ctx *c, double *p) {
     // the STOCHASTIC key, bit for bit (the checks compare bytes)
     std::memcpy(&p[17], &c->ph.seed, sizeof(uint64_t));
     p[18] = c->ph.wall_diffuse;
+    // 16-bit storage: the rounding of the stores (FP32 and FP64 ignore it)
+    p[19] = storage_bytes(c->ph.storage) == 2 ? c->ph.rounding : 0;
 }
 
 // Product-lattice bytes of a checkpoint: P buffers A and B, E_P, Acc_P.
@@ -1622,6 +1627,11 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
             return bfail(nullptr, LBM_EUNSUPPORTED, "STOCHASTIC sputtering is not available in batches");
         else if (bc[i].wall_diffuse != 0.0)
             return bfail(nullptr, LBM_EUNSUPPORTED, "the diffuse wall is not available in batches");
+        else if (bc[i].rounding == LBM_ROUND_STOCHASTIC && (bc[i].storage == LBM_STORE_F16 ||
+                                                           bc[i].storage == LBM_STORE_BF16))
+            // a captured batch graph replays the launch arguments, and with
+            // them the step key of the rounding words
+            return bfail(nullptr, LBM_EUNSUPPORTED, "stochastic rounding is not available in batches");
     for (int32_t i = 1; i < n; ++i)
         if (bc[i].storage != bc[0].storage || bc[i].sputter != bc[0].sputter || bc[i].coupling != bc[0].coupling ||
             bc[i].species_x != bc[0].species_x)

@@ -50,6 +50,7 @@ enum { SP_UNIFORM = 0, SP_WEIGHTED = 1, SP_BOUNCEBACK = 2, SP_STOCHASTIC = 3 };
 // one direction read neighbouring slots.
 constexpr int NSLOT = 18;
 enum { CP_PASSIVE = 0, CP_BARYCENTRIC = 1 };
+enum { ROUND_NEAREST = 0, ROUND_STOCHASTIC = 1 };
 enum { XB_PERIODIC = 0, XB_RESERVOIR = 1, XB_INFLOW = 2 };
 
 // Slots of the per-step partial sums (FP64).  The sweep writes four per
@@ -102,7 +103,8 @@ struct Physics {
     double in_scale, in_unscale;  // 2^S and 2^-S of the fixed-point In(k) sums
     int32_t sputter, coupling, species_x, storage;
     double p_stick_product;       // p_S^P
-    int32_t product, pad;         // 1: the product lattice P is evolved
+    int32_t product;              // 1: the product lattice P is evolved
+    int32_t rounding;             // ROUND_*: how 16-bit stores round (ignored by FP32 and FP64 storage)
     double wall_diffuse;          // sigma: diffuse fraction of the carrier's wall reflection
     uint64_t seed;                // STOCHASTIC: Philox key
     uint32_t step_ctr;            // STOCHASTIC: step whose collision produces the arrivals a launch sums

@@ -29,6 +29,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "fixed_point.h"
 #include "lbm_internal.h"
 
 namespace lbmk {
@@ -52,6 +53,9 @@ struct Store<ST_F32> {
     __device__ static S enc(T v) { return v; }
     __device__ static T ld(const S *p) { return *p; }
     __device__ static void st(S *p, T v) { *p = v; }
+    static constexpr bool ROUNDS = false;
+    __device__ static P enc2(T c, T r, uint32_t, uint32_t) { return P{c, r}; }
+    __device__ static S enc1(T v, uint32_t) { return v; }
 };
 template <>
 struct Store<ST_F16> {
@@ -62,6 +66,19 @@ struct Store<ST_F16> {
     __device__ static T ld(const S *p) { return static_cast<float>(*p); }
     __device__ static S enc(T v) { return static_cast<_Float16>(v); }  // round to nearest even
     __device__ static void st(S *p, T v) { *p = enc(v); }
+    // rounded by the word w (see lbmfx::round_words): nearest or stochastic
+    static constexpr bool ROUNDS = true;
+    __device__ static P enc2(T c, T r, uint32_t wc, uint32_t wr) {
+        P v = {};
+        v = __builtin_amdgcn_cvt_sr_f16_f32(v, c, wc, false);
+        v = __builtin_amdgcn_cvt_sr_f16_f32(v, r, wr, true);
+        return v;
+    }
+    __device__ static S enc1(T x, uint32_t w) {
+        P v = {};
+        v = __builtin_amdgcn_cvt_sr_f16_f32(v, x, w, false);
+        return v.x;
+    }
 };
 template <>
 struct Store<ST_BF16> {
@@ -76,6 +93,19 @@ struct Store<ST_BF16> {
         return (u & 0x7fffffffu) > 0x7f800000u ? uint16_t((u >> 16) | 0x40u) : uint16_t(rounded);  // NaN stays NaN
     }
     __device__ static void st(S *p, T v) { *p = enc(v); }
+    static constexpr bool ROUNDS = true;
+    using B2 = __bf16 __attribute__((ext_vector_type(2)));
+    __device__ static P enc2(T c, T r, uint32_t wc, uint32_t wr) {
+        B2 v = {};
+        v = __builtin_amdgcn_cvt_sr_bf16_f32(v, c, wc, false);
+        v = __builtin_amdgcn_cvt_sr_bf16_f32(v, r, wr, true);
+        return __builtin_bit_cast(P, v);
+    }
+    __device__ static S enc1(T x, uint32_t w) {
+        B2 v = {};
+        v = __builtin_amdgcn_cvt_sr_bf16_f32(v, x, w, false);
+        return __builtin_bit_cast(P, v).x;
+    }
 };
 template <>
 struct Store<ST_F64> {
@@ -86,6 +116,9 @@ struct Store<ST_F64> {
     __device__ static S enc(T v) { return v; }
     __device__ static T ld(const S *p) { return *p; }
     __device__ static void st(S *p, T v) { *p = v; }
+    static constexpr bool ROUNDS = false;
+    __device__ static P enc2(T c, T r, uint32_t, uint32_t) { return P{c, r}; }
+    __device__ static S enc1(T v, uint32_t) { return v; }
 };
 
 // Physical parameters in the compute type.
@@ -104,6 +137,9 @@ struct PhysK {
     double in_scale, in_unscale;  // fixed-point scale of the In(k) sums and its inverse
     int32_t sputter, coupling, species_x;
     uint32_t seed_lo, seed_hi, step_ctr;  // STOCHASTIC draws
+    // 16-bit stores: stochastic rounding on (sr), keys of this launch's
+    // rounding words for the population stores and the emission stores
+    uint32_t sr, sr_key, sr_key_e;
 };
 
 template <typename T>
@@ -133,6 +169,9 @@ PhysK<T> to_kernel(const Physics &p) {
     k.seed_lo = uint32_t(p.seed);
     k.seed_hi = uint32_t(p.seed >> 32);
     k.step_ctr = p.step_ctr;
+    k.sr = p.rounding == ROUND_STOCHASTIC && storage_bytes(p.storage) == 2;
+    k.sr_key = lbmfx::round_key(p.step_ctr, p.seed, 0u);
+    k.sr_key_e = lbmfx::round_key(p.step_ctr, p.seed, 1u);
     return k;
 }
 
@@ -200,15 +239,13 @@ __device__ __forceinline__ int random_exit(uint32_t step, uint32_t seed_lo, uint
 }
 
 // One term of an In(k) sum, f*_j = w_j (h_j + c_ref) of the stored value, in
-// fixed point: adding 1.5 * 2^52 to term * 2^S (|term * 2^S| < 2^51) leaves
-// round-to-nearest(term * 2^S) in the low mantissa bits, so the bit pattern
-// is MAGIC_BITS + that integer.  The sums add bit patterns; the reader
-// subtracts b(k) * MAGIC_BITS.
-constexpr double MAGIC = 6755399441055744.0;  // 1.5 * 2^52
-constexpr unsigned long long MAGIC_BITS = 0x4338000000000000ull;
+// fixed point (lbmfx::term: MAGIC_BITS + round(term * 2^S), or a poison
+// pattern the reader reports as non-finite).  The sums add bit patterns; the
+// reader subtracts b(k) * MAGIC_BITS.
+constexpr unsigned long long MAGIC_BITS = lbmfx::MAGIC_BITS;
 template <typename T>
 __device__ __forceinline__ unsigned long long in_term(T w, T h_stored, T cref, double scale) {
-    return static_cast<unsigned long long>(__double_as_longlong(fma(double(w * (h_stored + cref)), scale, MAGIC)));
+    return lbmfx::term(double(w * (h_stored + cref)), scale);
 }
 
 // ------------------------------------------------------------ helpers --
@@ -878,6 +915,8 @@ struct InOut {
 // Add this lane's post-collision reactant populations that head into
 // interface nodes (the reversed catalytic-source directions) to In(k) of
 // their targets, as fixed-point integers; kidx holds each direction's target.
+// hR holds the values as stored (the sweeps write the rounded 16-bit values
+// back before calling), so In(k) counts exactly the mass that left.
 template <int ST>
 __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const uint32_t *kidx, uint32_t cat_bits,
                                               const PhysK<typename Store<ST>::T> &ph,
@@ -888,7 +927,7 @@ __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const u
     for (int i = 1; i < 19; ++i) {
         if ((cat_bits >> i) & 1u) {
             const int j = opp(i);  // the link direction as seen from the interface node
-            const T stored = Store<ST>::cv(Store<ST>::enc(hR[j]));
+            const T stored = hR[j];  // the value as stored (the caller passes stored values)
             (void)__hip_atomic_fetch_add(&glb(inacc)[kidx[(i - 1) * 256 + threadIdx.x]],
                                          in_term<T>(wgt<T>(j), stored, cref, ph.in_scale), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
@@ -944,7 +983,7 @@ __device__ __forceinline__ void accumulate_in_random_direct(const Geometry &g, u
             const uint32_t k = kidx[(i - 1) * 256 + threadIdx.x];
             const int e = random_exit(ph.step_ctr, ph.seed_lo, ph.seed_hi, glb(g.ivox)[k], glb(g.imask)[k],
                                       uint32_t(vcode(j)));
-            const T stored = Store<ST>::cv(Store<ST>::enc(hR[j]));
+            const T stored = hR[j];  // as stored
             const unsigned long long term = in_term<T>(wgt<T>(j), stored, ph.cref, ph.in_scale) - MAGIC_BITS;
             (void)__hip_atomic_fetch_add(&glb(inacc)[uint64_t(uint32_t(e - 1)) * g.niface + k], term,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -968,7 +1007,7 @@ __device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned
         if (bal == 0u) continue;
         if (act) {
             const int j = opp(i);  // the link direction as seen from the interface node
-            const T stored = Store<ST>::cv(Store<ST>::enc(hR[j]));
+            const T stored = hR[j];  // as stored
             QueuedArrival a;
             a.term = in_term<T>(wgt<T>(j), stored, ph.cref, ph.in_scale) - MAGIC_BITS;
             a.k = kidx[(i - 1) * 256 + threadIdx.x];
@@ -1086,12 +1125,15 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
         collide(ph, m, hC, hR);
         using P = typename Store<ST>::P;
         uint32_t own_b = u.idx * uint32_t(sizeof(P));
+        const lbmfx::RoundWords rw = lbmfx::round_words(ph.sr != 0u, ph.sr_key, u.idx);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             // opaque per store: keeps each store in the scalar-base form instead
             // of a shared 64-bit vector address plus per-store 64-bit adds
             opaque(own_b);
-            st_at(static_cast<P *>(out.p(dslot(i))), own_b, pop_pair<ST>(hC[i], hR[i]));
+            const P v = Store<ST>::enc2(hC[i], hR[i], rw.at(2 * i), rw.at(2 * i + 1));
+            st_at(static_cast<P *>(out.p(dslot(i))), own_b, v);
+            if constexpr (Store<ST>::ROUNDS) hR[i] = Store<ST>::cv(v.y);
         }
         // In(k) of the next step's interface: what leaves towards interface nodes
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
@@ -1164,10 +1206,16 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         collide(ph, m, hC, hR);
         using P = typename Store<ST>::P;
         uint32_t own_b = idx * uint32_t(sizeof(P));
+        // the rounding words of this node (16-bit storage; nearest unless
+        // stochastic rounding is on): 2i, 2i + 1 for the pair of direction i,
+        // 38 + i for the product
+        const lbmfx::RoundWords rw = lbmfx::round_words(ph.sr != 0u, ph.sr_key, idx);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             opaque(own_b);
-            st_stream(static_cast<P *>(out.p(dslot(i))), own_b, pop_pair<ST>(hC[i], hR[i]));
+            const P v = Store<ST>::enc2(hC[i], hR[i], rw.at(2 * i), rw.at(2 * i + 1));
+            st_stream(static_cast<P *>(out.p(dslot(i))), own_b, v);
+            if constexpr (Store<ST>::ROUNDS) hR[i] = Store<ST>::cv(v.y);
         }
         if constexpr (PROD) {
             using S = typename Store<ST>::S;
@@ -1176,7 +1224,9 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 opaque(ownp_b);
-                st_stream(static_cast<S *>(pk.out.p(dslot(i))), ownp_b, Store<ST>::enc(hP[i]));
+                const S v = Store<ST>::enc1(hP[i], rw.at(38 + i));
+                st_stream(static_cast<S *>(pk.out.p(dslot(i))), ownp_b, v);
+                if constexpr (Store<ST>::ROUNDS) hP[i] = Store<ST>::cv(v);
             }
             if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(pk.inacc, kidx, cat_bits, ph, hP, T(0));
             if (reservoir && (first_x || last_x)) {
@@ -1320,7 +1370,7 @@ __device__ __forceinline__ double take_in(unsigned long long *inacc, int64_t k, 
     const long long fixed = static_cast<long long>(raw);
     // a term outside the fixed-point range (|term| >= 2^51 / 2^S) cannot
     // come from a bounded state; report it through the NaN watchdog
-    return (fixed > (1ll << 55) || fixed < -(1ll << 55)) ? __builtin_nan("") : double(fixed) * unscale;
+    return lbmfx::sum_in_range(fixed) ? double(fixed) * unscale : __builtin_nan("");
 }
 
 template <int ST>
@@ -1331,6 +1381,9 @@ __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::
     using S = typename Store<ST>::S;
     const int64_t k = int64_t(block) * blockDim.x + threadIdx.x;
     double arrived[1] = {0.0}, arrived_p[1] = {0.0};
+    // rounding words of the emission stores: t = exit e (STOCHASTIC), else 0
+    // for E(k) and 1 for E_P(k)
+    const lbmfx::RoundWords rw = lbmfx::round_words(ph.sr != 0u, ph.sr_key_e, uint32_t(k));
     if (k < it.n && ph.sputter == SP_STOCHASTIC) {
         // one In slot per exit direction; each re-emits (1 - p_S) of its sum
         // along its own exit (stored divided by w_e, like WEIGHTED's E)
@@ -1342,11 +1395,10 @@ __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::
                 const uint64_t slot = uint64_t(uint32_t(e - 1)) * uint64_t(it.n) + uint64_t(k);
                 const long long fixed = static_cast<long long>(glb(it.inacc)[slot]);
                 glb(it.inacc)[slot] = 0ull;
-                const double ine = (fixed > (1ll << 55) || fixed < -(1ll << 55)) ? __builtin_nan("")
-                                                                                 : double(fixed) * ph.in_unscale;
+                const double ine = lbmfx::sum_in_range(fixed) ? double(fixed) * ph.in_unscale : __builtin_nan("");
                 in += ine;
                 st_at(emit, uint32_t(slot) * uint32_t(sizeof(S)),
-                      Store<ST>::enc(T(double(ph.keep) * ine * inv_wgt<double>(e))));
+                      Store<ST>::enc1(T(double(ph.keep) * ine * inv_wgt<double>(e)), rw.at(e)));
             }
         }
         glb(it.acc)[k] += in;
@@ -1357,14 +1409,14 @@ __device__ __forceinline__ void interface_block(const PhysK<typename Store<ST>::
         glb(it.acc)[k] += in;
         const double scale = glb(it.scale)[k];
         if (ph.sputter != SP_BOUNCEBACK)
-            st_at(emit, uint32_t(k) * uint32_t(sizeof(S)), Store<ST>::enc(T(double(ph.keep) * in * scale)));
+            st_at(emit, uint32_t(k) * uint32_t(sizeof(S)), Store<ST>::enc1(T(double(ph.keep) * in * scale), rw.at(0)));
         arrived[0] = in;
         if (pi.inacc) {
             const double inp = take_in(pi.inacc, k, b, ph.in_unscale);
             glb(pi.acc)[k] += inp;
             if (ph.sputter != SP_BOUNCEBACK)
                 st_at(static_cast<S *>(pi.emit), uint32_t(k) * uint32_t(sizeof(S)),
-                      Store<ST>::enc(T((double(ph.a_r) * in + double(ph.a_p) * inp) * scale)));
+                      Store<ST>::enc1(T((double(ph.a_r) * in + double(ph.a_p) * inp) * scale), rw.at(1)));
             arrived_p[0] = inp;
         }
     }

@@ -27,6 +27,7 @@ SPUTTER_UNIFORM, SPUTTER_WEIGHTED, SPUTTER_BOUNCEBACK, SPUTTER_STOCHASTIC = 0, 1
 COUPLE_PASSIVE, COUPLE_BARYCENTRIC = 0, 1
 XBC_PERIODIC, XBC_RESERVOIR, XBC_INFLOW = 0, 1, 2
 STORE_F32, STORE_F16, STORE_BF16, STORE_F64 = 0, 1, 2, 3
+ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
 TUNE_YTILE, TUNE_SWEEP = 0, 1
 STORAGE_BYTES = {STORE_F32: 4, STORE_F16: 2, STORE_BF16: 2, STORE_F64: 8}
 STORAGE_NAMES = {STORE_F32: "f32", STORE_F16: "f16", STORE_BF16: "bf16", STORE_F64: "f64"}
@@ -51,7 +52,7 @@ class lbm_bc(ctypes.Structure):
     _fields_ = [("sputter", ctypes.c_int32), ("coupling", ctypes.c_int32), ("species_x", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("p_stick", ctypes.c_double), ("c_inlet", ctypes.c_double),
                 ("rho0", ctypes.c_double), ("c0", ctypes.c_double), ("c_ref", ctypes.c_double),
-                ("force", ctypes.c_double * 3), ("product", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("force", ctypes.c_double * 3), ("product", ctypes.c_int32), ("rounding", ctypes.c_int32),
                 ("p_stick_product", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("wall_diffuse", ctypes.c_double)]
 
@@ -218,10 +219,10 @@ def _geometry(vox, pore_size):
 
 def _bc(sputter=SPUTTER_UNIFORM, coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32,
         p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0), product=False,
-        p_stick_product=0.0, seed=0, wall_diffuse=0.0):
+        p_stick_product=0.0, seed=0, wall_diffuse=0.0, rounding=ROUND_NEAREST):
     return lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
                   float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]),
-                  int(bool(product)), 0, float(p_stick_product), int(seed), float(wall_diffuse))
+                  int(bool(product)), int(rounding), float(p_stick_product), int(seed), float(wall_diffuse))
 
 
 def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc_kw):
@@ -229,7 +230,7 @@ def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc
     lbm_device struct holder (see use_torch) or None for hipMalloc and the
     null stream; bc_kw are the lbm_bc fields (sputter, coupling, species_x,
     storage, p_stick, c_inlet, rho0, c0, c_ref, force, product,
-    p_stick_product).  Returns the raw
+    p_stick_product, seed, wall_diffuse, rounding).  Returns the raw
     context handle."""
     vox, g = _geometry(vox, pore_size)
     bc = _bc(**bc_kw)
@@ -259,7 +260,7 @@ class Sim:
     default method: product=True with p_stick_product (the product lattice;
     product_fields() and the product totals), sputter=SPUTTER_STOCHASTIC with
     seed (random sputtering matrix), wall_diffuse=sigma (diffuse carrier
-    wall)."""
+    wall), rounding=ROUND_STOCHASTIC (stochastic rounding of 16-bit stores)."""
 
     def __init__(self, vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, use_torch=True, stream=None, **kw):
         self._h = None

