@@ -286,6 +286,24 @@ lbm_status lbm_fields(lbm_ctx *c, double *rho, double *u, double *conc);
  * n_nodes), queued on the context stream without synchronising. */
 lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc);
 
+/* lbm_fields_noalloc - lbm_fields for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same outputs, bit for bit, through a fixed device
+ * scratch instead of temporary buffers.  Calls no hipMalloc or hipFree and
+ * takes nothing from lbm_device.alloc.
+ *
+ * rho, u (3 N, component-major), conc: host, caller-owned, N = nx ny nz
+ * doubles each (u: 3 N); NULL = skip.  Synchronises the context's stream.
+ * The fields pass through a 32 MiB device array (one per GPU, held until the
+ * process ends) in passes of whole x-rows, 5 nx doubles a row.  Calls on one
+ * GPU share that array: calls that overlap in time on one GPU (from several
+ * threads or streams) race and must be serialised by the caller.  Makes the
+ * context's device current for the call and restores the caller's.
+ * Errors: LBM_EINVAL for a NULL context or an x-row that does not fit the
+ * scratch (not reachable with nx <= 4096); LBM_EDEVICE when the scratch
+ * cannot be resolved on the device or a launch or copy fails. */
+lbm_status lbm_fields_noalloc(lbm_ctx *c, double *rho, double *u, double *conc);
+
 /*
  * lbm_conversion_map - per voxel, the reactant converted at that catalytic
  * node so far: p p_S^R sum_t In(k, t), where In(k, t) is everything arriving

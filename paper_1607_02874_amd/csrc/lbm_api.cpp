@@ -71,6 +71,7 @@ struct lbm_ctx {
     void *d_pop[2] = {nullptr, nullptr};
     double *d_part = nullptr;
     DevTotals *d_tot = nullptr;
+    int device = 0;       // the HIP device the context was created on
     int cur = 0;          // d_pop[cur] holds the post-collision state of the current step
     int64_t step = 0;
     int64_t blocks_sweep = 0, blocks_iface = 0;
@@ -595,6 +596,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     if (!c) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
     if (dev) c->dev = *dev;
     c->stream = static_cast<hipStream_t>(c->dev.stream);
+    c->device = device;
     c->nx = g->nx;
     c->ny = g->ny;
     c->nz = g->nz;
@@ -857,6 +859,48 @@ lbm_status lbm_fields(lbm_ctx *c, double *rho, double *u, double *conc) {
         if (d[k]) (c->dev.free ? c->dev.free(d[k], c->dev.user) : (void)hipFree(d[k]));
     if (st != LBM_OK) return st;
     if (e != hipSuccess) return hip_fail(c, e, "fields copy");
+    return LBM_OK;
+}
+
+lbm_status lbm_fields_noalloc(lbm_ctx *c, double *rho, double *u, double *conc) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (!rho && !u && !conc) return LBM_OK;
+    // whole x-rows per pass through the device scratch: rho, three velocity
+    // components and conc, 5 nx doubles a row
+    const int64_t rows = int64_t(c->ny) * c->nz, n = c->n;
+    const int64_t per_pass = FIELDS_SCRATCH_DOUBLES / (5 * int64_t(c->nx));
+    if (per_pass < 1) return fail(c, LBM_EINVAL, "one x-row of fields exceeds the 32 MiB scratch");
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+    if (prev != c->device) {
+        e = hipSetDevice(c->device);
+        if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    }
+    double *scr = nullptr;
+    e = scratch_address(c->device, &scr);
+    if (e == hipSuccess) {
+        const int mode = c->step == 0 ? 2 : 1;
+        const void *fin = c->d_pop[1 - c->cur];
+        const Geometry g = geometry(c);
+        for (int64_t r0 = 0; r0 < rows && e == hipSuccess; r0 += per_pass) {
+            const int64_t r1 = std::min(rows, r0 + per_pass);
+            const int64_t len = (r1 - r0) * c->nx, off = r0 * c->nx;
+            double *s_rho = scr, *s_u = scr + len, *s_c = scr + 4 * len;
+            e = launch_fields_rows(g, c->ph, fin, c->d_emit, mode, rho ? s_rho : nullptr, u ? s_u : nullptr,
+                                   conc ? s_c : nullptr, true, r0, r1, len, c->stream);
+            // the next pass's kernel is queued behind these copies on the same stream
+            if (e == hipSuccess && rho)
+                e = hipMemcpyAsync(rho + off, s_rho, size_t(len) * 8, hipMemcpyDeviceToHost, c->stream);
+            for (int a = 0; a < 3 && e == hipSuccess && u; ++a)
+                e = hipMemcpyAsync(u + a * n + off, s_u + a * len, size_t(len) * 8, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess && conc)
+                e = hipMemcpyAsync(conc + off, s_c, size_t(len) * 8, hipMemcpyDeviceToHost, c->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (prev != c->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(c, e, "allocation-free fields");
     return LBM_OK;
 }
 

@@ -165,6 +165,17 @@ int64_t sweep_blocks_c(const Geometry &g);
 // double arrays when out_f64 is set; any output may be null.
 hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
                          void *rho, void *u, void *conc, bool out_f64, hipStream_t s);
+// The same for the x-rows [row0, row1) only, written from index 0 of each
+// output with velocity component stride cs.
+hipError_t launch_fields_rows(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
+                              void *rho, void *u, void *conc, bool out_f64, int64_t row0, int64_t row1, int64_t cs,
+                              hipStream_t s);
+// Allocation-free field readback: the device scratch (FIELDS_SCRATCH_DOUBLES
+// doubles, one copy per GPU) and the address of `device`'s copy, which must
+// be the current device at the first call for it.
+constexpr int64_t FIELDS_SCRATCH_DOUBLES = int64_t(4) << 20;  // 32 MiB
+constexpr int MAX_SCRATCH_DEVICES = 64;
+hipError_t scratch_address(int device, double **out);
 // A box of voxels: origin and extent, inside the lattice.
 struct Window {
     int32_t x0, y0, z0, wx, wy, wz;

@@ -26,6 +26,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1266,14 +1267,16 @@ __global__ __launch_bounds__(256, ST == ST_F64 ? 1 : (sizeof(typename Store<ST>:
     sweep_block<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
 }
 
+// Outputs cover the x-rows [row0, row1) (row = z ny + y): voxel v of those
+// rows goes to index v - row0 nx, velocity component a to a cs + that index.
 template <int ST, bool LOCAL, typename OUT>
 __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store<ST>::T> ph,
                                                  Slots in, const typename Store<ST>::S *__restrict__ emit,
-                                                 OUT *rho, OUT *vel,
-                                                 OUT *conc) {
+                                                 OUT *rho, OUT *vel, OUT *conc, int64_t row0, int64_t row1,
+                                                 int64_t cs) {
     using T = typename Store<ST>::T;
     const WaveUnit u = locate(g, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))));
-    if (!u.valid || u.x >= g.nx) return;
+    if (!u.valid || u.x >= g.nx || u.row < row0 || u.row >= row1) return;
     T r = 0, ux = 0, uy = 0, uz = 0, c = 0;
     if (u.active) {
         T hC[19], hR[19];
@@ -1295,14 +1298,13 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
         uy = m.uy;
         uz = m.uz;
     }
-    const int64_t n = int64_t(g.nx) * g.ny * g.nz;
-    const int64_t v = int64_t(u.row) * g.nx + u.x;
+    const int64_t v = (int64_t(u.row) - row0) * g.nx + u.x;
     if (rho) rho[v] = OUT(r);
     if (conc) conc[v] = OUT(c);
     if (vel) {
         vel[v] = OUT(ux);
-        vel[n + v] = OUT(uy);
-        vel[2 * n + v] = OUT(uz);
+        vel[cs + v] = OUT(uy);
+        vel[2 * cs + v] = OUT(uz);
     }
 }
 
@@ -1984,6 +1986,13 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
 
 hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode, void *rho,
                          void *u, void *conc, bool out_f64, hipStream_t s) {
+    const int64_t rows = int64_t(g.ny) * g.nz;
+    return launch_fields_rows(g, ph, fin, emit, mode, rho, u, conc, out_f64, 0, rows, rows * g.nx, s);
+}
+
+hipError_t launch_fields_rows(const Geometry &g, const Physics &ph, const void *fin, const void *emit, int mode,
+                              void *rho, void *u, void *conc, bool out_f64, int64_t row0, int64_t row1, int64_t cs,
+                              hipStream_t s) {
     return dispatch(ph.storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         using SS = typename Store<ST>::S;
@@ -1995,15 +2004,19 @@ hipError_t launch_fields(const Geometry &g, const Physics &ph, const void *fin, 
         if (out_f64) {
             double *a = static_cast<double *>(rho), *b = static_cast<double *>(u), *c = static_cast<double *>(conc);
             if (mode == 2)
-                hipLaunchKernelGGL((k_fields<ST, true, double>), grid, block, 0, s, g, k, f, e, a, b, c);
+                hipLaunchKernelGGL((k_fields<ST, true, double>), grid, block, 0, s, g, k, f, e, a, b, c, row0, row1,
+                                   cs);
             else
-                hipLaunchKernelGGL((k_fields<ST, false, double>), grid, block, 0, s, g, k, f, e, a, b, c);
+                hipLaunchKernelGGL((k_fields<ST, false, double>), grid, block, 0, s, g, k, f, e, a, b, c, row0, row1,
+                                   cs);
         } else {
             float *a = static_cast<float *>(rho), *b = static_cast<float *>(u), *c = static_cast<float *>(conc);
             if (mode == 2)
-                hipLaunchKernelGGL((k_fields<ST, true, float>), grid, block, 0, s, g, k, f, e, a, b, c);
+                hipLaunchKernelGGL((k_fields<ST, true, float>), grid, block, 0, s, g, k, f, e, a, b, c, row0, row1,
+                                   cs);
             else
-                hipLaunchKernelGGL((k_fields<ST, false, float>), grid, block, 0, s, g, k, f, e, a, b, c);
+                hipLaunchKernelGGL((k_fields<ST, false, float>), grid, block, 0, s, g, k, f, e, a, b, c, row0, row1,
+                                   cs);
         }
         return hipGetLastError();
     });
@@ -2167,6 +2180,34 @@ hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compa
         hipLaunchKernelGGL(k_reduce_batch, dim3(unsigned(n)), dim3(256), 0, s, d_reduce);
         return hipGetLastError();
     });
+}
+
+// ------------------------------------------------ allocation-free entry --
+// Scratch of lbm_fields_noalloc: a bounce buffer for field rows, in every
+// GPU's copy of the code object, held until the process ends.  Host code
+// never uses the array's name as an address (in host code it is a stand-in
+// for the device object): scratch_address asks the runtime for the address of
+// the current device's copy, once per device, and callers pass that pointer.
+static __device__ __align__(256) double scratch[FIELDS_SCRATCH_DOUBLES];
+
+hipError_t scratch_address(int device, double **out) {
+    static std::mutex mu;
+    static double *addr[MAX_SCRATCH_DEVICES] = {};
+    if (device < 0 || device >= MAX_SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the lookup needs that device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<double *>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace lbmk

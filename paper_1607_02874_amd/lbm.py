@@ -113,6 +113,7 @@ def _load():
                              P(lbm_info)]),
         "lbm_fields": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_fields_device": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+        "lbm_fields_noalloc": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_conversion_map": (st, [ctx, ctypes.c_void_p]),
         "lbm_product_fields": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_populations": (st, [ctx, P(ctypes.c_int32), P(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p]),
@@ -307,6 +308,14 @@ class Sim:
         u = np.zeros(3 * self.n)
         c = np.zeros(self.n)
         _check(_LIB.lbm_fields(self._h, rho.ctypes.data, u.ctypes.data, c.ctypes.data), self._h)
+        return rho.reshape(self.shape), u.reshape((3,) + self.shape), c.reshape(self.shape)
+
+    def fields_noalloc(self):
+        """fields() through lbm_fields_noalloc (no device allocation)."""
+        rho = np.zeros(self.n)
+        u = np.zeros(3 * self.n)
+        c = np.zeros(self.n)
+        _check(_LIB.lbm_fields_noalloc(self._h, rho.ctypes.data, u.ctypes.data, c.ctypes.data), self._h)
         return rho.reshape(self.shape), u.reshape((3,) + self.shape), c.reshape(self.shape)
 
     def fields_device(self, rho=None, u=None, conc=None):
