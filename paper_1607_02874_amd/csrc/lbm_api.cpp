@@ -78,7 +78,7 @@ struct lbm_ctx {
     int ytile = 16;       // rows per y-tile of the sweep traversal
     // node-compact sweep: per-node coordinates and wave launch order;
     // compact = 1 selects it (needs ny, nz <= 1024)
-    uint32_t *d_pos = nullptr, *d_worder = nullptr;
+    uint32_t *d_pos = nullptr, *d_worder = nullptr, *d_wunits = nullptr;
     int64_t nwaves = 0;
     bool compact_ok = false;
     int compact = 0;
@@ -168,6 +168,7 @@ Geometry geometry(const lbm_ctx *c) {
     g.nfluid = c->nfluid;
     g.pos = c->d_pos;
     g.worder = c->d_worder;
+    g.wunits = c->d_wunits;
     g.nwaves = uint32_t(c->nwaves);
     g.pad2 = 0;
     g.ivox = c->d_iface_vox;
@@ -182,6 +183,24 @@ int64_t nslot(const lbm_ctx *c) { return c->ph.sputter == SP_STOCHASTIC ? NSLOT 
 // Sweep blocks of the variant in use (the partial sums have one row each).
 int64_t active_sweep_blocks(const lbm_ctx *c) {
     return c->compact ? sweep_blocks_c(geometry(c)) : c->blocks_sweep;
+}
+
+// Per compact wave w: the (row, chunk) unit of its first node, u0 = (z ny +
+// y) W + x / 64, and the number of consecutive units its 64 nodes span
+// (capped at 63), as u0 | nu << 26 (u0 < 2^26 since ny, nz <= 1024 and
+// W <= 64).  The sweep loads its wavefront's records cooperatively when nu is
+// small, and finds each lane's coordinates from them.
+void build_wave_units(const lbm_ctx *c, const std::vector<uint32_t> &pos, std::vector<uint32_t> &wunits) {
+    auto unit = [&](uint32_t p) {
+        const uint32_t x = p & 0xfffu, y = (p >> 12) & 0x3ffu, z = p >> 22;
+        return (z * uint32_t(c->ny) + y) * uint32_t(c->W) + (x >> 6);
+    };
+    wunits.resize(size_t(c->nwaves));
+    for (int64_t w = 0; w < c->nwaves; ++w) {
+        const int64_t last = std::min<int64_t>(c->nfluid, w * 64 + 64) - 1;
+        const uint32_t u0 = unit(pos[size_t(w * 64)]), u1 = unit(pos[size_t(last)]);
+        wunits[size_t(w)] = u0 | (std::min<uint32_t>(u1 - u0 + 1u, 63u) << 26);
+    }
 }
 
 // Launch order of the node-compact waves: wave w (storage indices 64 w ..)
@@ -546,8 +565,9 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
         info->n_interface = niface;
         info->n_catalytic_links = c.nlinks;
         // the buffers lbm_create allocates (populations and emission, chunk
-        // records and traversal tables, interface arrays, coordinates and wave
-        // order of the compact sweep, partial sums), each rounded up to 256 B
+        // records and traversal tables, interface arrays, coordinates, wave
+        // order and wave units of the compact sweep, partial sums), each
+        // rounded up to 256 B
         auto r256 = [](int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); };
         const int64_t chunks = rows * c.W;
         const int64_t blocks = ((chunks + 3) / 4 + 7) / 8 * 8;
@@ -557,7 +577,7 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
                         r256(chunks * 4) + 2 * r256(niface * 4) + 2 * r256(niface * 8) + r256(ns * niface * 8) +
                         r256((4 * blocks + 2 * ((niface + 255) / 256) + 2 * FOLD_BLOCKS * NPART) * 8) +
                         r256(int64_t(sizeof(DevTotals)));
-        if (compact) bytes += r256(nfp * 4) + r256((c.nfluid + 63) / 64 * 4);
+        if (compact) bytes += r256(nfp * 4) + 2 * r256((c.nfluid + 63) / 64 * 4);
         if (bc->product) {
             // P buffers and E_P, In_P and Acc_P, P partial sums
             const int64_t blocks_c = ((c.nfluid + 63) / 64 + 3) / 4;
@@ -664,7 +684,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         c->nwaves = (c->nfluid + 63) / 64;
         // node-compact sweep tables (coordinates packed as x | y << 12 | z << 22)
         c->compact_ok = c->ny <= 1024 && c->nz <= 1024 && c->nfluid > 0;
-        std::vector<uint32_t> pos, worder;
+        std::vector<uint32_t> pos, worder, wunits;
         if (c->compact_ok) {
             pos.assign(size_t(c->nfp), 0);
             size_t r = 0;
@@ -674,6 +694,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
                         if (c->vox[size_t((int64_t(z) * c->ny + y) * c->nx + x)] == LBM_FLUID)
                             pos[r++] = uint32_t(x) | (uint32_t(y) << 12) | (uint32_t(z) << 22);
             build_wave_order(c, pos, std::min(c->ytile, c->ny), worder);
+            build_wave_units(c, pos, wunits);
             c->compact = 1;
         }
         if (c->ph.product && !c->compact_ok) {
@@ -714,6 +735,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         if (c->compact_ok) {
             c->d_pos = static_cast<uint32_t *>(dev_alloc(c, pos.size() * 4));
             c->d_worder = static_cast<uint32_t *>(dev_alloc(c, worder.size() * 4));
+            c->d_wunits = static_cast<uint32_t *>(dev_alloc(c, wunits.size() * 4));
         }
         // One pool: population buffers A and B, then the emission array (one
         // element per interface node, indexed by interface index, plus one:
@@ -745,7 +767,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         }
         if (!c->d_chunks || !c->d_order || !c->d_inacc || !c->d_iface_vox || !c->d_iface_mask || !c->d_iface_scale || !c->d_acc || !c->d_emit ||
             !c->d_pop[0] || !c->d_pop[1] || !c->d_part || !c->d_tot || !prod_ok ||
-            (c->compact_ok && (!c->d_pos || !c->d_worder))) {
+            (c->compact_ok && (!c->d_pos || !c->d_worder || !c->d_wunits))) {
             release(c);
             delete c;
             return fail(nullptr, LBM_ENOMEM, "device allocation failed");
@@ -763,6 +785,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         if (c->compact_ok) {
             up(c->d_pos, pos.data(), pos.size() * 4);
             up(c->d_worder, worder.data(), worder.size() * 4);
+            up(c->d_wunits, wunits.data(), wunits.size() * 4);
         }
         if (e == hipSuccess) e = hipMemsetAsync(c->d_acc, 0, size_t(c->niface) * 8, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->d_emit, 0, (size_t(nslot(c) * c->niface) + 1) * sb, c->stream);

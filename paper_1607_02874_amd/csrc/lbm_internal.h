@@ -86,6 +86,7 @@ struct Geometry {
     // indices per wave); null when the lattice is too large for `pos`.
     const uint32_t *pos;      // per gas node: x | y << 12 | z << 22
     const uint32_t *worder;   // launch order of the 64-node waves
+    const uint32_t *wunits;   // per wave: first (row, chunk) unit | units spanned << 26
     uint32_t nwaves;          // ceil(nfluid / 64)
     int32_t pad2;
     // interface list (voxel index and active-link mask per interface node),

@@ -605,6 +605,101 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     cat_out = cat_bits;
 }
 
+// The 64 consecutive gas nodes of a compact wavefront lie in a few
+// consecutive (row, chunk) units of the lattice (at 256^3, porosity 0.61: at
+// most 3 for 93 % of the wavefronts, at most 7 for all but 1 in 40,000), and
+// the nine source-row records a lane needs are those of its unit shifted by
+// the nine (c_y, c_z) classes.  When the wavefront spans at most WREC_UNITS
+// units (host table g.wunits: first unit u0 and count nu), its lanes load all
+// 9 x nu records once (one record per lane, two vector loads in all) into the
+// wavefront's LDS slice, and each lane reads its nine from there instead of
+// issuing nine loads of its own.  The records of the wavefront's own units
+// (class 0) also give each lane its coordinates: lane `rank` lies in the last
+// unit whose first gas node is at or before it, at the (rank - base)-th gas
+// bit of that unit, so no per-node coordinate is read.  Called by every lane
+// of a valid wavefront; returns false, with nothing loaded, when the
+// wavefront spans more units.
+constexpr uint32_t WREC_UNITS = 7;
+// (c_y + 1) and (c_z + 1) of the nine classes, two bits each, class order as CYS / CZS
+constexpr uint32_t CLS_CY1 = (1u << 0) | (2u << 2) | (0u << 4) | (1u << 6) | (1u << 8) | (2u << 10) | (2u << 12) |
+                             (0u << 14) | (0u << 16);
+constexpr uint32_t CLS_CZ1 = (1u << 0) | (1u << 2) | (1u << 4) | (2u << 6) | (0u << 8) | (2u << 10) | (0u << 12) |
+                             (0u << 14) | (2u << 16);
+
+// Bit index of the k-th (from 0) set bit of m (k < popcount(m)).
+__device__ __forceinline__ uint32_t kth_set_bit(uint64_t m, uint32_t k) {
+    uint32_t v = uint32_t(m), pos = 0u;
+    uint32_t c = uint32_t(__popc(v));
+    if (k >= c) {
+        k -= c;
+        v = uint32_t(m >> 32);
+        pos = 32u;
+    }
+#pragma unroll
+    for (uint32_t w = 16u; w >= 1u; w >>= 1) {
+        c = uint32_t(__popc(v & ((1u << w) - 1u)));
+        const bool up = k >= c;
+        k -= up ? c : 0u;
+        v = up ? v >> w : v;
+        pos += up ? w : 0u;
+    }
+    return pos;
+}
+
+struct WaveRecords {
+    ChunkInfo rec[9 * WREC_UNITS];
+    uint32_t upos[WREC_UNITS];  // x of the unit's first voxel | y << 12 | z << 22
+};
+
+__device__ __forceinline__ bool wave_records(const Geometry &g, uint32_t w, uint32_t rank, bool active,
+                                             WaveRecords &wr, uint32_t &wunit, uint32_t &pos) {
+    const uint32_t wu = glb(g.wunits)[w];
+    const uint32_t u0 = wu & ((1u << 26) - 1u), nu = wu >> 26;
+    if (nu > WREC_UNITS) return false;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t W = uint32_t(g.W), ny = uint32_t(g.ny), nz = uint32_t(g.nz);
+    if (lane < 9u * nu) {
+        const uint32_t cls = lane / nu, j = lane - cls * nu;
+        const uint32_t u = u0 + j;
+        const uint32_t row = u / W, chunk = u - row * W;
+        const uint32_t zr = row / ny, yr = row - zr * ny;
+        // source row of the class: (y - c_y, z - c_z), periodic
+        const uint32_t cy1 = (CLS_CY1 >> (2u * cls)) & 3u, cz1 = (CLS_CZ1 >> (2u * cls)) & 3u;
+        uint32_t ys = yr + ny + 1u - cy1, zs = zr + nz + 1u - cz1;
+        ys = ys >= ny ? ys - ny : ys;
+        ys = ys >= ny ? ys - ny : ys;
+        zs = zs >= nz ? zs - nz : zs;
+        zs = zs >= nz ? zs - nz : zs;
+        const LBM_GLOBAL ChunkInfo &src = glb(g.chunks)[(zs * ny + ys) * W + chunk];
+        ChunkInfo &dst = wr.rec[cls * WREC_UNITS + j];
+        dst.fluid = src.fluid;
+        dst.cat = src.cat;
+        dst.base = src.base;
+        dst.ibase = src.ibase;
+        dst.prev = src.prev;
+        dst.next = src.next;
+        if (cls == 0u) wr.upos[j] = (chunk << 6) | (yr << 12) | (zr << 22);
+    }
+    // the wavefront's LDS writes before its reads
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    uint32_t jj = 0u, kb = 0u;
+    uint64_t fm = 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < WREC_UNITS; ++j) {
+        if (j < nu) {
+            const uint64_t f = wr.rec[j].fluid;
+            const uint32_t b = wr.rec[j].base;
+            const bool here = f != 0u && b <= rank;
+            jj = here ? j : jj;
+            kb = here ? b : kb;
+            fm = here ? f : fm;
+        }
+    }
+    wunit = jj;
+    pos = active ? wr.upos[jj] + kth_set_bit(fm, rank - kb) : 0u;
+    return true;
+}
+
 // The same pull for the node-compact sweep: each lane is one gas node at
 // (x, y, z) with storage index idx, lanes of a wave need not share a row.  For
 // each of the nine source rows a lane reads the record of its own chunk in
@@ -630,7 +725,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
                                        const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
                                        int z, typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
                                        uint32_t &cat_out, uint32_t *kidx, const ProdK<ST> &pk,
-                                       typename Store<ST>::T (&hP)[19]) {
+                                       typename Store<ST>::T (&hP)[19], const ChunkInfo *wrec, uint32_t wunit) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     using P = typename Store<ST>::P;
@@ -658,21 +753,28 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     const uint32_t shr = ledge ? 0u : xl - 1u;
     const uint64_t below = (uint64_t(1) << xl) - 1u;
 
-    // phase 1: the nine records
+    // phase 1: the nine records, from the wavefront's LDS copy (wrec, see
+    // wave_records) or, where the wavefront spans too many units, each lane's
+    // own loads
     ChunkInfo rec[9];
+    if (wrec) {
 #pragma unroll
-    for (int cls = 0; cls < 9; ++cls) {
-        int ys = y - CYS[cls], zs = z - CZS[cls];
-        ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
-        zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
-        const uint32_t rown = uint32_t(zs) * uint32_t(g.ny) + uint32_t(ys);
-        const LBM_GLOBAL ChunkInfo &src = glb(g.chunks)[rown * uint32_t(g.W) + chunk];
-        rec[cls].fluid = src.fluid;
-        rec[cls].cat = src.cat;
-        rec[cls].base = src.base;
-        rec[cls].ibase = src.ibase;
-        rec[cls].prev = src.prev;
-        rec[cls].next = src.next;
+        for (int cls = 0; cls < 9; ++cls) rec[cls] = wrec[cls * WREC_UNITS + wunit];
+    } else {
+#pragma unroll
+        for (int cls = 0; cls < 9; ++cls) {
+            int ys = y - CYS[cls], zs = z - CZS[cls];
+            ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+            zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
+            const uint32_t rown = uint32_t(zs) * uint32_t(g.ny) + uint32_t(ys);
+            const LBM_GLOBAL ChunkInfo &src = glb(g.chunks)[rown * uint32_t(g.W) + chunk];
+            rec[cls].fluid = src.fluid;
+            rec[cls].cat = src.cat;
+            rec[cls].base = src.base;
+            rec[cls].ibase = src.ibase;
+            rec[cls].prev = src.prev;
+            rec[cls].next = src.next;
+        }
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -1170,13 +1272,17 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
     const uint32_t idx = w * 64u + (threadIdx.x & 63u);
     const bool active = wvalid && int64_t(idx) < g.nfluid;
     __shared__ uint32_t kidx[18 * 256];
+    __shared__ WaveRecords wrec_all[4];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    uint32_t wunit = 0, p = 0;
+    const bool coop = wvalid && wave_records(g, w, idx, active, wrec_all[wave], wunit, p);
+    if (!coop && active) p = glb(g.pos)[idx];
+    const int x = int(p & 0xfffu), y = int((p >> 12) & 0x3ffu), z = int(p >> 22);
     if (active) {
-        const uint32_t p = glb(g.pos)[idx];
-        const int x = int(p & 0xfffu), y = int((p >> 12) & 0x3ffu), z = int(p >> 22);
         T hC[19], hR[19], hP[19];  // hP: product lattice (unused without it)
         uint32_t cat_bits;
-        pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx, pk, hP);
+        pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx, pk, hP,
+                       coop ? wrec_all[wave].rec : nullptr, wunit);
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
