@@ -25,7 +25,7 @@ thread_local std::string g_create_error;
 
 constexpr double CS = 0.57735026918962576451;  // lattice sound speed 1/sqrt(3)
 constexpr int TIMING_RING = 512;
-constexpr uint64_t CKPT_MAGIC = 0x3647504b434d424cull;  // "LBMCKPG6"
+constexpr uint64_t CKPT_MAGIC = 0x3747504b434d424cull;  // "LBMCKPG7"
 
 struct StepEvents {
     hipEvent_t ev[8];  // start/stop of the front launch, xflux, sweep, closing reduction
@@ -49,6 +49,7 @@ struct lbm_ctx {
     // sizes and parameters
     int nx = 0, ny = 0, nz = 0, W = 0;
     int64_t n = 0, nfluid = 0, nfp = 0, niface = 0, nlinks = 0;
+    uint32_t lay_ss = 0, lay_bs = 0;  // population layout (Geometry::lay_ss / lay_bs)
     double kn = 0, da = 0, delta = 0, p = 0;
     int p_clamped = 0;
     Physics ph{};
@@ -165,6 +166,8 @@ Geometry geometry(const lbm_ctx *c) {
     g.units = uint32_t(int64_t(c->ny) * c->nz * c->W);
     g.niface = uint32_t(c->niface);
     g.nfp = c->nfp;
+    g.lay_ss = c->lay_ss;
+    g.lay_bs = c->lay_bs;
     g.nfluid = c->nfluid;
     g.pos = c->d_pos;
     g.worder = c->d_worder;
@@ -669,6 +672,17 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         // one spare element per direction array at least: the last one holds
         // the inlet ghost population of the reactant
         c->nfp = (c->nfluid + 1 + 127) / 128 * 128;
+        // Population layout: blocks of 64 consecutive nodes holding all 19
+        // slots when a whole pair buffer fits the kernels' 32-bit offsets (a
+        // wavefront then reads its own and its neighbours' populations from
+        // few contiguous blocks and writes one), else slot-major.
+        if (uint64_t(19) * uint64_t(c->nfp) * 2 * uint64_t(storage_bytes(bc->storage)) < (uint64_t(1) << 32)) {
+            c->lay_ss = 64;
+            c->lay_bs = 19 * 64;
+        } else {
+            c->lay_ss = uint32_t(c->nfp);
+            c->lay_bs = 64;
+        }
         std::vector<uint32_t> ivox, imask;
         std::vector<double> iscale;
         build_interface(c, ivox, imask, iscale);

@@ -88,6 +88,12 @@ struct Geometry {
     const uint32_t *worder;   // launch order of the 64-node waves
     const uint32_t *wunits;   // per wave: first (row, chunk) unit | units spanned << 26
     uint32_t nwaves;          // ceil(nfluid / 64)
+    // Population layout: element (node n, slot s) of a population array
+    // (pairs, or single product populations) is s lay_ss + (n >> 6) lay_bs +
+    // (n & 63).  Blocked: lay_ss = 64, lay_bs = 19 * 64 (the 19 slots of 64
+    // consecutive nodes form one contiguous block); slot-major: lay_ss = nfp,
+    // lay_bs = 64 (element n of slot s at s nfp + n).
+    uint32_t lay_ss, lay_bs;
     int32_t pad2;
     // interface list (voxel index and active-link mask per interface node),
     // read by the STOCHASTIC sweeps to key and resolve each draw

@@ -257,6 +257,14 @@ template <typename T>
 __device__ __forceinline__ LBM_GLOBAL T *glb(T *p) {
     return (LBM_GLOBAL T *)(p);
 }
+// Element index of node n inside one slot of a population array (see
+// Geometry::lay_ss / lay_bs); the slot adds s lay_ss elements.  n < 2^30, so
+// n >> 6 and lay_bs fit the 24-bit multiplier.
+__device__ __forceinline__ uint32_t node_elem(const Geometry &g, uint32_t n) {
+    return __umul24(n >> 6, g.lay_bs) + (n & 63u);
+}
+__device__ __forceinline__ uint64_t slot_elem(const Geometry &g, int slot) { return uint64_t(uint32_t(slot)) * g.lay_ss; }
+
 // Keep a selected value opaque to the optimizer (no instruction is emitted):
 // stops it from folding a select into the address arithmetic and turning the
 // select back into divergent branches.
@@ -374,10 +382,11 @@ __device__ __forceinline__ void st_stream(S *base, uint32_t byte_off, S v) {
     __builtin_nontemporal_store(v, (LBM_GLOBAL S *)((LBM_GLOBAL char *)(base) + byte_off));
 }
 
-// A population buffer: 19 direction arrays (slots dslot(i)) of `stride`
-// bytes each from `base`.  Element n of a direction array is the pair
-// (carrier, reactant) of gas node n, so the common pull, where both lattices
-// take the same source, is one load and the store of a direction one store.
+// A population buffer: 19 slots (dslot(i)) of `stride` bytes each from
+// `base` (stride = lay_ss elements); node n of a slot is element
+// node_elem(n).  An element is the pair (carrier, reactant) of a gas node, so
+// the common pull, where both lattices take the same source, is one load and
+// the store of a direction one store.
 // A direction's base address is formed in scalar registers where it is used
 // (one 64-bit multiply-add), so the kernels do not hold 38 pointers in scalar
 // registers.  (The create path guarantees that two direction arrays span
@@ -484,8 +493,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     using S = typename Store<ST>::S;
     using P = typename Store<ST>::P;
     constexpr uint32_t SB = sizeof(S), PB = 2 * SB;
-    const int64_t nfp = g.nfp;
-    const uint32_t nfp_b = uint32_t(nfp) * PB;   // one direction array, in bytes
+    const uint32_t nfp_b = in.stride;   // one slot, in bytes
     const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
     // SP: the sputter mode (bits 0-1) and the INFLOW flag, fixed at compile
     // time for the sweeps, or -1 to read both from ph
@@ -496,7 +504,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
     const bool diffuse = SP >= 0 ? (SP & SP_DIFFUSE_FLAG) != 0 : ph.sigma != T(0);
     uint32_t solid_bits = 0;  // directions whose source is solid (the carrier reflects there)
     auto base = [&](int slot) { return in.p(slot); };
-    const uint32_t own_b = u.idx * PB;
+    const uint32_t own_b = node_elem(g, u.idx) * PB;
     // wave-uniform shape of the chunk
     const int nvalid = min(64, g.nx - 64 * u.chunk);
     const int last_lane = nvalid - 1;
@@ -564,7 +572,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         // or the bounce-back is an offset of 0 or nfp elements plus a node.
         const uint32_t half = dslot(i) < dslot(opp(i)) ? 0u : nfp_b;  // i's array inside the pair
         const uint32_t bb_b = own_b + (nfp_b - half);                   // own opp(i) entry
-        const uint32_t pull_b = rank * PB + half;
+        const uint32_t pull_b = node_elem(g, rank) * PB + half;
         // both lattices from the gas source, or both bounced back
         pc[i] = ld_pop<ST>(base(pair_slot(i)), lane_in(F) ? pull_b : bb_b);
         solid_bits |= lane_in(F) ? 0u : (1u << i);
@@ -578,7 +586,8 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         ro[i] = S(0);
         if (outlet)
             ro[i] = ld_at(static_cast<const S *>(base(pair_slot(i))),
-                          (lane_in(outlet & I.fluid) ? rank_of_mask(I.fluid, I.base) * PB + half : bb_b) + SB);
+                          (lane_in(outlet & I.fluid) ? node_elem(g, rank_of_mask(I.fluid, I.base)) * PB + half : bb_b) +
+                              SB);
         // emission of a catalytic source, by interface index (element 0 when not used)
         re[i] = ld_at(emit, lane_in(EMIT) ? (stoch ? uint32_t(i - 1) * g.niface + irank : irank) * SB : 0u);
         if (kidx) kidx[(i - 1) * 256 + threadIdx.x] = irank;
@@ -733,8 +742,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     // source row class (cy, cz) of each group of directions in ORDER
     constexpr int CYS[9] = {0, 1, -1, 0, 0, 1, 1, -1, -1};
     constexpr int CZS[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
-    const int64_t nfp = g.nfp;
-    const uint32_t nfp_b = uint32_t(nfp) * PB;
+    const uint32_t nfp_b = in.stride;   // one slot, in bytes
     const bool reservoir = ph.species_x != XB_PERIODIC;  // inlet and outlet ghost planes
     // SP: the sputter mode (bits 0-1) and the INFLOW flag, fixed at compile
     // time for the sweeps, or -1 to read both from ph
@@ -745,7 +753,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     const bool diffuse = SP >= 0 ? (SP & SP_DIFFUSE_FLAG) != 0 : ph.sigma != T(0);
     uint32_t solid_bits = 0;  // directions whose source is solid (the carrier reflects there)
     auto base = [&](int slot) { return in.p(slot); };
-    const uint32_t own_b = idx * PB;
+    const uint32_t own_e = node_elem(g, idx), own_b = own_e * PB;
     const uint32_t xl = uint32_t(x) & 63u, chunk = uint32_t(x) >> 6;
     const bool ledge = xl == 0u;                       // x - 1 lies in the previous chunk (or wraps)
     const bool redge = xl == 63u || x == g.nx - 1;     // x + 1 lies in the next chunk (or wraps)
@@ -828,7 +836,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     S re[19], ro[19];
     constexpr bool PROD = SP >= 0 && (SP & SP_PRODUCT_FLAG) != 0;
     S pp[PROD ? 19 : 1], pe[PROD ? 19 : 1], po[PROD ? 19 : 1];
-    const uint32_t nfpp_b = uint32_t(nfp) * SB, ownp_b = idx * SB;  // product buffer: one population per element
+    const uint32_t nfpp_b = pk.in.stride, ownp_b = own_e * SB;  // product buffer: one population per element
     pc[0] = ld_pop<ST>(base(dslot(0)), own_b);
     if constexpr (PROD) pp[0] = ld_at(static_cast<const S *>(pk.in.p(dslot(0))), ownp_b);
     const bool any_outlet = reservoir && __builtin_amdgcn_ballot_w64(last_x) != 0u;
@@ -845,7 +853,8 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             const bool F = (wf >> bit) & 1u;
             const uint32_t half = dslot(i) < dslot(opp(i)) ? 0u : nfp_b;
             const uint32_t bb_b = own_b + (nfp_b - half);
-            const uint32_t pull_b = rk[cls][bit] * PB + half;
+            const uint32_t rke = node_elem(g, rk[cls][bit]);
+            const uint32_t pull_b = rke * PB + half;
             uint32_t c_b = F ? pull_b : bb_b;
             solid_bits |= F ? 0u : (1u << i);
             opaque(c_b);
@@ -858,7 +867,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             ro[i] = S(0);
             if (cx == -1 && any_outlet) {
                 const bool F0 = (wf >> 1) & 1u;
-                uint32_t o_b = (last_x && F0 ? rk[cls][1] * PB + half : bb_b) + SB;
+                uint32_t o_b = (last_x && F0 ? node_elem(g, rk[cls][1]) * PB + half : bb_b) + SB;
                 opaque(o_b);
                 ro[i] = ld_at(static_cast<const S *>(base(pair_slot(i))), o_b);
             }
@@ -866,7 +875,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
                 const uint32_t halfp = dslot(i) < dslot(opp(i)) ? 0u : nfpp_b;
                 const uint32_t bbp_b = ownp_b + (nfpp_b - halfp);
                 const S *pbase = static_cast<const S *>(pk.in.p(pair_slot(i)));
-                uint32_t p_b = F ? rk[cls][bit] * SB + halfp : bbp_b;
+                uint32_t p_b = F ? rke * SB + halfp : bbp_b;
                 opaque(p_b);
                 pp[i] = ld_at(pbase, p_b);
                 uint32_t e_b = bounce ? 0u : kidx[(i - 1) * 256 + threadIdx.x] * SB;
@@ -875,7 +884,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
                 po[i] = S(0);
                 if (cx == -1 && any_outlet) {
                     const bool F0 = (wf >> 1) & 1u;
-                    uint32_t o_b = last_x && F0 ? rk[cls][1] * SB + halfp : bbp_b;
+                    uint32_t o_b = last_x && F0 ? node_elem(g, rk[cls][1]) * SB + halfp : bbp_b;
                     opaque(o_b);
                     po[i] = ld_at(pbase, o_b);
                 }
@@ -1138,11 +1147,13 @@ __device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned
 
 template <int ST>
 __device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double c_in, const char *pop,
-                                             uint32_t stride, uint32_t idx, bool first_x, bool last_x) {
+                                             uint32_t stride, uint32_t elem, bool first_x, bool last_x) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
-    // the node's own reactant population of direction i
-    auto own = [&](int i) { return Store<ST>::ld(reinterpret_cast<const S *>(pop + dslot(i) * stride) + 2 * idx + 1); };
+    // the node's own reactant population of direction i (elem: its element index)
+    auto own = [&](int i) {
+        return Store<ST>::ld(reinterpret_cast<const S *>(pop + uint64_t(dslot(i)) * stride) + 2 * uint64_t(elem) + 1);
+    };
     double fin = 0.0, fout = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
@@ -1159,11 +1170,13 @@ __device__ __noinline__ InOut boundary_tally(typename Store<ST>::T c_ref, double
 // populations at x = 0 along c_x = -1; out_out, those at x = nx - 1 along
 // c_x = +1 (what the outlet ghost returned is subtracted by the caller).
 template <int ST>
-__device__ __noinline__ InOut product_tally(const char *pop, uint32_t stride, uint32_t idx, bool first_x,
+__device__ __noinline__ InOut product_tally(const char *pop, uint32_t stride, uint32_t elem, bool first_x,
                                             bool last_x) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
-    auto own = [&](int i) { return Store<ST>::ld(reinterpret_cast<const S *>(pop + dslot(i) * stride) + idx); };
+    auto own = [&](int i) {
+        return Store<ST>::ld(reinterpret_cast<const S *>(pop + uint64_t(dslot(i)) * stride) + elem);
+    };
     double oin = 0.0, oout = 0.0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
@@ -1227,7 +1240,7 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
         }
         collide(ph, m, hC, hR);
         using P = typename Store<ST>::P;
-        uint32_t own_b = u.idx * uint32_t(sizeof(P));
+        uint32_t own_b = node_elem(g, u.idx) * uint32_t(sizeof(P));
         const lbmfx::RoundWords rw = lbmfx::round_words(ph.sr != 0u, ph.sr_key, u.idx);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
@@ -1246,7 +1259,8 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
                 accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
         }
         if (reservoir && (first_x || last_x)) {
-            const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, u.idx, first_x,
+            const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, node_elem(g, u.idx),
+                                               first_x,
                                                last_x);
             acc[2] += f.in;
             acc[3] += f.out;
@@ -1312,7 +1326,8 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         }
         collide(ph, m, hC, hR);
         using P = typename Store<ST>::P;
-        uint32_t own_b = idx * uint32_t(sizeof(P));
+        const uint32_t own_e = node_elem(g, idx);
+        uint32_t own_b = own_e * uint32_t(sizeof(P));
         // the rounding words of this node (16-bit storage; nearest unless
         // stochastic rounding is on): 2i, 2i + 1 for the pair of direction i,
         // 38 + i for the product
@@ -1327,7 +1342,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         if constexpr (PROD) {
             using S = typename Store<ST>::S;
             collide_product(ph, m, rp, hP);
-            uint32_t ownp_b = idx * uint32_t(sizeof(S));
+            uint32_t ownp_b = own_e * uint32_t(sizeof(S));
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 opaque(ownp_b);
@@ -1337,7 +1352,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
             }
             if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(pk.inacc, kidx, cat_bits, ph, hP, T(0));
             if (reservoir && (first_x || last_x)) {
-                const InOut f = product_tally<ST>(pk.in.base, pk.in.stride, idx, first_x, last_x);
+                const InOut f = product_tally<ST>(pk.in.base, pk.in.stride, node_elem(g, idx), first_x, last_x);
                 accp[1] += f.in;
                 accp[2] += f.out;
             }
@@ -1349,7 +1364,8 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
                 accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
         }
         if (reservoir && (first_x || last_x)) {
-            const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, idx, first_x,
+            const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, node_elem(g, idx),
+                                               first_x,
                                                last_x);
             acc[2] += f.in;
             acc[3] += f.out;
@@ -1389,7 +1405,8 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
         if (LOCAL) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                const typename Store<ST>::P v = static_cast<const typename Store<ST>::P *>(in.p(dslot(i)))[u.idx];
+                const typename Store<ST>::P v =
+                    static_cast<const typename Store<ST>::P *>(in.p(dslot(i)))[node_elem(g, u.idx)];
                 hC[i] = Store<ST>::cv(v.x);
                 hR[i] = Store<ST>::cv(v.y);
             }
@@ -1431,8 +1448,8 @@ __global__ __launch_bounds__(256) void k_init(Geometry g, PhysK<typename Store<S
         // reservoir population, which no kernel needs to read)
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            pre2[dslot(i) * g.nfp + n] = pop_pair<ST>(T(0), ph.h_inlet);
-            post2[dslot(i) * g.nfp + n] = pop_pair<ST>(T(0), ph.h_inlet);
+            pre2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(T(0), ph.h_inlet);
+            post2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(T(0), ph.h_inlet);
         }
         return;
     }
@@ -1440,12 +1457,12 @@ __global__ __launch_bounds__(256) void k_init(Geometry g, PhysK<typename Store<S
     for (int i = 0; i < 19; ++i) {
         hC[i] = ph.h0c;
         hR[i] = ph.h0r;
-        pre2[dslot(i) * g.nfp + n] = pop_pair<ST>(hC[i], hR[i]);
+        pre2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(hC[i], hR[i]);
     }
     const Mom<T> m = moments(ph, hC, hR);
     collide(ph, m, hC, hR);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) post2[dslot(i) * g.nfp + n] = pop_pair<ST>(hC[i], hR[i]);
+    for (int i = 0; i < 19; ++i) post2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(hC[i], hR[i]);
 }
 
 __device__ __forceinline__ uint32_t rank_of(const Geometry &g, int row, int x, bool *fluid) {
@@ -1554,7 +1571,8 @@ __global__ __launch_bounds__(256) void k_populations(Geometry g, PhysK<typename 
         if (LOCAL) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                const typename Store<ST>::P v = static_cast<const typename Store<ST>::P *>(in.p(dslot(i)))[u.idx];
+                const typename Store<ST>::P v =
+                    static_cast<const typename Store<ST>::P *>(in.p(dslot(i)))[node_elem(g, u.idx)];
                 hC[i] = Store<ST>::cv(v.x);
                 hR[i] = Store<ST>::cv(v.y);
             }
@@ -1600,7 +1618,8 @@ __global__ __launch_bounds__(256) void k_in_init(Geometry g, PhysK<typename Stor
             bool fl;
             const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
             const unsigned long long term =
-                in_term<T>(wgt<T>(j), Store<ST>::ld(fin + 2 * (dslot(j) * g.nfp + r) + 1), ph.cref, ph.in_scale);
+                in_term<T>(wgt<T>(j), Store<ST>::ld(fin + 2 * (slot_elem(g, dslot(j)) + node_elem(g, r)) + 1), ph.cref,
+                           ph.in_scale);
             sum += term;
             if (ph.sputter == SP_STOCHASTIC) {
                 const int e = random_exit(ph.step_ctr, ph.seed_lo, ph.seed_hi, v, mask, uint32_t(vcode(j)));
@@ -1642,7 +1661,8 @@ __global__ __launch_bounds__(256) void k_in_init_p(Geometry g, PhysK<typename St
             zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
             bool fl;
             const uint32_t r = rank_of(g, zs * g.ny + ys, xs, &fl);
-            sum += in_term<T>(wgt<T>(j), Store<ST>::ld(finp + dslot(j) * g.nfp + r), T(0), ph.in_scale);
+            sum += in_term<T>(wgt<T>(j), Store<ST>::ld(finp + slot_elem(g, dslot(j)) + node_elem(g, r)), T(0),
+                              ph.in_scale);
         }
     }
     inacc[k] = sum;
@@ -1676,8 +1696,10 @@ __global__ __launch_bounds__(256) void k_product_field(Geometry g, PhysK<typenam
         return;
     }
     const bool xper = ph.species_x == XB_PERIODIC;
-    auto popp = [&](int i, uint32_t r) { return Store<ST>::ld(finp + dslot(i) * g.nfp + r); };
-    auto popr = [&](int i, uint32_t r) { return Store<ST>::ld(fin + 2 * (dslot(i) * g.nfp + r) + 1); };
+    auto popp = [&](int i, uint32_t r) { return Store<ST>::ld(finp + slot_elem(g, dslot(i)) + node_elem(g, r)); };
+    auto popr = [&](int i, uint32_t r) {
+        return Store<ST>::ld(fin + 2 * (slot_elem(g, dslot(i)) + node_elem(g, r)) + 1);
+    };
     double rho = 0.0;
 #pragma unroll 1
     for (int i = 0; i < 19; ++i) {
@@ -2021,7 +2043,7 @@ Slots slots_of(const Geometry &g, const void *buf) {
     Slots sl;
     using S = typename Store<ST>::S;
     sl.base = static_cast<const char *>(buf);
-    sl.stride = uint32_t(uint64_t(g.nfp) * 2 * sizeof(S));
+    sl.stride = uint32_t(uint64_t(g.lay_ss) * 2 * sizeof(S));
     sl.pad = 0;
     return sl;
 }
@@ -2035,7 +2057,7 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
         const Slots in = slots_of<ST>(g, fin);
         OutSlots out;
         out.base = static_cast<char *>(fout);
-        out.stride = uint32_t(uint64_t(g.nfp) * 2 * sizeof(SS));
+        out.stride = uint32_t(uint64_t(g.lay_ss) * 2 * sizeof(SS));
         out.pad = 0;
         const dim3 grid(unsigned(sweep_blocks(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
@@ -2060,7 +2082,7 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
         const Slots in = slots_of<ST>(g, fin);
         OutSlots out;
         out.base = static_cast<char *>(fout);
-        out.stride = uint32_t(uint64_t(g.nfp) * 2 * sizeof(SS));
+        out.stride = uint32_t(uint64_t(g.lay_ss) * 2 * sizeof(SS));
         out.pad = 0;
         const dim3 grid(static_cast<unsigned>(sweep_blocks_c(g))), block(256);
         const SS *e = static_cast<const SS *>(emit);
@@ -2068,7 +2090,7 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
         if (prod) {
             ProdK<ST> pk{};
             pk.in.base = static_cast<const char *>(prod->fin);
-            pk.in.stride = uint32_t(uint64_t(g.nfp) * sizeof(SS));
+            pk.in.stride = uint32_t(uint64_t(g.lay_ss) * sizeof(SS));
             pk.out.base = static_cast<char *>(prod->fout);
             pk.out.stride = pk.in.stride;
             pk.emit = static_cast<const SS *>(prod->emit);
