@@ -76,6 +76,7 @@ struct lbm_ctx {
     int cur = 0;          // d_pop[cur] holds the post-collision state of the current step
     int64_t step = 0;
     int64_t blocks_sweep = 0, blocks_iface = 0;
+    int64_t part_rows = 0;    // sweep-partial rows reserved in d_part (the larger sweep variant's blocks)
     int ytile = 16;       // rows per y-tile of the sweep traversal
     // node-compact sweep: per-node coordinates and wave launch order;
     // compact = 1 selects it (needs ny, nz <= 1024)
@@ -356,9 +357,9 @@ void drain_slot(lbm_ctx *c, StepEvents &r) {
 // Partial-sum layout in d_part: sweep partials (4 per sweep block), then the
 // interface partials and the fold outputs, two of each alternating with the
 // step's parity (a front launch writes step t's while it reads step t - 1's).
-double *part_iface(const lbm_ctx *c, int64_t t) { return c->d_part + 4 * c->blocks_sweep + (t & 1) * c->blocks_iface; }
+double *part_iface(const lbm_ctx *c, int64_t t) { return c->d_part + 4 * c->part_rows + (t & 1) * c->blocks_iface; }
 double *part_fold(const lbm_ctx *c, int64_t t) {
-    return c->d_part + 4 * c->blocks_sweep + 2 * c->blocks_iface + (t & 1) * int64_t(FOLD_BLOCKS) * NPART;
+    return c->d_part + 4 * c->part_rows + 2 * c->blocks_iface + (t & 1) * int64_t(FOLD_BLOCKS) * NPART;
 }
 double *part_iface_p(const lbm_ctx *c, int64_t t) {
     return c->d_partP + 3 * c->rows_partP + (t & 1) * c->blocks_iface;
@@ -573,8 +574,10 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
         // rounded up to 256 B
         auto r256 = [](int64_t b) { return std::max<int64_t>((b + 255) / 256 * 256, 256); };
         const int64_t chunks = rows * c.W;
-        const int64_t blocks = ((chunks + 3) / 4 + 7) / 8 * 8;
         const bool compact = g->ny <= 1024 && g->nz <= 1024 && c.nfluid > 0;
+        // partial-sum rows: the larger of the chunk sweep's blocks (four
+        // wavefronts each) and the compact sweep's (one wavefront each)
+        const int64_t blocks = std::max(((chunks + 3) / 4 + 7) / 8 * 8, compact ? ((c.nfluid + 63) / 64 + 7) / 8 * 8 : 0);
         const int64_t ns = bc->sputter == LBM_SPUTTER_STOCHASTIC ? NSLOT : 1;
         int64_t bytes = r256((76 * nfp + ns * niface + 1) * sb) + r256(chunks * int64_t(sizeof(ChunkInfo))) +
                         r256(chunks * 4) + 2 * r256(niface * 4) + 2 * r256(niface * 8) + r256(ns * niface * 8) +
@@ -583,8 +586,7 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
         if (compact) bytes += r256(nfp * 4) + 2 * r256((c.nfluid + 63) / 64 * 4);
         if (bc->product) {
             // P buffers and E_P, In_P and Acc_P, P partial sums
-            const int64_t blocks_c = ((c.nfluid + 63) / 64 + 3) / 4;
-            const int64_t rows_p = std::max(blocks, (blocks_c + 7) / 8 * 8);
+            const int64_t rows_p = blocks;  // as for the sweep partials above
             bytes += r256((38 * nfp + niface + 1) * sb) + 2 * r256(niface * 8) +
                      r256((3 * rows_p + 2 * ((niface + 255) / 256)) * 8);
         }
@@ -733,6 +735,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
         }
         const Geometry gtmp = geometry(c);
         c->blocks_sweep = sweep_blocks(gtmp);
+        c->part_rows = std::max(c->blocks_sweep, c->compact_ok ? sweep_blocks_c(gtmp) : int64_t(0));
         c->blocks_iface = interface_blocks(c->niface);
 
         const int sb = storage_bytes(c->ph.storage);
@@ -761,7 +764,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
             c->d_pop[1] = pool + size_t(38) * c->nfp * sb;
             c->d_emit = pool + size_t(76) * c->nfp * sb;
         }
-        const int64_t nparts = 4 * c->blocks_sweep + 2 * c->blocks_iface + 2 * FOLD_BLOCKS * NPART;
+        const int64_t nparts = 4 * c->part_rows + 2 * c->blocks_iface + 2 * FOLD_BLOCKS * NPART;
         c->d_part = static_cast<double *>(dev_alloc(c, size_t(nparts) * 8));
         c->d_tot = static_cast<DevTotals *>(dev_alloc(c, sizeof(DevTotals)));
         bool prod_ok = true;
@@ -1744,7 +1747,7 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
         for (lbm_ctx *c : b->ctx) b->compact = b->compact && c->compact_ok;
         int64_t nb_max = 0, ni = 0;
         for (lbm_ctx *c : b->ctx) {
-            nb_max += c->blocks_sweep;  // the chunk sweep has the most blocks
+            nb_max += c->part_rows;  // the larger sweep variant's block count
             ni += c->blocks_iface;
         }
         if (nb_max >= (int64_t(1) << 31) || ni >= (int64_t(1) << 31)) {

@@ -303,6 +303,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
         for (int k = 0; k < NV; ++k) glb(out)[k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
 }
 
+// The same for a block of one wavefront: lane 0 writes the wavefront's sums.
+template <int NV>
+__device__ __forceinline__ void wave_partials(double (&v)[NV], double *out) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if ((threadIdx.x & 63u) == 0u)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) glb(out)[k] = v[k];
+}
+
 // Where a wavefront sits: which row and chunk, and this lane's node.
 struct WaveUnit {
     int row, chunk, lane, x, y, z;
@@ -628,6 +638,10 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
 // bit of that unit, so no per-node coordinate is read.  Called by every lane
 // of a valid wavefront; returns false, with nothing loaded, when the
 // wavefront spans more units.
+// The node-compact sweep runs one wavefront per block: its lanes share no
+// LDS or barrier with other wavefronts, so a wavefront that finishes early
+// frees its slot without waiting for its neighbours.
+constexpr uint32_t CTHREADS = 64;
 constexpr uint32_t WREC_UNITS = 7;
 // (c_y + 1) and (c_z + 1) of the nine classes, two bits each, class order as CYS / CZS
 constexpr uint32_t CLS_CY1 = (1u << 0) | (2u << 2) | (0u << 4) | (1u << 6) | (1u << 8) | (2u << 10) | (2u << 12) |
@@ -822,7 +836,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             const bool outlet = reservoir && cx == -1 && last_x;
             const bool CAT = !F && C && !inlet && !outlet;
             const uint32_t irank = cx == 0 ? i0 : (cx == 1 ? im : ip);
-            kidx[(i - 1) * 256 + threadIdx.x] = CAT ? irank : 0u;
+            kidx[(i - 1) * CTHREADS + threadIdx.x] = CAT ? irank : 0u;
             cat_bits |= CAT ? (1u << i) : 0u;
         }
     }
@@ -860,8 +874,8 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             opaque(c_b);
             pc[i] = ld_pop<ST>(base(pair_slot(i)), c_b);
             uint32_t v_b = bounce ? 0u
-                                  : (stoch ? uint32_t(i - 1) * g.niface + kidx[(i - 1) * 256 + threadIdx.x]
-                                           : kidx[(i - 1) * 256 + threadIdx.x]) * SB;
+                                  : (stoch ? uint32_t(i - 1) * g.niface + kidx[(i - 1) * CTHREADS + threadIdx.x]
+                                           : kidx[(i - 1) * CTHREADS + threadIdx.x]) * SB;
             opaque(v_b);
             re[i] = ld_at(emit, v_b);
             ro[i] = S(0);
@@ -878,7 +892,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
                 uint32_t p_b = F ? rke * SB + halfp : bbp_b;
                 opaque(p_b);
                 pp[i] = ld_at(pbase, p_b);
-                uint32_t e_b = bounce ? 0u : kidx[(i - 1) * 256 + threadIdx.x] * SB;
+                uint32_t e_b = bounce ? 0u : kidx[(i - 1) * CTHREADS + threadIdx.x] * SB;
                 opaque(e_b);
                 pe[i] = ld_at(pk.emit, e_b);
                 po[i] = S(0);
@@ -1029,7 +1043,7 @@ struct InOut {
 // their targets, as fixed-point integers; kidx holds each direction's target.
 // hR holds the values as stored (the sweeps write the rounded 16-bit values
 // back before calling), so In(k) counts exactly the mass that left.
-template <int ST>
+template <int ST, uint32_t KS = 256>
 __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const uint32_t *kidx, uint32_t cat_bits,
                                               const PhysK<typename Store<ST>::T> &ph,
                                               const typename Store<ST>::T (&hR)[19],
@@ -1040,7 +1054,7 @@ __device__ __forceinline__ void accumulate_in(unsigned long long *inacc, const u
         if ((cat_bits >> i) & 1u) {
             const int j = opp(i);  // the link direction as seen from the interface node
             const T stored = hR[j];  // the value as stored (the caller passes stored values)
-            (void)__hip_atomic_fetch_add(&glb(inacc)[kidx[(i - 1) * 256 + threadIdx.x]],
+            (void)__hip_atomic_fetch_add(&glb(inacc)[kidx[(i - 1) * KS + threadIdx.x]],
                                          in_term<T>(wgt<T>(j), stored, cref, ph.in_scale), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1109,8 +1123,8 @@ __device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned
                                                      const PhysK<typename Store<ST>::T> &ph,
                                                      const typename Store<ST>::T (&hR)[19]) {
     using T = typename Store<ST>::T;
-    __shared__ QueuedArrival queue[4][ARRIVAL_QUEUE];
-    QueuedArrival *q = queue[threadIdx.x >> 6];
+    __shared__ QueuedArrival queue[ARRIVAL_QUEUE];  // one wavefront per block
+    QueuedArrival *q = queue;
     uint32_t qn = 0;  // the same in every lane of the wavefront
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
@@ -1122,7 +1136,7 @@ __device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned
             const T stored = hR[j];  // as stored
             QueuedArrival a;
             a.term = in_term<T>(wgt<T>(j), stored, ph.cref, ph.in_scale) - MAGIC_BITS;
-            a.k = kidx[(i - 1) * 256 + threadIdx.x];
+            a.k = kidx[(i - 1) * CTHREADS + threadIdx.x];
             a.code = uint32_t(vcode(j));
             const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32),
                                                              __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
@@ -1269,8 +1283,9 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
     block_sum<4>(acc, part + int64_t(block) * 4);
 }
 
-// One block of the node-compact sweep: wave slot `block * 4 + wave` takes
-// the 64 gas nodes of wave worder[slot] (storage indices 64 w .. 64 w + 63).
+// One block (one wavefront) of the node-compact sweep: wave slot `block`
+// takes the 64 gas nodes of wave worder[slot] (storage indices 64 w .. 64 w +
+// 63).
 template <int ST, int SP>
 __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph,
                                               const Slots &in, const OutSlots &out,
@@ -1279,24 +1294,23 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
     using T = typename Store<ST>::T;
     constexpr bool PROD = (SP & SP_PRODUCT_FLAG) != 0;
     double accp[3] = {0.0, 0.0, 0.0};  // product mass, out through the inlet face, out through the outlet face
-    const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
-    const uint32_t slot = block * 4u + wave;
+    const uint32_t slot = block;
     const bool wvalid = slot < g.nwaves;
     const uint32_t w = glb(g.worder)[wvalid ? slot : 0u];
     const uint32_t idx = w * 64u + (threadIdx.x & 63u);
     const bool active = wvalid && int64_t(idx) < g.nfluid;
-    __shared__ uint32_t kidx[18 * 256];
-    __shared__ WaveRecords wrec_all[4];
+    __shared__ uint32_t kidx[18 * CTHREADS];
+    __shared__ WaveRecords wrec;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     uint32_t wunit = 0, p = 0;
-    const bool coop = wvalid && wave_records(g, w, idx, active, wrec_all[wave], wunit, p);
+    const bool coop = wvalid && wave_records(g, w, idx, active, wrec, wunit, p);
     if (!coop && active) p = glb(g.pos)[idx];
     const int x = int(p & 0xfffu), y = int((p >> 12) & 0x3ffu), z = int(p >> 22);
     if (active) {
         T hC[19], hR[19], hP[19];  // hP: product lattice (unused without it)
         uint32_t cat_bits;
         pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx, pk, hP,
-                       coop ? wrec_all[wave].rec : nullptr, wunit);
+                       coop ? wrec.rec : nullptr, wunit);
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
@@ -1350,7 +1364,8 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
                 st_stream(static_cast<S *>(pk.out.p(dslot(i))), ownp_b, v);
                 if constexpr (Store<ST>::ROUNDS) hP[i] = Store<ST>::cv(v);
             }
-            if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) accumulate_in<ST>(pk.inacc, kidx, cat_bits, ph, hP, T(0));
+            if (__builtin_amdgcn_ballot_w64(cat_bits != 0u))
+                accumulate_in<ST, CTHREADS>(pk.inacc, kidx, cat_bits, ph, hP, T(0));
             if (reservoir && (first_x || last_x)) {
                 const InOut f = product_tally<ST>(pk.in.base, pk.in.stride, node_elem(g, idx), first_x, last_x);
                 accp[1] += f.in;
@@ -1361,7 +1376,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
             if constexpr ((SP & 3) == SP_STOCHASTIC)
                 accumulate_in_random<ST>(g, g.inacc, kidx, cat_bits, ph, hR);
             else
-                accumulate_in<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
+                accumulate_in<ST, CTHREADS>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
         }
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, node_elem(g, idx),
@@ -1371,12 +1386,12 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
             acc[3] += f.out;
         }
     }
-    block_sum<4>(acc, part + int64_t(block) * 4);
-    if constexpr (PROD) block_sum<3>(accp, pk.part + int64_t(block) * 3);
+    wave_partials<4>(acc, part + int64_t(block) * 4);
+    if constexpr (PROD) wave_partials<3>(accp, pk.part + int64_t(block) * 3);
 }
 
 template <int ST, int SP>
-__global__ __launch_bounds__(256, ST == ST_F64 ? 1 : ((SP & SP_PRODUCT_FLAG) ? 3 : 5)) void k_sweep_c(
+__global__ __launch_bounds__(CTHREADS, ST == ST_F64 ? 1 : ((SP & SP_PRODUCT_FLAG) ? 3 : 5)) void k_sweep_c(
     Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
     const typename Store<ST>::S *__restrict__ emit, double *__restrict__ part, ProdK<ST> pk) {
     sweep_block_c<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))), pk);
@@ -1898,7 +1913,7 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const SampleK<ST> *__restri
 }
 
 template <int ST, int SP>
-__global__ __launch_bounds__(256) void k_sweep_batch_c(const SampleK<ST> *__restrict__ smp,
+__global__ __launch_bounds__(CTHREADS, ST == ST_F64 ? 1 : 5) void k_sweep_batch_c(const SampleK<ST> *__restrict__ smp,
                                                         const uint32_t *__restrict__ block_sample, int parity) {
     const uint32_t b = uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x)));
     const SampleK<ST> &d = smp[__builtin_amdgcn_readfirstlane(block_sample[b])];
@@ -2071,7 +2086,7 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
     });
 }
 
-int64_t sweep_blocks_c(const Geometry &g) { return ((int64_t(g.nwaves) + 3) / 4 + 7) / 8 * 8; }
+int64_t sweep_blocks_c(const Geometry &g) { return (int64_t(g.nwaves) + 7) / 8 * 8; }
 
 hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
                           double *part, hipStream_t s, const ProdStep *prod) {
@@ -2084,7 +2099,7 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
         out.base = static_cast<char *>(fout);
         out.stride = uint32_t(uint64_t(g.lay_ss) * 2 * sizeof(SS));
         out.pad = 0;
-        const dim3 grid(static_cast<unsigned>(sweep_blocks_c(g))), block(256);
+        const dim3 grid(static_cast<unsigned>(sweep_blocks_c(g))), block(CTHREADS);
         const SS *e = static_cast<const SS *>(emit);
         const PhysK<T> k = to_kernel<T>(ph);
         if (prod) {
@@ -2275,7 +2290,7 @@ hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool comp
     return dispatch(storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         const SampleK<ST> *rec = static_cast<const SampleK<ST> *>(d_records);
-        const dim3 grid(static_cast<unsigned>(sweep_blocks_total)), block(256);
+        const dim3 grid(static_cast<unsigned>(sweep_blocks_total)), block(compact ? CTHREADS : 256u);
         return dispatch_sp(sweep_code(sputter, species_x), [&](auto sp) {
             constexpr int SP = decltype(sp)::value;
             if (compact)
