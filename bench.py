@@ -91,22 +91,103 @@ def measured_traffic(kernel, workload, storage_name, sweep, ytile):
     return None
 
 
-def cpu_baseline(vox256, w, steps):
-    """Time the FP64 oracle on the 64^3 crop of the same geometry."""
+def cpu_info():
+    """CPU model and core counts of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(vox256, w, steps, multi_steps=100, single_steps=12, runs=3):
+    """The FP64 oracle on the 64^3 crop of the same geometry: one run of
+    `steps` on all threads for the error check, then the median of `runs`
+    timed runs on all threads and on one thread."""
+    import statistics
+
     import oracle
 
     crop = __import__("paper_1607_02874_amd.inputs", fromlist=["crop"]).crop(vox256, 64, 64, 64)
     p, _ = oracle.p_from_da(w.da, w.pore_size)
-    o = oracle.Oracle(crop, tau=w.tau, p=p, p_stick=w.p_stick, c_inlet=w.c_inlet, force=w.force())
+
+    def make():
+        return oracle.Oracle(crop, tau=w.tau, p=p, p_stick=w.p_stick, c_inlet=w.c_inlet, force=w.force())
+
+    all_threads = oracle.threads()
+    o = make()
     t0 = time.perf_counter()
     o.step(steps)
-    dt = time.perf_counter() - t0
+    dt_ref = time.perf_counter() - t0
     ref = o.fields() + (o.conversion_map(),)
     o.close()
-    return crop, ref, {"value": crop.size * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
-                       "kind": "oracle",
-                       "sample": f"64^3 crop of the 256^3 sample (outlet planes 60-63 gas), {steps} steps, FP64 C "
-                                 f"oracle, OpenMP over z-planes, {dt:.1f} s"}
+
+    def timed(threads, n):
+        oracle.set_threads(threads)
+        o = make()
+        o.step(1)
+        t = time.perf_counter()
+        o.step(n)
+        dt = time.perf_counter() - t
+        o.close()
+        return crop.size * n / dt / 1e6
+
+    multi = [timed(all_threads, multi_steps) for _ in range(runs)]
+    single = [timed(1, single_steps) for _ in range(runs)]
+    oracle.set_threads(all_threads)
+    return crop, ref, {"value": round(statistics.median(multi), 3), "unit": "MLUPS", "cores": all_threads,
+                       "kind": "oracle", "single_thread": round(statistics.median(single), 3),
+                       "runs": runs, **cpu_info(),
+                       "sample": f"64^3 crop of the 256^3 sample (outlet planes 60-63 gas), FP64 C oracle, OpenMP "
+                                 f"over z-planes: median of {runs} runs of {multi_steps} steps on {all_threads} "
+                                 f"threads and of {runs} runs of {single_steps} steps on 1 thread; the error "
+                                 f"check's {steps} steps took {dt_ref:.1f} s on {all_threads} threads"}
+
+
+def copy_ceiling(gib=2, reps=5):
+    """HBM copy rate of this GPU with the library's streaming copy (one
+    16-byte element per thread, non-temporal): median of `reps` copies of
+    `gib` GiB, timed with HIP events on the current stream."""
+    import statistics
+
+    import torch
+
+    from paper_1607_02874_amd import lbm
+
+    n = gib << 30
+    a = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    lib = lbm.library()
+
+    def copy():
+        st = lib.lbm_stream_copy(b.data_ptr(), a.data_ptr(), n, stream.cuda_stream)
+        if st != lbm.LBM_OK:
+            raise RuntimeError(f"lbm_stream_copy failed with status {st}")
+
+    copy()
+    copy()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        copy()
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del a, b
+    ms = statistics.median(times)
+    return {"copy_GBps": round(2 * n / (ms * 1e-3) / 1e9, 1), "copy_bytes": 2 * n, "kernel": "k_stream_copy",
+            "method": f"median of {reps} device copies of {gib} GiB"}
 
 
 def crop_errors(crop, ref, w, steps, storage):
@@ -791,6 +872,8 @@ def main():
     sim.close()
     log(f"elapsed {elapsed:.3f} s, totals {tot}")
 
+    ceiling = copy_ceiling()
+    log(f"copy ceiling {ceiling}")
     if args.copy_calib:
         a = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -812,7 +895,8 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(kname, w.name, args.storage,
                                                 "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile),
-                    "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2)}
+                    "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2),
+                    "ceiling": {**ceiling, "frac_of_copy": round(achieved / ceiling["copy_GBps"], 4)}}
     kernels = None
     if kt:
         kernels = {k: round(kt["ms_" + k] / max(kt["n_" + k], 1) * 1e3, 2) for k in ("sweep", "interface", "reduce")}

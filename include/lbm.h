@@ -304,6 +304,14 @@ lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc);
  * cannot be resolved on the device or a launch or copy fails. */
 lbm_status lbm_fields_noalloc(lbm_ctx *c, double *rho, double *u, double *conc);
 
+/* lbm_stream_copy - the HBM streaming reference that the sweep's bandwidth
+ * is reported against (not part of the method): copies `bytes` from src to
+ * dst, both device memory, on `stream` (NULL = the null stream),
+ * asynchronously, one 16-byte element per thread with non-temporal loads and
+ * stores.  bytes and both pointers must be multiples of 16 (LBM_EINVAL);
+ * the buffers must not overlap.  LBM_EDEVICE when the launch fails. */
+lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 /*
  * lbm_conversion_map - per voxel, the reactant converted at that catalytic
  * node so far: p p_S^R sum_t In(k, t), where In(k, t) is everything arriving

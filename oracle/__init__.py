@@ -84,6 +84,7 @@ def lib():
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.orc_guo_source.argtypes = [ctypes.c_double, dp, dp, dp]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_philox4x32_10.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib = L
     return _lib
@@ -145,6 +146,12 @@ def philox4x32_10(ctr, key):
 
 def threads():
     return lib().orc_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops from now on (results are the
+    same for any count)."""
+    lib().orc_set_threads(int(n))
 
 
 class Oracle:

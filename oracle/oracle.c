@@ -838,3 +838,15 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the next parallel regions (for timing single-thread and
+ * all-core runs); results do not depend on it. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -944,6 +944,15 @@ lbm_status lbm_fields_noalloc(lbm_ctx *c, double *rho, double *u, double *conc) 
     return LBM_OK;
 }
 
+lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    if (bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16 != 0)
+        return fail(nullptr, LBM_EINVAL, "bytes and both pointers must be multiples of 16");
+    const hipError_t e = launch_stream_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "stream copy launch");
+    return LBM_OK;
+}
+
 lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
     return fields_impl(c, rho, u, conc, false);
@@ -1539,10 +1548,16 @@ struct lbm_batch {
     int parity = 0;
     bool use_graph = false;
     hipStream_t capture = nullptr;
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};  // two steps starting at buffer parity 0 / 1
+    // captured step loops starting at buffer parity 0 / 1: [0] two steps,
+    // [1] LONG_GRAPH_STEPS steps (both even, so a replay keeps the parity)
+    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     std::string err;
 };
+
+// Steps of the long captured loop: replays of it carry a batch's runs of
+// many steps with one graph launch per 64 steps.
+constexpr int64_t LONG_GRAPH_STEPS = 64;
 
 namespace {
 
@@ -1558,10 +1573,11 @@ lbm_status bfail(lbm_batch *b, lbm_status s, const std::string &msg) {
 
 void batch_release(lbm_batch *b) {
     if (b->stream || !b->ctx.empty()) (void)hipStreamSynchronize(b->stream);
-    for (int k = 0; k < 2; ++k) {
-        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
-        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
-    }
+    for (int l = 0; l < 2; ++l)
+        for (int k = 0; k < 2; ++k) {
+            if (b->exec[l][k]) (void)hipGraphExecDestroy(b->exec[l][k]);
+            if (b->graph[l][k]) (void)hipGraphDestroy(b->graph[l][k]);
+        }
     if (b->capture) (void)hipStreamDestroy(b->capture);
     for (void *p : b->allocations) {
         if (b->dev.free)
@@ -1594,28 +1610,29 @@ lbm_status batch_launch(lbm_batch *b, int parity, hipStream_t s) {
     return LBM_OK;
 }
 
-// Capture two consecutive steps starting at buffer parity `parity` on a
-// private stream; the executable graph is later launched on the batch stream.
-lbm_status batch_capture(lbm_batch *b, int parity) {
+// Capture `steps` (even) consecutive steps starting at buffer parity
+// `parity` on a private stream, as loop `l` (0: two steps, 1: the long
+// loop); the executable graph is later launched on the batch stream.
+lbm_status batch_capture(lbm_batch *b, int l, int parity, int64_t steps) {
     hipError_t e = hipSuccess;
     if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    lbm_status st = batch_launch(b, parity, b->capture);
-    if (st == LBM_OK) st = batch_launch(b, 1 - parity, b->capture);
+    lbm_status st = LBM_OK;
+    for (int64_t k = 0; k < steps && st == LBM_OK; ++k) st = batch_launch(b, int((parity + k) & 1), b->capture);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->capture, &g);
     if (st != LBM_OK) {
         if (g) (void)hipGraphDestroy(g);
         return st;
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[parity], g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[l][parity], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        b->exec[parity] = nullptr;
+        b->exec[l][parity] = nullptr;
         return bfail(b, LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
-    b->graph[parity] = g;
+    b->graph[l][parity] = g;
     return LBM_OK;
 }
 
@@ -1687,12 +1704,13 @@ lbm_status batch_tables(lbm_batch *b) {
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch upload: ") + hipGetErrorString(e));
     // captured graphs hold the old launch shapes
-    for (int k = 0; k < 2; ++k) {
-        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
-        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
-        b->exec[k] = nullptr;
-        b->graph[k] = nullptr;
-    }
+    for (int l = 0; l < 2; ++l)
+        for (int k = 0; k < 2; ++k) {
+            if (b->exec[l][k]) (void)hipGraphExecDestroy(b->exec[l][k]);
+            if (b->graph[l][k]) (void)hipGraphDestroy(b->graph[l][k]);
+            b->exec[l][k] = nullptr;
+            b->graph[l][k] = nullptr;
+        }
     return LBM_OK;
 }
 
@@ -1790,17 +1808,21 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
     int64_t done = 0;
     lbm_status failed = LBM_OK;
     if (b->use_graph) {
-        while (done + 2 <= n) {
-            if (!b->exec[b->parity]) {
-                failed = batch_capture(b, b->parity);
-                if (failed != LBM_OK) break;
+        // the long loop while at least LONG_GRAPH_STEPS remain, then two-step loops
+        for (int l = 1; l >= 0 && failed == LBM_OK; --l) {
+            const int64_t len = l ? LONG_GRAPH_STEPS : 2;
+            while (done + len <= n) {
+                if (!b->exec[l][b->parity]) {
+                    failed = batch_capture(b, l, b->parity, len);
+                    if (failed != LBM_OK) break;
+                }
+                const hipError_t e = hipGraphLaunch(b->exec[l][b->parity], b->stream);
+                if (e != hipSuccess) {
+                    failed = bfail(b, LBM_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+                    break;
+                }
+                done += len;
             }
-            const hipError_t e = hipGraphLaunch(b->exec[b->parity], b->stream);
-            if (e != hipSuccess) {
-                failed = bfail(b, LBM_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
-                break;
-            }
-            done += 2;
         }
     }
     for (; failed == LBM_OK && done < n; ++done) {
@@ -1809,7 +1831,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
         b->parity = 1 - b->parity;
     }
     n = done;  // the steps actually queued
-    // two-step graph replays leave the parity unchanged; the per-sample
+    // graph replays (even step counts) leave the parity unchanged; the per-sample
     // contexts track the same parity and step count
     for (lbm_ctx *c : b->ctx) {
         c->cur = b->parity;

@@ -183,6 +183,8 @@ hipError_t launch_fields_rows(const Geometry &g, const Physics &ph, const void *
 constexpr int64_t FIELDS_SCRATCH_DOUBLES = int64_t(4) << 20;  // 32 MiB
 constexpr int MAX_SCRATCH_DEVICES = 64;
 hipError_t scratch_address(int device, double **out);
+// Streaming device copy of `bytes` (a multiple of 16, 16-byte aligned).
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // A box of voxels: origin and extent, inside the lattice.
 struct Window {
     int32_t x0, y0, z0, wx, wy, wz;

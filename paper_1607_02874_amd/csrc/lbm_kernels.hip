@@ -2353,4 +2353,26 @@ hipError_t scratch_address(int device, double **out) {
     return hipSuccess;
 }
 
+// ------------------------------------------------- HBM copy reference --
+// The streaming copy the sweep's bandwidth is compared with: one 16-byte
+// element per thread, non-temporal load and store (on MI355X the fastest of
+// the copy forms tried: more elements per thread, or cached accesses, run
+// slower).  Not part of the method.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                      uint64_t n) {
+    const uint64_t i = uint64_t(blockIdx.x) * 256u + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    const uint64_t n = bytes / 16u;
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255u) / 256u;
+    if (blocks > 0xffffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stream_copy, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<const u32x4 *>(src),
+                       static_cast<u32x4 *>(dst), n);
+    return hipGetLastError();
+}
+
 }  // namespace lbmk

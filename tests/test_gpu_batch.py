@@ -111,6 +111,56 @@ def test_batch_graph_replays_match_eager():
                 assert np.array_equal(graphed.conversion_map(i), eager.conversion_map(i)), (rep, i)
 
 
+def test_batch_long_graph_replays_match_eager():
+    """Runs of 64 steps and more replay the captured 64-step loop (then pairs
+    and one eager step for the rest); after every replay, with eager work and
+    synchronisations in between, the graphed batch equals eager stepping."""
+    samples = mixed_samples()[:3]
+    with lbm.Batch(samples) as eager, lbm.Batch(samples, graph=True) as graphed:
+        for rep, n in enumerate((64, 64 + 2 + 1, 128, 64)):
+            print(f"long graph replay {rep} ({n} steps)", flush=True)
+            graphed.step(n)
+            eager.step(n)
+            graphed.synchronize()
+            eager.synchronize()
+            for i in range(len(samples)):
+                assert graphed.totals(i) == eager.totals(i), (rep, i)
+                ge, ee = graphed.fields(i), eager.fields(i)
+                assert all(np.array_equal(a, b) for a, b in zip(ge, ee)), (rep, i)
+                assert np.array_equal(graphed.conversion_map(i), eager.conversion_map(i)), (rep, i)
+
+
+def test_batch64_smallest_samples_match_oracle():
+    """The 64-sample batch workload (sides U{48..128}, porosity U[0.5, 0.75],
+    tau U[0.55, 1.2], Da log-uniform in [0.01, 100]) stepped as one batch for
+    its 1000 steps (graph replays); the 8 smallest samples, at full size,
+    against the FP64 oracle within the FP32 target 1e-5."""
+    from parity import run_oracle as _run_oracle
+
+    ws = inputs.batch_samples(64, 2000)
+    samples = [dict(vox=w.voxels(), da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
+                    c_inlet=w.c_inlet) for w in ws]
+    steps = ws[0].steps
+    assert steps == 1000
+    smallest = sorted(range(len(ws)), key=lambda i: (ws[i].nx, i))[:8]
+    print("batch64: stepping", steps, "steps; checking samples", smallest, flush=True)
+    with lbm.Batch(samples, graph=True) as b:
+        b.step(steps)
+        b.synchronize()
+        got = {i: (b.fields(i), b.conversion_map(i)) for i in smallest}
+    for i in smallest:
+        smp = samples[i]
+        c = case(smp["vox"], steps, da=smp["da"], tau=smp["tau"], pore_size=smp["pore_size"],
+                 p_stick=smp["p_stick"], force=smp["force"])
+        ref = _run_oracle(c)
+        (rho, u, conc), conv = got[i]
+        e = errors(dict(rho=rho, u=u, conc=conc, conv=conv), ref, c["vox"])
+        print(f"batch sample {i} side {ws[i].nx} tau {ws[i].tau[0]:.3f} Da {ws[i].da:.3g} vs oracle",
+              {k: f"{v:.2e}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+        for k in ("rho", "u", "conc", "conv"):
+            assert e[k] < 1e-5, (i, k, e[k])
+
+
 def test_batch_sample_matches_oracle():
     samples = mixed_samples()
     smp = samples[0]
