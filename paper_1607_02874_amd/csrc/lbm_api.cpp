@@ -175,6 +175,8 @@ Geometry geometry(const lbm_ctx *c) {
     g.wunits = c->d_wunits;
     g.nwaves = uint32_t(c->nwaves);
     g.pad2 = 0;
+    g.inv_W = 1.0 / double(c->W);
+    g.inv_ny = 1.0 / double(c->ny);
     g.ivox = c->d_iface_vox;
     g.imask = c->d_iface_mask;
     return g;

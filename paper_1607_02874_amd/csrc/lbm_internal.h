@@ -95,6 +95,10 @@ struct Geometry {
     // lay_bs = 64 (element n of slot s at s nfp + n).
     uint32_t lay_ss, lay_bs;
     int32_t pad2;
+    // 1 / W and 1 / ny: the compact sweep splits unit indices u = row W +
+    // chunk and rows = z ny + y as trunc((n + 1/2) / d) in FP64, exact for
+    // n < 2^26 and d <= 2^12.
+    double inv_W, inv_ny;
     // interface list (voxel index and active-link mask per interface node),
     // read by the STOCHASTIC sweeps to key and resolve each draw
     const uint32_t *ivox, *imask;

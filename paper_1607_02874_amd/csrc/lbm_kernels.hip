@@ -626,23 +626,24 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
 
 // The 64 consecutive gas nodes of a compact wavefront lie in a few
 // consecutive (row, chunk) units of the lattice (at 256^3, porosity 0.61: at
-// most 3 for 93 % of the wavefronts, at most 7 for all but 1 in 40,000), and
+// most 3 for 93 % of the wavefronts, at most 4 for 99.7 %), and
 // the nine source-row records a lane needs are those of its unit shifted by
 // the nine (c_y, c_z) classes.  When the wavefront spans at most WREC_UNITS
 // units (host table g.wunits: first unit u0 and count nu), its lanes load all
-// 9 x nu records once (one record per lane, two vector loads in all) into the
-// wavefront's LDS slice, and each lane reads its nine from there instead of
-// issuing nine loads of its own.  The records of the wavefront's own units
-// (class 0) also give each lane its coordinates: lane `rank` lies in the last
-// unit whose first gas node is at or before it, at the (rank - base)-th gas
-// bit of that unit, so no per-node coordinate is read.  Called by every lane
-// of a valid wavefront; returns false, with nothing loaded, when the
-// wavefront spans more units.
+// 9 x nu records once (one record per lane) and store each in the wavefront's
+// LDS slice in a form that leaves each lane little work of its own (XRec
+// below).  The records of the wavefront's own units (class 0) also give each
+// lane its coordinates: lane `rank` lies in the last unit whose first gas
+// node is at or before it, at the (rank - base)-th gas bit of that unit, so
+// no per-node coordinate is read.  Called by every lane of a valid wavefront;
+// returns false, with nothing loaded, when the wavefront spans more units.
 // The node-compact sweep runs one wavefront per block: its lanes share no
 // LDS or barrier with other wavefronts, so a wavefront that finishes early
 // frees its slot without waiting for its neighbours.
+// WREC_UNITS = 4 keeps the LDS of a block (records and kidx) within 1/24 of
+// a CU's, so six wavefronts per SIMD fit.
 constexpr uint32_t CTHREADS = 64;
-constexpr uint32_t WREC_UNITS = 7;
+constexpr uint32_t WREC_UNITS = 4;
 // (c_y + 1) and (c_z + 1) of the nine classes, two bits each, class order as CYS / CZS
 constexpr uint32_t CLS_CY1 = (1u << 0) | (2u << 2) | (0u << 4) | (1u << 6) | (1u << 8) | (2u << 10) | (2u << 12) |
                              (0u << 14) | (0u << 16);
@@ -669,10 +670,53 @@ __device__ __forceinline__ uint32_t kth_set_bit(uint64_t m, uint32_t k) {
     return pos;
 }
 
+// One source-row record as the lanes read it.  E is the 66-bit window string
+// of a chunk: E[0] the voxel left of the chunk (periodic), E[1 + b] voxel b
+// of the chunk, and E[p] with p = min(64, nx - 64 chunk) + 1 the voxel right
+// of its last voxel (periodic), held in three words; the gas (f) and
+// interface (c) strings are kept apart.  A lane at chunk offset xl finds
+// its three bits (x - 1, x, x + 1) at E[xl .. xl + 2], one funnel shift of
+// words xl / 32 and xl / 32 + 1.  q[k] = base - E[0] + (set bits of E below
+// bit 32 k), so the rank of x (the storage index of x if gas, of the next
+// gas voxel otherwise) is q[k] + (set bits of word k below bit (xl + 1) %
+// 32), k = (xl + 1) / 32: storage indices (and interface indices) run in (z,
+// y, x) order, so within a row the gas neighbours of x are rank - 1 and rank
+// + 1.  Only the periodic wrap of x needs the stored neighbours: pv (x = 0:
+// the index of voxel nx - 1) and nv (x = nx - 1: the index of voxel 0).
+// Words interleave as (E_f[k], q_f[k]) pairs so that both reads of a lane
+// come as two-word LDS reads from one address.
+struct XRec {
+    uint32_t f[6];  // E_f[0], q_f[0], E_f[1], q_f[1], E_f[2], q_f[2]
+    uint32_t c[6];  // the same for the interface string
+    uint32_t pv, nv;  // storage / interface index of the periodic neighbours (NB_IDX bits)
+};
+
 struct WaveRecords {
-    ChunkInfo rec[9 * WREC_UNITS];
+    XRec rec[WREC_UNITS * 9];  // unit-major: rec[j * 9 + cls]
+    uint64_t ufm[WREC_UNITS];  // gas mask of the wavefront's own unit j (class 0)
+    uint32_t ubase[WREC_UNITS];
     uint32_t upos[WREC_UNITS];  // x of the unit's first voxel | y << 12 | z << 22
 };
+
+// trunc((n + 1/2) * inv): n / d for n < 2^26, d <= 2^12, inv = 1 / d in FP64
+__device__ __forceinline__ uint32_t div_recip(uint32_t n, double inv) {
+    return uint32_t(__builtin_fma(double(n), inv, 0.5 * inv));
+}
+
+// E string words and rank offsets of one mask (see XRec).
+__device__ __forceinline__ void window_words(uint64_t m, uint32_t left, uint32_t right, uint32_t p, uint32_t base,
+                                             uint32_t (&w)[6]) {
+    uint64_t lo = (m << 1) | uint64_t(left);
+    uint32_t hi = uint32_t(m >> 63);
+    lo |= p < 64u ? uint64_t(right) << p : 0u;
+    hi |= p >= 64u ? right << (p - 64u) : 0u;
+    w[0] = uint32_t(lo);
+    w[2] = uint32_t(lo >> 32);
+    w[4] = hi;
+    w[1] = base - left;
+    w[3] = w[1] + uint32_t(__popc(w[0]));
+    w[5] = w[3] + uint32_t(__popc(w[2]));
+}
 
 __device__ __forceinline__ bool wave_records(const Geometry &g, uint32_t w, uint32_t rank, bool active,
                                              WaveRecords &wr, uint32_t &wunit, uint32_t &pos) {
@@ -680,12 +724,12 @@ __device__ __forceinline__ bool wave_records(const Geometry &g, uint32_t w, uint
     const uint32_t u0 = wu & ((1u << 26) - 1u), nu = wu >> 26;
     if (nu > WREC_UNITS) return false;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t W = uint32_t(g.W), ny = uint32_t(g.ny), nz = uint32_t(g.nz);
+    const uint32_t ny = uint32_t(g.ny), nz = uint32_t(g.nz);
     if (lane < 9u * nu) {
-        const uint32_t cls = lane / nu, j = lane - cls * nu;
+        const uint32_t j = lane / 9u, cls = lane - 9u * j;
         const uint32_t u = u0 + j;
-        const uint32_t row = u / W, chunk = u - row * W;
-        const uint32_t zr = row / ny, yr = row - zr * ny;
+        const uint32_t row = div_recip(u, g.inv_W), chunk = u - row * uint32_t(g.W);
+        const uint32_t zr = div_recip(row, g.inv_ny), yr = row - zr * ny;
         // source row of the class: (y - c_y, z - c_z), periodic
         const uint32_t cy1 = (CLS_CY1 >> (2u * cls)) & 3u, cz1 = (CLS_CZ1 >> (2u * cls)) & 3u;
         uint32_t ys = yr + ny + 1u - cy1, zs = zr + nz + 1u - cz1;
@@ -693,15 +737,26 @@ __device__ __forceinline__ bool wave_records(const Geometry &g, uint32_t w, uint
         ys = ys >= ny ? ys - ny : ys;
         zs = zs >= nz ? zs - nz : zs;
         zs = zs >= nz ? zs - nz : zs;
-        const LBM_GLOBAL ChunkInfo &src = glb(g.chunks)[(zs * ny + ys) * W + chunk];
-        ChunkInfo &dst = wr.rec[cls * WREC_UNITS + j];
-        dst.fluid = src.fluid;
-        dst.cat = src.cat;
-        dst.base = src.base;
-        dst.ibase = src.ibase;
-        dst.prev = src.prev;
-        dst.next = src.next;
-        if (cls == 0u) wr.upos[j] = (chunk << 6) | (yr << 12) | (zr << 22);
+        const LBM_GLOBAL ChunkInfo &src = glb(g.chunks)[(zs * ny + ys) * uint32_t(g.W) + chunk];
+        const uint64_t fm = src.fluid, cm = src.cat;
+        const uint32_t pv = src.prev, nv = src.next, base = src.base;
+        const uint32_t p = min(64u, uint32_t(g.nx) - 64u * chunk) + 1u;
+        XRec &dst = wr.rec[lane];
+        uint32_t wf[6], wc[6];
+        window_words(fm, pv >> 31, nv >> 31, p, base, wf);
+        window_words(cm, (pv >> 30) & 1u, (nv >> 30) & 1u, p, src.ibase, wc);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            dst.f[k] = wf[k];
+            dst.c[k] = wc[k];
+        }
+        dst.pv = pv & NB_IDX;
+        dst.nv = nv & NB_IDX;
+        if (cls == 0u) {
+            wr.ufm[j] = fm;
+            wr.ubase[j] = base;
+            wr.upos[j] = (chunk << 6) | (yr << 12) | (zr << 22);
+        }
     }
     // the wavefront's LDS writes before its reads
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -710,8 +765,8 @@ __device__ __forceinline__ bool wave_records(const Geometry &g, uint32_t w, uint
 #pragma unroll
     for (uint32_t j = 0; j < WREC_UNITS; ++j) {
         if (j < nu) {
-            const uint64_t f = wr.rec[j].fluid;
-            const uint32_t b = wr.rec[j].base;
+            const uint64_t f = wr.ufm[j];
+            const uint32_t b = wr.ubase[j];
             const bool here = f != 0u && b <= rank;
             jj = here ? j : jj;
             kb = here ? b : kb;
@@ -721,6 +776,49 @@ __device__ __forceinline__ bool wave_records(const Geometry &g, uint32_t w, uint
     wunit = jj;
     pos = active ? wr.upos[jj] + kth_set_bit(fm, rank - kb) : 0u;
     return true;
+}
+
+// What a lane takes from one source row: its three gas and interface bits
+// (x - 1, x, x + 1 in bits 0-2) and the ranks of x in the row's storage and
+// interface numbering, plus the row's periodic neighbour indices.
+struct RowWin {
+    uint32_t wf, wc, r0, i0, pv, nv;
+};
+
+// From the LDS form; rf / rr point at the record's words xl / 32 and
+// (xl + 1) / 32 pairs (f[2 k]), mr masks the bits below (xl + 1) % 32.
+__device__ __forceinline__ RowWin row_window(const uint32_t *rw, const uint32_t *rr, const XRec &R, uint32_t sw,
+                                             uint32_t mr) {
+    RowWin o;
+    o.wf = __builtin_amdgcn_alignbit(rw[2], rw[0], sw) & 7u;
+    o.wc = __builtin_amdgcn_alignbit(rw[8], rw[6], sw) & 7u;
+    o.r0 = rr[1] + uint32_t(__popc(rr[0] & mr));
+    o.i0 = rr[7] + uint32_t(__popc(rr[6] & mr));
+    o.pv = R.pv;
+    o.nv = R.nv;
+    return o;
+}
+
+// From a chunk record in registers (wavefronts that span too many units).
+__device__ __forceinline__ RowWin row_window(const ChunkInfo &R, uint32_t xl, bool ledge, bool redge) {
+    const uint32_t shr = ledge ? 0u : xl - 1u;
+    const uint64_t below = (uint64_t(1) << xl) - 1u;
+    const uint64_t fm = R.fluid, cm = R.cat;
+    const uint32_t pv = R.prev, nv = R.next;
+    uint32_t wf = uint32_t(ledge ? fm << 1 : fm >> shr) & 7u;
+    uint32_t wc = uint32_t(ledge ? cm << 1 : cm >> shr) & 7u;
+    wf |= ledge ? (pv >> 31) : 0u;
+    wc |= ledge ? ((pv >> 30) & 1u) : 0u;
+    wf = redge ? (wf & 3u) | ((nv >> 31) << 2) : wf;
+    wc = redge ? (wc & 3u) | (((nv >> 30) & 1u) << 2) : wc;
+    RowWin o;
+    o.wf = wf;
+    o.wc = wc;
+    o.r0 = R.base + uint32_t(__popcll(fm & below));
+    o.i0 = R.ibase + uint32_t(__popcll(cm & below));
+    o.pv = pv & NB_IDX;
+    o.nv = nv & NB_IDX;
+    return o;
 }
 
 // The same pull for the node-compact sweep: each lane is one gas node at
@@ -748,7 +846,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
                                        const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
                                        int z, typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
                                        uint32_t &cat_out, uint32_t *kidx, const ProdK<ST> &pk,
-                                       typename Store<ST>::T (&hP)[19], const ChunkInfo *wrec, uint32_t wunit) {
+                                       typename Store<ST>::T (&hP)[19], const XRec *wrec, uint32_t wunit) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     using P = typename Store<ST>::P;
@@ -772,17 +870,51 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     const bool ledge = xl == 0u;                       // x - 1 lies in the previous chunk (or wraps)
     const bool redge = xl == 63u || x == g.nx - 1;     // x + 1 lies in the next chunk (or wraps)
     const bool first_x = x == 0, last_x = x == g.nx - 1;
-    const uint32_t shr = ledge ? 0u : xl - 1u;
-    const uint64_t below = (uint64_t(1) << xl) - 1u;
 
-    // phase 1: the nine records, from the wavefront's LDS copy (wrec, see
-    // wave_records) or, where the wavefront spans too many units, each lane's
-    // own loads
-    ChunkInfo rec[9];
-    if (wrec) {
+    // phases 1 and 2: per source-row class, the lane's window bits and ranks
+    // (RowWin), from the wavefront's LDS records (wrec, see wave_records) or,
+    // where the wavefront spans too many units, from nine records of its own,
+    // all requested before any is used.  Then the ranks of x - 1, x, x + 1
+    // (rank - 1 and rank + 1 inside the row, the stored neighbours across the
+    // periodic wrap), the catalytic sources, and their interface indices to
+    // kidx.
+    uint32_t wins = 0;  // three gas bits (x - 1, x, x + 1) per class
+    uint32_t rk[9][3];  // storage index of x - 1, x, x + 1 in each source row (where gas)
+    uint32_t cat_bits = 0;
+    // catalytic sources need a gas-free interface voxel; the reservoir planes
+    // take the place of the wrapped x - 1 at x = 0 and x + 1 at x = nx - 1
+    const uint32_t cat_ok = 7u & ~((reservoir && first_x) ? 1u : 0u) & ~((reservoir && last_x) ? 4u : 0u);
+    auto take = [&](const int cls, const RowWin &W) {
+        const int cy = CYS[cls], cz = CZS[cls];
+        rk[cls][1] = W.r0;
+        rk[cls][0] = first_x ? W.pv : W.r0 - 1u;
+        rk[cls][2] = last_x ? W.nv : W.r0 + ((W.wf >> 1) & 1u);
+        const uint32_t im = first_x ? W.pv : W.i0 - 1u;
+        const uint32_t ip = last_x ? W.nv : W.i0 + ((W.wc >> 1) & 1u);
+        const uint32_t cw = W.wc & ~W.wf & cat_ok;
+        wins |= W.wf << (3 * cls);
 #pragma unroll
-        for (int cls = 0; cls < 9; ++cls) rec[cls] = wrec[cls * WREC_UNITS + wunit];
+        for (int k = 0; k < 18; ++k) {
+            const int i = ORDER[k];
+            if (CY[i] != cy || CZ[i] != cz) continue;
+            const int cx = CX[i];
+            const int bit = 1 - cx;
+            const uint32_t m = uint32_t(int32_t(cw << (31 - bit)) >> 31);  // all ones where catalytic
+            const uint32_t irank = cx == 0 ? W.i0 : (cx == 1 ? im : ip);
+            kidx[(i - 1) * CTHREADS + threadIdx.x] = m & irank;
+            cat_bits |= m & (1u << i);
+        }
+    };
+    if (wrec) {
+        const XRec *R0 = wrec + wunit * 9u;
+        const uint32_t sw = xl & 31u, kw = xl >> 5, kr = (xl + 1u) >> 5;
+        const uint32_t mr = (1u << ((xl + 1u) & 31u)) - 1u;
+        const uint32_t *rw = R0[0].f + 2u * kw, *rr = R0[0].f + 2u * kr;
+        constexpr uint32_t XW = sizeof(XRec) / 4u;
+#pragma unroll
+        for (int cls = 0; cls < 9; ++cls) take(cls, row_window(rw + cls * XW, rr + cls * XW, R0[cls], sw, mr));
     } else {
+        ChunkInfo rec[9];
 #pragma unroll
         for (int cls = 0; cls < 9; ++cls) {
             int ys = y - CYS[cls], zs = z - CZS[cls];
@@ -797,48 +929,9 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             rec[cls].prev = src.prev;
             rec[cls].next = src.next;
         }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-
-    // phase 2: windows, ranks, catalytic links; interface indices to kidx
-    uint32_t wins = 0;  // three gas bits (x - 1, x, x + 1) per class
-    uint32_t rk[9][3];  // storage index of x - 1, x, x + 1 in each source row (where gas)
-    uint32_t cat_bits = 0;
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int cls = 0; cls < 9; ++cls) {
-        const int cy = CYS[cls], cz = CZS[cls];
-        const ChunkInfo &R = rec[cls];
-        const uint64_t fm = R.fluid, cm = R.cat;
-        const uint32_t pv = R.prev, nv = R.next;
-        // bit 0: x - 1, bit 1: x, bit 2: x + 1
-        uint32_t wf = uint32_t(ledge ? fm << 1 : fm >> shr) & 7u;
-        uint32_t wc = uint32_t(ledge ? cm << 1 : cm >> shr) & 7u;
-        wf |= ledge ? (pv >> 31) : 0u;
-        wc |= ledge ? ((pv >> 30) & 1u) : 0u;
-        wf = redge ? (wf & 3u) | ((nv >> 31) << 2) : wf;
-        wc = redge ? (wc & 3u) | (((nv >> 30) & 1u) << 2) : wc;
-        const uint32_t r0 = R.base + uint32_t(__popcll(fm & below));
-        rk[cls][1] = r0;
-        rk[cls][0] = ledge ? (pv & NB_IDX) : r0 - 1u;
-        rk[cls][2] = redge ? (nv & NB_IDX) : r0 + ((wf >> 1) & 1u);
-        const uint32_t i0 = R.ibase + uint32_t(__popcll(cm & below));
-        const uint32_t im = ledge ? (pv & NB_IDX) : i0 - 1u;
-        const uint32_t ip = redge ? (nv & NB_IDX) : i0 + ((wc >> 1) & 1u);
-        wins |= wf << (3 * cls);
-#pragma unroll
-        for (int k = 0; k < 18; ++k) {
-            const int i = ORDER[k];
-            if (CY[i] != cy || CZ[i] != cz) continue;
-            const int cx = CX[i];
-            const uint32_t bit = uint32_t(1 - cx);
-            const bool F = (wf >> bit) & 1u, C = (wc >> bit) & 1u;
-            const bool inlet = reservoir && cx == 1 && first_x;
-            const bool outlet = reservoir && cx == -1 && last_x;
-            const bool CAT = !F && C && !inlet && !outlet;
-            const uint32_t irank = cx == 0 ? i0 : (cx == 1 ? im : ip);
-            kidx[(i - 1) * CTHREADS + threadIdx.x] = CAT ? irank : 0u;
-            cat_bits |= CAT ? (1u << i) : 0u;
-        }
+        for (int cls = 0; cls < 9; ++cls) take(cls, row_window(rec[cls], xl, ledge, redge));
     }
 
     // phase 3: every population and emission load.  One load per direction
@@ -865,12 +958,13 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             const int cx = CX[i];
             const uint32_t bit = uint32_t(1 - cx);
             const bool F = (wf >> bit) & 1u;
+            const uint32_t fmask = uint32_t(int32_t(wf << (31 - bit)) >> 31);  // all ones where the source is gas
             const uint32_t half = dslot(i) < dslot(opp(i)) ? 0u : nfp_b;
             const uint32_t bb_b = own_b + (nfp_b - half);
             const uint32_t rke = node_elem(g, rk[cls][bit]);
             const uint32_t pull_b = rke * PB + half;
-            uint32_t c_b = F ? pull_b : bb_b;
-            solid_bits |= F ? 0u : (1u << i);
+            uint32_t c_b = (pull_b & fmask) | (bb_b & ~fmask);
+            solid_bits |= ~fmask & (1u << i);
             opaque(c_b);
             pc[i] = ld_pop<ST>(base(pair_slot(i)), c_b);
             uint32_t v_b = bounce ? 0u
