@@ -153,6 +153,39 @@ def cpu_baseline(vox256, w, steps, multi_steps=100, single_steps=12, runs=3):
                                  f"check's {steps} steps took {dt_ref:.1f} s on {all_threads} threads"}
 
 
+def cpu_baseline_batch(ws, n_samples=8, steps=20, runs=3):
+    """The FP64 oracle on the n_samples smallest samples of the batch (their
+    own tau, Da and geometry), all threads: median of `runs` runs of `steps`
+    steps over those samples, in MLUPS of the samples' nodes."""
+    import statistics
+
+    import oracle
+
+    small = sorted(ws, key=lambda w: w.nx * w.ny * w.nz)[:n_samples]
+    voxs = [w.voxels() for w in small]
+    nodes = sum(v.size for v in voxs)
+
+    def run():
+        t = 0.0
+        for w, v in zip(small, voxs):
+            p, _ = oracle.p_from_da(w.da, w.pore_size)
+            o = oracle.Oracle(v, tau=w.tau, p=p, p_stick=w.p_stick, c_inlet=w.c_inlet, force=w.force())
+            o.step(1)
+            t0 = time.perf_counter()
+            o.step(steps)
+            t += time.perf_counter() - t0
+            o.close()
+        return nodes * steps / t / 1e6
+
+    vals = [run() for _ in range(runs)]
+    sides = ", ".join(str(w.nx) for w in small)
+    return {"value": round(statistics.median(vals), 3), "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+            "runs": runs, **cpu_info(),
+            "sample": f"the {n_samples} smallest samples of the same 64-sample batch (cubes of side {sides}; "
+                      f"{nodes} nodes), FP64 C oracle, OpenMP over z-planes: median of {runs} runs of {steps} "
+                      f"steps of each"}
+
+
 def copy_ceiling(gib=2, reps=5):
     """HBM copy rate of this GPU with the library's streaming copy (one
     16-byte element per thread, non-temporal): median of `reps` copies of
@@ -253,9 +286,21 @@ def run_batch(args):
     infos = [batch.info(i) for i in range(len(samples))]
     log(f"batched: timing {args.steps} steps")
     t_batch = timed(batch.step, batch.synchronize, args.steps)
+    # the batched sweep's launch duration: captured graphs cannot hold timing
+    # events, so a second pass of eager steps brackets every sweep with HIP
+    # events on the batch stream
+    t_steps = min(args.steps, 200)
+    batch.set_timing(True)
+    batch.step(t_steps)
+    kt = batch.kernel_times()
+    batch.set_timing(False)
+    t_sweep = kt["ms_sweep"] / max(kt["n_sweep"], 1) * 1e-3
     batch.close()
-    sims = [lbm.Sim(s["vox"], da=s["da"], tau=s["tau"], pore_size=s["pore_size"], force=s["force"],
-                    p_stick=s["p_stick"], c_inlet=s["c_inlet"], storage=storage) for s in samples]
+    ceiling = copy_ceiling()
+    log(f"copy ceiling {ceiling}")
+    sims = [] if args.no_sequential else [
+        lbm.Sim(s["vox"], da=s["da"], tau=s["tau"], pore_size=s["pore_size"], force=s["force"],
+                p_stick=s["p_stick"], c_inlet=s["c_inlet"], storage=storage) for s in samples]
     for sim in sims:  # the sequential runs autotune each sample on its own
         if args.no_autotune or args.ytile is not None or args.sweep is not None:
             sim.set_tunable(lbm.TUNE_SWEEP, sweep_variant)
@@ -272,16 +317,26 @@ def run_batch(args):
         for sim in sims:
             sim.synchronize()
 
-    log(f"sequential: timing {args.steps} steps of each sample")
-    t_seq = timed(seq_step, seq_sync, args.steps)
+    t_seq = None
+    if sims:
+        log(f"sequential: timing {args.steps} steps of each sample")
+        t_seq = timed(seq_step, seq_sync, args.steps)
     for sim in sims:
         sim.close()
 
     s_bytes = lbm.STORAGE_BYTES[storage]
     step_bytes = sum(algorithmic_bytes(i, s_bytes)["step"] for i in infos)
+    sweep_bytes = sum(algorithmic_bytes(i, s_bytes)["sweep"] for i in infos)
     ms_step = t_batch / args.steps * 1e3
     mlups = n_nodes * args.steps / t_batch / 1e6
-    achieved = step_bytes / (ms_step * 1e-3) / 1e9
+    achieved = sweep_bytes / t_sweep / 1e9
+    storage_name = {v: k for k, v in STORAGES.items()}[storage]
+    traffic = measured_traffic("k_sweep_batch_c", "batch64", storage_name,
+                               "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile_batch)
+    cpu = None
+    if args.cpu_steps > 0:
+        log("oracle on the 8 smallest samples of the batch")
+        cpu = cpu_baseline_batch(ws)
     line = {
         "metric": "MLUPS (flow+species) and % of HBM roofline at stated error vs FP64 oracle",
         "value": round(mlups, 1),
@@ -299,14 +354,18 @@ def run_batch(args):
                                "length 6, tau U[0.55,1.2], Da logU[0.01,100], seeds 2000+s",
                    "n_nodes": n_nodes, "n_fluid": n_fluid, "graph": not args.no_graph,
                    "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks", "ytile": ytile_batch,
-                   "sequential_mlups": round(n_nodes * args.steps / t_seq / 1e6, 1),
-                   "sequential_ms_per_step": round(t_seq / args.steps * 1e3, 4),
-                   "speedup_vs_sequential": round(t_seq / t_batch, 3),
-                   "step_bytes": step_bytes},
-        "roofline": {"bound": "hbm", "kernel": "whole step (interface + sweep + reductions)",
+                   "sequential_mlups": round(n_nodes * args.steps / t_seq / 1e6, 1) if t_seq else None,
+                   "sequential_ms_per_step": round(t_seq / args.steps * 1e3, 4) if t_seq else None,
+                   "speedup_vs_sequential": round(t_seq / t_batch, 3) if t_seq else None,
+                   "step_bytes": step_bytes, "step_GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1)},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_batch_c",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
-        "cpu_baseline": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": sweep_bytes, "avg_launch_us": round(t_sweep * 1e6, 2),
+                     "timing": f"HIP events around each batched sweep of {kt['n_sweep']} eager steps after "
+                               f"the timed graph replays",
+                     "ceiling": {**ceiling, "frac_of_copy": round(achieved / ceiling["copy_GBps"], 4)}},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -764,6 +823,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300, help="oracle steps on the 64^3 crop (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 4 GiB device copy (counter calibration)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch workload: skip stepping the samples one after another (for profiling runs)")
     ap.add_argument("--ytile", type=int, default=None, help="sweep y-tile height (default: the library's)")
     ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
     ap.add_argument("--sweep", type=int, default=None, choices=(0, 1),

@@ -154,6 +154,22 @@ typedef struct {
                                  w_i; 0 = halfway bounce-back.  Rarefaction (Kn)
                                  enters through tau_gas.  Not with the product
                                  lattice or in batches (LBM_EUNSUPPORTED) */
+    double wall_accommodation;/* sigma_v in [0, 1]; 0: sigma is wall_diffuse.
+                                 > 0: sigma is derived from Kn (wall_diffuse
+                                 must be 0, LBM_EINVAL otherwise) so that
+                                 force-driven flow between two planes
+                                 pore_size nodes apart has Maxwell's
+                                 first-order slip length ((2 - sigma_v) /
+                                 sigma_v) Kn delta (J. C. Maxwell, Phil. Trans.
+                                 R. Soc. 170, 231, 1879; Kn of Eq. (knudsen)):
+                                 the lattice wall's exact slip length is
+                                 sigma (2 tau - 1) / (2 (2 - sigma))
+                                 + (16 tau^2 - 16 tau + 1) / (12 delta).
+                                 Clamped to [0, 1] where no sigma reaches
+                                 Maxwell's slip (bounce-back already slips
+                                 more at large tau); lbm_info reports the
+                                 value and the clamp.  Same restrictions as
+                                 wall_diffuse */
 } lbm_bc;
 
 /* Optional device hooks.  stream: a hipStream_t all work is queued on
@@ -202,6 +218,9 @@ typedef struct {
     int64_t n_interface;           /* catalytic nodes with b(k) >= 1 */
     int64_t n_catalytic_links;     /* sum_k b(k) */
     int64_t device_bytes;          /* device memory held by the context */
+    double wall_sigma;             /* diffuse fraction of the gas wall in use */
+    int32_t wall_clamped;          /* 1 when the Kn relation clamped it to [0, 1] */
+    int32_t reserved_info;
 } lbm_info;
 
 /* Per-kernel device time accumulated while timing is enabled.
@@ -459,6 +478,15 @@ lbm_status lbm_batch_set_tunable(lbm_batch *b, int32_t which, int64_t value);
 lbm_status lbm_batch_get_tunable(const lbm_batch *b, int32_t which, int64_t *value);
 /* lbm_autotune for the batched sweep: one variant and y-tile for the batch. */
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, double *best_ms);
+/* Sweep timing of a batch, for measurement: lbm_batch_set_timing(b, 2)
+ * records HIP events on the batch stream around the batched sweep of every
+ * step (0 stops; 1 is not supported, LBM_EINVAL) and resets the sums.
+ * While it is on, lbm_batch_step launches every step directly (captured
+ * graphs cannot hold the events).  lbm_batch_kernel_times synchronises the
+ * stream and reports ms_sweep / n_sweep of the steps since the reset (the
+ * other fields zero). */
+lbm_status lbm_batch_set_timing(lbm_batch *b, int32_t enable);
+lbm_status lbm_batch_kernel_times(lbm_batch *b, lbm_kernel_times_t *t);
 const char *lbm_batch_last_error(const lbm_batch *b);
 void lbm_batch_destroy(lbm_batch *b);
 

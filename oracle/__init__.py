@@ -76,6 +76,9 @@ def lib():
         L.orc_link_counts.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_d3q19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_d3q19.restype = ctypes.c_int
+        L.orc_wall_sigma_from_kn.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_int)]
+        L.orc_wall_sigma_from_kn.restype = ctypes.c_double
         for name in ("orc_kn_from_tau", "orc_tau_from_kn", "orc_da_from_p"):
             getattr(L, name).argtypes = [ctypes.c_double, ctypes.c_double]
             getattr(L, name).restype = ctypes.c_double
@@ -108,6 +111,14 @@ def kn_from_tau(tau, delta):
 
 def tau_from_kn(kn, delta):
     return lib().orc_tau_from_kn(kn, delta)
+
+
+def wall_sigma_from_kn(kn, delta, accommodation=1.0):
+    """(sigma, clamped): diffuse fraction of the gas wall that gives Maxwell's
+    first-order slip at kn (orc_wall_sigma_from_kn)."""
+    cl = ctypes.c_int(0)
+    s = lib().orc_wall_sigma_from_kn(kn, delta, accommodation, ctypes.byref(cl))
+    return s, bool(cl.value)
 
 
 def p_from_da(da, delta):

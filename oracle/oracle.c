@@ -173,6 +173,51 @@ double orc_tau_from_kn(double kn, double delta)
     return 0.5 + kn * delta / sqrt(1.0 / 3.0);
 }
 
+/* Diffuse fraction sigma of the gas wall that gives Maxwell's first-order
+ * slip at Knudsen number kn (test infrastructure: the relation the library
+ * applies when a tangential accommodation coefficient is given).
+ *
+ * Maxwell's slip law (J. C. Maxwell, Phil. Trans. R. Soc. 170, 231, 1879):
+ * u_s = ((2 - sigma_v) / sigma_v) lambda du/dn at the wall, sigma_v the
+ * tangential momentum accommodation coefficient, lambda = Kn delta the mean
+ * free path of Eq. (knudsen).  The lattice wall (a fraction sigma reflected
+ * diffusely, 1 - sigma bounced back) has its own slip, fixed by tau and
+ * sigma; it is found from the exact steady solution of force-driven flow F in
+ * a plane channel of N = delta gas nodes with that wall (populations depend
+ * on the wall-normal coordinate only; BGK with Guo forcing, halfway walls):
+ *   rho u(y) = M0 - (K / 2) (y - y_c)^2,  K = F / nu,  nu = (tau - 1/2) / 3,
+ *   M0 = K [ (N - 1)^2 / 8 + N (1 + sigma (tau - 1)) / (2 (2 - sigma))
+ *            + (8 tau^2 - 8 tau - 1) / 12 ],
+ * y_c the channel centre and the walls halfway outside the first and last
+ * gas nodes.  Its value at the wall over the wall shear rate K N / 2 (per rho)
+ * is the lattice slip length
+ *   l_s = sigma (2 tau - 1) / (2 (2 - sigma)) + (16 tau^2 - 16 tau + 1) / (12 N),
+ * and setting l_s = ((2 - sigma_v) / sigma_v) Kn N gives s = sigma / (2 - sigma)
+ * in closed form; sigma = 2 s / (1 + s), clamped to [0, 1] (*clamped = 1 when
+ * the lattice wall cannot reach Maxwell's slip: below sigma = 0 the
+ * bounce-back slip of large tau already exceeds it).  tau follows from kn by
+ * Eq. (knudsen). */
+double orc_wall_sigma_from_kn(double kn, double delta, double accommodation, int *clamped)
+{
+    const double tau = orc_tau_from_kn(kn, delta);
+    const double N = delta;
+    const double A = (2.0 - accommodation) / accommodation;
+    const double target = A * kn * N;                                    /* Maxwell slip length */
+    const double bb = (16.0 * tau * tau - 16.0 * tau + 1.0) / (12.0 * N); /* slip length of bounce-back */
+    const double s = (target - bb) * 2.0 / (2.0 * tau - 1.0);            /* sigma / (2 - sigma) */
+    double sigma = 2.0 * s / (1.0 + s);
+    int cl = 0;
+    if (!(s >= 0.0)) {
+        sigma = 0.0;
+        cl = 1;
+    } else if (sigma > 1.0) {
+        sigma = 1.0;
+        cl = 1;
+    }
+    if (clamped) *clamped = cl;
+    return sigma;
+}
+
 /* Damkohler number Da = tau_ch / tau_tr, Eq. (Da_def), with the chemical time
  * tau_ch = dt / p = 1 / p in lattice units and the transport time
  * tau_tr = delta / v, v taken as the lattice sound speed ("Results &

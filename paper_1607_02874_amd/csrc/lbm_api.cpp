@@ -52,6 +52,7 @@ struct lbm_ctx {
     uint32_t lay_ss = 0, lay_bs = 0;  // population layout (Geometry::lay_ss / lay_bs)
     double kn = 0, da = 0, delta = 0, p = 0;
     int p_clamped = 0;
+    int wall_clamped = 0;  // the Kn relation clamped the wall's diffuse fraction
     Physics ph{};
     std::vector<uint8_t> vox;
     std::vector<uint32_t> iface_vox;  // host copy for the conversion map
@@ -464,7 +465,11 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
     if (bc->sputter < 0 || bc->sputter > 3) return fail(nullptr, LBM_EUNSUPPORTED, "unknown sputter mode");
     if (!(bc->wall_diffuse >= 0.0 && bc->wall_diffuse <= 1.0))
         return fail(nullptr, LBM_EINVAL, "wall_diffuse must be in [0, 1]");
-    if (bc->product && bc->wall_diffuse != 0.0)
+    if (!(bc->wall_accommodation >= 0.0 && bc->wall_accommodation <= 1.0))
+        return fail(nullptr, LBM_EINVAL, "wall_accommodation must be in [0, 1]");
+    if (bc->wall_accommodation > 0.0 && bc->wall_diffuse != 0.0)
+        return fail(nullptr, LBM_EINVAL, "give wall_diffuse or wall_accommodation, not both");
+    if (bc->product && (bc->wall_diffuse != 0.0 || bc->wall_accommodation != 0.0))
         return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available with a diffuse wall");
     if (bc->product && bc->sputter == LBM_SPUTTER_STOCHASTIC)
         return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available with STOCHASTIC sputtering");
@@ -508,9 +513,39 @@ namespace {
 struct ParamMap {
     double tau_gas, tau_species, kn, p;
     int clamped;
+    double wall_sigma;  // diffuse fraction of the gas wall in use
+    int wall_clamped;   // 1 when the Kn relation had to clamp it to [0, 1]
 };
 
-lbm_status param_map(const lbm_geometry *g, double kn, double da, const double tau[2], ParamMap *m) {
+// Diffuse fraction of the gas wall for Maxwell's first-order slip (J. C.
+// Maxwell, Phil. Trans. R. Soc. 170, 231, 1879): slip length
+// ((2 - sigma_v) / sigma_v) lambda with lambda = Kn delta (Eq. (knudsen)),
+// sigma_v the tangential momentum accommodation.  The lattice wall (sigma
+// diffuse, 1 - sigma bounced back) has, in force-driven flow between two
+// planes delta nodes apart, the exact slip length
+//   sigma (2 tau - 1) / (2 (2 - sigma)) + (16 tau^2 - 16 tau + 1) / (12 delta)
+// (the second term is halfway bounce-back's, zero at (tau - 1/2)^2 = 3/16),
+// so sigma / (2 - sigma) follows in closed form.  Clamped to [0, 1]: where
+// the bounce-back slip of large tau already exceeds Maxwell's, sigma = 0.
+double wall_sigma_for_slip(double tau, double delta, double accommodation, int *clamped) {
+    const double maxwell = (2.0 - accommodation) / accommodation * (CS * (tau - 0.5) / delta) * delta;
+    const double bounce = (16.0 * tau * tau - 16.0 * tau + 1.0) / (12.0 * delta);
+    const double ratio = 2.0 * (maxwell - bounce) / (2.0 * tau - 1.0);  // sigma / (2 - sigma)
+    *clamped = 0;
+    if (!(ratio >= 0.0)) {
+        *clamped = 1;
+        return 0.0;
+    }
+    const double sigma = 2.0 * ratio / (1.0 + ratio);
+    if (sigma > 1.0) {
+        *clamped = 1;
+        return 1.0;
+    }
+    return sigma;
+}
+
+lbm_status param_map(const lbm_geometry *g, double kn, double da, const double tau[2], const lbm_bc *bc,
+                     ParamMap *m) {
     const double delta = g->pore_size;
     double tau_gas = tau[0];
     if (tau_gas == 0.0) tau_gas = 0.5 + kn * delta / CS;
@@ -524,6 +559,10 @@ lbm_status param_map(const lbm_geometry *g, double kn, double da, const double t
     double p = std::isinf(da) ? 0.0 : CS / (da * delta);
     m->clamped = p > 1.0;
     m->p = m->clamped ? 1.0 : p;
+    m->wall_sigma = bc->wall_diffuse;
+    m->wall_clamped = 0;
+    if (bc->wall_accommodation > 0.0)
+        m->wall_sigma = wall_sigma_for_slip(tau_gas, delta, bc->wall_accommodation, &m->wall_clamped);
     return LBM_OK;
 }
 
@@ -538,7 +577,7 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
     if (st != LBM_OK) return st;
     if (!info) return fail(nullptr, LBM_EINVAL, "info is NULL");
     ParamMap m;
-    st = param_map(g, kn, da, tau, &m);
+    st = param_map(g, kn, da, tau, bc, &m);
     if (st != LBM_OK) return st;
     try {
         lbm_ctx c;
@@ -565,6 +604,8 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
         info->da = da;
         info->pore_size = g->pore_size;
         info->p_clamped = m.clamped;
+        info->wall_sigma = m.wall_sigma;
+        info->wall_clamped = m.wall_clamped;
         info->storage = bc->storage;
         info->n_nodes = c.n;
         info->n_fluid = c.nfluid;
@@ -604,11 +645,13 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     lbm_status st = validate(g, kn, da, tau, bc, out);
     if (st != LBM_OK) return st;
     ParamMap m;
-    st = param_map(g, kn, da, tau, &m);
+    st = param_map(g, kn, da, tau, bc, &m);
     if (st != LBM_OK) return st;
     const double delta = g->pore_size;
     const double tau_gas = m.tau_gas, tau_species = m.tau_species, kn_of_tau = m.kn, p = m.p;
     const int clamped = m.clamped;
+    const double wall_sigma = m.wall_sigma;
+    const int wall_clamped = m.wall_clamped;
 
     int device = 0;
     hipError_t e = hipGetDevice(&device);
@@ -634,6 +677,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->delta = delta;
     c->p = p;
     c->p_clamped = clamped;
+    c->wall_clamped = wall_clamped;
     c->ph.tau_gas = tau_gas;
     c->ph.tau_species = tau_species;
     for (int a = 0; a < 3; ++a) c->ph.force[a] = bc->force[a];
@@ -664,7 +708,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.product = bc->product;
     c->ph.p_stick_product = bc->product ? bc->p_stick_product : 0.0;
     c->ph.seed = bc->seed;
-    c->ph.wall_diffuse = bc->wall_diffuse;
+    c->ph.wall_diffuse = wall_sigma;
     c->ph.rounding = bc->rounding;
     c->ph.step_ctr = 0;  // the initial state is the collision of step 0
 
@@ -1083,6 +1127,8 @@ lbm_status lbm_query(const lbm_ctx *c, lbm_info *info) {
     info->da = c->da;
     info->pore_size = c->delta;
     info->p_clamped = c->p_clamped;
+    info->wall_sigma = c->ph.wall_diffuse;
+    info->wall_clamped = c->wall_clamped;
     info->storage = c->ph.storage;
     info->n_nodes = c->n;
     info->n_fluid = c->nfluid;
@@ -1554,6 +1600,14 @@ struct lbm_batch {
     // [1] LONG_GRAPH_STEPS steps (both even, so a replay keeps the parity)
     hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // sweep timing (lbm_batch_set_timing): one start/stop event pair per
+    // eager step in a ring, drained into ms_sweep / n_sweep
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ring;
+    std::vector<bool> ring_pending;
+    int ring_next = 0;
+    double ms_sweep = 0.0;
+    int64_t n_sweep = 0;
     std::string err;
 };
 
@@ -1575,6 +1629,12 @@ lbm_status bfail(lbm_batch *b, lbm_status s, const std::string &msg) {
 
 void batch_release(lbm_batch *b) {
     if (b->stream || !b->ctx.empty()) (void)hipStreamSynchronize(b->stream);
+    for (auto &ev : b->ring) {
+        if (ev.first) (void)hipEventDestroy(ev.first);
+        if (ev.second) (void)hipEventDestroy(ev.second);
+    }
+    b->ring.clear();
+    b->ring_pending.clear();
     for (int l = 0; l < 2; ++l)
         for (int k = 0; k < 2; ++k) {
             if (b->exec[l][k]) (void)hipGraphExecDestroy(b->exec[l][k]);
@@ -1603,10 +1663,30 @@ void *batch_alloc(lbm_batch *b, size_t bytes) {
     return p;
 }
 
-lbm_status batch_launch(lbm_batch *b, int parity, hipStream_t s) {
+void batch_drain(lbm_batch *b, size_t k) {
+    if (!b->ring_pending[k]) return;
+    float ms = 0.0f;
+    (void)hipEventSynchronize(b->ring[k].second);
+    if (hipEventElapsedTime(&ms, b->ring[k].first, b->ring[k].second) == hipSuccess) {
+        b->ms_sweep += ms;
+        b->n_sweep += 1;
+    }
+    b->ring_pending[k] = false;
+}
+
+lbm_status batch_launch(lbm_batch *b, int parity, hipStream_t s, bool timed = false) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        const size_t k = size_t(b->ring_next);
+        b->ring_next = (b->ring_next + 1) % int(b->ring.size());
+        batch_drain(b, k);
+        e0 = b->ring[k].first;
+        e1 = b->ring[k].second;
+        b->ring_pending[k] = true;
+    }
     hipError_t e = launch_batch_step(b->storage, b->sputter, b->species_x, b->compact, b->d_records, b->d_sweep_sample,
                                      b->sweep_blocks_total, b->d_iface_sample, b->iface_blocks_total, b->d_reduce,
-                                     int(b->ctx.size()), parity, s);
+                                     int(b->ctx.size()), parity, s, e0, e1);
     if (e != hipSuccess) return bfail(b, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
                                       std::string("batch step launch: ") + hipGetErrorString(e));
     return LBM_OK;
@@ -1729,7 +1809,7 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
             return bfail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available in batches");
         else if (bc[i].sputter == LBM_SPUTTER_STOCHASTIC)
             return bfail(nullptr, LBM_EUNSUPPORTED, "STOCHASTIC sputtering is not available in batches");
-        else if (bc[i].wall_diffuse != 0.0)
+        else if (bc[i].wall_diffuse != 0.0 || bc[i].wall_accommodation != 0.0)
             return bfail(nullptr, LBM_EUNSUPPORTED, "the diffuse wall is not available in batches");
         else if (bc[i].rounding == LBM_ROUND_STOCHASTIC && (bc[i].storage == LBM_STORE_F16 ||
                                                            bc[i].storage == LBM_STORE_BF16))
@@ -1809,7 +1889,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
     }
     int64_t done = 0;
     lbm_status failed = LBM_OK;
-    if (b->use_graph) {
+    if (b->use_graph && !b->timing) {
         // the long loop while at least LONG_GRAPH_STEPS remain, then two-step loops
         for (int l = 1; l >= 0 && failed == LBM_OK; --l) {
             const int64_t len = l ? LONG_GRAPH_STEPS : 2;
@@ -1828,7 +1908,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
         }
     }
     for (; failed == LBM_OK && done < n; ++done) {
-        failed = batch_launch(b, b->parity, b->stream);
+        failed = batch_launch(b, b->parity, b->stream, b->timing);
         if (failed != LBM_OK) break;
         b->parity = 1 - b->parity;
     }
@@ -1850,6 +1930,38 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
         }
     }
     return failed;
+}
+
+lbm_status lbm_batch_set_timing(lbm_batch *b, int32_t enable) {
+    if (!b) return LBM_EINVAL;
+    if (enable != 0 && enable != 2) return bfail(b, LBM_EINVAL, "batch timing must be 0 or 2 (the sweep)");
+    if (enable && b->ring.empty()) {
+        b->ring.assign(TIMING_RING, {nullptr, nullptr});
+        b->ring_pending.assign(TIMING_RING, false);
+        for (auto &ev : b->ring) {
+            hipError_t e = hipEventCreate(&ev.first);
+            if (e == hipSuccess) e = hipEventCreate(&ev.second);
+            if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("event create: ") + hipGetErrorString(e));
+        }
+    }
+    if (enable) {
+        std::fill(b->ring_pending.begin(), b->ring_pending.end(), false);
+        b->ms_sweep = 0.0;
+        b->n_sweep = 0;
+    }
+    b->timing = enable != 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_kernel_times(lbm_batch *b, lbm_kernel_times_t *t) {
+    if (!b || !t) return LBM_EINVAL;
+    const hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("synchronize: ") + hipGetErrorString(e));
+    for (size_t k = 0; k < b->ring.size(); ++k) batch_drain(b, k);
+    *t = lbm_kernel_times_t{};
+    t->ms_sweep = b->ms_sweep;
+    t->n_sweep = b->n_sweep;
+    return LBM_OK;
 }
 
 lbm_status lbm_batch_fields(lbm_batch *b, int32_t i, double *rho, double *u, double *conc) {

@@ -257,6 +257,7 @@ hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool comp
 // buffer `parity` of every sample, writing the other) and reduction.
 hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compact, const void *d_records,
                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, const uint32_t *iface_sample,
-                             int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s);
+                             int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s,
+                             hipEvent_t sweep_start = nullptr, hipEvent_t sweep_stop = nullptr);
 
 }  // namespace lbmk

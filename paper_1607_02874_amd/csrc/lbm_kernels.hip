@@ -2398,7 +2398,8 @@ hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool comp
 
 hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compact, const void *d_records,
                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, const uint32_t *iface_sample,
-                             int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s) {
+                             int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s,
+                             hipEvent_t sweep_start, hipEvent_t sweep_stop) {
     return dispatch(storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         const SampleK<ST> *rec = static_cast<const SampleK<ST> *>(d_records);
@@ -2408,8 +2409,12 @@ hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compa
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        hipError_t e = launch_batch_sweep(storage, sputter, species_x, compact, d_records, sweep_sample,
-                                          sweep_blocks_total, parity, s);
+        hipError_t e = sweep_start ? hipEventRecord(sweep_start, s) : hipSuccess;
+        if (e != hipSuccess) return e;
+        e = launch_batch_sweep(storage, sputter, species_x, compact, d_records, sweep_sample, sweep_blocks_total,
+                               parity, s);
+        if (e != hipSuccess) return e;
+        e = sweep_stop ? hipEventRecord(sweep_stop, s) : hipSuccess;
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_fold_batch, dim3(FOLD_BLOCKS, unsigned(n)), dim3(256), 0, s, d_reduce);
         e = hipGetLastError();

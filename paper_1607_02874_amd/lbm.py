@@ -54,7 +54,7 @@ class lbm_bc(ctypes.Structure):
                 ("rho0", ctypes.c_double), ("c0", ctypes.c_double), ("c_ref", ctypes.c_double),
                 ("force", ctypes.c_double * 3), ("product", ctypes.c_int32), ("rounding", ctypes.c_int32),
                 ("p_stick_product", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("wall_diffuse", ctypes.c_double)]
+                ("wall_diffuse", ctypes.c_double), ("wall_accommodation", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -78,7 +78,8 @@ class lbm_info(ctypes.Structure):
                 ("p", ctypes.c_double), ("da", ctypes.c_double), ("pore_size", ctypes.c_double),
                 ("p_clamped", ctypes.c_int32), ("storage", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
                 ("n_fluid", ctypes.c_int64), ("n_interface", ctypes.c_int64),
-                ("n_catalytic_links", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("n_catalytic_links", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("wall_sigma", ctypes.c_double), ("wall_clamped", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
 
 
 class lbm_kernel_times_t(ctypes.Structure):
@@ -141,6 +142,8 @@ def _load():
         "lbm_batch_query": (st, [ctx, ctypes.c_int32, P(lbm_info)]),
         "lbm_batch_synchronize": (st, [ctx]),
         "lbm_batch_set_graph": (st, [ctx, ctypes.c_int32]),
+        "lbm_batch_set_timing": (st, [ctx, ctypes.c_int32]),
+        "lbm_batch_kernel_times": (st, [ctx, P(lbm_kernel_times_t)]),
         "lbm_batch_set_tunable": (st, [ctx, ctypes.c_int32, ctypes.c_int64]),
         "lbm_batch_get_tunable": (st, [ctx, ctypes.c_int32, P(ctypes.c_int64)]),
         "lbm_batch_last_error": (ctypes.c_char_p, [ctx]),
@@ -221,10 +224,11 @@ def _geometry(vox, pore_size):
 
 def _bc(sputter=SPUTTER_UNIFORM, coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32,
         p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0), product=False,
-        p_stick_product=0.0, seed=0, wall_diffuse=0.0, rounding=ROUND_NEAREST):
+        p_stick_product=0.0, seed=0, wall_diffuse=0.0, rounding=ROUND_NEAREST, wall_accommodation=0.0):
     return lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
                   float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]),
-                  int(bool(product)), int(rounding), float(p_stick_product), int(seed), float(wall_diffuse))
+                  int(bool(product)), int(rounding), float(p_stick_product), int(seed), float(wall_diffuse),
+                  float(wall_accommodation))
 
 
 def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc_kw):
@@ -232,7 +236,7 @@ def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc
     lbm_device struct holder (see use_torch) or None for hipMalloc and the
     null stream; bc_kw are the lbm_bc fields (sputter, coupling, species_x,
     storage, p_stick, c_inlet, rho0, c0, c_ref, force, product,
-    p_stick_product, seed, wall_diffuse, rounding).  Returns the raw
+    p_stick_product, seed, wall_diffuse, rounding, wall_accommodation).  Returns the raw
     context handle."""
     vox, g = _geometry(vox, pore_size)
     bc = _bc(**bc_kw)
@@ -262,7 +266,9 @@ class Sim:
     default method: product=True with p_stick_product (the product lattice;
     product_fields() and the product totals), sputter=SPUTTER_STOCHASTIC with
     seed (random sputtering matrix), wall_diffuse=sigma (diffuse carrier
-    wall), rounding=ROUND_STOCHASTIC (stochastic rounding of 16-bit stores)."""
+    wall) or wall_accommodation=sigma_v (the diffuse fraction derived from Kn
+    for Maxwell's slip; info()["wall_sigma"] reports it),
+    rounding=ROUND_STOCHASTIC (stochastic rounding of 16-bit stores)."""
 
     def __init__(self, vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, use_torch=True, stream=None, **kw):
         self._h = None
@@ -467,6 +473,15 @@ class Batch:
 
     def set_tunable(self, which, value):
         _bcheck(_LIB.lbm_batch_set_tunable(self._h, int(which), int(value)), self._h)
+
+    def set_timing(self, on=True):
+        """Events around every batched sweep (steps then run without graphs)."""
+        _bcheck(_LIB.lbm_batch_set_timing(self._h, 2 if on else 0), self._h)
+
+    def kernel_times(self):
+        t = lbm_kernel_times_t()
+        _bcheck(_LIB.lbm_batch_kernel_times(self._h, ctypes.byref(t)), self._h)
+        return {"ms_sweep": t.ms_sweep, "n_sweep": t.n_sweep}
 
     def autotune(self, reps=5):
         ms = ctypes.c_double()

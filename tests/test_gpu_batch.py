@@ -111,6 +111,31 @@ def test_batch_graph_replays_match_eager():
                 assert np.array_equal(graphed.conversion_map(i), eager.conversion_map(i)), (rep, i)
 
 
+def test_batch_sweep_timing_counts_every_sweep_and_leaves_results_unchanged():
+    """lbm_batch_set_timing(2) brackets each batched sweep with events: the
+    kernel times count every timed step (graphs are bypassed while it is on),
+    the results equal untimed graphed stepping, and disabling it resumes the
+    graph path."""
+    samples = mixed_samples()[:3]
+    with lbm.Batch(samples, graph=True) as timed, lbm.Batch(samples, graph=True) as plain:
+        timed.set_timing(True)
+        timed.step(5)
+        plain.step(5)
+        kt = timed.kernel_times()
+        assert kt["n_sweep"] == 5 and kt["ms_sweep"] > 0.0, kt
+        timed.set_timing(False)
+        timed.step(4)
+        plain.step(4)
+        assert timed.kernel_times()["n_sweep"] == 5  # no events after disabling
+        timed.synchronize()
+        plain.synchronize()
+        for i in range(len(samples)):
+            assert timed.totals(i) == plain.totals(i), i
+            assert all(np.array_equal(a, b) for a, b in zip(timed.fields(i), plain.fields(i))), i
+        with pytest.raises(lbm.LbmError):  # per-launch timing of every kernel is not offered for batches
+            lbm._bcheck(lbm._LIB.lbm_batch_set_timing(timed._h, 1), timed._h)
+
+
 def test_batch_long_graph_replays_match_eager():
     """Runs of 64 steps and more replay the captured 64-step loop (then pairs
     and one eager step for the rest); after every replay, with eager work and

@@ -139,3 +139,50 @@ def test_diffuse_wall_16bit_storage(storage, rounding):
     e = errs(run_gpu(c, storage, 1, rounding), run_oracle(c), c["vox"])
     for k in ("rho", "u", "conc", "conv"):
         assert e[k] < 1e-3, (k, e[k])
+
+
+# ---- the diffuse fraction derived from Kn (lbm_bc.wall_accommodation) ----
+
+@pytest.mark.parametrize("storage,bar", [(F64, 1e-12), (F32, 1e-5)])
+@pytest.mark.parametrize("kn", [0.02, 0.08])
+def test_kn_wall_matches_oracle(kn, storage, bar):
+    """wall_accommodation = 1 on a porous sample: the library derives sigma
+    from Kn (reported in info) and its run equals the oracle run with the
+    oracle's own sigma for that Kn."""
+    vox = inputs.PLAIN_32.voxels()
+    delta = 4.0
+    sigma, _ = oracle.wall_sigma_from_kn(kn, delta, 1.0)
+    tau = oracle.tau_from_kn(kn, delta)
+    c = wcase(vox, 60, tau=(tau, 0.9), pore_size=delta, sigma=sigma)
+    r = run_oracle(c)
+    with lbm.Sim(c["vox"], da=c["da"], kn=kn, tau=(0.0, 0.9), pore_size=delta, p_stick=c["p_stick"],
+                 c_inlet=c["c_inlet"], c0=c["c0"], force=c["force"], species_x=XBC[c["species_x"]],
+                 storage=storage, wall_accommodation=1.0) as s:
+        info = s.info()
+        assert info["wall_sigma"] == pytest.approx(sigma, rel=1e-14) and not info["wall_clamped"]
+        assert info["tau_gas"] == pytest.approx(tau, rel=1e-14)
+        s.step(c["steps"])
+        rho, u, conc = s.fields()
+        g = dict(rho=rho, u=u, conc=conc, conv=s.conversion_map(), totals=s.totals())
+    e = errs(g, r, vox)
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < bar, (k, e[k])
+
+
+def test_kn_wall_channel_has_maxwell_slip_on_gpu():
+    """The forced plane channel of 8 gas rows at Kn = 0.05 on the FP64 build,
+    run to steady state: the slip length of its profile is Maxwell's
+    ((2 - sigma_v) / sigma_v) Kn delta, sigma_v = 1."""
+    N, kn, F = 8, 0.05, 1e-6
+    vox = inputs.channel(N, nx=1, nz=1)
+    with lbm.Sim(vox, da=1.0, kn=kn, tau=(0.0, 0.7), pore_size=float(N), force=(F, 0.0, 0.0), p_stick=0.0,
+                 species_x=lbm.XBC_PERIODIC, storage=F64, wall_accommodation=1.0) as s:
+        nu = (s.info()["tau_gas"] - 0.5) / 3.0
+        s.step(int(60 * N * N / nu) + 200)
+        rho, u, _ = s.fields()
+    m = (rho * u[0])[0, :N, 0]
+    y = np.arange(N, dtype=np.float64)
+    c2, c1, c0 = np.polyfit(y, m, 2)
+    yw = -0.5
+    slip = (c2 * yw * yw + c1 * yw + c0) / (2 * c2 * yw + c1)
+    assert slip == pytest.approx(kn * N, rel=1e-8)
