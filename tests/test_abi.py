@@ -20,9 +20,38 @@ def test_every_declared_function_is_exported():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_geometry) == 32
-    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lbm.lbm_totals_t) == 8 + 6 * 8 + 8 + 4 * 8
     assert ctypes.sizeof(lbm.lbm_device) == 32
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Sizes and field offsets of the binding's structs equal what a C
+    compiler makes of include/lbm.h."""
+    import os
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"lbm_geometry": lbm.lbm_geometry, "lbm_bc": lbm.lbm_bc, "lbm_totals_t": lbm.lbm_totals_t,
+               "lbm_info": lbm.lbm_info, "lbm_kernel_times_t": lbm.lbm_kernel_times_t}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lbm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
 
 
 def _create(vox, **kw):
