@@ -107,6 +107,21 @@ typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2, LBM_STO
  * (LBM_EUNSUPPORTED), whose captured graphs replay the step key. */
 typedef enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 } lbm_rounding;
 
+/*
+ * Velocity set.  D3Q19 (default) runs every option of this header.  D2Q9 is
+ * the paper's own lattice (Appendix "Numerical Method", Fig. A1: weights 4/9,
+ * 1/9, 1/36; a catalytic node has at most 8 active links) on one plane:
+ * geometry nz = 1, FP64 storage and arithmetic, sputter UNIFORM, WEIGHTED or
+ * BOUNCEBACK, either coupling, every species x-boundary, the product
+ * lattice, the diffuse or Kn-derived carrier wall.  On a D2Q9 context
+ * lbm_step, lbm_fields, lbm_conversion_map, lbm_product_fields, lbm_totals,
+ * lbm_query, lbm_active_links, lbm_synchronize and lbm_destroy work as
+ * documented (u_z = 0); the other entry points return LBM_EUNSUPPORTED, and
+ * batches take D3Q19 samples only.  A non-finite total is reported by
+ * lbm_totals (LBM_ENONFINITE).
+ */
+typedef enum { LBM_LATTICE_D3Q19 = 0, LBM_LATTICE_D2Q9 = 1 } lbm_lattice;
+
 typedef struct {
     int32_t nx, ny, nz;       /* lattice size, each >= 1; nx <= 4096 */
     int32_t reserved0;
@@ -170,6 +185,8 @@ typedef struct {
                                  more at large tau); lbm_info reports the
                                  value and the clamp.  Same restrictions as
                                  wall_diffuse */
+    int32_t lattice;          /* lbm_lattice (0 = D3Q19) */
+    int32_t reserved_bc;      /* must be 0 */
 } lbm_bc;
 
 /* Optional device hooks.  stream: a hipStream_t all work is queued on

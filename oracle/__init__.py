@@ -15,6 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_D2Q9 = os.path.join(HERE, "liboracle_d2q9.so")  # the same source built for the paper's D2Q9
 
 UNIFORM, WEIGHTED, BOUNCEBACK, STOCHASTIC = 0, 1, 2, 3
 PASSIVE, BARYCENTRIC = 0, 1
@@ -22,14 +23,16 @@ XPERIODIC, XRESERVOIR, XINFLOW = 0, 1, 2
 
 
 def build(force=True):
-    """Compile oracle.c with gcc (plain C, OpenMP, no FMA contraction)."""
-    if not force and os.path.exists(LIB):
-        return LIB
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-Wall", "-o", tmp, SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    """Compile oracle.c with gcc (plain C, OpenMP, no FMA contraction), once
+    for D3Q19 and once for D2Q9."""
+    for path, extra in ((LIB, []), (LIB_D2Q9, ["-DORC_D2Q9"])):
+        if not force and os.path.exists(path):
+            continue
+        tmp = path + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-Wall", *extra, "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, path)
     return LIB
 
 
@@ -45,15 +48,17 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("wall_diffuse", ctypes.c_double)]
 
 
-_lib = None
+_libs = {}
+LATTICES = {"D3Q19": LIB, "D2Q9": LIB_D2Q9}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = ctypes.CDLL(LIB)
+def lib(lattice="D3Q19"):
+    """The oracle library of one velocity set (D3Q19 default, or D2Q9)."""
+    if lattice not in _libs:
+        path = LATTICES[lattice]
+        if not os.path.exists(path):
+            build(force=False)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_create.restype = ctypes.c_void_p
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -89,19 +94,21 @@ def lib():
         L.orc_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_philox4x32_10.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-        _lib = L
-    return _lib
+        _libs[lattice] = L
+    return _libs[lattice]
 
 
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def d3q19():
-    c = np.zeros((19, 3), dtype=np.int32)
-    w = np.zeros(19)
-    opp = np.zeros(19, dtype=np.int32)
-    lib().orc_d3q19(c.ctypes.data, w.ctypes.data, opp.ctypes.data)
+def d3q19(lattice="D3Q19"):
+    """(c, w, opp) of the oracle's velocity set (D3Q19, or D2Q9 with lattice="D2Q9")."""
+    q = 19 if lattice == "D3Q19" else 9
+    c = np.zeros((q, 3), dtype=np.int32)
+    w = np.zeros(q)
+    opp = np.zeros(q, dtype=np.int32)
+    assert lib(lattice).orc_d3q19(c.ctypes.data, w.ctypes.data, opp.ctypes.data) == q
     return c, w, opp
 
 
@@ -171,10 +178,15 @@ class Oracle:
 
     def __init__(self, vox, tau=(0.8, 0.7), p=0.1, p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0,
                  force=(0.0, 0.0, 0.0), sputter=UNIFORM, coupling=PASSIVE, species_x=XRESERVOIR,
-                 product=False, p_stick_product=0.0, seed=0, wall_diffuse=0.0):
+                 product=False, p_stick_product=0.0, seed=0, wall_diffuse=0.0, lattice="D3Q19"):
         vox = np.ascontiguousarray(vox, dtype=np.uint8)
         assert vox.ndim == 3
         self.nz, self.ny, self.nx = vox.shape
+        if lattice == "D2Q9" and self.nz != 1:
+            raise ValueError("D2Q9 runs on one z-plane (nz = 1)")
+        self.lattice = lattice
+        self.q = 19 if lattice == "D3Q19" else 9
+        self._L = lib(lattice)
         self.n = vox.size
         self.vox = vox
         prm = Params()
@@ -188,14 +200,14 @@ class Oracle:
         prm.seed = int(seed)
         prm.wall_diffuse = float(wall_diffuse)
         self.params = prm
-        h = lib().orc_create(self.nx, self.ny, self.nz, vox.ctypes.data, ctypes.byref(prm))
+        h = self._L.orc_create(self.nx, self.ny, self.nz, vox.ctypes.data, ctypes.byref(prm))
         if not h:
             raise MemoryError("orc_create failed")
         self._h = h
 
     def close(self):
         if self._h:
-            lib().orc_destroy(self._h)
+            self._L.orc_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -205,28 +217,28 @@ class Oracle:
             pass
 
     def step(self, n=1):
-        lib().orc_step(self._h, int(n))
+        self._L.orc_step(self._h, int(n))
 
     @property
     def step_count(self):
-        return lib().orc_step_count(self._h)
+        return self._L.orc_step_count(self._h)
 
     def fields(self):
         shape = (self.nz, self.ny, self.nx)
         rho = np.zeros(self.n)
         u = np.zeros(3 * self.n)
         c = np.zeros(self.n)
-        lib().orc_fields(self._h, rho.ctypes.data, u.ctypes.data, c.ctypes.data)
+        self._L.orc_fields(self._h, rho.ctypes.data, u.ctypes.data, c.ctypes.data)
         return rho.reshape(shape), u.reshape((3,) + shape), c.reshape(shape)
 
     def conversion_map(self):
         out = np.zeros(self.n)
-        lib().orc_conversion_map(self._h, out.ctypes.data)
+        self._L.orc_conversion_map(self._h, out.ctypes.data)
         return out.reshape((self.nz, self.ny, self.nx))
 
     def totals(self):
         t = np.zeros(6)
-        lib().orc_totals(self._h, t.ctypes.data)
+        self._L.orc_totals(self._h, t.ctypes.data)
         keys = ("mass_gas", "mass_species", "converted", "lost", "influx", "outflux")
         return dict(zip(keys, t.tolist()))
 
@@ -236,38 +248,38 @@ class Oracle:
         c = np.zeros(self.n)
         t = np.zeros(4)
         st = np.zeros(self.n)
-        lib().orc_product(self._h, c.ctypes.data, t.ctypes.data, st.ctypes.data)
+        self._L.orc_product(self._h, c.ctypes.data, t.ctypes.data, st.ctypes.data)
         keys = ("mass_product", "lost_product", "product_out_inlet", "product_out_outlet")
         return c.reshape(shape), dict(zip(keys, t.tolist())), st.reshape(shape)
 
     def product_flux(self):
         """Phi_P(x): sum over each cross-section of rho_P u_x."""
         phi = np.zeros(self.nx)
-        lib().orc_product_flux(self._h, phi.ctypes.data)
+        self._L.orc_product_flux(self._h, phi.ctypes.data)
         return phi
 
     def get_state_product(self):
-        fP = np.zeros((self.n, 19))
-        lib().orc_get_state_product(self._h, fP.ctypes.data)
+        fP = np.zeros((self.n, self.q))
+        self._L.orc_get_state_product(self._h, fP.ctypes.data)
         return fP
 
     def set_state_product(self, fP):
         a = np.ascontiguousarray(fP, dtype=np.float64)
-        lib().orc_set_state_product(self._h, a.ctypes.data)
+        self._L.orc_set_state_product(self._h, a.ctypes.data)
 
     def link_counts(self):
         b = np.zeros(self.n, dtype=np.uint8)
-        lib().orc_link_counts(self._h, b.ctypes.data)
+        self._L.orc_link_counts(self._h, b.ctypes.data)
         return b.reshape((self.nz, self.ny, self.nx))
 
     def get_state(self):
-        fC = np.zeros((self.n, 19))
-        fR = np.zeros((self.n, 19))
-        lib().orc_get_state(self._h, fC.ctypes.data, fR.ctypes.data)
+        fC = np.zeros((self.n, self.q))
+        fR = np.zeros((self.n, self.q))
+        self._L.orc_get_state(self._h, fC.ctypes.data, fR.ctypes.data)
         return fC, fR
 
     def set_state(self, fC=None, fR=None):
         a = None if fC is None else np.ascontiguousarray(fC, dtype=np.float64)
         b = None if fR is None else np.ascontiguousarray(fR, dtype=np.float64)
-        lib().orc_set_state(self._h, None if a is None else a.ctypes.data,
+        self._L.orc_set_state(self._h, None if a is None else a.ctypes.data,
                             None if b is None else b.ctypes.data)

@@ -7,7 +7,7 @@
  * shares no code, header or table with that path.
  *
  * Plain, slow and obviously correct on purpose: array-of-structures storage
- * f[node][19], one loop per step of the method, FP64 throughout, a fixed
+ * f[node][Q], one loop per step of the method, FP64 throughout, a fixed
  * summation order (directions ascending, nodes in (z, y, x) order, interface
  * nodes in index order).  The only parallelism is OpenMP over z-planes in the
  * collision and streaming loops, where every node writes only its own entries,
@@ -23,7 +23,10 @@
  *     barycentric velocity sum_a rho_a u_a / sum_a rho_a (moment equations);
  *   - the lattice is D3Q19 (weights 1/3, 1/18, 1/36), the 3-D counterpart of
  *     the paper's D2Q9; it meets the paper's weight constraints
- *     sum w = 1, sum w c = 0, sum w c c = cs^2 I;
+ *     sum w = 1, sum w c = 0, sum w c c = cs^2 I.  The same source built with
+ *     ORC_D2Q9 defined is the paper's own D2Q9 (weights 4/9, 1/9, 1/36) on
+ *     one z-plane: every step below is written for any velocity set, and a
+ *     catalytic node then has at most 8 active links;
  *   - the "sputtering" stick-and-react boundary condition, first line of the
  *     eqnarray (f_R_in / f_P_in): a reactant population arriving at a catalytic
  *     node along an active link is re-emitted into the gas with probability
@@ -97,6 +100,18 @@
 #include <omp.h>
 #endif
 
+#ifdef ORC_D2Q9
+/* D2Q9, the paper's lattice (Appendix "Numerical Method", Fig. A1): rest
+ * (w = 4/9), 4 axis links (w = 1/9), 4 diagonals (w = 1/36), all with c_z = 0;
+ * the lattice is one z-plane (nz = 1). */
+#define Q 9
+static const int CX[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+static const int CY[Q] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+static const int CZ[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+static const double WT[Q] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+#else
 #define Q 19
 
 /* D3Q19: rest, 6 axis links (w = 1/18), 12 face diagonals (w = 1/36). */
@@ -108,6 +123,7 @@ static const double WT[Q] = {1.0 / 3.0,
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 static const int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+#endif
 
 enum { ORC_FLUID = 0, ORC_INERT = 1, ORC_CATALYTIC = 2 };
 enum { ORC_UNIFORM = 0, ORC_WEIGHTED = 1, ORC_BOUNCEBACK = 2, ORC_STOCHASTIC = 3 };
@@ -148,6 +164,8 @@ typedef struct {
 
 /* ---------------------------------------------------------------- tables -- */
 
+/* The velocity set of this build (D3Q19, or D2Q9 when built with
+ * ORC_D2Q9): c[3 i + a], w[i], opp[i]; returns Q. */
 int orc_d3q19(int *c, double *w, int *opp)
 {
     for (int i = 0; i < Q; ++i) {

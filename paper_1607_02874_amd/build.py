@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm2d_kernels.hip", "lbm_api.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of every kernel: the flag removes the

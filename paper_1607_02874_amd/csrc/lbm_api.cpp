@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "lbm2d.h"
 #include "lbm_internal.h"
 
 using namespace lbmk;
@@ -53,6 +54,8 @@ struct lbm_ctx {
     double kn = 0, da = 0, delta = 0, p = 0;
     int p_clamped = 0;
     int wall_clamped = 0;  // the Kn relation clamped the wall's diffuse fraction
+    int lattice = LBM_LATTICE_D3Q19;
+    lbm2d::Dev d2{};       // device state of a D2Q9 context
     Physics ph{};
     std::vector<uint8_t> vox;
     std::vector<uint32_t> iface_vox;  // host copy for the conversion map
@@ -469,7 +472,17 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
         return fail(nullptr, LBM_EINVAL, "wall_accommodation must be in [0, 1]");
     if (bc->wall_accommodation > 0.0 && bc->wall_diffuse != 0.0)
         return fail(nullptr, LBM_EINVAL, "give wall_diffuse or wall_accommodation, not both");
-    if (bc->product && (bc->wall_diffuse != 0.0 || bc->wall_accommodation != 0.0))
+    if (bc->reserved_bc != 0) return fail(nullptr, LBM_EINVAL, "reserved fields must be 0");
+    if (bc->lattice != LBM_LATTICE_D3Q19 && bc->lattice != LBM_LATTICE_D2Q9)
+        return fail(nullptr, LBM_EINVAL, "lattice must be LBM_LATTICE_D3Q19 or LBM_LATTICE_D2Q9");
+    if (bc->lattice == LBM_LATTICE_D2Q9) {
+        if (g->nz != 1) return fail(nullptr, LBM_EINVAL, "D2Q9 runs on one plane (nz = 1)");
+        if (bc->storage != LBM_STORE_F64) return fail(nullptr, LBM_EUNSUPPORTED, "D2Q9 runs in FP64 storage only");
+        if (bc->sputter == LBM_SPUTTER_STOCHASTIC)
+            return fail(nullptr, LBM_EUNSUPPORTED, "STOCHASTIC sputtering is not available on D2Q9");
+        if (bc->product && bc->coupling != LBM_COUPLE_PASSIVE)
+            return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice needs PASSIVE coupling");
+    } else if (bc->product && (bc->wall_diffuse != 0.0 || bc->wall_accommodation != 0.0))
         return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available with a diffuse wall");
     if (bc->product && bc->sputter == LBM_SPUTTER_STOCHASTIC)
         return fail(nullptr, LBM_EUNSUPPORTED, "the product lattice is not available with STOCHASTIC sputtering");
@@ -510,6 +523,178 @@ namespace {
 
 // Parameter maps: Eq. (knudsen) and Eq. (Da_def) with tau_ch = 1/p and
 // tau_tr = delta / cs.
+// ------------------------------------------------------------- D2Q9 path --
+// Active links of the catalytic nodes of a plane (bit j: the source k - c_j
+// is a gas node in the domain; x wraps only for a periodic species
+// boundary), and the counts lbm_info reports.
+struct Plane2D {
+    std::vector<uint16_t> mask;
+    int64_t nfluid = 0, niface = 0, nlinks = 0;
+};
+
+Plane2D plane_links(const uint8_t *vox, int nx, int ny, bool xper) {
+    Plane2D p;
+    p.mask.assign(size_t(nx) * ny, 0);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t k = size_t(y) * nx + x;
+            if (vox[k] == LBM_FLUID) ++p.nfluid;
+            if (vox[k] != LBM_CATALYTIC) continue;
+            uint16_t m = 0;
+            for (int j = 1; j < lbm2d::Q; ++j) {
+                int sx = x - lbm2d::CX[j];
+                const int sy = (y - lbm2d::CY[j] + ny) % ny;
+                if (xper) sx = (sx + nx) % nx;
+                if (sx < 0 || sx >= nx) continue;
+                if (vox[size_t(sy) * nx + sx] == LBM_FLUID) m |= uint16_t(1u << j);
+            }
+            p.mask[k] = m;
+            if (m) {
+                ++p.niface;
+                p.nlinks += __builtin_popcount(m);
+            }
+        }
+    return p;
+}
+
+// Device bytes of a D2Q9 context: voxels, link masks, three arrays of Q
+// populations per lattice (pre- and post-collision, emission), the running
+// In sums, the partial sums and the totals.
+int64_t plane_bytes(int64_t n, bool product) {
+    const int64_t nb = lbm2d::blocks(n);
+    const int64_t lat = product ? 3 : 2;
+    return n + 2 * n + lat * 3 * lbm2d::Q * n * 8 + (lat - 1) * n * 8 + nb * (lbm2d::NPI + lbm2d::NPS) * 8 +
+           lbm2d::NTOT * 8;
+}
+
+lbm_status create_plane(lbm_ctx *c, const lbm_geometry *g) {
+    const int64_t n = c->n;
+    Plane2D pl;
+    try {
+        pl = plane_links(g->voxels, g->nx, g->ny, c->ph.species_x == XB_PERIODIC);
+        c->vox.assign(g->voxels, g->voxels + n);
+    } catch (const std::bad_alloc &) {
+        return fail(c, LBM_ENOMEM, "host allocation failed");
+    }
+    c->nfluid = pl.nfluid;
+    c->niface = pl.niface;
+    c->nlinks = pl.nlinks;
+    lbm2d::Dev &d = c->d2;
+    d.nx = g->nx;
+    d.ny = g->ny;
+    d.n = n;
+    const bool prod = c->ph.product != 0;
+    const size_t pop = size_t(lbm2d::Q) * size_t(n) * 8, nb = size_t(lbm2d::blocks(n));
+    auto dbl = [&](size_t bytes) { return static_cast<double *>(dev_alloc(c, bytes)); };
+    uint8_t *vox = static_cast<uint8_t *>(dev_alloc(c, size_t(n)));
+    uint16_t *mask = static_cast<uint16_t *>(dev_alloc(c, size_t(n) * 2));
+    d.vox = vox;
+    d.mask = mask;
+    d.fC = dbl(pop);
+    d.fR = dbl(pop);
+    d.pC = dbl(pop);
+    d.pR = dbl(pop);
+    d.em = dbl(pop);
+    d.acc = dbl(size_t(n) * 8);
+    if (prod) {
+        d.fP = dbl(pop);
+        d.pP = dbl(pop);
+        d.emP = dbl(pop);
+        d.accP = dbl(size_t(n) * 8);
+    }
+    d.part_i = dbl(nb * lbm2d::NPI * 8);
+    d.part_s = dbl(nb * lbm2d::NPS * 8);
+    d.tot = dbl(lbm2d::NTOT * 8);
+    if (!vox || !mask || !d.fC || !d.fR || !d.pC || !d.pR || !d.em || !d.acc || !d.part_i || !d.part_s || !d.tot ||
+        (prod && (!d.fP || !d.pP || !d.emP || !d.accP)))
+        return fail(c, LBM_ENOMEM, "device allocation failed");
+    lbm2d::Params &P = d.ph;
+    P.tau_gas = c->ph.tau_gas;
+    P.tau_species = c->ph.tau_species;
+    P.p = c->ph.p;
+    P.p_stick = c->ph.p_stick;
+    P.p_stick_product = c->ph.p_stick_product;
+    P.c_inlet = c->ph.c_inlet;
+    P.force[0] = c->ph.force[0];
+    P.force[1] = c->ph.force[1];
+    P.sigma = c->ph.wall_diffuse;
+    P.sputter = c->ph.sputter;
+    P.coupling = c->ph.coupling;
+    P.species_x = c->ph.species_x;
+    P.product = c->ph.product;
+    hipError_t e = hipMemcpyAsync(vox, g->voxels, size_t(n), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(mask, pl.mask.data(), size_t(n) * 2, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d.tot, 0, lbm2d::NTOT * 8, c->stream);
+    if (e == hipSuccess) e = lbm2d::launch_init(d, c->ph.rho0, c->ph.c0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "D2Q9 set-up");
+    return LBM_OK;
+}
+
+lbm_status plane_unsupported(lbm_ctx *c, const char *what) {
+    return fail(c, LBM_EUNSUPPORTED, std::string(what) + " is not available on a D2Q9 context");
+}
+
+lbm_status step_plane(lbm_ctx *c, int64_t n) {
+    for (int64_t k = 0; k < n; ++k) {
+        const hipError_t e = lbm2d::launch_step(c->d2, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "D2Q9 step launch");
+        c->step += 1;
+    }
+    return LBM_OK;
+}
+
+// Moments on the device into scratch buffers, copied to the host arrays
+// (any may be NULL); with phi also rho_P and Phi_P.
+lbm_status fields_plane(lbm_ctx *c, double *rho, double *u, double *conc, double *rhoP, double *phi) {
+    const size_t n = size_t(c->n);
+    double *buf = static_cast<double *>(scratch_alloc(c, (6 * n + size_t(c->nx)) * 8));
+    if (!buf) return fail(c, LBM_ENOMEM, "field scratch allocation failed");
+    double *d_rho = buf, *d_u = buf + n, *d_conc = buf + 4 * n, *d_rp = buf + 5 * n, *d_phi = buf + 6 * n;
+    hipError_t e = lbm2d::launch_fields(c->d2, d_rho, d_u, d_conc, d_rp, phi ? d_phi : nullptr, c->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d_rho, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u, d_u, 3 * n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && conc) e = hipMemcpyAsync(conc, d_conc, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && rhoP) e = hipMemcpyAsync(rhoP, d_rp, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && phi) e = hipMemcpyAsync(phi, d_phi, size_t(c->nx) * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    scratch_free(c, buf);
+    if (e != hipSuccess) return hip_fail(c, e, "D2Q9 fields");
+    return LBM_OK;
+}
+
+// Per node: factor times the running In sum at catalytic nodes, 0 elsewhere.
+lbm_status plane_map(lbm_ctx *c, const double *d_acc, double factor, double *out) {
+    std::vector<double> acc(size_t(c->n));
+    hipError_t e = hipMemcpyAsync(acc.data(), d_acc, acc.size() * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "D2Q9 map copy");
+    for (size_t k = 0; k < acc.size(); ++k) out[k] = c->vox[k] == LBM_CATALYTIC ? factor * acc[k] : 0.0;
+    return LBM_OK;
+}
+
+lbm_status totals_plane(lbm_ctx *c, lbm_totals_t *t) {
+    double v[lbm2d::NTOT];
+    hipError_t e = hipMemcpyAsync(v, c->d2.tot, sizeof(v), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "D2Q9 totals copy");
+    *t = lbm_totals_t{};
+    t->step = c->step;
+    t->mass_gas = v[0];
+    t->mass_species = v[1];
+    t->converted = v[2];
+    t->lost = v[3];
+    t->influx = v[4];
+    t->outflux = v[5];
+    t->mass_product = v[6];
+    t->lost_product = v[7];
+    t->product_out_inlet = v[8];
+    t->product_out_outlet = v[9];
+    t->nonfinite = v[10] != 0.0;
+    if (t->nonfinite) return fail(c, LBM_ENONFINITE, "a global total became non-finite");
+    return LBM_OK;
+}
+
 struct ParamMap {
     double tau_gas, tau_species, kn, p;
     int clamped;
@@ -579,6 +764,30 @@ lbm_status lbm_inspect(const lbm_geometry *g, double kn, double da, const double
     ParamMap m;
     st = param_map(g, kn, da, tau, bc, &m);
     if (st != LBM_OK) return st;
+    if (bc->lattice == LBM_LATTICE_D2Q9) {
+        try {
+            const Plane2D pl = plane_links(g->voxels, g->nx, g->ny, bc->species_x == LBM_XBC_PERIODIC);
+            *info = lbm_info{};
+            info->tau_gas = m.tau_gas;
+            info->tau_species = m.tau_species;
+            info->kn = m.kn;
+            info->p = m.p;
+            info->da = da;
+            info->pore_size = g->pore_size;
+            info->p_clamped = m.clamped;
+            info->wall_sigma = m.wall_sigma;
+            info->wall_clamped = m.wall_clamped;
+            info->storage = bc->storage;
+            info->n_nodes = int64_t(g->nx) * g->ny;
+            info->n_fluid = pl.nfluid;
+            info->n_interface = pl.niface;
+            info->n_catalytic_links = pl.nlinks;
+            info->device_bytes = plane_bytes(info->n_nodes, bc->product != 0);
+        } catch (const std::bad_alloc &) {
+            return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+        }
+        return LBM_OK;
+    }
     try {
         lbm_ctx c;
         c.nx = g->nx;
@@ -711,6 +920,18 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.wall_diffuse = wall_sigma;
     c->ph.rounding = bc->rounding;
     c->ph.step_ctr = 0;  // the initial state is the collision of step 0
+
+    if (bc->lattice == LBM_LATTICE_D2Q9) {
+        c->lattice = LBM_LATTICE_D2Q9;
+        st = create_plane(c, g);
+        if (st != LBM_OK) {
+            g_create_error = c->err;
+            lbm_destroy(c);
+            return st;
+        }
+        *out = c;
+        return LBM_OK;
+    }
 
     try {
         c->vox.assign(g->voxels, g->voxels + c->n);
@@ -890,6 +1111,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
 lbm_status lbm_step(lbm_ctx *c, int64_t n) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
     if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+    if (c->lattice == LBM_LATTICE_D2Q9) return step_plane(c, n);
     lbm_status st = check_pending_flag(c);
     if (st != LBM_OK) return st;
     // the reductions of step s run in the front launches of steps s + 1 and
@@ -918,6 +1140,7 @@ static lbm_status fields_impl(lbm_ctx *c, void *rho, void *u, void *conc, bool f
 
 lbm_status lbm_fields(lbm_ctx *c, double *rho, double *u, double *conc) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (c->lattice == LBM_LATTICE_D2Q9) return fields_plane(c, rho, u, conc, nullptr, nullptr);
     const size_t n = size_t(c->n);
     double *d[3] = {nullptr, nullptr, nullptr};
     double *h[3] = {rho, u, conc};
@@ -950,6 +1173,7 @@ lbm_status lbm_fields(lbm_ctx *c, double *rho, double *u, double *conc) {
 
 lbm_status lbm_fields_noalloc(lbm_ctx *c, double *rho, double *u, double *conc) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_fields_noalloc");
     if (!rho && !u && !conc) return LBM_OK;
     // whole x-rows per pass through the device scratch: rho, three velocity
     // components and conc, 5 nx doubles a row
@@ -1001,11 +1225,13 @@ lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *strea
 
 lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_fields_device");
     return fields_impl(c, rho, u, conc, false);
 }
 
 lbm_status lbm_populations(lbm_ctx *c, const int32_t origin[3], const int32_t extent[3], double *fC, double *fR) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_populations");
     if (!origin || !extent || !fC || !fR) return fail(c, LBM_EINVAL, "NULL argument");
     const int dims[3] = {c->nx, c->ny, c->nz};
     for (int a = 0; a < 3; ++a)
@@ -1041,6 +1267,7 @@ lbm_status lbm_populations(lbm_ctx *c, const int32_t origin[3], const int32_t ex
 
 lbm_status lbm_conversion_map(lbm_ctx *c, double *conv) {
     if (!c || !conv) return fail(c, LBM_EINVAL, "NULL argument");
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_map(c, c->d2.acc, c->ph.p * c->ph.p_stick, conv);
     std::vector<double> acc(size_t(c->niface));
     hipError_t e = hipSuccess;
     if (c->niface) e = hipMemcpyAsync(acc.data(), c->d_acc, acc.size() * 8, hipMemcpyDeviceToHost, c->stream);
@@ -1055,6 +1282,13 @@ lbm_status lbm_conversion_map(lbm_ctx *c, double *conv) {
 lbm_status lbm_product_fields(lbm_ctx *c, double *conc, double *stuck, double *phi) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
     if (!c->ph.product) return fail(c, LBM_EUNSUPPORTED, "this context has no product lattice");
+    if (c->lattice == LBM_LATTICE_D2Q9) {
+        if (stuck) {
+            const lbm_status st = plane_map(c, c->d2.accP, c->ph.p_stick_product, stuck);
+            if (st != LBM_OK) return st;
+        }
+        return conc || phi ? fields_plane(c, nullptr, nullptr, nullptr, conc, phi) : LBM_OK;
+    }
     hipError_t e = hipSuccess;
     if (stuck) {
         std::vector<double> acc(size_t(c->niface));
@@ -1097,6 +1331,7 @@ lbm_status lbm_product_fields(lbm_ctx *c, double *conc, double *stuck, double *p
 
 lbm_status lbm_totals(lbm_ctx *c, lbm_totals_t *t) {
     if (!c || !t) return fail(c, LBM_EINVAL, "NULL argument");
+    if (c->lattice == LBM_LATTICE_D2Q9) return totals_plane(c, t);
     DevTotals d;
     hipError_t e = hipMemcpyAsync(&d, c->d_tot, sizeof(d), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1140,6 +1375,11 @@ lbm_status lbm_query(const lbm_ctx *c, lbm_info *info) {
 
 lbm_status lbm_active_links(const lbm_ctx *c, uint8_t *b) {
     if (!c || !b) return LBM_EINVAL;
+    if (c->lattice == LBM_LATTICE_D2Q9) {
+        const Plane2D pl = plane_links(c->vox.data(), c->nx, c->ny, c->ph.species_x == XB_PERIODIC);
+        for (size_t k = 0; k < pl.mask.size(); ++k) b[k] = uint8_t(__builtin_popcount(pl.mask[k]));
+        return LBM_OK;
+    }
     std::memset(b, 0, size_t(c->n));
     const bool xper = c->ph.species_x == XB_PERIODIC;
     // recount from the voxel map, the same rule the interface list uses
@@ -1172,6 +1412,7 @@ lbm_status lbm_synchronize(lbm_ctx *c) {
 
 lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value) {
     if (!c) return LBM_EINVAL;
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_set_tunable");
     if (which == LBM_TUNE_YTILE) {
         if (value < 1 || value > c->ny) return fail(c, LBM_EINVAL, "ytile must be in [1, ny]");
         if (int(value) == c->ytile) return LBM_OK;
@@ -1208,6 +1449,7 @@ lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value) {
 
 lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value) {
     if (!c || !value) return LBM_EINVAL;
+    if (c->lattice == LBM_LATTICE_D2Q9) return LBM_EUNSUPPORTED;
     if (which == LBM_TUNE_YTILE) {
         *value = c->ytile;
         return LBM_OK;
@@ -1221,6 +1463,7 @@ lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value) {
 
 lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable) {
     if (!c) return LBM_EINVAL;
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_set_timing");
     if (enable < 0 || enable > 2) return fail(c, LBM_EINVAL, "timing must be 0, 1 or 2");
     if (enable && c->ring.empty()) {
         c->ring.resize(TIMING_RING);
@@ -1243,6 +1486,7 @@ lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable) {
 
 lbm_status lbm_kernel_times(lbm_ctx *c, lbm_kernel_times_t *t) {
     if (!c || !t) return LBM_EINVAL;
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_kernel_times");
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "synchronize");
     for (auto &r : c->ring) drain_slot(c, r);
@@ -1297,6 +1541,7 @@ size_t ckpt_product_bytes(const lbm_ctx *c) {
 
 lbm_status lbm_save(lbm_ctx *c, const char *path) {
     if (!c || !path) return fail(c, LBM_EINVAL, "NULL argument");
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_save");
     CkptHeader h{};
     h.magic = CKPT_MAGIC;
     h.nx = c->nx;
@@ -1345,6 +1590,7 @@ lbm_status lbm_save(lbm_ctx *c, const char *path) {
 
 lbm_status lbm_load(lbm_ctx *c, const char *path) {
     if (!c || !path) return fail(c, LBM_EINVAL, "NULL argument");
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_load");
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(c, LBM_EINVAL, std::string("cannot open ") + path);
     CkptHeader h{};
@@ -1516,6 +1762,7 @@ extern "C" {
 
 lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_autotune");
     if (reps < 1 || reps > 1000) return fail(c, LBM_EINVAL, "reps must be in [1, 1000]");
     lbm_status st = check_pending_flag(c);
     if (st != LBM_OK) return st;
@@ -1811,6 +2058,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_geometry *g, const double *kn, 
             return bfail(nullptr, LBM_EUNSUPPORTED, "STOCHASTIC sputtering is not available in batches");
         else if (bc[i].wall_diffuse != 0.0 || bc[i].wall_accommodation != 0.0)
             return bfail(nullptr, LBM_EUNSUPPORTED, "the diffuse wall is not available in batches");
+        else if (bc[i].lattice != LBM_LATTICE_D3Q19)
+            return bfail(nullptr, LBM_EUNSUPPORTED, "batches take D3Q19 samples only");
         else if (bc[i].rounding == LBM_ROUND_STOCHASTIC && (bc[i].storage == LBM_STORE_F16 ||
                                                            bc[i].storage == LBM_STORE_BF16))
             // a captured batch graph replays the launch arguments, and with

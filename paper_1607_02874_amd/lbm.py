@@ -28,6 +28,7 @@ COUPLE_PASSIVE, COUPLE_BARYCENTRIC = 0, 1
 XBC_PERIODIC, XBC_RESERVOIR, XBC_INFLOW = 0, 1, 2
 STORE_F32, STORE_F16, STORE_BF16, STORE_F64 = 0, 1, 2, 3
 ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
+LATTICE_D3Q19, LATTICE_D2Q9 = 0, 1
 TUNE_YTILE, TUNE_SWEEP = 0, 1
 STORAGE_BYTES = {STORE_F32: 4, STORE_F16: 2, STORE_BF16: 2, STORE_F64: 8}
 STORAGE_NAMES = {STORE_F32: "f32", STORE_F16: "f16", STORE_BF16: "bf16", STORE_F64: "f64"}
@@ -54,7 +55,8 @@ class lbm_bc(ctypes.Structure):
                 ("rho0", ctypes.c_double), ("c0", ctypes.c_double), ("c_ref", ctypes.c_double),
                 ("force", ctypes.c_double * 3), ("product", ctypes.c_int32), ("rounding", ctypes.c_int32),
                 ("p_stick_product", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("wall_diffuse", ctypes.c_double), ("wall_accommodation", ctypes.c_double)]
+                ("wall_diffuse", ctypes.c_double), ("wall_accommodation", ctypes.c_double),
+                ("lattice", ctypes.c_int32), ("reserved_bc", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -224,11 +226,12 @@ def _geometry(vox, pore_size):
 
 def _bc(sputter=SPUTTER_UNIFORM, coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32,
         p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0), product=False,
-        p_stick_product=0.0, seed=0, wall_diffuse=0.0, rounding=ROUND_NEAREST, wall_accommodation=0.0):
+        p_stick_product=0.0, seed=0, wall_diffuse=0.0, rounding=ROUND_NEAREST, wall_accommodation=0.0,
+        lattice=LATTICE_D3Q19):
     return lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
                   float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]),
                   int(bool(product)), int(rounding), float(p_stick_product), int(seed), float(wall_diffuse),
-                  float(wall_accommodation))
+                  float(wall_accommodation), int(lattice), 0)
 
 
 def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc_kw):
@@ -236,7 +239,7 @@ def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc
     lbm_device struct holder (see use_torch) or None for hipMalloc and the
     null stream; bc_kw are the lbm_bc fields (sputter, coupling, species_x,
     storage, p_stick, c_inlet, rho0, c0, c_ref, force, product,
-    p_stick_product, seed, wall_diffuse, rounding, wall_accommodation).  Returns the raw
+    p_stick_product, seed, wall_diffuse, rounding, wall_accommodation, lattice).  Returns the raw
     context handle."""
     vox, g = _geometry(vox, pore_size)
     bc = _bc(**bc_kw)
@@ -268,7 +271,8 @@ class Sim:
     seed (random sputtering matrix), wall_diffuse=sigma (diffuse carrier
     wall) or wall_accommodation=sigma_v (the diffuse fraction derived from Kn
     for Maxwell's slip; info()["wall_sigma"] reports it),
-    rounding=ROUND_STOCHASTIC (stochastic rounding of 16-bit stores)."""
+    rounding=ROUND_STOCHASTIC (stochastic rounding of 16-bit stores),
+    lattice=LATTICE_D2Q9 (the paper's D2Q9 on one plane, FP64; see lbm.h)."""
 
     def __init__(self, vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, use_torch=True, stream=None, **kw):
         self._h = None

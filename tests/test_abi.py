@@ -20,7 +20,7 @@ def test_every_declared_function_is_exported():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_geometry) == 32
-    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lbm.lbm_totals_t) == 8 + 6 * 8 + 8 + 4 * 8
     assert ctypes.sizeof(lbm.lbm_device) == 32
 

@@ -11,7 +11,9 @@ in units of the entering concentration over L_y, with Pe = U_max L_y / D
 (wall shear 4 U_max / L_y).  The paper reports a mean absolute error of
 about 4 %.
 
-Here the channel is one z-plane of the 3-D lattice (z periodic): fluid rows
+The channel runs on the paper's own D2Q9 (FP64) and on one z-plane of the
+3-D lattice (z periodic; with p = p_S = 1 nothing is re-emitted, so the two
+evolve the same): fluid rows
 y = 1..50, a catalytic row y = 0 and an inert row y = 51.  The gradient
 follows from the absorbed flux, d[R]/dy = J / D with D = c_s^2 (tau_R - 1/2),
 J the reactant absorbed per wall node and step (the conversion map's growth
@@ -43,9 +45,13 @@ def channel():
     return vox
 
 
-@pytest.mark.parametrize("storage,species_x", [(0, lbm.XBC_RESERVOIR), (3, lbm.XBC_RESERVOIR), (0, lbm.XBC_INFLOW),
-                                               (3, lbm.XBC_INFLOW)])
-def test_leveque_reactive_channel(storage, species_x):
+D3, D2 = lbm.LATTICE_D3Q19, lbm.LATTICE_D2Q9
+
+
+@pytest.mark.parametrize("storage,species_x,lattice", [
+    (0, lbm.XBC_RESERVOIR, D3), (3, lbm.XBC_RESERVOIR, D3), (0, lbm.XBC_INFLOW, D3), (3, lbm.XBC_INFLOW, D3),
+    (3, lbm.XBC_RESERVOIR, D2), (3, lbm.XBC_INFLOW, D2)])
+def test_leveque_reactive_channel(storage, species_x, lattice):
     nu = (TAU_C - 0.5) / 3.0
     # discrete Poiseuille with halfway bounce-back: U_max = F (h^2 / (2 nu) - 1 / (8 nu) + 6 nu), h = L_y / 2
     force = UMAX / (LY**2 / (8.0 * nu) - 1.0 / (8.0 * nu) + 6.0 * nu)
@@ -53,7 +59,7 @@ def test_leveque_reactive_channel(storage, species_x):
     tau_r = 0.5 + 3.0 * diff
     vox = channel()
     with lbm.Sim(vox, da=1e-9, tau=(TAU_C, tau_r), pore_size=1.0, force=(force, 0.0, 0.0), p_stick=1.0,
-                 c_inlet=1.0, storage=storage, species_x=species_x) as s:
+                 c_inlet=1.0, storage=storage, species_x=species_x, lattice=lattice) as s:
         assert s.info()["p"] == 1.0  # instantaneous reaction
         s.step(99000)  # viscous time L_y^2 / nu = 25,000 steps; the boundary layer settles within that
         before = s.conversion_map()
@@ -72,7 +78,7 @@ def test_leveque_reactive_channel(storage, species_x):
     sel = (x > 5) & (x < LX - 10)
     mae = float(np.mean(np.abs(grad[sel] - leveque[sel])) / np.mean(leveque[sel]))
     raw = float(np.mean(np.abs(flux * LY / diff - leveque)[sel]) / np.mean(leveque[sel]))
-    print(f"Leveque channel storage {storage} species_x {species_x}: Pe {pe:.1f}, entering concentration "
+    print(f"Leveque channel lattice {lattice} storage {storage} species_x {species_x}: Pe {pe:.1f}, entering concentration "
           f"{entering:.4f} c_in, MAE {mae:.4f} (against c_in: {raw:.4f})", flush=True)
     if inflow:
         assert 0.95 < entering <= 1.0 + 1e-6, entering
@@ -81,7 +87,7 @@ def test_leveque_reactive_channel(storage, species_x):
     assert mae < 0.06, mae
 
 
-def reactor_eta(w, p, steps=60000, window=20000):
+def reactor_eta(w, p, steps=60000, window=20000, lattice=D3):
     """The paper's 2-D reactor (Table 1; the p and w/h sweep of "Results &
     Discussion") on one z-plane: efficiency of Eq. (eff) as product leaving
     through the outlet over the reactant inlet flow c_in sum_y u_x(0, y),
@@ -91,7 +97,7 @@ def reactor_eta(w, p, steps=60000, window=20000):
     c_in = 0.2
     with lbm.Sim(vox, da=math.sqrt(1.0 / 3.0) / (p * 3.0), tau=(4.0, 4.0), pore_size=3.0, force=(4e-5, 0.0, 0.0),
                  rho0=0.8, c_inlet=c_in, p_stick=0.95, species_x=lbm.XBC_INFLOW, product=True,
-                 p_stick_product=0.0) as s:
+                 p_stick_product=0.0, lattice=lattice, storage=3 if lattice == D2 else 0) as s:
         s.step(steps - window)
         t0, q0 = s.totals(), float(s.fields()[1][0, 0, gas, 0].sum())
         s.step(window)
@@ -100,7 +106,8 @@ def reactor_eta(w, p, steps=60000, window=20000):
     return (t1["product_out_outlet"] - t0["product_out_outlet"]) / (window * c_in * q), q / int(gas.sum())
 
 
-def test_reactor2d_efficiency_trends():
+@pytest.mark.parametrize("lattice", [D3, D2])
+def test_reactor2d_efficiency_trends(lattice):
     """The paper's qualitative findings on its 2-D reactor: the efficiency
     grows with the reaction probability, and the ingot thickness matters
     little next to its perimeter (a five times thicker ingot, five times the
@@ -108,9 +115,9 @@ def test_reactor2d_efficiency_trends():
     w/h -> 0).  The absolute level is not compared: the gas here is periodic
     and force-driven instead of the paper's velocity inlet, and the paper
     gives p_S^R as 0.95 (Table 1) and as about 0.5 (text)."""
-    res = {(w, p): reactor_eta(w, p) for w in (6, 30) for p in (0.35, 0.65)}
+    res = {(w, p): reactor_eta(w, p, lattice=lattice) for w in (6, 30) for p in (0.35, 0.65)}
     for (w, p), (eta, u) in res.items():
-        print(f"w {w} p {p}: eta {eta:.4f}, inlet mean speed {u:.4f}", flush=True)
+        print(f"lattice {lattice} w {w} p {p}: eta {eta:.4f}, inlet mean speed {u:.4f}", flush=True)
         assert 0.05 < u < 0.1  # the paper's inlet speed is 0.08
         assert eta > 0.0
     for w in (6, 30):

@@ -95,3 +95,24 @@ def test_planned_device_bytes_scale_with_storage():
     # the population buffers dominate: 76 arrays of >= n_fluid elements
     assert by[lbm.STORE_F32] - by[lbm.STORE_F16] >= 76 * nf * 2
     assert by[lbm.STORE_F64] - by[lbm.STORE_F32] >= 76 * nf * 4
+
+
+def test_inspect_d2q9_counts_match_the_oracle():
+    """lbm_inspect of a D2Q9 plane (host only): gas nodes, interface nodes and
+    links as the D2Q9 oracle counts them (b(k) <= 8), and the device bytes of
+    the plane's arrays."""
+    import oracle
+
+    vox = inputs.disk_ingot(10, h=60, length=80, width=120, seed=2)
+    for xbc, obc in ((lbm.XBC_INFLOW, oracle.XINFLOW), (lbm.XBC_PERIODIC, oracle.XPERIODIC)):
+        for product in (False, True):
+            info = lbm.inspect(vox, 1.0, tau=(4.0, 4.0), pore_size=3.0, species_x=xbc, storage=3, product=product,
+                               lattice=lbm.LATTICE_D2Q9)
+            b = oracle.Oracle(vox, species_x=obc, lattice="D2Q9").link_counts()
+            assert info["n_nodes"] == vox.size
+            assert info["n_fluid"] == int((vox == inputs.FLUID).sum())
+            assert info["n_interface"] == int((b > 0).sum())
+            assert info["n_catalytic_links"] == int(b.sum(dtype=np.int64))
+            assert b.max() <= 8
+            lat = 3 if product else 2
+            assert info["device_bytes"] >= lat * 3 * 9 * vox.size * 8
