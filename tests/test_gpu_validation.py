@@ -84,7 +84,9 @@ def test_leveque_reactive_channel(storage, species_x, lattice):
         assert 0.95 < entering <= 1.0 + 1e-6, entering
     else:
         assert 0.7 < entering < 0.9, entering
-    assert mae < 0.06, mae
+    # measured: 3.77 % with INFLOW (against c_in), 5.00 % with RESERVOIR (normalised by the entering
+    # concentration), the same on both lattices; the paper reports about 4 %
+    assert mae < (0.045 if inflow else 0.055), mae
 
 
 def reactor_eta(w, p, steps=60000, window=20000, lattice=D3):
