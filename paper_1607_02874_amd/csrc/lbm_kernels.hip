@@ -1215,10 +1215,8 @@ template <int ST>
 __device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned long long *inacc,
                                                      const uint32_t *kidx, uint32_t cat_bits,
                                                      const PhysK<typename Store<ST>::T> &ph,
-                                                     const typename Store<ST>::T (&hR)[19]) {
+                                                     const typename Store<ST>::T (&hR)[19], QueuedArrival *q) {
     using T = typename Store<ST>::T;
-    __shared__ QueuedArrival queue[ARRIVAL_QUEUE];  // one wavefront per block
-    QueuedArrival *q = queue;
     uint32_t qn = 0;  // the same in every lane of the wavefront
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
@@ -1251,6 +1249,73 @@ __device__ __forceinline__ void accumulate_in_random(const Geometry &g, unsigned
         draw_queued(q, qn, g.ivox, g.imask, inacc, g.niface, ph.step_ctr, ph.seed_lo, ph.seed_hi);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
+}
+
+// The same terms as accumulate_in, queued densely in LDS direction by
+// direction and added 64 per pass: a wavefront issues about one atomic
+// instruction per 64 arrivals instead of one per direction in which any of
+// its lanes has a catalytic source.  The sums are integers, so In(k) holds the
+// same bits as with accumulate_in.
+__device__ __forceinline__ void add_queued(const QueuedArrival *q, uint32_t n, unsigned long long *inacc) {
+    const uint64_t live = __builtin_amdgcn_read_exec();
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(live >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(live), 0u));
+    const uint32_t lanes = uint32_t(__popcll(live));
+    for (uint32_t t = rank; t < n; t += lanes) {
+        const QueuedArrival a = q[t];
+        (void)__hip_atomic_fetch_add(&glb(inacc)[a.k], a.term, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ void accumulate_in_queued(unsigned long long *inacc, const uint32_t *kidx,
+                                                     uint32_t cat_bits, const PhysK<typename Store<ST>::T> &ph,
+                                                     const typename Store<ST>::T (&hR)[19],
+                                                     typename Store<ST>::T cref, QueuedArrival *q) {
+    using T = typename Store<ST>::T;
+    uint32_t qn = 0;  // the same in every lane of the wavefront
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const bool act = (cat_bits >> i) & 1u;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(act);
+        if (bal == 0u) continue;
+        if (act) {
+            const int j = opp(i);  // the link direction as seen from the interface node
+            QueuedArrival a;
+            a.term = in_term<T>(wgt<T>(j), hR[j], cref, ph.in_scale);
+            a.k = kidx[(i - 1) * CTHREADS + threadIdx.x];
+            a.code = 0u;
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+            q[qn + below] = a;
+        }
+        qn += uint32_t(__popcll(bal));
+        if (qn >= 64u) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            add_queued(q, qn, inacc);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            qn = 0;
+        }
+    }
+    if (qn > 0u) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        add_queued(q, qn, inacc);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+// The compact sweep's choice: queued at FP32 and FP64 storage, whose sweeps
+// are bound by vector-memory instructions (measured at 256^3 FP32: 648 ->
+// 636 us); direct at 16 bits, where the queue's extra VALU and LDS work costs
+// more than the instructions it saves (455 -> 468 us).
+template <int ST>
+__device__ __forceinline__ void accumulate_in_c(unsigned long long *inacc, const uint32_t *kidx, uint32_t cat_bits,
+                                                const PhysK<typename Store<ST>::T> &ph,
+                                                const typename Store<ST>::T (&hR)[19], typename Store<ST>::T cref,
+                                                QueuedArrival *q) {
+    if constexpr (sizeof(typename Store<ST>::S) == 2)
+        accumulate_in<ST, CTHREADS>(inacc, kidx, cat_bits, ph, hR, cref);
+    else
+        accumulate_in_queued<ST>(inacc, kidx, cat_bits, ph, hR, cref, q);
 }
 
 template <int ST>
@@ -1394,7 +1459,13 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
     const uint32_t idx = w * 64u + (threadIdx.x & 63u);
     const bool active = wvalid && int64_t(idx) < g.nfluid;
     __shared__ uint32_t kidx[18 * CTHREADS];
-    __shared__ WaveRecords wrec;
+    // the records are dead once the pull has read them; the arrival queue
+    // of the In(k) sums reuses their LDS
+    __shared__ union {
+        WaveRecords wrec;
+        QueuedArrival queue[ARRIVAL_QUEUE];
+    } lds;
+    WaveRecords &wrec = lds.wrec;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     uint32_t wunit = 0, p = 0;
     const bool coop = wvalid && wave_records(g, w, idx, active, wrec, wunit, p);
@@ -1440,12 +1511,25 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         // stochastic rounding is on): 2i, 2i + 1 for the pair of direction i,
         // 38 + i for the product
         const lbmfx::RoundWords rw = lbmfx::round_words(ph.sr != 0u, ph.sr_key, idx);
+        auto store_pairs = [&](const bool stochastic) {
 #pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            opaque(own_b);
-            const P v = Store<ST>::enc2(hC[i], hR[i], rw.at(2 * i), rw.at(2 * i + 1));
-            st_stream(static_cast<P *>(out.p(dslot(i))), own_b, v);
-            if constexpr (Store<ST>::ROUNDS) hR[i] = Store<ST>::cv(v.y);
+            for (int i = 0; i < 19; ++i) {
+                opaque(own_b);
+                // rounding to nearest uses one constant word: no per-word arithmetic
+                const uint32_t wc = stochastic ? rw.at(2 * i) : lbmfx::ROUND_NEAREST_BITS;
+                const uint32_t wr = stochastic ? rw.at(2 * i + 1) : lbmfx::ROUND_NEAREST_BITS;
+                const P v = Store<ST>::enc2(hC[i], hR[i], wc, wr);
+                st_stream(static_cast<P *>(out.p(dslot(i))), own_b, v);
+                if constexpr (Store<ST>::ROUNDS) hR[i] = Store<ST>::cv(v.y);
+            }
+        };
+        if constexpr (Store<ST>::ROUNDS) {
+            if (ph.sr != 0u)
+                store_pairs(true);
+            else
+                store_pairs(false);
+        } else {
+            store_pairs(false);
         }
         if constexpr (PROD) {
             using S = typename Store<ST>::S;
@@ -1459,7 +1543,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
                 if constexpr (Store<ST>::ROUNDS) hP[i] = Store<ST>::cv(v);
             }
             if (__builtin_amdgcn_ballot_w64(cat_bits != 0u))
-                accumulate_in<ST, CTHREADS>(pk.inacc, kidx, cat_bits, ph, hP, T(0));
+                accumulate_in_c<ST>(pk.inacc, kidx, cat_bits, ph, hP, T(0), lds.queue);
             if (reservoir && (first_x || last_x)) {
                 const InOut f = product_tally<ST>(pk.in.base, pk.in.stride, node_elem(g, idx), first_x, last_x);
                 accp[1] += f.in;
@@ -1468,9 +1552,9 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         }
         if (__builtin_amdgcn_ballot_w64(cat_bits != 0u)) {
             if constexpr ((SP & 3) == SP_STOCHASTIC)
-                accumulate_in_random<ST>(g, g.inacc, kidx, cat_bits, ph, hR);
+                accumulate_in_random<ST>(g, g.inacc, kidx, cat_bits, ph, hR, lds.queue);
             else
-                accumulate_in<ST, CTHREADS>(g.inacc, kidx, cat_bits, ph, hR, ph.cref);
+                accumulate_in_c<ST>(g.inacc, kidx, cat_bits, ph, hR, ph.cref, lds.queue);
         }
         if (reservoir && (first_x || last_x)) {
             const InOut f = boundary_tally<ST>(ph.cref, inflow ? 0.0 : ph.c_in, in.base, in.stride, node_elem(g, idx),
