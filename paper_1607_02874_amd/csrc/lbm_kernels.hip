@@ -69,14 +69,17 @@ struct Store<ST_F16> {
     __device__ static void st(S *p, T v) { *p = enc(v); }
     // rounded by the word w (see lbmfx::round_words): nearest or stochastic
     static constexpr bool ROUNDS = true;
+    // each conversion writes one half of its operand and keeps the other:
+    // starting from the bits of c (whose register is free after the call)
+    // spares a register clear per pair, and both halves are overwritten
     __device__ static P enc2(T c, T r, uint32_t wc, uint32_t wr) {
-        P v = {};
+        P v = __builtin_bit_cast(P, c);
         v = __builtin_amdgcn_cvt_sr_f16_f32(v, c, wc, false);
         v = __builtin_amdgcn_cvt_sr_f16_f32(v, r, wr, true);
         return v;
     }
     __device__ static S enc1(T x, uint32_t w) {
-        P v = {};
+        P v = __builtin_bit_cast(P, x);
         v = __builtin_amdgcn_cvt_sr_f16_f32(v, x, w, false);
         return v.x;
     }
@@ -97,13 +100,13 @@ struct Store<ST_BF16> {
     static constexpr bool ROUNDS = true;
     using B2 = __bf16 __attribute__((ext_vector_type(2)));
     __device__ static P enc2(T c, T r, uint32_t wc, uint32_t wr) {
-        B2 v = {};
+        B2 v = __builtin_bit_cast(B2, c);  // both halves overwritten (see Store<ST_F16>)
         v = __builtin_amdgcn_cvt_sr_bf16_f32(v, c, wc, false);
         v = __builtin_amdgcn_cvt_sr_bf16_f32(v, r, wr, true);
         return __builtin_bit_cast(P, v);
     }
     __device__ static S enc1(T x, uint32_t w) {
-        B2 v = {};
+        B2 v = __builtin_bit_cast(B2, x);
         v = __builtin_amdgcn_cvt_sr_bf16_f32(v, x, w, false);
         return __builtin_bit_cast(P, v).x;
     }
@@ -821,6 +824,77 @@ __device__ __forceinline__ RowWin row_window(const ChunkInfo &R, uint32_t xl, bo
     return o;
 }
 
+// Emission values of a wavefront's catalytic sources, read densely: the
+// lanes list the interface indices of their catalytic sources in LDS,
+// direction by direction at their rank among the lanes that have one (ballot
+// and mbcnt), read the list 64 entries per pass, and take their values back
+// in the same order.  A wavefront issues about one load per 64 sources
+// instead of one per direction; the values are those of the direct reads.
+// Wavefronts with more sources than the LDS list holds, or with idle
+// lanes, read directly.
+// gather: GATHER_BYTES of the wavefront's LDS, values first, then indices.
+constexpr uint32_t GATHER_BYTES = 2048;
+template <int ST>
+__device__ __forceinline__ void gather_emission(const typename Store<ST>::S *__restrict__ emit, const uint32_t *kidx,
+                                                uint32_t cat_bits, uint32_t *gather,
+                                                typename Store<ST>::S (&re)[19]) {
+    using S = typename Store<ST>::S;
+    constexpr uint32_t CAP = GATHER_BYTES / (sizeof(S) + 4) / 64 * 64;  // 256 at FP32, 128 at FP64
+    constexpr uint32_t PASSES = CAP / 64;
+    S *vals = reinterpret_cast<S *>(gather);
+    uint32_t *keys = gather + CAP * sizeof(S) / 4;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t total = 0;  // the same in every lane
+#pragma unroll
+    for (int i = 1; i < 19; ++i)
+        total += uint32_t(__popcll(__builtin_amdgcn_ballot_w64((cat_bits >> i) & 1u)));
+    // the passes deal list entry t to lane t mod 64: a wavefront with idle
+    // lanes (the last one of the domain) would leave their entries unread
+    if (total > CAP || __builtin_amdgcn_read_exec() != ~0ull) {
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+            uint32_t v_b = kidx[(i - 1) * CTHREADS + threadIdx.x] * uint32_t(sizeof(S));
+            opaque(v_b);
+            re[i] = ld_at(emit, v_b);
+        }
+        return;
+    }
+    // the pull's LDS reads (the records this space held) before these writes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    uint32_t at = 0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const bool act = (cat_bits >> i) & 1u;
+        const uint64_t b = __builtin_amdgcn_ballot_w64(act);
+        if (act) keys[at + bits_below_lane(b)] = kidx[(i - 1) * CTHREADS + threadIdx.x];
+        at += uint32_t(__popcll(b));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    S v[PASSES];
+#pragma unroll
+    for (uint32_t q = 0; q < PASSES; ++q) {
+        v[q] = S(0);
+        if (q * 64u < total) {  // wave-uniform: only the passes the list needs
+            const uint32_t t = q * 64u + lane;
+            uint32_t v_b = (t < total ? keys[t] : 0u) * uint32_t(sizeof(S));
+            opaque(v_b);
+            v[q] = ld_at(emit, v_b);
+        }
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < PASSES; ++q)
+        if (q * 64u + lane < total) vals[q * 64u + lane] = v[q];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    at = 0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        const bool act = (cat_bits >> i) & 1u;
+        const uint64_t b = __builtin_amdgcn_ballot_w64(act);
+        re[i] = act ? vals[at + bits_below_lane(b)] : S(0);
+        at += uint32_t(__popcll(b));
+    }
+}
+
 // The same pull for the node-compact sweep: each lane is one gas node at
 // (x, y, z) with storage index idx, lanes of a wave need not share a row.  For
 // each of the nine source rows a lane reads the record of its own chunk in
@@ -846,7 +920,8 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
                                        const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
                                        int z, typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
                                        uint32_t &cat_out, uint32_t *kidx, const ProdK<ST> &pk,
-                                       typename Store<ST>::T (&hP)[19], const XRec *wrec, uint32_t wunit) {
+                                       typename Store<ST>::T (&hP)[19], const XRec *wrec, uint32_t wunit,
+                                       uint32_t *gather) {
     using T = typename Store<ST>::T;
     using S = typename Store<ST>::S;
     using P = typename Store<ST>::P;
@@ -942,6 +1017,12 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     P pc[19];
     S re[19], ro[19];
     constexpr bool PROD = SP >= 0 && (SP & SP_PRODUCT_FLAG) != 0;
+    // Emission reads gathered densely (see gather_emission) where the sweep
+    // is bound by vector-memory instructions: FP32 and FP64 storage, the
+    // UNIFORM and WEIGHTED modes (one emission value per interface node), no
+    // product lattice.
+    constexpr bool GATHER = SP >= 0 && sizeof(S) >= 4 && !PROD &&
+                            ((SP & 3) == SP_UNIFORM || (SP & 3) == SP_WEIGHTED);
     S pp[PROD ? 19 : 1], pe[PROD ? 19 : 1], po[PROD ? 19 : 1];
     const uint32_t nfpp_b = pk.in.stride, ownp_b = own_e * SB;  // product buffer: one population per element
     pc[0] = ld_pop<ST>(base(dslot(0)), own_b);
@@ -967,11 +1048,13 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             solid_bits |= ~fmask & (1u << i);
             opaque(c_b);
             pc[i] = ld_pop<ST>(base(pair_slot(i)), c_b);
-            uint32_t v_b = bounce ? 0u
-                                  : (stoch ? uint32_t(i - 1) * g.niface + kidx[(i - 1) * CTHREADS + threadIdx.x]
-                                           : kidx[(i - 1) * CTHREADS + threadIdx.x]) * SB;
-            opaque(v_b);
-            re[i] = ld_at(emit, v_b);
+            if constexpr (!GATHER) {
+                uint32_t v_b = bounce ? 0u
+                                      : (stoch ? uint32_t(i - 1) * g.niface + kidx[(i - 1) * CTHREADS + threadIdx.x]
+                                               : kidx[(i - 1) * CTHREADS + threadIdx.x]) * SB;
+                opaque(v_b);
+                re[i] = ld_at(emit, v_b);
+            }
             ro[i] = S(0);
             if (cx == -1 && any_outlet) {
                 const bool F0 = (wf >> 1) & 1u;
@@ -999,6 +1082,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
             }
         }
     }
+    if constexpr (GATHER) gather_emission<ST>(emit, kidx, cat_bits, gather, re);
     __builtin_amdgcn_sched_barrier(0);
     const T h_in = Store<ST>::cv(Store<ST>::enc(ph.h_inlet));
     const bool inlet = reservoir && first_x, outlet = reservoir && last_x;
@@ -1465,6 +1549,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         WaveRecords wrec;
         QueuedArrival queue[ARRIVAL_QUEUE];
     } lds;
+    static_assert(sizeof(lds) >= GATHER_BYTES, "the emission gather list lives in the records' LDS");
     WaveRecords &wrec = lds.wrec;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     uint32_t wunit = 0, p = 0;
@@ -1475,7 +1560,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
         T hC[19], hR[19], hP[19];  // hP: product lattice (unused without it)
         uint32_t cat_bits;
         pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx, pk, hP,
-                       coop ? wrec.rec : nullptr, wunit);
+                       coop ? wrec.rec : nullptr, wunit, reinterpret_cast<uint32_t *>(lds.queue));
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
         acc[1] = double(m.rr);
