@@ -186,12 +186,37 @@ def cpu_baseline_batch(ws, n_samples=8, steps=20, runs=3):
                       f"steps of each"}
 
 
-def copy_ceiling(gib=2, reps=5):
-    """HBM copy rate of this GPU with the library's streaming copy (one
-    16-byte element per thread, non-temporal): median of `reps` copies of
-    `gib` GiB, timed with HIP events on the current stream."""
+def _median_event_ms(launch, stream, reps):
+    """Median over `reps` launches of their time between HIP events recorded
+    on `stream` (the stream the launch uses), after two untimed launches."""
     import statistics
 
+    import torch
+
+    launch()
+    launch()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        launch()
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times)
+
+
+PULL_SIDE = 256  # the pull-streaming reference runs on a dense periodic 256^3 lattice
+
+
+def copy_ceiling(pair_bytes=None, gib=2, reps=5):
+    """HBM copy rate of this GPU with the library's streaming copy (one
+    16-byte element per thread, non-temporal): median of `reps` copies of
+    `gib` GiB, timed with HIP events on the current stream.  With
+    `pair_bytes` (a population pair: 4, 8 or 16 bytes), also the rate of
+    lbm_stream_pull: one D3Q19 pull-streaming pass, no collision, over a dense
+    periodic 256^3 lattice in the sweep's blocked layout (the sweep's
+    population traffic in its own access pattern)."""
     import torch
 
     from paper_1607_02874_amd import lbm
@@ -207,20 +232,38 @@ def copy_ceiling(gib=2, reps=5):
         if st != lbm.LBM_OK:
             raise RuntimeError(f"lbm_stream_copy failed with status {st}")
 
-    copy()
-    copy()
-    times = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        copy()
-        e1.record(stream)
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1))
+    ms = _median_event_ms(copy, stream, reps)
     del a, b
-    ms = statistics.median(times)
-    return {"copy_GBps": round(2 * n / (ms * 1e-3) / 1e9, 1), "copy_bytes": 2 * n, "kernel": "k_stream_copy",
-            "method": f"median of {reps} device copies of {gib} GiB"}
+    out = {"copy_GBps": round(2 * n / (ms * 1e-3) / 1e9, 1), "copy_bytes": 2 * n, "kernel": "k_stream_copy",
+           "method": f"median of {reps} device copies of {gib} GiB"}
+    if pair_bytes:
+        side = PULL_SIDE
+        nodes = side ** 3
+        nbuf = (nodes + 63) // 64 * 64 * 19 * pair_bytes
+        a = torch.zeros(nbuf, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+
+        def pull():
+            st = lib.lbm_stream_pull(b.data_ptr(), a.data_ptr(), side, side, side, pair_bytes, stream.cuda_stream)
+            if st != lbm.LBM_OK:
+                raise RuntimeError(f"lbm_stream_pull failed with status {st}")
+
+        ms = _median_event_ms(pull, stream, reps)
+        del a, b
+        moved = 2 * 19 * pair_bytes * nodes
+        out.update({"pull_GBps": round(moved / (ms * 1e-3) / 1e9, 1), "pull_bytes": moved, "pull_us": round(ms * 1e3, 2),
+                    "pull_kernel": "k_stream_pull",
+                    "pull_method": f"median of {reps} D3Q19 pull-streaming passes (no collision) over a dense "
+                                   f"periodic {side}^3 lattice in the blocked layout, {pair_bytes}-byte pairs"})
+    return out
+
+
+def ceiling_fracs(ceiling, achieved):
+    """The achieved rate as fractions of the copy (and pull-streaming) rates."""
+    f = {"frac_of_copy": round(achieved / ceiling["copy_GBps"], 4)}
+    if "pull_GBps" in ceiling:
+        f["frac_of_pull"] = round(achieved / ceiling["pull_GBps"], 4)
+    return f
 
 
 def crop_errors(crop, ref, w, steps, storage):
@@ -296,7 +339,7 @@ def run_batch(args):
     batch.set_timing(False)
     t_sweep = kt["ms_sweep"] / max(kt["n_sweep"], 1) * 1e-3
     batch.close()
-    ceiling = copy_ceiling()
+    ceiling = copy_ceiling(2 * lbm.STORAGE_BYTES[storage])
     log(f"copy ceiling {ceiling}")
     sims = [] if args.no_sequential else [
         lbm.Sim(s["vox"], da=s["da"], tau=s["tau"], pore_size=s["pore_size"], force=s["force"],
@@ -364,7 +407,7 @@ def run_batch(args):
                      "bytes_per_launch": sweep_bytes, "avg_launch_us": round(t_sweep * 1e6, 2),
                      "timing": f"HIP events around each batched sweep of {kt['n_sweep']} eager steps after "
                                f"the timed graph replays",
-                     "ceiling": {**ceiling, "frac_of_copy": round(achieved / ceiling["copy_GBps"], 4)}},
+                     "ceiling": {**ceiling, **ceiling_fracs(ceiling, achieved)}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -944,7 +987,7 @@ def main():
     sim.close()
     log(f"elapsed {elapsed:.3f} s, totals {tot}")
 
-    ceiling = copy_ceiling()
+    ceiling = copy_ceiling(2 * lbm.STORAGE_BYTES[storage])
     log(f"copy ceiling {ceiling}")
     if args.copy_calib:
         a = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
@@ -968,7 +1011,7 @@ def main():
                     "traffic": measured_traffic(kname, w.name, args.storage,
                                                 "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile),
                     "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2),
-                    "ceiling": {**ceiling, "frac_of_copy": round(achieved / ceiling["copy_GBps"], 4)}}
+                    "ceiling": {**ceiling, **ceiling_fracs(ceiling, achieved)}}
     kernels = None
     if kt:
         kernels = {k: round(kt["ms_" + k] / max(kt["n_" + k], 1) * 1e3, 2) for k in ("sweep", "interface", "reduce")}

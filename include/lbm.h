@@ -348,6 +348,24 @@ lbm_status lbm_fields_noalloc(lbm_ctx *c, double *rho, double *u, double *conc);
  * the buffers must not overlap.  LBM_EDEVICE when the launch fails. */
 lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/* lbm_stream_pull - the streaming reference for the sweep's own access
+ * pattern (not part of the method): one pull-streaming pass of D3Q19 with no
+ * collision over a dense periodic nx x ny x nz lattice, in the blocked
+ * population layout the sweep uses.  Node n = x + nx (y + ny z) of the
+ * lattice reads element i of its upwind neighbour (x - c_ix, y - c_iy,
+ * z - c_iz), periodic in all three axes, and writes it to its own slot i:
+ * the population traffic of a sweep over a lattice of gas nodes only, one
+ * pair of pair_bytes per direction and node.
+ * Layout of src and dst (device memory, caller-owned, each
+ * ceil(nx ny nz / 64) * 64 * 19 * pair_bytes bytes): element (n, i) at
+ * index (n / 64) * 1216 + 64 i + n % 64.  pair_bytes: 4 (16-bit storage),
+ * 8 (FP32) or 16 (FP64).  Asynchronous on `stream` (NULL = the null stream).
+ * Errors: LBM_EINVAL for NULL or misaligned pointers, overlapping buffers,
+ * sizes below 1, ny or nz above 65535, more than 2^27 nodes, or another
+ * pair_bytes; LBM_EDEVICE when the launch fails. */
+lbm_status lbm_stream_pull(void *dst, const void *src, int32_t nx, int32_t ny, int32_t nz, int32_t pair_bytes,
+                           void *stream);
+
 /*
  * lbm_conversion_map - per voxel, the reactant converted at that catalytic
  * node so far: p p_S^R sum_t In(k, t), where In(k, t) is everything arriving

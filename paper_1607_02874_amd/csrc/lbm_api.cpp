@@ -1223,6 +1223,25 @@ lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, void *strea
     return LBM_OK;
 }
 
+lbm_status lbm_stream_pull(void *dst, const void *src, int32_t nx, int32_t ny, int32_t nz, int32_t pair_bytes,
+                           void *stream) {
+    if (!dst || !src) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    if (nx < 1 || ny < 1 || nz < 1 || ny > 65535 || nz > 65535)
+        return fail(nullptr, LBM_EINVAL, "nx, ny, nz must be >= 1, ny and nz <= 65535");
+    if (uint64_t(nx) * uint64_t(ny) * uint64_t(nz) > (uint64_t(1) << 27))  // element indices stay 32-bit
+        return fail(nullptr, LBM_EINVAL, "nx ny nz must not exceed 2^27 nodes");
+    if (pair_bytes != 4 && pair_bytes != 8 && pair_bytes != 16)
+        return fail(nullptr, LBM_EINVAL, "pair_bytes must be 4, 8 or 16");
+    const uintptr_t a = reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src);
+    if (a % uintptr_t(pair_bytes) != 0) return fail(nullptr, LBM_EINVAL, "pointers must be aligned to pair_bytes");
+    const uint64_t bytes = stream_pull_elements(nx, ny, nz) * uint64_t(pair_bytes);
+    const uintptr_t d = reinterpret_cast<uintptr_t>(dst), r = reinterpret_cast<uintptr_t>(src);
+    if (d < r + bytes && r < d + bytes) return fail(nullptr, LBM_EINVAL, "the buffers must not overlap");
+    const hipError_t e = launch_stream_pull(dst, src, nx, ny, nz, pair_bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "stream pull launch");
+    return LBM_OK;
+}
+
 lbm_status lbm_fields_device(lbm_ctx *c, float *rho, float *u, float *conc) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
     if (c->lattice == LBM_LATTICE_D2Q9) return plane_unsupported(c, "lbm_fields_device");

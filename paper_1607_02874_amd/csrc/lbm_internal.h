@@ -189,6 +189,11 @@ constexpr int MAX_SCRATCH_DEVICES = 64;
 hipError_t scratch_address(int device, double **out);
 // Streaming device copy of `bytes` (a multiple of 16, 16-byte aligned).
 hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Pull-streaming reference pass (no collision) over a dense periodic lattice
+// in the blocked layout, one element of pair_bytes (4, 8 or 16) per direction
+// and node; each buffer holds stream_pull_elements(nx, ny, nz) elements.
+uint64_t stream_pull_elements(int nx, int ny, int nz);
+hipError_t launch_stream_pull(void *dst, const void *src, int nx, int ny, int nz, int pair_bytes, hipStream_t s);
 // A box of voxels: origin and extent, inside the lattice.
 struct Window {
     int32_t x0, y0, z0, wx, wy, wz;

@@ -915,7 +915,7 @@ __device__ __forceinline__ void gather_emission(const typename Store<ST>::S *__r
 // catalytic source E_P(k) (or, for reversal, p p_S^R times the reactant plus
 // 1 - p_S^P times the product population that arrived along the reversed
 // link: second sputtering equation).
-template <int ST, int SP>
+template <int ST, int SP, bool GATHER_OK = true>
 __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
                                        const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
                                        int z, typename Store<ST>::T (&hC)[19], typename Store<ST>::T (&hR)[19],
@@ -1020,8 +1020,10 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     // Emission reads gathered densely (see gather_emission) where the sweep
     // is bound by vector-memory instructions: FP32 and FP64 storage, the
     // UNIFORM and WEIGHTED modes (one emission value per interface node), no
-    // product lattice.
-    constexpr bool GATHER = SP >= 0 && sizeof(S) >= 4 && !PROD &&
+    // product lattice, and not in the batched sweep (GATHER_OK false): the
+    // gather measured 630 against 634 us for the 256^3 sweep, but 2216
+    // against 2166 us for the 64-sample batched sweep.
+    constexpr bool GATHER = GATHER_OK && SP >= 0 && sizeof(S) >= 4 && !PROD &&
                             ((SP & 3) == SP_UNIFORM || (SP & 3) == SP_WEIGHTED);
     S pp[PROD ? 19 : 1], pe[PROD ? 19 : 1], po[PROD ? 19 : 1];
     const uint32_t nfpp_b = pk.in.stride, ownp_b = own_e * SB;  // product buffer: one population per element
@@ -1529,7 +1531,7 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
 // One block (one wavefront) of the node-compact sweep: wave slot `block`
 // takes the 64 gas nodes of wave worder[slot] (storage indices 64 w .. 64 w +
 // 63).
-template <int ST, int SP>
+template <int ST, int SP, bool GATHER_OK = true>
 __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph,
                                               const Slots &in, const OutSlots &out,
                                               const typename Store<ST>::S *__restrict__ emit,
@@ -1559,7 +1561,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
     if (active) {
         T hC[19], hR[19], hP[19];  // hP: product lattice (unused without it)
         uint32_t cat_bits;
-        pull_c<ST, SP>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx, pk, hP,
+        pull_c<ST, SP, GATHER_OK>(g, ph, in, emit, idx, x, y, z, hC, hR, cat_bits, kidx, pk, hP,
                        coop ? wrec.rec : nullptr, wunit, reinterpret_cast<uint32_t *>(lds.queue));
         const Mom<T> m = moments(ph, hC, hR);
         acc[0] = double(m.rc);
@@ -2182,7 +2184,7 @@ __global__ __launch_bounds__(CTHREADS, ST == ST_F64 ? 1 : 5) void k_sweep_batch_
     const SampleK<ST> &d = smp[__builtin_amdgcn_readfirstlane(block_sample[b])];
     const Slots &in = d.pop[parity];
     const OutSlots &out = reinterpret_cast<const OutSlots &>(d.pop[1 - parity]);
-    sweep_block_c<ST, SP>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0, ProdK<ST>{});
+    sweep_block_c<ST, SP, false>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0, ProdK<ST>{});
 }
 
 template <int ST>
@@ -2640,6 +2642,59 @@ hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStrea
     if (blocks > 0xffffffffull) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_stream_copy, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<const u32x4 *>(src),
                        static_cast<u32x4 *>(dst), n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------- pull-streaming reference --
+// The data movement of the sweep without its arithmetic: one pull-streaming
+// pass of D3Q19 over a dense periodic nx x ny x nz lattice stored in the
+// sweep's blocked layout (the 19 slots of 64 consecutive nodes contiguous).
+// Node n = x + nx (y + ny z) reads element i of its upwind neighbour
+// (x - c_ix, y - c_iy, z - c_iz) and writes it to its own slot i, one
+// non-temporal load and store per direction and node.  A population pair of
+// the sweep is one element E (4, 8 or 16 bytes).  Not part of the method.
+template <typename E>
+__global__ __launch_bounds__(256) void k_stream_pull(const E *__restrict__ src, E *__restrict__ dst, int nx, int ny,
+                                                     int nz) {
+    const int x = int(blockIdx.x) * 256 + int(threadIdx.x), y = int(blockIdx.y), z = int(blockIdx.z);
+    if (x >= nx) return;
+    const uint32_t n = uint32_t(x) + uint32_t(nx) * (uint32_t(y) + uint32_t(ny) * uint32_t(z));
+    const uint32_t own = (n >> 6) * (19u * 64u) + (n & 63u);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        int xs = x - CX[i], ys = y - CY[i], zs = z - CZ[i];
+        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+        ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+        zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
+        const uint32_t m = uint32_t(xs) + uint32_t(nx) * (uint32_t(ys) + uint32_t(ny) * uint32_t(zs));
+        const E v = __builtin_nontemporal_load(src + (m >> 6) * (19u * 64u) + uint32_t(i) * 64u + (m & 63u));
+        __builtin_nontemporal_store(v, dst + own + uint32_t(i) * 64u);
+    }
+}
+
+uint64_t stream_pull_elements(int nx, int ny, int nz) {
+    const uint64_t n = uint64_t(nx) * uint64_t(ny) * uint64_t(nz);
+    return (n + 63u) / 64u * 64u * 19u;
+}
+
+hipError_t launch_stream_pull(void *dst, const void *src, int nx, int ny, int nz, int pair_bytes, hipStream_t s) {
+    const dim3 grid(unsigned((nx + 255) / 256), unsigned(ny), unsigned(nz)), block(256);
+    switch (pair_bytes) {
+    case 4:
+        hipLaunchKernelGGL(k_stream_pull<uint32_t>, grid, block, 0, s, static_cast<const uint32_t *>(src),
+                           static_cast<uint32_t *>(dst), nx, ny, nz);
+        break;
+    case 8:
+        hipLaunchKernelGGL(k_stream_pull<uint64_t>, grid, block, 0, s, static_cast<const uint64_t *>(src),
+                           static_cast<uint64_t *>(dst), nx, ny, nz);
+        break;
+    case 16:
+        hipLaunchKernelGGL(k_stream_pull<u32x4>, grid, block, 0, s, static_cast<const u32x4 *>(src),
+                           static_cast<u32x4 *>(dst), nx, ny, nz);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -118,6 +118,8 @@ def _load():
         "lbm_fields_device": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_fields_noalloc": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_stream_copy": (st, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+        "lbm_stream_pull": (st, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_void_p]),
         "lbm_conversion_map": (st, [ctx, ctypes.c_void_p]),
         "lbm_product_fields": (st, [ctx, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "lbm_populations": (st, [ctx, P(ctypes.c_int32), P(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p]),

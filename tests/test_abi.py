@@ -111,6 +111,24 @@ def test_null_arguments():
     L.lbm_destroy(None)  # no-op
 
 
+@pytest.mark.parametrize("args, msg", [
+    ((None, 1024, 4, 4, 4, 8), b"NULL"),
+    ((4096, 1024, 0, 4, 4, 8), b">= 1"),
+    ((4096, 1024, 4, 70000, 4, 8), b"65535"),
+    ((4096, 1024, 1024, 1024, 512, 8), b"2^27"),
+    ((4096, 1024, 4, 4, 4, 12), b"pair_bytes"),
+    ((4100, 1024, 4, 4, 4, 8), b"aligned"),
+    ((4096, 4096 + 64, 4, 4, 4, 8), b"overlap"),
+])
+def test_stream_pull_rejects_invalid_arguments_before_device_work(args, msg):
+    """The checks come before any HIP call, so they run without a GPU (the
+    addresses are never dereferenced)."""
+    L = lbm.library()
+    dst, src, nx, ny, nz, pb = args
+    assert L.lbm_stream_pull(dst, src, nx, ny, nz, pb, None) == lbm.LBM_EINVAL
+    assert msg in L.lbm_last_error(None)
+
+
 def _batch_args(n, storages=None, taus=None):
     geoms = (lbm.lbm_geometry * max(n, 1))()
     bcs = (lbm.lbm_bc * max(n, 1))()
