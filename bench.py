@@ -67,11 +67,11 @@ def algorithmic_bytes(info, s, product=False, stochastic=False):
     return {"sweep": sweep, "interface": iface, "step": sweep + iface}
 
 
-def measured_traffic(kernel, workload, storage_name, sweep, ytile):
+def measured_traffic(kernel, workload, storage_name, sweep, ytile, emission):
     """Calibrated HBM bytes per launch from the PMC records in
     profiles/traffic.json, or None when no record matches this kernel,
-    workload, storage and launch shape, or the kernel source has changed
-    since the counters were taken."""
+    workload, storage and launch shape (sweep variant, y-tile, emission read
+    mode), or the kernel source has changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -79,7 +79,8 @@ def measured_traffic(kernel, workload, storage_name, sweep, ytile):
         with open(path) as f:
             recs = json.load(f).get(kernel, [])
         for rec in recs:
-            if (rec["workload"], rec["storage"], rec["sweep"], rec["ytile"]) != (workload, storage_name, sweep, ytile):
+            if (rec["workload"], rec["storage"], rec["sweep"], rec["ytile"], rec.get("emission")) != (
+                    workload, storage_name, sweep, ytile, emission):
                 continue
             with open(os.path.join(ROOT, rec["source"]), "rb") as f:
                 if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
@@ -89,6 +90,16 @@ def measured_traffic(kernel, workload, storage_name, sweep, ytile):
     except (OSError, KeyError, ValueError):
         return None
     return None
+
+
+def emission_mode(tunable, storage, applies=True):
+    """The compact sweep's emission reads as run: "gather" where the
+    LBM_TUNE_EMISSION value asks for it and the gather applies (FP32 or FP64
+    storage, UNIFORM or WEIGHTED sputtering, no product lattice), else
+    "direct"."""
+    from paper_1607_02874_amd import lbm
+
+    return "gather" if applies and tunable == 1 and storage in (lbm.STORE_F32, lbm.STORE_F64) else "direct"
 
 
 def cpu_info():
@@ -320,12 +331,15 @@ def run_batch(args):
         batch.set_tunable(lbm.TUNE_SWEEP, args.sweep)
     if args.ytile:
         batch.set_tunable(lbm.TUNE_YTILE, args.ytile)
-    if not args.no_autotune and args.ytile is None and args.sweep is None:
+    if args.emission is not None:
+        batch.set_tunable(lbm.TUNE_EMISSION, args.emission)
+    if not args.no_autotune and args.ytile is None and args.sweep is None and args.emission is None:
         ms = batch.autotune(3)
         log(f"autotune: sweep {batch.get_tunable(lbm.TUNE_SWEEP)} ytile {batch.get_tunable(lbm.TUNE_YTILE)} "
             f"({ms * 1e3:.1f} us)")
     sweep_variant = batch.get_tunable(lbm.TUNE_SWEEP)
     ytile_batch = batch.get_tunable(lbm.TUNE_YTILE)
+    emission = emission_mode(batch.get_tunable(lbm.TUNE_EMISSION), storage)
     infos = [batch.info(i) for i in range(len(samples))]
     log(f"batched: timing {args.steps} steps")
     t_batch = timed(batch.step, batch.synchronize, args.steps)
@@ -375,7 +389,7 @@ def run_batch(args):
     achieved = sweep_bytes / t_sweep / 1e9
     storage_name = {v: k for k, v in STORAGES.items()}[storage]
     traffic = measured_traffic("k_sweep_batch_c", "batch64", storage_name,
-                               "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile_batch)
+                               "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile_batch, emission)
     cpu = None
     if args.cpu_steps > 0:
         log("oracle on the 8 smallest samples of the batch")
@@ -397,6 +411,7 @@ def run_batch(args):
                                "length 6, tau U[0.55,1.2], Da logU[0.01,100], seeds 2000+s",
                    "n_nodes": n_nodes, "n_fluid": n_fluid, "graph": not args.no_graph,
                    "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks", "ytile": ytile_batch,
+                   "emission": emission,
                    "sequential_mlups": round(n_nodes * args.steps / t_seq / 1e6, 1) if t_seq else None,
                    "sequential_ms_per_step": round(t_seq / args.steps * 1e3, 4) if t_seq else None,
                    "speedup_vs_sequential": round(t_seq / t_batch, 3) if t_seq else None,
@@ -706,7 +721,7 @@ def run_product(args):
                      "achieved": round(ab["sweep"] / t_sweep / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ab["sweep"] / t_sweep / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("k_sweep_c", w.name + "_product", storage_name, "node-compact",
-                                                 ytile),
+                                                 ytile, "direct"),
                      "algorithmic_bytes": ab["sweep"],
                      "ceiling": {**ceiling, "frac_of_copy": round(ab["sweep"] / t_sweep / 1e9 / ceiling["copy_GBps"], 4)}},
         "cpu_baseline": None,
@@ -774,7 +789,8 @@ def run_stochastic(args):
                      "traffic": measured_traffic("k_sweep_c" if sweep_variant == 1 else "k_sweep",
                                                  w.name + "_stochastic", {0: "f32", 1: "f16", 2: "bf16",
                                                                           3: "f64"}[storage],
-                                                 "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile),
+                                                 "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile,
+                                                 "direct"),
                      "algorithmic_bytes": ab["sweep"],
                      "ceiling": {**ceiling, "frac_of_copy": round(ab["sweep"] / t_sweep / 1e9 / ceiling["copy_GBps"], 4)}},
         "cpu_baseline": None,
@@ -883,6 +899,9 @@ def main():
     ap.add_argument("--scan-ytile", default="", help="comma list of y-tile heights to time before the run")
     ap.add_argument("--sweep", type=int, default=None, choices=(0, 1),
                     help="sweep variant: 1 node-compact (library default), 0 one wave per 64-voxel chunk")
+    ap.add_argument("--emission", type=int, default=None, choices=(0, 1),
+                    help="emission reads of the compact sweep: 1 gathered through LDS (a context's default), "
+                         "0 direct (a batch's default); single and batch workloads")
     ap.add_argument("--workload", default="single", choices=("single", "batch", "precision", "membrane", "shard", "product", "reactor2d", "stochastic"),
                     help="single: the 256^3 sample; batch: the 64-sample mixed batch; precision: 512^3 "
                          "with FP32/FP16/BF16 storage against the FP64 build; membrane: 1024x512x512 layer; "
@@ -952,12 +971,15 @@ def main():
             log(f"ytile {yt}: sweep {kt['ms_sweep'] / kt['n_sweep'] * 1e3:.1f} us")
     if args.ytile:
         sim.set_tunable(lbm.TUNE_YTILE, args.ytile)
+    if args.emission is not None:
+        sim.set_tunable(lbm.TUNE_EMISSION, args.emission)
     tuned = None
-    if not args.no_autotune and args.ytile is None and args.sweep is None:
+    if not args.no_autotune and args.ytile is None and args.sweep is None and args.emission is None:
         tuned = sim.autotune(10)
         log(f"autotune: sweep {sim.get_tunable(lbm.TUNE_SWEEP)} ytile {sim.get_tunable(lbm.TUNE_YTILE)} "
-            f"({tuned * 1e3:.1f} us)")
+            f"emission {sim.get_tunable(lbm.TUNE_EMISSION)} ({tuned * 1e3:.1f} us)")
     sweep_variant = sim.get_tunable(lbm.TUNE_SWEEP)
+    emission = emission_mode(sim.get_tunable(lbm.TUNE_EMISSION), storage)
     sim.step(args.warmup)
     sim.synchronize()
     torch.cuda.synchronize()
@@ -1009,7 +1031,8 @@ def main():
         roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(kname, w.name, args.storage,
-                                                "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile),
+                                                "node-compact" if sweep_variant == 1 else "64-voxel chunks", ytile,
+                                                emission),
                     "bytes_per_launch": ab["sweep"], "avg_launch_us": round(t_sweep * 1e6, 2),
                     "ceiling": {**ceiling, **ceiling_fracs(ceiling, achieved)}}
     kernels = None
@@ -1046,7 +1069,7 @@ def main():
                    "n_catalytic_links": info["n_catalytic_links"], "mflups": round(mlups * info["n_fluid"] / n, 1),
                    "step_bytes": ab["step"], "step_GBps": round(ab["step"] / (ms_step * 1e-3) / 1e9, 1),
                    "kernel_us": kernels, "ytile": ytile, "autotuned": tuned is not None,
-                   "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks"},
+                   "sweep": "node-compact" if sweep_variant == 1 else "64-voxel chunks", "emission": emission},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": None if errs is None else {

@@ -426,16 +426,24 @@ lbm_status lbm_synchronize(lbm_ctx *c);
  * voxels leave lanes idle).  The two compute the same values; the totals
  * may differ in the last bits (per-block partial sums group nodes
  * differently).  The compact sweep needs ny, nz <= 1024 (LBM_EUNSUPPORTED
- * otherwise). */
-typedef enum { LBM_TUNE_YTILE = 0, LBM_TUNE_SWEEP = 1 } lbm_tunable;
+ * otherwise).
+ * LBM_TUNE_EMISSION: how the compact sweep reads the emission values of its
+ * catalytic sources: 1 (default for a context) = each full wavefront lists
+ * its sources in LDS and reads them 64 per pass; 0 = one read per direction
+ * and lane.  Both read the same values, so every result is bit-identical.
+ * It has an effect only with FP32 or FP64 storage, UNIFORM or WEIGHTED
+ * sputtering and no product lattice; elsewhere the value is kept and
+ * ignored. */
+typedef enum { LBM_TUNE_YTILE = 0, LBM_TUNE_SWEEP = 1, LBM_TUNE_EMISSION = 2 } lbm_tunable;
 lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value);   /* LBM_EINVAL: unknown or out of range */
 lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value);
 
 /*
  * lbm_autotune - pick the launch shape: time `reps` (1..1000) sweeps for each
  * candidate (sweep variant x y-tile in {4, 8, 16, 32, 64, 128}, clamped to
- * ny) in two interleaved rounds and keep the candidate with the fastest
- * round.  The trial sweeps run in place; the population
+ * ny; for the compact sweep also both LBM_TUNE_EMISSION modes where that
+ * tunable has an effect) in two interleaved rounds and keep the candidate
+ * with the fastest round.  The trial sweeps run in place; the population
  * buffer and In(k) accumulators they overwrite are saved to temporary device memory
  * first and restored afterwards, so the state (and every later result) is
  * exactly as before the call.  best_ms (may be NULL) receives the mean sweep
@@ -508,7 +516,9 @@ lbm_status lbm_batch_synchronize(lbm_batch *b);
 lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t enable);
 /* Tunables of every sample (see lbm_set_tunable).  LBM_TUNE_SWEEP applies to
  * the whole batch (1 needs every sample to support the compact sweep);
- * LBM_TUNE_YTILE is clamped to each sample's ny; get reports sample 0's. */
+ * LBM_TUNE_YTILE is clamped to each sample's ny; get reports sample 0's.
+ * LBM_TUNE_EMISSION applies to the batched sweep (default 0 for a batch:
+ * direct reads); changing it discards the captured step graphs. */
 lbm_status lbm_batch_set_tunable(lbm_batch *b, int32_t which, int64_t value);
 lbm_status lbm_batch_get_tunable(const lbm_batch *b, int32_t which, int64_t *value);
 /* lbm_autotune for the batched sweep: one variant and y-tile for the batch. */

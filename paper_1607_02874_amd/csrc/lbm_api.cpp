@@ -920,6 +920,7 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.wall_diffuse = wall_sigma;
     c->ph.rounding = bc->rounding;
     c->ph.step_ctr = 0;  // the initial state is the collision of step 0
+    c->ph.emission_gather = 1;  // measured faster for a single context at 256^3 (LBM_TUNE_EMISSION)
 
     if (bc->lattice == LBM_LATTICE_D2Q9) {
         c->lattice = LBM_LATTICE_D2Q9;
@@ -1463,6 +1464,11 @@ lbm_status lbm_set_tunable(lbm_ctx *c, int32_t which, int64_t value) {
         c->compact = int(value);
         return LBM_OK;
     }
+    if (which == LBM_TUNE_EMISSION) {
+        if (value != 0 && value != 1) return fail(c, LBM_EINVAL, "emission read mode must be 0 or 1");
+        c->ph.emission_gather = uint32_t(value);
+        return LBM_OK;
+    }
     return fail(c, LBM_EINVAL, "unknown tunable");
 }
 
@@ -1475,6 +1481,10 @@ lbm_status lbm_get_tunable(const lbm_ctx *c, int32_t which, int64_t *value) {
     }
     if (which == LBM_TUNE_SWEEP) {
         *value = c->compact;
+        return LBM_OK;
+    }
+    if (which == LBM_TUNE_EMISSION) {
+        *value = c->ph.emission_gather;
         return LBM_OK;
     }
     return LBM_EINVAL;
@@ -1678,19 +1688,25 @@ lbm_status lbm_load(lbm_ctx *c, const char *path) {
 namespace {
 
 struct Candidate {
-    int compact, ytile;
+    int compact, ytile, gather;
 };
 
-std::vector<Candidate> tuning_candidates(bool compact_ok, int ny, bool compact_only = false) {
+// Sweep variant x y-tile, and for the compact sweep both emission read modes
+// where the gather applies (`gather_ok`); elsewhere the candidates keep the
+// current mode `gather_now`, which has no effect there.
+std::vector<Candidate> tuning_candidates(bool compact_ok, int ny, bool compact_only, bool gather_ok, int gather_now) {
     std::vector<Candidate> out;
     const int ytiles[] = {4, 8, 16, 32, 64, 128};
     for (int v = compact_only ? 1 : 0; v <= (compact_ok ? 1 : 0); ++v) {
-        int last = -1;
-        for (int yt : ytiles) {
-            const int t = std::min(yt, ny);
-            if (t == last) continue;
-            out.push_back({v, t});
-            last = t;
+        const bool both = v == 1 && gather_ok;
+        for (int gm = both ? 0 : gather_now; gm <= (both ? 1 : gather_now); ++gm) {
+            int last = -1;
+            for (int yt : ytiles) {
+                const int t = std::min(yt, ny);
+                if (t == last) continue;
+                out.push_back({v, t, gm});
+                last = t;
+            }
         }
     }
     return out;
@@ -1789,10 +1805,12 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
     if (e != hipSuccess) return hip_fail(c, e, "autotune");
     Saved sv;
     st = save_written(c, sv, scratch_alloc);
-    const Candidate keep{c->compact, c->ytile};
+    const Candidate keep{c->compact, c->ytile, int(c->ph.emission_gather)};
     Candidate best = keep;
     float best_t = 0.0f;
-    const std::vector<Candidate> cands = tuning_candidates(c->compact_ok, c->ny, c->ph.product != 0);
+    const std::vector<Candidate> cands =
+        tuning_candidates(c->compact_ok, c->ny, c->ph.product != 0,
+                          emission_gather_applies(c->ph.storage, c->ph.sputter, c->ph.product != 0), keep.gather);
     std::vector<float> t_min(cands.size(), 0.0f);
     // two interleaved rounds; each candidate keeps its faster round
     for (int round = 0; round < 2 && st == LBM_OK; ++round) {
@@ -1800,6 +1818,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
             const Candidate &cd = cands[ci];
             st = lbm_set_tunable(c, LBM_TUNE_YTILE, cd.ytile);
             if (st == LBM_OK) st = lbm_set_tunable(c, LBM_TUNE_SWEEP, cd.compact);
+            if (st == LBM_OK) st = lbm_set_tunable(c, LBM_TUNE_EMISSION, cd.gather);
             if (st != LBM_OK) break;
             const Geometry g = geometry(c);
             const void *fin = c->d_pop[c->cur];
@@ -1829,6 +1848,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t reps, double *best_ms) {
     const Candidate use = st == LBM_OK ? best : keep;
     lbm_status ts = lbm_set_tunable(c, LBM_TUNE_YTILE, use.ytile);
     if (ts == LBM_OK) ts = lbm_set_tunable(c, LBM_TUNE_SWEEP, use.compact);
+    if (ts == LBM_OK) ts = lbm_set_tunable(c, LBM_TUNE_EMISSION, use.gather);
     if (st != LBM_OK) return st;
     if (rs != LBM_OK) return rs;
     if (ts != LBM_OK) return ts;
@@ -1854,6 +1874,10 @@ struct lbm_batch {
     hipStream_t stream = nullptr;
     int storage = 0, sputter = 0, species_x = 0;  // shared by every sample
     bool compact = false;  // node-compact sweep for every sample (all support it)
+    // emission reads of the compact sweep gathered through LDS where that
+    // applies (LBM_TUNE_EMISSION); direct by default, measured faster on the
+    // 64-sample batch
+    bool gather = false;
     std::vector<void *> allocations;
     void *d_records = nullptr;
     ReduceK *d_reduce = nullptr;
@@ -1950,7 +1974,8 @@ lbm_status batch_launch(lbm_batch *b, int parity, hipStream_t s, bool timed = fa
         e1 = b->ring[k].second;
         b->ring_pending[k] = true;
     }
-    hipError_t e = launch_batch_step(b->storage, b->sputter, b->species_x, b->compact, b->d_records, b->d_sweep_sample,
+    hipError_t e = launch_batch_step(b->storage, b->sputter, b->species_x, b->compact, b->gather, b->d_records,
+                                     b->d_sweep_sample,
                                      b->sweep_blocks_total, b->d_iface_sample, b->iface_blocks_total, b->d_reduce,
                                      int(b->ctx.size()), parity, s, e0, e1);
     if (e != hipSuccess) return bfail(b, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
@@ -2000,6 +2025,17 @@ lbm_status batch_forward(lbm_batch *b, int32_t i, lbm_status st) {
 // block count for the batch's sweep variant), the block-to-sample tables and
 // the device records; every context is switched to the batch's variant so a
 // sample's single-context calls match its batched steps.
+// Destroy the captured step graphs (they hold the launches as captured).
+void drop_graphs(lbm_batch *b) {
+    for (int l = 0; l < 2; ++l)
+        for (int k = 0; k < 2; ++k) {
+            if (b->exec[l][k]) (void)hipGraphExecDestroy(b->exec[l][k]);
+            if (b->graph[l][k]) (void)hipGraphDestroy(b->graph[l][k]);
+            b->exec[l][k] = nullptr;
+            b->graph[l][k] = nullptr;
+        }
+}
+
 lbm_status batch_tables(lbm_batch *b) {
     const int n = int(b->ctx.size());
     for (lbm_ctx *c : b->ctx) c->compact = b->compact ? 1 : 0;
@@ -2051,14 +2087,7 @@ lbm_status batch_tables(lbm_batch *b) {
                            b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch upload: ") + hipGetErrorString(e));
-    // captured graphs hold the old launch shapes
-    for (int l = 0; l < 2; ++l)
-        for (int k = 0; k < 2; ++k) {
-            if (b->exec[l][k]) (void)hipGraphExecDestroy(b->exec[l][k]);
-            if (b->graph[l][k]) (void)hipGraphDestroy(b->graph[l][k]);
-            b->exec[l][k] = nullptr;
-            b->graph[l][k] = nullptr;
-        }
+    drop_graphs(b);  // captured graphs hold the old launch shapes
     return LBM_OK;
 }
 
@@ -2283,6 +2312,17 @@ lbm_status lbm_batch_set_tunable(lbm_batch *b, int32_t which, int64_t value) {
         b->compact = value == 1;
         return batch_tables(b);
     }
+    if (which == LBM_TUNE_EMISSION) {
+        if (value != 0 && value != 1) return bfail(b, LBM_EINVAL, "emission read mode must be 0 or 1");
+        if (b->gather != (value == 1)) {
+            // the stream may still replay a graph that holds the old launch
+            const hipError_t e = hipStreamSynchronize(b->stream);
+            if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("set tunable: ") + hipGetErrorString(e));
+            drop_graphs(b);
+            b->gather = value == 1;
+        }
+        return LBM_OK;
+    }
     if (which == LBM_TUNE_YTILE) {
         if (value < 1) return bfail(b, LBM_EINVAL, "ytile must be >= 1");
         for (size_t i = 0; i < b->ctx.size(); ++i) {
@@ -2299,6 +2339,10 @@ lbm_status lbm_batch_get_tunable(const lbm_batch *b, int32_t which, int64_t *val
     if (!b || !value || b->ctx.empty()) return LBM_EINVAL;
     if (which == LBM_TUNE_SWEEP) {
         *value = b->compact ? 1 : 0;
+        return LBM_OK;
+    }
+    if (which == LBM_TUNE_EMISSION) {
+        *value = b->gather ? 1 : 0;
         return LBM_OK;
     }
     return lbm_get_tunable(b->ctx[0], which, value);
@@ -2325,21 +2369,24 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, double *best_ms) {
         st = save_written(b->ctx[i], sv[i], scratch_alloc);
         if (st != LBM_OK) st = batch_forward(b, int32_t(i), st);
     }
-    const Candidate keep{b->compact ? 1 : 0, b->ctx[0]->ytile};
+    const Candidate keep{b->compact ? 1 : 0, b->ctx[0]->ytile, b->gather ? 1 : 0};
     Candidate best = keep;
     float best_t = 0.0f;
-    const std::vector<Candidate> cands = tuning_candidates(compact_ok, ny_max);
+    const std::vector<Candidate> cands =
+        tuning_candidates(compact_ok, ny_max, false,
+                          emission_gather_applies(b->storage, b->sputter, b->ctx[0]->ph.product != 0), keep.gather);
     std::vector<float> t_min(cands.size(), 0.0f);
     for (int round = 0; round < 2 && st == LBM_OK; ++round) {
         for (size_t ci = 0; ci < cands.size(); ++ci) {
             const Candidate &cd = cands[ci];
             st = lbm_batch_set_tunable(b, LBM_TUNE_YTILE, cd.ytile);
             if (st == LBM_OK) st = lbm_batch_set_tunable(b, LBM_TUNE_SWEEP, cd.compact);
+            if (st == LBM_OK) st = lbm_batch_set_tunable(b, LBM_TUNE_EMISSION, cd.gather);
             if (st != LBM_OK) break;
             const int parity = b->parity;
             float ms = 0.0f;
             st = time_launches(b->stream, reps, [&]() {
-                return launch_batch_sweep(b->storage, b->sputter, b->species_x, b->compact, b->d_records,
+                return launch_batch_sweep(b->storage, b->sputter, b->species_x, b->compact, b->gather, b->d_records,
                                           b->d_sweep_sample,
                                           b->sweep_blocks_total, parity, b->stream);
             }, &ms, &b->err);
@@ -2361,6 +2408,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, double *best_ms) {
     const Candidate use = st == LBM_OK ? best : keep;
     lbm_status ts = lbm_batch_set_tunable(b, LBM_TUNE_YTILE, use.ytile);
     if (ts == LBM_OK) ts = lbm_batch_set_tunable(b, LBM_TUNE_SWEEP, use.compact);
+    if (ts == LBM_OK) ts = lbm_batch_set_tunable(b, LBM_TUNE_EMISSION, use.gather);
     if (st != LBM_OK) return st;
     if (rs != LBM_OK) return bfail(b, rs, "autotune restore failed");
     if (ts != LBM_OK) return ts;

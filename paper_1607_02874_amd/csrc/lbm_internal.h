@@ -119,7 +119,7 @@ struct Physics {
     double wall_diffuse;          // sigma: diffuse fraction of the carrier's wall reflection
     uint64_t seed;                // STOCHASTIC: Philox key
     uint32_t step_ctr;            // STOCHASTIC: step whose collision produces the arrivals a launch sums
-    uint32_t pad3;
+    uint32_t emission_gather;     // 1: the compact sweep gathers emission reads through LDS where that applies
 };
 
 // Device buffers of the product lattice for one step (all null / unused when
@@ -187,6 +187,10 @@ hipError_t launch_fields_rows(const Geometry &g, const Physics &ph, const void *
 constexpr int64_t FIELDS_SCRATCH_DOUBLES = int64_t(4) << 20;  // 32 MiB
 constexpr int MAX_SCRATCH_DEVICES = 64;
 hipError_t scratch_address(int device, double **out);
+// Whether the compact sweep's emission gather is a choice for this storage,
+// sputter mode and product setting (FP32 / FP64, UNIFORM / WEIGHTED, no
+// product lattice); elsewhere the emission tunable has no effect.
+bool emission_gather_applies(int storage, int sputter, bool product);
 // Streaming device copy of `bytes` (a multiple of 16, 16-byte aligned).
 hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Pull-streaming reference pass (no collision) over a dense periodic lattice
@@ -255,12 +259,15 @@ struct ReduceK {
 // built from `smp` (synchronous on `s`).
 size_t batch_record_bytes(int storage);
 hipError_t batch_upload(int storage, const BatchSample *smp, int n, void *d_records, hipStream_t s);
-// The batched sweep alone (reads buffer `parity` of every sample).
-hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool compact, const void *d_records,
-                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, int parity, hipStream_t s);
+// The batched sweep alone (reads buffer `parity` of every sample).  gather:
+// the compact sweep gathers its emission reads through LDS where that
+// applies (emission_gather_applies).
+hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool compact, bool gather,
+                              const void *d_records, const uint32_t *sweep_sample, int64_t sweep_blocks_total,
+                              int parity, hipStream_t s);
 // One step of every sample: batched interface, sweep (reading population
 // buffer `parity` of every sample, writing the other) and reduction.
-hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compact, const void *d_records,
+hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compact, bool gather, const void *d_records,
                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, const uint32_t *iface_sample,
                              int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s,
                              hipEvent_t sweep_start = nullptr, hipEvent_t sweep_stop = nullptr);

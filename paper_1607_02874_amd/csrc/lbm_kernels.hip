@@ -915,6 +915,14 @@ __device__ __forceinline__ void gather_emission(const typename Store<ST>::S *__r
 // catalytic source E_P(k) (or, for reversal, p p_S^R times the reactant plus
 // 1 - p_S^P times the product population that arrived along the reversed
 // link: second sputtering equation).
+// The sweeps where the emission gather is a choice: FP32 and FP64 storage,
+// UNIFORM and WEIGHTED sputtering, no product lattice.
+template <int ST, int SP>
+constexpr bool gather_applies() {
+    return SP >= 0 && sizeof(typename Store<ST>::S) >= 4 && (SP & SP_PRODUCT_FLAG) == 0 &&
+           ((SP & 3) == SP_UNIFORM || (SP & 3) == SP_WEIGHTED);
+}
+
 template <int ST, int SP, bool GATHER_OK = true>
 __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename Store<ST>::T> &ph, const Slots &in,
                                        const typename Store<ST>::S *__restrict__ emit, uint32_t idx, int x, int y,
@@ -1017,14 +1025,14 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
     P pc[19];
     S re[19], ro[19];
     constexpr bool PROD = SP >= 0 && (SP & SP_PRODUCT_FLAG) != 0;
-    // Emission reads gathered densely (see gather_emission) where the sweep
-    // is bound by vector-memory instructions: FP32 and FP64 storage, the
-    // UNIFORM and WEIGHTED modes (one emission value per interface node), no
-    // product lattice, and not in the batched sweep (GATHER_OK false): the
-    // gather measured 630 against 634 us for the 256^3 sweep, but 2216
-    // against 2166 us for the 64-sample batched sweep.
-    constexpr bool GATHER = GATHER_OK && SP >= 0 && sizeof(S) >= 4 && !PROD &&
-                            ((SP & 3) == SP_UNIFORM || (SP & 3) == SP_WEIGHTED);
+    // Emission reads gathered densely (see gather_emission) where the
+    // launch asks for it (GATHER_OK, the emission tunable) and the gather
+    // applies (gather_applies: FP32 and FP64 storage, the UNIFORM and
+    // WEIGHTED modes with one emission value per interface node, no product
+    // lattice).  It trades vector-memory loads for VALU work; which wins
+    // depends on the workload (630 against 634 us for the 256^3 sweep, 2216
+    // against 2166 us for the 64-sample batched sweep), so it is measured.
+    constexpr bool GATHER = GATHER_OK && gather_applies<ST, SP>();
     S pp[PROD ? 19 : 1], pe[PROD ? 19 : 1], po[PROD ? 19 : 1];
     const uint32_t nfpp_b = pk.in.stride, ownp_b = own_e * SB;  // product buffer: one population per element
     pc[0] = ld_pop<ST>(base(dslot(0)), own_b);
@@ -1655,11 +1663,11 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
     if constexpr (PROD) wave_partials<3>(accp, pk.part + int64_t(block) * 3);
 }
 
-template <int ST, int SP>
+template <int ST, int SP, bool G>
 __global__ __launch_bounds__(CTHREADS, ST == ST_F64 ? 1 : ((SP & SP_PRODUCT_FLAG) ? 3 : 5)) void k_sweep_c(
     Geometry g, PhysK<typename Store<ST>::T> ph, Slots in, OutSlots out,
     const typename Store<ST>::S *__restrict__ emit, double *__restrict__ part, ProdK<ST> pk) {
-    sweep_block_c<ST, SP>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))), pk);
+    sweep_block_c<ST, SP, G>(g, ph, in, out, emit, part, uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x))), pk);
 }
 
 template <int ST, int SP>
@@ -2177,14 +2185,14 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const SampleK<ST> *__restri
     sweep_block<ST, SP>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0);
 }
 
-template <int ST, int SP>
+template <int ST, int SP, bool G>
 __global__ __launch_bounds__(CTHREADS, ST == ST_F64 ? 1 : 5) void k_sweep_batch_c(const SampleK<ST> *__restrict__ smp,
                                                         const uint32_t *__restrict__ block_sample, int parity) {
     const uint32_t b = uint32_t(xcd_block(int(blockIdx.x), int(gridDim.x)));
     const SampleK<ST> &d = smp[__builtin_amdgcn_readfirstlane(block_sample[b])];
     const Slots &in = d.pop[parity];
     const OutSlots &out = reinterpret_cast<const OutSlots &>(d.pop[1 - parity]);
-    sweep_block_c<ST, SP, false>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0, ProdK<ST>{});
+    sweep_block_c<ST, SP, G>(d.g, d.ph, in, out, d.emit, d.part_sweep, b - d.block0, ProdK<ST>{});
 }
 
 template <int ST>
@@ -2353,6 +2361,10 @@ hipError_t launch_sweep(const Geometry &g, const Physics &ph, const void *fin, v
 
 int64_t sweep_blocks_c(const Geometry &g) { return (int64_t(g.nwaves) + 7) / 8 * 8; }
 
+bool emission_gather_applies(int storage, int sputter, bool product) {
+    return (storage == ST_F32 || storage == ST_F64) && !product && (sputter == SP_UNIFORM || sputter == SP_WEIGHTED);
+}
+
 hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin, void *fout, const void *emit,
                           double *part, hipStream_t s, const ProdStep *prod) {
     return dispatch(ph.storage, [&](auto st) {
@@ -2377,14 +2389,22 @@ hipError_t launch_sweep_c(const Geometry &g, const Physics &ph, const void *fin,
             pk.inacc = prod->inacc;
             pk.part = prod->part_sweep;
             return dispatch_sp_product(sweep_code(ph.sputter, ph.species_x), [&](auto sp) {
-                hipLaunchKernelGGL((k_sweep_c<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part,
-                                   pk);
+                hipLaunchKernelGGL((k_sweep_c<ST, decltype(sp)::value, false>), grid, block, 0, s, g, k, in, out, e,
+                                   part, pk);
                 return hipGetLastError();
             });
         }
+        const bool gather = ph.emission_gather != 0;
         auto go = [&](auto sp) {
-            hipLaunchKernelGGL((k_sweep_c<ST, decltype(sp)::value>), grid, block, 0, s, g, k, in, out, e, part,
-                               ProdK<ST>{});
+            constexpr int SP = decltype(sp)::value;
+            if constexpr (gather_applies<ST, SP>()) {
+                if (gather) {
+                    hipLaunchKernelGGL((k_sweep_c<ST, SP, true>), grid, block, 0, s, g, k, in, out, e, part,
+                                       ProdK<ST>{});
+                    return hipGetLastError();
+                }
+            }
+            hipLaunchKernelGGL((k_sweep_c<ST, SP, false>), grid, block, 0, s, g, k, in, out, e, part, ProdK<ST>{});
             return hipGetLastError();
         };
         if (ph.wall_diffuse != 0.0) return dispatch_sp_diffuse(sweep_code(ph.sputter, ph.species_x), go);
@@ -2550,16 +2570,23 @@ hipError_t batch_upload(int storage, const BatchSample *smp, int n, void *d_reco
     });
 }
 
-hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool compact, const void *d_records,
-                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, int parity, hipStream_t s) {
+hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool compact, bool gather,
+                              const void *d_records, const uint32_t *sweep_sample, int64_t sweep_blocks_total,
+                              int parity, hipStream_t s) {
     return dispatch(storage, [&](auto st) {
         constexpr int ST = decltype(st)::value;
         const SampleK<ST> *rec = static_cast<const SampleK<ST> *>(d_records);
         const dim3 grid(static_cast<unsigned>(sweep_blocks_total)), block(compact ? CTHREADS : 256u);
         return dispatch_sp(sweep_code(sputter, species_x), [&](auto sp) {
             constexpr int SP = decltype(sp)::value;
+            if constexpr (gather_applies<ST, SP>()) {
+                if (compact && gather) {
+                    hipLaunchKernelGGL((k_sweep_batch_c<ST, SP, true>), grid, block, 0, s, rec, sweep_sample, parity);
+                    return hipGetLastError();
+                }
+            }
             if (compact)
-                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP>), grid, block, 0, s, rec, sweep_sample, parity);
+                hipLaunchKernelGGL((k_sweep_batch_c<ST, SP, false>), grid, block, 0, s, rec, sweep_sample, parity);
             else
                 hipLaunchKernelGGL((k_sweep_batch<ST, SP>), grid, block, 0, s, rec, sweep_sample, parity);
             return hipGetLastError();
@@ -2567,7 +2594,7 @@ hipError_t launch_batch_sweep(int storage, int sputter, int species_x, bool comp
     });
 }
 
-hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compact, const void *d_records,
+hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compact, bool gather, const void *d_records,
                              const uint32_t *sweep_sample, int64_t sweep_blocks_total, const uint32_t *iface_sample,
                              int64_t iface_blocks_total, const ReduceK *d_reduce, int n, int parity, hipStream_t s,
                              hipEvent_t sweep_start, hipEvent_t sweep_stop) {
@@ -2582,8 +2609,8 @@ hipError_t launch_batch_step(int storage, int sputter, int species_x, bool compa
         }
         hipError_t e = sweep_start ? hipEventRecord(sweep_start, s) : hipSuccess;
         if (e != hipSuccess) return e;
-        e = launch_batch_sweep(storage, sputter, species_x, compact, d_records, sweep_sample, sweep_blocks_total,
-                               parity, s);
+        e = launch_batch_sweep(storage, sputter, species_x, compact, gather, d_records, sweep_sample,
+                               sweep_blocks_total, parity, s);
         if (e != hipSuccess) return e;
         e = sweep_stop ? hipEventRecord(sweep_stop, s) : hipSuccess;
         if (e != hipSuccess) return e;

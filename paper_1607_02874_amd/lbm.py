@@ -29,7 +29,7 @@ XBC_PERIODIC, XBC_RESERVOIR, XBC_INFLOW = 0, 1, 2
 STORE_F32, STORE_F16, STORE_BF16, STORE_F64 = 0, 1, 2, 3
 ROUND_NEAREST, ROUND_STOCHASTIC = 0, 1
 LATTICE_D3Q19, LATTICE_D2Q9 = 0, 1
-TUNE_YTILE, TUNE_SWEEP = 0, 1
+TUNE_YTILE, TUNE_SWEEP, TUNE_EMISSION = 0, 1, 2
 STORAGE_BYTES = {STORE_F32: 4, STORE_F16: 2, STORE_BF16: 2, STORE_F64: 8}
 STORAGE_NAMES = {STORE_F32: "f32", STORE_F16: "f16", STORE_BF16: "bf16", STORE_F64: "f64"}
 # Direction numbering of lbm_populations (as documented in include/lbm.h).

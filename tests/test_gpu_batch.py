@@ -66,6 +66,25 @@ def test_batch_bit_identical_to_single_samples(storage, sputter):
             assert b.totals(i)["step"] == steps
 
 
+def test_batch_emission_modes_agree_and_graphs_follow():
+    """LBM_TUNE_EMISSION on a batch (default 0, direct reads): with the
+    emission gather the batch gives the same bits, and a change after graphs
+    were captured discards them, so the replays use the new launch."""
+    samples = mixed_samples()
+    with lbm.Batch(samples) as a, lbm.Batch(samples, graph=True) as b:
+        assert a.get_tunable(lbm.TUNE_EMISSION) == 0
+        b.step(4)  # captures the step graphs with direct reads
+        b.set_tunable(lbm.TUNE_EMISSION, 1)
+        assert b.get_tunable(lbm.TUNE_EMISSION) == 1
+        with pytest.raises(lbm.LbmError) as e:
+            b.set_tunable(lbm.TUNE_EMISSION, -1)
+        assert e.value.status == lbm.LBM_EINVAL
+        b.step(8)
+        a.step(12)
+        for i in range(len(samples)):
+            assert_same(b, i, (a.fields(i), a.conversion_map(i), a.totals(i)))
+
+
 def test_batch_barycentric_periodic_matches_single():
     samples = mixed_samples(coupling=lbm.COUPLE_BARYCENTRIC, species_x=lbm.XBC_PERIODIC)
     for s in samples:
@@ -244,6 +263,7 @@ def test_batch_autotune_leaves_state_unchanged():
         assert a.autotune(reps=2) > 0
         b.set_tunable(lbm.TUNE_SWEEP, a.get_tunable(lbm.TUNE_SWEEP))
         b.set_tunable(lbm.TUNE_YTILE, a.get_tunable(lbm.TUNE_YTILE))
+        b.set_tunable(lbm.TUNE_EMISSION, a.get_tunable(lbm.TUNE_EMISSION))
         a.step(8)
         b.step(17)
         for i in range(len(samples)):

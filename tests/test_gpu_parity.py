@@ -426,10 +426,12 @@ def test_autotune_leaves_state_unchanged():
     ms = a.autotune(reps=2)
     assert ms > 0
     variant, ytile = a.get_tunable(lbm.TUNE_SWEEP), a.get_tunable(lbm.TUNE_YTILE)
+    emission = a.get_tunable(lbm.TUNE_EMISSION)
     a.step(10)
     b = make_sim(c, F32)
     b.set_tunable(lbm.TUNE_SWEEP, variant)
     b.set_tunable(lbm.TUNE_YTILE, ytile)
+    b.set_tunable(lbm.TUNE_EMISSION, emission)
     b.step(20)
     fa, fb = a.fields(), b.fields()
     assert all(np.array_equal(x, y) for x, y in zip(fa, fb))
@@ -440,6 +442,42 @@ def test_autotune_leaves_state_unchanged():
         assert abs(ta[k] - tb[k]) <= 1e-12 * max(abs(tb[k]), abs(tb["mass_gas"])), k
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("storage,sputter,species_x", [(F32, "UNIFORM", "RESERVOIR"), (F32, "WEIGHTED", "INFLOW"),
+                                                       (F64, "UNIFORM", "PERIODIC"), (F64, "WEIGHTED", "RESERVOIR")])
+def test_emission_read_modes_are_bit_identical(storage, sputter, species_x):
+    """LBM_TUNE_EMISSION: the compact sweep's emission reads gathered through
+    LDS (1, a context's default) and read once per direction (0) give the same
+    state bit for bit.  The 32^3 sample's wavefronts take the gather; the
+    random geometry (30 % catalytic voxels, about 300 sources per wavefront)
+    takes the direct fallback; the last wavefront of each has idle lanes."""
+    from paper_1607_02874_amd import lbm
+
+    rng = np.random.default_rng(5)
+    ragged = np.where(rng.random((5, 6, 70)) < 0.3, 2, 0).astype(np.uint8)
+    ragged[:, :, 0] = 0
+    for vox in (PLAIN.voxels(), ragged):
+        c = case(vox, 15, da=0.5, tau=(0.8, 0.7), pore_size=3.0, force=(2e-5, 1e-6, 0.0), p_stick=0.8, c0=0.2,
+                 sputter=sputter, species_x=species_x)
+        runs = []
+        for mode in (1, 0):
+            print(f"emission mode {mode} storage {storage} {sputter} {species_x} {vox.shape}", flush=True)
+            s = make_sim(c, storage)
+            assert s.get_tunable(lbm.TUNE_EMISSION) == 1
+            s.set_tunable(lbm.TUNE_EMISSION, mode)
+            assert s.get_tunable(lbm.TUNE_EMISSION) == mode
+            s.step(15)
+            runs.append((s.fields(), s.conversion_map(), s.totals()))
+            if mode == 0:
+                with pytest.raises(lbm.LbmError) as e:
+                    s.set_tunable(lbm.TUNE_EMISSION, 2)
+                assert e.value.status == lbm.LBM_EINVAL
+            s.close()
+        (fa, ca, ta), (fb, cb, tb) = runs
+        assert all(np.array_equal(x, y) for x, y in zip(fa, fb))
+        assert np.array_equal(ca, cb)
+        assert ta == tb
 
 
 @pytest.mark.parametrize("c_inlet,c0", [(1000.0, 200.0), (1e-6, 0.0), (0.0, 0.0)])
