@@ -26,7 +26,7 @@ thread_local std::string g_create_error;
 
 constexpr double CS = 0.57735026918962576451;  // lattice sound speed 1/sqrt(3)
 constexpr int TIMING_RING = 512;
-constexpr uint64_t CKPT_MAGIC = 0x3747504b434d424cull;  // "LBMCKPG7"
+constexpr uint64_t CKPT_MAGIC = 0x3847504b434d424cull;  // "LBMCKPG8"
 
 struct StepEvents {
     hipEvent_t ev[8];  // start/stop of the front launch, xflux, sweep, closing reduction
@@ -494,6 +494,7 @@ lbm_status validate(const lbm_geometry *g, double kn, double da, const double ta
     if (!(bc->c0 >= 0.0) || !std::isfinite(bc->c0)) return fail(nullptr, LBM_EINVAL, "c0 must be >= 0");
     if (!(bc->rho0 > 0.0) || !std::isfinite(bc->rho0)) return fail(nullptr, LBM_EINVAL, "rho0 must be > 0");
     if (!std::isfinite(bc->c_ref)) return fail(nullptr, LBM_EINVAL, "c_ref must be finite");
+    if (!(std::fabs(bc->store_ux) < 0.2)) return fail(nullptr, LBM_EINVAL, "store_ux must satisfy |store_ux| < 0.2");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(bc->force[a])) return fail(nullptr, LBM_EINVAL, "force must be finite");
     if (!(kn >= 0.0) || !std::isfinite(kn)) return fail(nullptr, LBM_EINVAL, "kn must be finite and >= 0");
@@ -894,6 +895,8 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.c0 = bc->c0;
     c->ph.c_inlet = bc->species_x != LBM_XBC_PERIODIC ? bc->c_inlet : 0.0;
     c->ph.rho_ref = bc->rho0;
+    // the reference flow of the carrier's stored deviations: 16-bit storage only
+    c->ph.store_ux = storage_bytes(bc->storage) == 2 && bc->lattice == LBM_LATTICE_D3Q19 ? bc->store_ux : 0.0;
     // Species populations are stored unshifted by default (c_ref = 0): the
     // concentration is depleted next to the catalyst, and a shift would cost
     // relative precision exactly where the conversion is decided.
@@ -1524,7 +1527,7 @@ lbm_status lbm_kernel_times(lbm_ctx *c, lbm_kernel_times_t *t) {
 }
 
 namespace {
-constexpr int NPARAMS = 20;
+constexpr int NPARAMS = 21;
 
 struct CkptHeader {
     uint64_t magic;
@@ -1558,6 +1561,7 @@ void pack_params(const lbm_ctx *c, double *p) {
     p[18] = c->ph.wall_diffuse;
     // 16-bit storage: the rounding of the stores (FP32 and FP64 ignore it)
     p[19] = storage_bytes(c->ph.storage) == 2 ? c->ph.rounding : 0;
+    p[20] = c->ph.store_ux;  // the stored carrier deviations depend on it
 }
 
 // Product-lattice bytes of a checkpoint: P buffers A and B, E_P, Acc_P.

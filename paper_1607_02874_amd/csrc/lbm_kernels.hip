@@ -137,6 +137,7 @@ struct PhysK {
     T a_r, a_p;       // product re-emission: p p_S^R of the reactant, 1 - p_S^P of the product
     T sigma;          // diffuse fraction of the carrier's wall reflection
     T h0c, h0r;       // initial state, normalised: rho0 - rho_ref, c0 - c_ref
+    T us3;            // 16-bit storage: the carrier stores h_i - c_ix us3 (3 store_ux; 0 otherwise)
     double c_in;      // reservoir concentration (influx tally)
     double in_scale, in_unscale;  // fixed-point scale of the In(k) sums and its inverse
     int32_t sputter, coupling, species_x;
@@ -164,6 +165,7 @@ PhysK<T> to_kernel(const Physics &p) {
     k.sigma = T(p.wall_diffuse);
     k.h0c = T(p.rho0 - p.rho_ref);
     k.h0r = T(p.c0 - p.c_ref);
+    k.us3 = T(3.0 * p.store_ux);
     k.c_in = p.c_inlet;
     k.in_scale = p.in_scale;
     k.in_unscale = p.in_unscale;
@@ -444,6 +446,42 @@ __device__ __forceinline__ void diffuse_wall(T sigma, uint32_t solid_bits, T (&h
         if ((solid_bits >> i) & 1u) hC[i] = hC[i] + sigma * (mh - hC[i]);
 }
 
+// Reference flow of the carrier's 16-bit storage: slot i stores
+// h_i - c_ix us3 (us3 = 3 store_ux, the part of the equilibrium deviation
+// linear in a reference x-velocity), so a flow near that velocity stores
+// small values.  After a pull, direction i holds population i of the source
+// (stored less c_ix us3) or, where the source is solid, the node's own
+// opp(i) (stored less -c_ix us3): the term is added back with the sign the
+// source gives.  Uniform branches: nothing runs when us3 is 0, and FP32 and
+// FP64 storage never shift.
+template <int ST>
+__device__ __forceinline__ void carrier_unshift(const PhysK<typename Store<ST>::T> &ph, uint32_t solid_bits,
+                                                typename Store<ST>::T (&hC)[19]) {
+    using T = typename Store<ST>::T;
+    if constexpr (Store<ST>::ROUNDS) {
+        if (ph.us3 != T(0)) {
+#pragma unroll
+            for (int i = 1; i < 19; ++i) {
+                if (CX[i] == 0) continue;
+                const T a = T(CX[i]) * ph.us3;
+                hC[i] += ((solid_bits >> i) & 1u) ? -a : a;
+            }
+        }
+    }
+}
+// ... and the term taken off before the carrier's own populations are stored
+template <int ST>
+__device__ __forceinline__ void carrier_shift(const PhysK<typename Store<ST>::T> &ph, typename Store<ST>::T (&hC)[19]) {
+    using T = typename Store<ST>::T;
+    if constexpr (Store<ST>::ROUNDS) {
+        if (ph.us3 != T(0)) {
+#pragma unroll
+            for (int i = 1; i < 19; ++i)
+                if (CX[i] != 0) hC[i] -= T(CX[i]) * ph.us3;
+        }
+    }
+}
+
 // The product lattice as the sweep sees it: P population buffers (one
 // population per element, same slot order as the pair buffers), E_P(k),
 // In_P(k) and the sweep's three P partials per block.
@@ -622,6 +660,7 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
+    carrier_unshift<ST>(ph, solid_bits, hC);
     if (diffuse && solid_bits != 0u) diffuse_wall(ph.sigma, solid_bits, hC);
     if (inflow && first_chunk && lane_in(lane0)) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
@@ -1117,6 +1156,7 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
     if constexpr (PROD) hP[0] = Store<ST>::cv(pp[0]);
+    carrier_unshift<ST>(ph, solid_bits, hC);
     if (diffuse && solid_bits != 0u) diffuse_wall(ph.sigma, solid_bits, hC);
     if (inflow && __builtin_amdgcn_ballot_w64(first_x) != 0u && first_x) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
@@ -1506,6 +1546,7 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
                 if (CX[i] == 1) acc[2] += double(wgt<T>(i) * (hR[i] + ph.cref));
         }
         collide(ph, m, hC, hR);
+        carrier_shift<ST>(ph, hC);
         using P = typename Store<ST>::P;
         uint32_t own_b = node_elem(g, u.idx) * uint32_t(sizeof(P));
         const lbmfx::RoundWords rw = lbmfx::round_words(ph.sr != 0u, ph.sr_key, u.idx);
@@ -1599,6 +1640,7 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
                 if (CX[i] == 1) acc[2] += double(wgt<T>(i) * (hR[i] + ph.cref));
         }
         collide(ph, m, hC, hR);
+        carrier_shift<ST>(ph, hC);
         using P = typename Store<ST>::P;
         const uint32_t own_e = node_elem(g, idx);
         uint32_t own_b = own_e * uint32_t(sizeof(P));
@@ -1698,6 +1740,7 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
                 hC[i] = Store<ST>::cv(v.x);
                 hR[i] = Store<ST>::cv(v.y);
             }
+            carrier_unshift<ST>(ph, 0u, hC);  // slot i holds the node's own population i
         } else {
             uint32_t cat_bits;
             pull<ST, -1>(g, ph, in, emit, u, hC, hR, cat_bits);
@@ -1745,10 +1788,16 @@ __global__ __launch_bounds__(256) void k_init(Geometry g, PhysK<typename Store<S
     for (int i = 0; i < 19; ++i) {
         hC[i] = ph.h0c;
         hR[i] = ph.h0r;
-        pre2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(hC[i], hR[i]);
     }
+    T sC[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) sC[i] = hC[i];
+    carrier_shift<ST>(ph, sC);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) pre2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(sC[i], hR[i]);
     const Mom<T> m = moments(ph, hC, hR);
     collide(ph, m, hC, hR);
+    carrier_shift<ST>(ph, hC);
 #pragma unroll
     for (int i = 0; i < 19; ++i) post2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(hC[i], hR[i]);
 }
@@ -1864,6 +1913,7 @@ __global__ __launch_bounds__(256) void k_populations(Geometry g, PhysK<typename 
                 hC[i] = Store<ST>::cv(v.x);
                 hR[i] = Store<ST>::cv(v.y);
             }
+            carrier_unshift<ST>(ph, 0u, hC);  // slot i holds the node's own population i
         } else {
             uint32_t cat_bits;
             pull<ST, -1>(g, ph, in, emit, u, hC, hR, cat_bits);

@@ -56,7 +56,7 @@ class lbm_bc(ctypes.Structure):
                 ("force", ctypes.c_double * 3), ("product", ctypes.c_int32), ("rounding", ctypes.c_int32),
                 ("p_stick_product", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("wall_diffuse", ctypes.c_double), ("wall_accommodation", ctypes.c_double),
-                ("lattice", ctypes.c_int32), ("reserved_bc", ctypes.c_int32)]
+                ("lattice", ctypes.c_int32), ("reserved_bc", ctypes.c_int32), ("store_ux", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -229,11 +229,11 @@ def _geometry(vox, pore_size):
 def _bc(sputter=SPUTTER_UNIFORM, coupling=COUPLE_PASSIVE, species_x=XBC_RESERVOIR, storage=STORE_F32,
         p_stick=0.95, c_inlet=1.0, rho0=1.0, c0=0.0, c_ref=-1.0, force=(0.0, 0.0, 0.0), product=False,
         p_stick_product=0.0, seed=0, wall_diffuse=0.0, rounding=ROUND_NEAREST, wall_accommodation=0.0,
-        lattice=LATTICE_D3Q19):
+        lattice=LATTICE_D3Q19, store_ux=0.0):
     return lbm_bc(int(sputter), int(coupling), int(species_x), int(storage), float(p_stick), float(c_inlet),
                   float(rho0), float(c0), float(c_ref), (ctypes.c_double * 3)(*[float(f) for f in force]),
                   int(bool(product)), int(rounding), float(p_stick_product), int(seed), float(wall_diffuse),
-                  float(wall_accommodation), int(lattice), 0)
+                  float(wall_accommodation), int(lattice), 0, float(store_ux))
 
 
 def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc_kw):
@@ -241,7 +241,7 @@ def lbm_create(vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, device=None, **bc
     lbm_device struct holder (see use_torch) or None for hipMalloc and the
     null stream; bc_kw are the lbm_bc fields (sputter, coupling, species_x,
     storage, p_stick, c_inlet, rho0, c0, c_ref, force, product,
-    p_stick_product, seed, wall_diffuse, rounding, wall_accommodation, lattice).  Returns the raw
+    p_stick_product, seed, wall_diffuse, rounding, wall_accommodation, lattice, store_ux).  Returns the raw
     context handle."""
     vox, g = _geometry(vox, pore_size)
     bc = _bc(**bc_kw)
@@ -274,6 +274,8 @@ class Sim:
     wall) or wall_accommodation=sigma_v (the diffuse fraction derived from Kn
     for Maxwell's slip; info()["wall_sigma"] reports it),
     rounding=ROUND_STOCHASTIC (stochastic rounding of 16-bit stores),
+    store_ux=U (16-bit storage: the carrier stores its deviation less the
+    part linear in a reference x-velocity U),
     lattice=LATTICE_D2Q9 (the paper's D2Q9 on one plane, FP64; see lbm.h)."""
 
     def __init__(self, vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, use_torch=True, stream=None, **kw):

@@ -39,7 +39,8 @@ def make_sim(c, storage):
     return lbm.Sim(c["vox"], da=c["da"], tau=c["tau"], pore_size=c["pore_size"], p_stick=c["p_stick"],
                    c_inlet=c["c_inlet"], c0=c["c0"], rho0=c["rho0"], force=c["force"],
                    sputter=SPUTTER[c["sputter"]], coupling=COUPLING[c["coupling"]],
-                   species_x=XBC[c["species_x"]], storage=storage, rounding=c.get("rounding", NEAREST))
+                   species_x=XBC[c["species_x"]], storage=storage, rounding=c.get("rounding", NEAREST),
+                   store_ux=c.get("store_ux", 0.0))
 
 
 def run_gpu(c, storage):
@@ -89,6 +90,11 @@ def errors(gpu, ref, vox):
     for k in ("rho", "conc"):
         e[k + "_solid_zero"] = bool((gpu[k][~gas] == 0).all())
     return e
+
+
+def mean_ux(gpu, vox):
+    """Mean x-velocity over the gas nodes of a run's output."""
+    return float(gpu["u"][0][vox == inputs.FLUID].mean())
 
 
 def totals_rel(gpu, ref):

@@ -20,7 +20,7 @@ def test_every_declared_function_is_exported():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_geometry) == 32
-    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(lbm.lbm_bc) == 16 + 5 * 8 + 24 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lbm.lbm_totals_t) == 8 + 6 * 8 + 8 + 4 * 8
     assert ctypes.sizeof(lbm.lbm_device) == 32
 
@@ -79,6 +79,8 @@ def _create(vox, **kw):
     (dict(product=True, p_stick_product=-0.1), "p_stick_product"),
     (dict(wall_diffuse=1.5), "wall_diffuse"),
     (dict(wall_diffuse=-0.5), "wall_diffuse"),
+    (dict(storage=1, store_ux=0.25), "store_ux"),
+    (dict(storage=2, store_ux=float("nan")), "store_ux"),
 ])
 def test_invalid_parameters_are_rejected(kw, msg):
     vox = np.zeros((4, 4, 8), np.uint8)

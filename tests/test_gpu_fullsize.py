@@ -216,6 +216,48 @@ def test_membrane_column_crop_matches_oracle(column_ref, storage, rounding):
         assert e[k] < bar, (k, e[k])
 
 
+# Measured with the reference flow: BF16 with stochastic rounding meets the
+# target (u 9.2e-4 from 1.07e-3, conc 9.8e-4); with rounding to nearest the
+# shift cuts FP16's u from 1.28e-2 to 4.2e-3, but the unshifted reactant keeps
+# conc at 5.5e-3.
+SHIFT_MISS = {
+    (F16, 0): "FP16, nearest, reference flow: u 4.2e-3 (from 1.28e-2), conc 5.5e-3 (reactant not shifted)",
+    (BF16, 0): "BF16, nearest, reference flow: u 5.7e-2, conc 1.0e-2",
+}
+
+
+def _shift_param(storage, rounding):
+    miss = SHIFT_MISS.get((storage, rounding))
+    marks = [pytest.mark.xfail(reason=miss, strict=False)] if miss else []
+    return pytest.param(storage, rounding, marks=marks, id=f"s{storage}-r{rounding}")
+
+
+@pytest.mark.parametrize("storage,rounding", [_shift_param(F16, 0), _shift_param(BF16, 1), _shift_param(BF16, 0)])
+def test_membrane_column_with_reference_flow(column_ref, storage, rounding):
+    """The column with the carrier's 16-bit storage shifted by a reference
+    flow (store_ux: the FP32 path's mean x-velocity over the gas nodes): in
+    the free gas the stored carrier deviations are then nearly zero."""
+    from parity import errors, mean_ux
+
+    w = inputs.MEMBRANE_1024
+    vox, steps, ref = column_ref
+    kw = dict(da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick, c_inlet=w.c_inlet,
+              c0=w.c_inlet)
+    with lbm.Sim(vox, **kw) as s:
+        s.step(steps)
+        ux = mean_ux(dict(u=s.fields()[1]), vox)
+    assert 0.0 < ux < 0.1
+    with lbm.Sim(vox, storage=storage, rounding=rounding, store_ux=ux, **kw) as s:
+        s.step(steps)
+        rho, u, conc = s.fields()
+        gpu = dict(rho=rho, u=u, conc=conc, conv=s.conversion_map())
+    e = errors(gpu, ref, vox)
+    print("membrane column, reference flow", storage, rounding, f"store_ux {ux:.4g}",
+          {k: f"{v:.2e}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < 1e-3, (k, e[k])
+
+
 def test_membrane_1024x512x512_sampled_boxes_one_step(vox_membrane):
     """The largest single-GPU case (268 M nodes, FP32): boxes across the
     porous layer x in [384, 640)."""

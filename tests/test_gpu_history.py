@@ -21,7 +21,7 @@ import pytest
 import oracle
 from paper_1607_02874_amd import inputs, lbm
 
-from parity import errors
+from parity import errors, mean_ux
 
 pytestmark = pytest.mark.gpu
 
@@ -40,9 +40,9 @@ def _run_oracle(vox, w, da, steps):
     return out
 
 
-def _run_gpu(vox, w, da, steps, storage=F32, rounding=NEAREST):
+def _run_gpu(vox, w, da, steps, storage=F32, rounding=NEAREST, store_ux=0.0):
     with lbm.Sim(vox, da=da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
-                 c_inlet=w.c_inlet, storage=storage, rounding=rounding) as s:
+                 c_inlet=w.c_inlet, storage=storage, rounding=rounding, store_ux=store_ux) as s:
         s.step(steps)
         rho, u, conc = s.fields()
         return dict(rho=rho, u=u, conc=conc, conv=s.conversion_map(), p=s.info()["p"])
@@ -119,3 +119,30 @@ def test_precision_workload_crop(crop128, storage, rounding):
         _report(f"128^3 crop of the 512^3 geometry, {steps} steps vs {label}, storage {storage} r{rounding}", e)
         for k in ("rho", "u", "conc", "conv"):
             assert e[k] < bar, (steps, k, e[k])
+
+
+# The same crop with the carrier's 16-bit storage shifted by a reference flow
+# (store_ux: the mean x-velocity of the FP32 path after 300 steps).  Here the
+# mean flow is slow (0.0029) and the shift gains little for BF16 (measured).
+SHIFT_MISS = {
+    (BF16, STOCHASTIC): "BF16, stochastic rounding, reference flow: u 1.07e-3 after 300 steps (1.22e-3 unshifted)",
+    (BF16, NEAREST): "BF16, nearest, reference flow: u 4.4e-3, conc 2.4e-3 after 300 steps",
+}
+
+
+def _ps(storage, rounding):
+    miss = SHIFT_MISS.get((storage, rounding))
+    marks = [pytest.mark.xfail(reason=miss, strict=False)] if miss else []
+    return pytest.param(storage, rounding, marks=marks, id=f"s{storage}-r{rounding}")
+
+
+@pytest.mark.parametrize("storage,rounding", [_ps(F16, NEAREST), _ps(BF16, STOCHASTIC), _ps(BF16, NEAREST)])
+def test_precision_workload_crop_with_reference_flow(crop128, storage, rounding):
+    w, vox, ref300, ref1000 = crop128
+    ux = mean_ux(_run_gpu(vox, w, w.da, 300), vox)
+    assert 0.0 < ux < 0.05
+    for steps, ref, label in ((300, ref300, "oracle"), (w.steps, ref1000, "FP64 build")):
+        e = errors(_run_gpu(vox, w, w.da, steps, storage, rounding, ux), ref, vox)
+        _report(f"128^3 crop, {steps} steps vs {label}, storage {storage} r{rounding}, store_ux {ux:.4g}", e)
+        for k in ("rho", "u", "conc", "conv"):
+            assert e[k] < 1e-3, (steps, k, e[k])

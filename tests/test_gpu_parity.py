@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_1607_02874_amd import inputs
 
-from parity import NEAREST, STOCHASTIC, case, errors, make_sim, run_gpu, run_oracle, totals_rel
+from parity import NEAREST, STOCHASTIC, case, errors, make_sim, mean_ux, run_gpu, run_oracle, totals_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -88,6 +88,67 @@ def test_plain_16bit_storage_error(plain_ref, storage, rounding):
     _report(f"{ {F16: 'f16', BF16: 'bf16'}[storage]} rounding {rounding}", e)
     for k in ("rho", "u", "conc"):
         assert e[k] < 1e-3, (k, e[k])
+
+
+# The carrier's 16-bit storage with a reference flow (store_ux): the stored
+# deviations lose the part linear in the mean x-velocity, which dominates
+# them in the directions along the flow, so their rounding errors shrink.
+# The reference velocity is the FP32 path's own mean over the gas nodes, as
+# a user would take it from an FP32 run.
+# Measured: BF16 with stochastic rounding u 7.9e-4 (from 1.23e-3), conc
+# 9.1e-4.  With rounding to nearest the reactant lattice, which the shift
+# leaves alone, still misses.
+@pytest.mark.parametrize("storage,rounding", [
+    (F16, NEAREST), (F16, STOCHASTIC),
+    pytest.param(BF16, NEAREST, marks=pytest.mark.xfail(
+        reason="BF16, nearest: conc 1.28e-3 (the reactant is not shifted; u 6.5e-4)", strict=False)),
+    (BF16, STOCHASTIC)])
+def test_plain_16bit_storage_with_reference_flow(plain_ref, storage, rounding):
+    c, ref = plain_ref
+    ux = mean_ux(run_gpu(c, F32), c["vox"])
+    assert 0.0 < ux < 0.05
+    gpu = run_gpu(dict(c, rounding=rounding, store_ux=ux), storage)
+    e = errors(gpu, ref, c["vox"])
+    _report(f"{ {F16: 'f16', BF16: 'bf16'}[storage]} rounding {rounding}, store_ux {ux:.4g}", e)
+    for k in ("rho", "u", "conc"):
+        assert e[k] < 1e-3, (k, e[k])
+
+
+def test_reference_flow_is_ignored_by_fp32_and_fp64():
+    c = plain_case(steps=30)
+    for storage in (F32, F64):
+        a, b = run_gpu(c, storage), run_gpu(dict(c, store_ux=0.05), storage)
+        for k in ("rho", "u", "conc", "conv"):
+            assert np.array_equal(a[k], b[k]), (storage, k)
+
+
+def test_reference_flow_checkpoint(tmp_path):
+    """A 16-bit run with a reference flow resumes bit for bit from its
+    checkpoint; a context with another reference flow refuses it (its
+    stored deviations mean other populations)."""
+    from paper_1607_02874_amd import lbm
+
+    c = dict(plain_case(steps=30), store_ux=0.01)
+    whole = make_sim(c, F16)
+    whole.step(30)
+    want = whole.fields()
+    whole.close()
+    first = make_sim(c, F16)
+    first.step(12)
+    first.save(tmp_path / "ck.bin")
+    first.close()
+    second = make_sim(c, F16)
+    second.load(tmp_path / "ck.bin")
+    second.step(18)
+    got = second.fields()
+    second.close()
+    for a, b in zip(want, got):
+        assert np.array_equal(a, b)
+    other = make_sim(dict(c, store_ux=0.0), F16)
+    with pytest.raises(lbm.LbmError) as e:
+        other.load(tmp_path / "ck.bin")
+    assert e.value.status == lbm.LBM_EINVAL
+    other.close()
 
 
 def test_geometry_bookkeeping_is_exact(plain_ref):
