@@ -502,14 +502,16 @@ void lbm_destroy(lbm_ctx *c);
  * lbm_batch_create - n >= 1 samples; sample i takes g[i], kn[i] (kn may be
  *       NULL: all "not given"), da[i], tau[i] and bc[i] with the meaning of
  *       lbm_create.  bc[i].storage, .sputter, .coupling and .species_x must
- *       be equal for all samples (LBM_EINVAL otherwise).  dev as in
+ *       be equal for all samples (LBM_EINVAL otherwise); the other fields,
+ *       store_ux included, may differ.  dev as in
  *       lbm_create_on; every sample and the batch use its stream.  A failed
  *       create releases everything, sets *out = NULL and leaves a message
  *       naming the sample in lbm_batch_last_error(NULL).
  * lbm_batch_step - advance every sample n >= 0 steps (asynchronous).  With
- *       graphs enabled (lbm_batch_set_graph) pairs of steps replay one
- *       captured HIP graph.  LBM_ENONFINITE as for lbm_step, with the sample
- *       named in the message.
+ *       graphs enabled (lbm_batch_set_graph) the steps replay captured HIP
+ *       graphs: a 64-step loop while at least 64 steps remain, then a 2-step
+ *       loop, and an odd last step launched directly.  LBM_ENONFINITE as for
+ *       lbm_step, with the sample named in the message.
  * lbm_batch_fields / _conversion_map / _totals / _query - lbm_fields,
  *       lbm_conversion_map, lbm_totals and lbm_query of sample i
  *       (0 <= i < n, LBM_EINVAL otherwise).

@@ -66,6 +66,18 @@ def test_batch_bit_identical_to_single_samples(storage, sputter):
             assert b.totals(i)["step"] == steps
 
 
+def test_batch_reference_flow_per_sample():
+    """16-bit samples with different reference flows (lbm_bc.store_ux) in
+    one batch step exactly as they do alone."""
+    samples = mixed_samples(storage=BF16)
+    for smp, ux in zip(samples, (0.0, 0.01, 0.02, -0.005, 0.004)):
+        smp["store_ux"] = ux
+    with lbm.Batch(samples) as b:
+        b.step(17)
+        for i, smp in enumerate(samples):
+            assert_same(b, i, single(smp, 17))
+
+
 def test_batch_emission_modes_agree_and_graphs_follow():
     """LBM_TUNE_EMISSION on a batch (default 0, direct reads): with the
     emission gather the batch gives the same bits, and a change after graphs
