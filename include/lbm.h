@@ -92,8 +92,8 @@ typedef enum { LBM_XBC_PERIODIC = 0, LBM_XBC_RESERVOIR = 1, LBM_XBC_INFLOW = 2 }
  * h_i = f_i / w_i - rho_ref of each population from the rest equilibrium of
  * the reference density (rho_ref = rho0 for the carrier, c_ref for the
  * species).  F32, F16 and BF16 compute in FP32; F64 stores and computes in
- * FP64 (a reference build).  16-bit formats round as lbm_bc.rounding says;
- * their carrier deviation can also drop a reference flow (lbm_bc.store_ux). */
+ * FP64 (a reference build).  16-bit formats round as lbm_bc.rounding says.
+ * The carrier's deviation can also drop a reference flow (lbm_bc.store_ux). */
 typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2, LBM_STORE_F64 = 3 } lbm_storage;
 
 /* Rounding of 16-bit stores (F16, BF16; FP32 and FP64 storage ignore it).
@@ -188,18 +188,21 @@ typedef struct {
                                  wall_diffuse */
     int32_t lattice;          /* lbm_lattice (0 = D3Q19) */
     int32_t reserved_bc;      /* must be 0 */
-    double store_ux;          /* 16-bit storage: x-velocity U of the carrier's
-                                 storage reference, |U| < 0.2 (LBM_EINVAL
-                                 otherwise).  The carrier stores
+    double store_ux;          /* reference flow: x-velocity U, |U| < 0.2
+                                 (LBM_EINVAL otherwise).  The carrier is
+                                 stored and relaxed in the shifted form
                                  h_i = f_i / w_i - rho_ref - 3 c_ix U: its
                                  deviation from the rest equilibrium minus the
-                                 part linear in U, so in a flow with mean
-                                 x-velocity near U the stored values, and with
-                                 them their rounding errors, shrink.  The
-                                 arithmetic and every result are the same for
-                                 any U up to that rounding.  0 = unshifted.
-                                 Ignored by FP32 and FP64 storage and by the
-                                 D2Q9 lattice */
+                                 part linear in U (the equilibrium takes the
+                                 same shift, the moments add U back).  In a
+                                 flow with mean x-velocity near U the values
+                                 stored and computed, and with them their
+                                 rounding errors, shrink; the results are the
+                                 same for any U up to that rounding.  0 =
+                                 unshifted.  FP16, BF16 and FP64 storage;
+                                 ignored by FP32 storage (whose sweep has no
+                                 registers to spare for it) and by the D2Q9
+                                 lattice */
 } lbm_bc;
 
 /* Optional device hooks.  stream: a hipStream_t all work is queued on

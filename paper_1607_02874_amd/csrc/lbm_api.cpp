@@ -895,8 +895,9 @@ lbm_status lbm_create_on(const lbm_geometry *g, double kn, double da, const doub
     c->ph.c0 = bc->c0;
     c->ph.c_inlet = bc->species_x != LBM_XBC_PERIODIC ? bc->c_inlet : 0.0;
     c->ph.rho_ref = bc->rho0;
-    // the reference flow of the carrier's stored deviations: 16-bit storage only
-    c->ph.store_ux = storage_bytes(bc->storage) == 2 && bc->lattice == LBM_LATTICE_D3Q19 ? bc->store_ux : 0.0;
+    // the reference flow of the carrier's shifted form (D3Q19; not with FP32
+    // storage, whose sweep has no registers to spare for it)
+    c->ph.store_ux = bc->lattice == LBM_LATTICE_D3Q19 && bc->storage != LBM_STORE_F32 ? bc->store_ux : 0.0;
     // Species populations are stored unshifted by default (c_ref = 0): the
     // concentration is depleted next to the catalyst, and a shift would cost
     // relative precision exactly where the conversion is decided.
@@ -1561,7 +1562,7 @@ void pack_params(const lbm_ctx *c, double *p) {
     p[18] = c->ph.wall_diffuse;
     // 16-bit storage: the rounding of the stores (FP32 and FP64 ignore it)
     p[19] = storage_bytes(c->ph.storage) == 2 ? c->ph.rounding : 0;
-    p[20] = c->ph.store_ux;  // the stored carrier deviations depend on it
+    p[20] = c->ph.store_ux;  // the stored carrier values depend on it
 }
 
 // Product-lattice bytes of a checkpoint: P buffers A and B, E_P, Acc_P.

@@ -120,7 +120,7 @@ struct Physics {
     uint64_t seed;                // STOCHASTIC: Philox key
     uint32_t step_ctr;            // STOCHASTIC: step whose collision produces the arrivals a launch sums
     uint32_t emission_gather;     // 1: the compact sweep gathers emission reads through LDS where that applies
-    double store_ux;              // 16-bit storage: the carrier stores h_i - 3 c_ix store_ux (0 otherwise)
+    double store_ux;              // the carrier is stored and relaxed as h_i - 3 c_ix store_ux (D3Q19; 0 with FP32 storage)
 };
 
 // Device buffers of the product lattice for one step (all null / unused when

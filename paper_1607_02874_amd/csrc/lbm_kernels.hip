@@ -137,7 +137,7 @@ struct PhysK {
     T a_r, a_p;       // product re-emission: p p_S^R of the reactant, 1 - p_S^P of the product
     T sigma;          // diffuse fraction of the carrier's wall reflection
     T h0c, h0r;       // initial state, normalised: rho0 - rho_ref, c0 - c_ref
-    T us3;            // 16-bit storage: the carrier stores h_i - c_ix us3 (3 store_ux; 0 otherwise)
+    T usx, us3;       // reference flow U of the carrier's shifted form (store_ux) and 3 U
     double c_in;      // reservoir concentration (influx tally)
     double in_scale, in_unscale;  // fixed-point scale of the In(k) sums and its inverse
     int32_t sputter, coupling, species_x;
@@ -165,6 +165,7 @@ PhysK<T> to_kernel(const Physics &p) {
     k.sigma = T(p.wall_diffuse);
     k.h0c = T(p.rho0 - p.rho_ref);
     k.h0r = T(p.c0 - p.c_ref);
+    k.usx = T(p.store_ux);
     k.us3 = T(3.0 * p.store_ux);
     k.c_in = p.c_inlet;
     k.in_scale = p.in_scale;
@@ -446,39 +447,45 @@ __device__ __forceinline__ void diffuse_wall(T sigma, uint32_t solid_bits, T (&h
         if ((solid_bits >> i) & 1u) hC[i] = hC[i] + sigma * (mh - hC[i]);
 }
 
-// Reference flow of the carrier's 16-bit storage: slot i stores
-// h_i - c_ix us3 (us3 = 3 store_ux, the part of the equilibrium deviation
-// linear in a reference x-velocity), so a flow near that velocity stores
-// small values.  After a pull, direction i holds population i of the source
-// (stored less c_ix us3) or, where the source is solid, the node's own
-// opp(i) (stored less -c_ix us3): the term is added back with the sign the
-// source gives.  Uniform branches: nothing runs when us3 is 0, and FP32 and
-// FP64 storage never shift.
-template <int ST>
-__device__ __forceinline__ void carrier_unshift(const PhysK<typename Store<ST>::T> &ph, uint32_t solid_bits,
-                                                typename Store<ST>::T (&hC)[19]) {
-    using T = typename Store<ST>::T;
-    if constexpr (Store<ST>::ROUNDS) {
-        if (ph.us3 != T(0)) {
+// Reference flow of the carrier (lbm_bc.store_ux = U): the carrier is stored
+// and relaxed in the shifted form h'_i = h_i - 3 c_ix U, its deviation less
+// the part of the equilibrium linear in a reference x-velocity.  In a flow
+// near U these values are small, so their rounding (storage and arithmetic)
+// is too.  The form is exact algebra: sum_i w_i h'_i = sum_i w_i h_i and
+// sum_i w_i c_ix h'_i = sum_i w_i c_ix h_i - U (moments add U back), and
+// the equilibrium takes the same shift (collide).  Uniform branches: nothing
+// runs when U is 0.  FP32 storage takes no reference flow (the host keeps U
+// at 0 there), so its pulls carry none of this code.
+//
+// After a pull, direction i holds population i of a gas source (already in
+// the shifted form of direction i) or, where the source is solid, the node's
+// own opp(i), shifted as opp(i): c_ix us3 too high for direction i.  These
+// steps take the bounced values down in two halves, so that between them
+// they are true deviations (the diffuse wall mixes them there).
+template <typename T>
+__device__ __forceinline__ void bounced_half_shift(const PhysK<T> &ph, uint32_t solid_bits, T (&hC)[19]) {
 #pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                if (CX[i] == 0) continue;
-                const T a = T(CX[i]) * ph.us3;
-                hC[i] += ((solid_bits >> i) & 1u) ? -a : a;
-            }
-        }
+    for (int i = 1; i < 19; ++i) {
+        if (CX[i] == 0) continue;
+        if ((solid_bits >> i) & 1u) hC[i] -= T(CX[i]) * ph.us3;
     }
 }
-// ... and the term taken off before the carrier's own populations are stored
-template <int ST>
-__device__ __forceinline__ void carrier_shift(const PhysK<typename Store<ST>::T> &ph, typename Store<ST>::T (&hC)[19]) {
-    using T = typename Store<ST>::T;
-    if constexpr (Store<ST>::ROUNDS) {
-        if (ph.us3 != T(0)) {
+// true deviations -> shifted form (initial state)
+template <typename T>
+__device__ __forceinline__ void carrier_shift(const PhysK<T> &ph, T (&hC)[19]) {
+    if (ph.us3 != T(0)) {
 #pragma unroll
-            for (int i = 1; i < 19; ++i)
-                if (CX[i] != 0) hC[i] -= T(CX[i]) * ph.us3;
-        }
+        for (int i = 1; i < 19; ++i)
+            if (CX[i] != 0) hC[i] -= T(CX[i]) * ph.us3;
+    }
+}
+// shifted form -> true deviations (population readback)
+template <typename T>
+__device__ __forceinline__ void carrier_unshift(const PhysK<T> &ph, T (&hC)[19]) {
+    if (ph.us3 != T(0)) {
+#pragma unroll
+        for (int i = 1; i < 19; ++i)
+            if (CX[i] != 0) hC[i] += T(CX[i]) * ph.us3;
     }
 }
 
@@ -505,7 +512,8 @@ __device__ __forceinline__ void inflow_ghost(const PhysK<T> &ph, const T (&hC)[1
     T d, jx, jy, jz;
     weighted_moments(hC, d, jx, jy, jz);
     const T inv = T(1) / (ph.rref + d);
-    const T ux = (jx + T(0.5) * ph.fx) * inv, uy = (jy + T(0.5) * ph.fy) * inv, uz = (jz + T(0.5) * ph.fz) * inv;
+    // the carrier is in its shifted form (reference flow usx)
+    const T ux = (jx + ph.usx + T(0.5) * ph.fx) * inv, uy = (jy + T(0.5) * ph.fy) * inv, uz = (jz + T(0.5) * ph.fz) * inv;
     const T uu = ux * ux + uy * uy + uz * uz;
     const T cin = T(ph.c_in);
 #pragma unroll
@@ -660,8 +668,13 @@ __device__ __forceinline__ void pull(const Geometry &g, const PhysK<typename Sto
         const T v_cat = bounce ? ph.keep * (v + ph.cref) - ph.cref : (uniform ? e * inv_wgt<T>(i) : e) - ph.cref;
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
-    carrier_unshift<ST>(ph, solid_bits, hC);
+    // the reference flow (none with FP32 storage, whose sweep is register bound)
+    const bool shifted = ST != ST_F32 && ph.us3 != T(0);
+    if constexpr (ST != ST_F32)
+        if (shifted) bounced_half_shift(ph, solid_bits, hC);
     if (diffuse && solid_bits != 0u) diffuse_wall(ph.sigma, solid_bits, hC);
+    if constexpr (ST != ST_F32)
+        if (shifted) bounced_half_shift(ph, solid_bits, hC);
     if (inflow && first_chunk && lane_in(lane0)) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
@@ -1156,8 +1169,13 @@ __device__ __forceinline__ void pull_c(const Geometry &g, const PhysK<typename S
         hR[i] = ((cat_bits >> i) & 1u) ? v_cat : v;
     }
     if constexpr (PROD) hP[0] = Store<ST>::cv(pp[0]);
-    carrier_unshift<ST>(ph, solid_bits, hC);
+    // the reference flow (none with FP32 storage, whose sweep is register bound)
+    const bool shifted = ST != ST_F32 && ph.us3 != T(0);
+    if constexpr (ST != ST_F32)
+        if (shifted) bounced_half_shift(ph, solid_bits, hC);
     if (diffuse && solid_bits != 0u) diffuse_wall(ph.sigma, solid_bits, hC);
+    if constexpr (ST != ST_F32)
+        if (shifted) bounced_half_shift(ph, solid_bits, hC);
     if (inflow && __builtin_amdgcn_ballot_w64(first_x) != 0u && first_x) inflow_ghost(ph, hC, hR);
     cat_out = cat_bits;
 }
@@ -1205,7 +1223,7 @@ __device__ __forceinline__ Mom<T> moments(const PhysK<T> &ph, const T (&hC)[19],
         weighted_moments(hR, m.dr, rx, ry, rz);
         m.rr = ph.cref + m.dr;
         const T inv = T(1) / (m.rc + m.rr);
-        m.ux = (jx + rx + T(0.5) * ph.fx) * inv;
+        m.ux = (jx + ph.usx + rx + T(0.5) * ph.fx) * inv;
         m.uy = (jy + ry + T(0.5) * ph.fy) * inv;
         m.uz = (jz + rz + T(0.5) * ph.fz) * inv;
     } else {
@@ -1220,7 +1238,8 @@ __device__ __forceinline__ Mom<T> moments(const PhysK<T> &ph, const T (&hC)[19],
         m.dr = wgt<T>(0) * hR[0] + wgt<T>(1) * axis + wgt<T>(4) * diag;
         m.rr = ph.cref + m.dr;
         const T inv = T(1) / m.rc;
-        m.ux = (jx + T(0.5) * ph.fx) * inv;
+        // jx is the shifted form's x-moment: the true one less usx
+        m.ux = (jx + ph.usx + T(0.5) * ph.fx) * inv;
         m.uy = (jy + T(0.5) * ph.fy) * inv;
         m.uz = (jz + T(0.5) * ph.fz) * inv;
     }
@@ -1228,7 +1247,8 @@ __device__ __forceinline__ Mom<T> moments(const PhysK<T> &ph, const T (&hC)[19],
 }
 
 // BGK collision in normalised form: h* = h - omega (h - heq) (+ Guo / w_i on
-// the carrier), heq_i = (rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u).
+// the carrier), heq_i = (rho - rho_ref) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u);
+// the carrier's h and heq both in the shifted form (less 3 c_ix U).
 // Directions are taken in opposite pairs (c.u and c.F change sign), which
 // shares most of the arithmetic between the two.
 template <typename T>
@@ -1246,7 +1266,9 @@ __device__ __forceinline__ void collide(const PhysK<T> &ph, const Mom<T> &m, T (
         const T cu = T(CX[i]) * m.ux + T(CY[i]) * m.uy + T(CZ[i]) * m.uz;
         const T cf = T(CX[i]) * ph.fx + T(CY[i]) * ph.fy + T(CZ[i]) * ph.fz;  // wave-uniform
         const T q = T(4.5) * cu * cu, l = T(3) * cu;
-        const T tc = base_c + m.rc * q, sc = m.rc * l;
+        // the carrier's linear equilibrium term 3 rho c.u in its shifted form
+        // (less 3 c_x U)
+        const T tc = base_c + m.rc * q, sc = m.rc * l - T(CX[i]) * ph.us3;
         const T tr = base_r + m.rr * q, sr = m.rr * l;
         const T a = guo9 * cu * cf - guo3 * uf, b = guo3 * cf;  // Guo term: a + b (i), a - b (opp)
         hC[i] = hC[i] - ph.om_c * (hC[i] - (tc + sc)) + (a + b);
@@ -1546,7 +1568,6 @@ __device__ __forceinline__ void sweep_block(const Geometry &g, const PhysK<typen
                 if (CX[i] == 1) acc[2] += double(wgt<T>(i) * (hR[i] + ph.cref));
         }
         collide(ph, m, hC, hR);
-        carrier_shift<ST>(ph, hC);
         using P = typename Store<ST>::P;
         uint32_t own_b = node_elem(g, u.idx) * uint32_t(sizeof(P));
         const lbmfx::RoundWords rw = lbmfx::round_words(ph.sr != 0u, ph.sr_key, u.idx);
@@ -1640,7 +1661,6 @@ __device__ __forceinline__ void sweep_block_c(const Geometry &g, const PhysK<typ
                 if (CX[i] == 1) acc[2] += double(wgt<T>(i) * (hR[i] + ph.cref));
         }
         collide(ph, m, hC, hR);
-        carrier_shift<ST>(ph, hC);
         using P = typename Store<ST>::P;
         const uint32_t own_e = node_elem(g, idx);
         uint32_t own_b = own_e * uint32_t(sizeof(P));
@@ -1740,7 +1760,6 @@ __global__ __launch_bounds__(256) void k_fields(Geometry g, PhysK<typename Store
                 hC[i] = Store<ST>::cv(v.x);
                 hR[i] = Store<ST>::cv(v.y);
             }
-            carrier_unshift<ST>(ph, 0u, hC);  // slot i holds the node's own population i
         } else {
             uint32_t cat_bits;
             pull<ST, -1>(g, ph, in, emit, u, hC, hR, cat_bits);
@@ -1789,15 +1808,11 @@ __global__ __launch_bounds__(256) void k_init(Geometry g, PhysK<typename Store<S
         hC[i] = ph.h0c;
         hR[i] = ph.h0r;
     }
-    T sC[19];
+    carrier_shift(ph, hC);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) sC[i] = hC[i];
-    carrier_shift<ST>(ph, sC);
-#pragma unroll
-    for (int i = 0; i < 19; ++i) pre2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(sC[i], hR[i]);
+    for (int i = 0; i < 19; ++i) pre2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(hC[i], hR[i]);
     const Mom<T> m = moments(ph, hC, hR);
     collide(ph, m, hC, hR);
-    carrier_shift<ST>(ph, hC);
 #pragma unroll
     for (int i = 0; i < 19; ++i) post2[slot_elem(g, dslot(i)) + node_elem(g, uint32_t(n))] = pop_pair<ST>(hC[i], hR[i]);
 }
@@ -1913,11 +1928,11 @@ __global__ __launch_bounds__(256) void k_populations(Geometry g, PhysK<typename 
                 hC[i] = Store<ST>::cv(v.x);
                 hR[i] = Store<ST>::cv(v.y);
             }
-            carrier_unshift<ST>(ph, 0u, hC);  // slot i holds the node's own population i
         } else {
             uint32_t cat_bits;
             pull<ST, -1>(g, ph, in, emit, u, hC, hR, cat_bits);
         }
+        carrier_unshift(ph, hC);  // the populations themselves
     }
     if (!inside) return;
     const int64_t wn = int64_t(win.wx) * win.wy * win.wz;

@@ -274,8 +274,8 @@ class Sim:
     wall) or wall_accommodation=sigma_v (the diffuse fraction derived from Kn
     for Maxwell's slip; info()["wall_sigma"] reports it),
     rounding=ROUND_STOCHASTIC (stochastic rounding of 16-bit stores),
-    store_ux=U (16-bit storage: the carrier stores its deviation less the
-    part linear in a reference x-velocity U),
+    store_ux=U (a reference flow: the carrier is stored and relaxed as its
+    deviation less the part linear in the x-velocity U),
     lattice=LATTICE_D2Q9 (the paper's D2Q9 on one plane, FP64; see lbm.h)."""
 
     def __init__(self, vox, da, tau=(0.0, 0.0), kn=0.0, pore_size=1.0, use_torch=True, stream=None, **kw):

@@ -114,12 +114,48 @@ def test_plain_16bit_storage_with_reference_flow(plain_ref, storage, rounding):
         assert e[k] < 1e-3, (k, e[k])
 
 
-def test_reference_flow_is_ignored_by_fp32_and_fp64():
+@pytest.mark.parametrize("sputter,coupling,species_x", [
+    ("UNIFORM", "PASSIVE", "RESERVOIR"),
+    ("BOUNCEBACK", "BARYCENTRIC", "INFLOW"),
+    ("WEIGHTED", "PASSIVE", "PERIODIC"),
+])
+def test_reference_flow_fp64_matches_oracle(sputter, coupling, species_x):
+    """The carrier in its shifted form (a reference flow far from the flow's
+    own) gives the oracle's fields to FP64 rounding: the shift is exact
+    algebra, through bounce-back, both couplings and the moving inlet."""
+    c = plain_case(steps=60, sputter=sputter, coupling=coupling, species_x=species_x, c0=0.2, p_stick=0.6)
+    ref = run_oracle(c)
+    gpu = run_gpu(dict(c, store_ux=0.05), F64)
+    e, t = errors(gpu, ref, c["vox"]), totals_rel(gpu, ref)
+    _report(f"reference flow 0.05, fp64, {sputter}-{coupling}-{species_x}", e, t)
+    for k in ("rho", "u", "conc", "conv"):
+        assert e[k] < 1e-12, (k, e[k])
+    for k, v in t.items():
+        assert v < 1e-11, (k, v)
+
+
+def test_reference_flow_is_ignored_by_fp32():
     c = plain_case(steps=30)
-    for storage in (F32, F64):
-        a, b = run_gpu(c, storage), run_gpu(dict(c, store_ux=0.05), storage)
-        for k in ("rho", "u", "conc", "conv"):
-            assert np.array_equal(a[k], b[k]), (storage, k)
+    a, b = run_gpu(c, F32), run_gpu(dict(c, store_ux=0.05), F32)
+    for k in ("rho", "u", "conc", "conv"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("storage", [F64, F16])
+def test_reference_flow_compact_and_chunk_sweeps_agree(storage):
+    from paper_1607_02874_amd import lbm
+
+    c = dict(plain_case(steps=23, sputter="BOUNCEBACK", species_x="PERIODIC", c0=0.2), store_ux=0.02)
+    out = []
+    for variant in (1, 0):
+        s = make_sim(c, storage)
+        s.set_tunable(lbm.TUNE_SWEEP, variant)
+        s.step(c["steps"])
+        out.append((s.fields(), s.conversion_map()))
+        s.close()
+    (fa, ca), (fb, cb) = out
+    assert all(np.array_equal(a, b) for a, b in zip(fa, fb))
+    assert np.array_equal(ca, cb)
 
 
 def test_reference_flow_checkpoint(tmp_path):

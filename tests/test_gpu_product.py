@@ -49,7 +49,7 @@ def make_sim(c, storage, product=True, rounding=0):
     return lbm.Sim(c["vox"], da=c["da"], tau=c["tau"], pore_size=c["pore_size"], p_stick=c["p_stick"],
                    c_inlet=c["c_inlet"], c0=c["c0"], force=c["force"], sputter=SPUTTER[c["sputter"]],
                    species_x=XBC[c["species_x"]], storage=storage, product=product,
-                   p_stick_product=c["p_stick_product"], rounding=rounding)
+                   p_stick_product=c["p_stick_product"], rounding=rounding, store_ux=c.get("store_ux", 0.0))
 
 
 def run_gpu(c, storage, rounding=0):
@@ -88,6 +88,12 @@ def test_product_fp64_matches_oracle(sputter, species_x):
     ref = run_oracle(c)
     assert ref["totals"]["mass_product"] > 0.0 and ref["totals"]["lost_product"] > 0.0
     _check(product_errors(run_gpu(c, F64), ref, c["vox"]), 1e-12, 1e-11)
+
+
+def test_product_with_reference_flow_fp64_matches_oracle():
+    """The product lattice, advected by a carrier in its shifted form."""
+    c = dict(pcase(PLAIN.voxels(), 60, sputter="UNIFORM", species_x="INFLOW"), store_ux=0.03)
+    _check(product_errors(run_gpu(c, F64), run_oracle(c), c["vox"]), 1e-12, 1e-11)
 
 
 # BF16 with stochastic rounding sits at its 8-bit noise floor on the velocity

@@ -38,11 +38,11 @@ def run_oracle(c):
     return out
 
 
-def run_gpu(c, storage, variant, rounding=0):
+def run_gpu(c, storage, variant, rounding=0, store_ux=0.0):
     with lbm.Sim(c["vox"], da=c["da"], tau=c["tau"], pore_size=c["pore_size"], p_stick=c["p_stick"],
                  c_inlet=c["c_inlet"], c0=c["c0"], force=c["force"], sputter=SPUT[c["sputter"]][1],
                  species_x=XBC[c["species_x"]], storage=storage, seed=c["seed"], wall_diffuse=c["sigma"],
-                 rounding=rounding) as s:
+                 rounding=rounding, store_ux=store_ux) as s:
         s.set_tunable(lbm.TUNE_SWEEP, variant)
         s.step(c["steps"])
         rho, u, conc = s.fields()
@@ -68,6 +68,16 @@ def errs(g, r, vox):
 def test_diffuse_wall_fp64_matches_oracle(sigma, sputter, species_x, variant):
     c = wcase(inputs.PLAIN_32.voxels(), 50, sigma=sigma, sputter=sputter, species_x=species_x)
     e = errs(run_gpu(c, F64, variant), run_oracle(c), c["vox"])
+    for k, v in e.items():
+        assert v < (1e-11 if k.startswith("t_") else 1e-12), (k, v)
+
+
+@pytest.mark.parametrize("variant", [1, 0])
+def test_diffuse_wall_with_reference_flow_fp64_matches_oracle(variant):
+    """The diffuse wall mixes true deviations also when the carrier runs in
+    its shifted form (reference flow)."""
+    c = wcase(inputs.PLAIN_32.voxels(), 50, sigma=0.7, sputter="UNIFORM", species_x="RESERVOIR")
+    e = errs(run_gpu(c, F64, variant, store_ux=0.04), run_oracle(c), c["vox"])
     for k, v in e.items():
         assert v < (1e-11 if k.startswith("t_") else 1e-12), (k, v)
 
