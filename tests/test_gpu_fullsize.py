@@ -279,9 +279,9 @@ def column_fp64_5000(vox_membrane):
 
 
 # Measured over 5000 steps: FP32 drifts past 1e-5 in this column (u 7.7e-5,
-# conc 1.1e-4); a build that ran FP32 with the reference flow drifted the same
-# (u 8.8e-5), so the drift does not come from the size of the values the
-# carrier rounds.  FP16 with stochastic
+# conc 1.1e-4): every node of the uniform free gas makes the same FP32 error
+# summing its moments, step after step, and the relaxation turns it into a
+# momentum source (a build summing them in FP64 reached u 2.5e-6).  FP16 with stochastic
 # rounding stays within 1e-3 (u 2.9e-4); BF16's noise grows past it over this
 # history even with the reference flow, and rounding to nearest with the
 # reference flow accumulates a bias.
