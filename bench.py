@@ -431,7 +431,9 @@ def run_batch(args):
 def run_precision(args):
     """512^3 porous sample (porosity 0.70, correlation length 12, seed 1002):
     the same run with FP32, FP16 and BF16 storage (FP32 arithmetic) and the
-    FP64 build; per storage the throughput, the speedup over FP32 and the
+    FP64 build, and FP16 with stochastic rounding and BF16 with stochastic
+    rounding and the carrier's reference flow (the FP32 run's mean
+    x-velocity); per run the throughput, the speedup over FP32 and the
     L2-relative field errors against the FP64 build after the same steps."""
     import torch
 
@@ -443,10 +445,15 @@ def run_precision(args):
     gas = vox == 0
     log(f"geometry {w.nx}x{w.ny}x{w.nz} porosity {inputs.porosity(vox):.4f} ({time.perf_counter() - t0:.1f} s)")
     results, fields = {}, {}
-    for name in ("f64", "f32", "f16", "bf16"):
-        storage = STORAGES[name]
+    # name: storage, rounding of 16-bit stores, reference flow (the FP32 run's
+    # mean x-velocity over the gas nodes)
+    runs = {"f64": ("f64", 0, False), "f32": ("f32", 0, False), "f16": ("f16", 0, False), "bf16": ("bf16", 0, False),
+            "f16-sr": ("f16", 1, False), "bf16-sr-ref": ("bf16", 1, True)}
+    u_ref = 0.0
+    for name, (sname, rounding, shifted) in runs.items():
+        storage = STORAGES[sname]
         sim = lbm.Sim(vox, da=w.da, tau=w.tau, pore_size=w.pore_size, force=w.force(), p_stick=w.p_stick,
-                      c_inlet=w.c_inlet, storage=storage)
+                      c_inlet=w.c_inlet, storage=storage, rounding=rounding, store_ux=u_ref if shifted else 0.0)
         info = sim.info()
         if not args.no_autotune:
             sim.autotune(3)
@@ -466,7 +473,11 @@ def run_precision(args):
         sim.close()
         ab = algorithmic_bytes(info, lbm.STORAGE_BYTES[storage])
         t_sweep = kt["ms_sweep"] / kt["n_sweep"] * 1e-3
+        if name == "f32":
+            u_ref = float(u[0][gas].mean())
         results[name] = {"mlups": round(vox.size * args.steps / el / 1e6, 1),
+                         "rounding": "stochastic" if rounding else "nearest",
+                         "store_ux": round(u_ref, 6) if shifted else 0.0,
                          "sweep": sim_tunables,
                          "ms_per_step": round(el / args.steps * 1e3, 4),
                          "sweep_us": round(t_sweep * 1e6, 2),
@@ -480,7 +491,7 @@ def run_precision(args):
                                              for k, a, b in zip(("rho", "u", "conc", "conv"), got, ref)}
         del rho, u, c, conv
         log(f"{name}: {results[name]}")
-    for name in ("f16", "bf16"):
+    for name in ("f16", "bf16", "f16-sr", "bf16-sr-ref"):
         results[name]["speedup_vs_f32"] = round(results["f32"]["ms_per_step"] / results[name]["ms_per_step"], 3)
     best = "f16"
     line = {
